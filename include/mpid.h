@@ -1,0 +1,170 @@
+/*
+ * mpid.h -- C ABI of the MI355X (gfx950) column interpolative decomposition.
+ *
+ * The column ID approximates A (m x n) by k of its own columns,
+ *     A ~= A(:, J) P,   P = [I_k  T] Z^T,   T = R11^{-1} R12,
+ * where A Z = Q R is a column-pivoted QR truncated after k steps
+ * (Dunton & Fox, arXiv 2012.00706: Section 1.1, eq. (4)-(8); Algorithm 1 for
+ * the double-precision ID, Algorithm 2 for the mixed/low-precision ID).
+ *
+ * Conventions shared by every entry point
+ *   - Matrices are column-major.  "ld" arguments are leading dimensions in
+ *     elements.  Pointers are DEVICE pointers unless marked [host].
+ *   - The caller owns every buffer.  The library allocates no device memory
+ *     in these calls; scratch space is the caller's workspace ("work").
+ *   - Indices are 0-based.  perm is int32 with A(:, perm) = Q R, J = perm[0:k].
+ *   - R, T, Y and gradients are float64: products are evaluated in double
+ *     precision (remark after Lemma 1).
+ *   - "stream" is a hipStream_t passed as void*; NULL means the default stream.
+ *   - Synchronous return codes (< 0) report bad arguments, workspace and HIP
+ *     errors; numerical conditions are reported through "info" codes (> 0).
+ */
+#ifndef MPID_H
+#define MPID_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- return / info codes ------------------------------------------------ */
+#define ID_OK 0
+#define ID_ERR_ARG (-1)         /* invalid argument (null pointer, size, ld, option) */
+#define ID_ERR_DTYPE (-2)       /* unknown dtype or precision */
+#define ID_ERR_WORKSPACE (-3)   /* work_bytes smaller than id_workspace_size() */
+#define ID_ERR_HIP (-4)         /* a HIP runtime call failed */
+#define ID_ERR_UNSUPPORTED (-5) /* combination not supported */
+#define ID_INFO_NONFINITE 1     /* A holds NaN or Inf: nothing was factored (k = 0) */
+#define ID_INFO_SINGULAR 2      /* R11 has |R_ii| <= n * 2^-53 * |R_00|; T not formed */
+#define ID_INFO_RANK_FULL 3     /* k = n: T has no columns, P is a permutation */
+
+/* ---- storage dtype of A -------------------------------------------------- */
+#define ID_F32 0
+#define ID_F64 1
+
+/* ---- precision policy of the factorization -------------------------------
+ * ID_PREC_F64:        working copy, sweeps and the blocked trailing update in
+ *                     float64 (the double-precision ID of Algorithm 1).
+ * ID_PREC_MIXED_F16:  working copy in float32; the blocked trailing update on
+ *                     FP16 matrix cores with FP32 accumulation (operands scaled
+ *                     by powers of two, which is exact, so they stay in FP16
+ *                     range); column norms, R, the recomputation of norms and the
+ *                     triangular solve in float64 (Algorithm 2, mixed variant).
+ * ID_PREC_MIXED_BF16: as above with BF16 operands (no scaling needed).      */
+#define ID_PREC_F64 0
+#define ID_PREC_MIXED_F16 1
+#define ID_PREC_MIXED_BF16 2
+
+/* ---- adaptive rank rules (used when k_fixed == 0) ------------------------
+ * ID_RANK_PIVOT_REL: stop before step j >= 1 once the largest remaining column
+ *                    norm is <= rel_tol * |R_00|, or is zero.
+ * ID_RANK_FROB_REL:  stop once the Frobenius norm of the remaining block is
+ *                    <= rel_tol * ||A||_F (then ||A - A(:,J)P||_F <= rel_tol ||A||_F
+ *                    up to rounding).                                       */
+#define ID_RANK_PIVOT_REL 0
+#define ID_RANK_FROB_REL 1
+
+/* ---- flags --------------------------------------------------------------- */
+#define ID_FLAG_NO_PIVOT 1 /* unpivoted Householder QR (perm = identity) */
+
+typedef struct {
+  int32_t prec;      /* ID_PREC_* */
+  int32_t rank_rule; /* ID_RANK_* */
+  int64_t k_fixed;   /* > 0: exactly min(k_fixed, k_max) steps; 0: adaptive */
+  double rel_tol;    /* adaptive tolerance, >= 0 */
+  int64_t k_max;     /* cap on k; 0 means min(m, n) */
+  int32_t nb;        /* panel width of the blocked update, 1..32; 0 = 32 */
+  int32_t flags;     /* ID_FLAG_* */
+} id_opts;
+
+/* Bytes of device workspace id_factor needs for an m x n input of storage
+ * dtype "dtype" under "opts" [host].  Returns 0 for invalid arguments. */
+size_t id_workspace_size(int64_t m, int64_t n, int32_t dtype, const id_opts* opts);
+
+/* Column-pivoted Householder QR of A truncated after k steps (Section 1.1,
+ * eq. (6)-(7); the MGSQR(A, k) step of Algorithms 1 and 2 -- computed here
+ * with Householder reflectors, a blocked trailing update and norm downdating).
+ *
+ *   A      [in]  m x n, lda >= max(1, m), storage dtype "dtype" (ID_F32/ID_F64).
+ *                Not modified.
+ *   opts   [host] precision, rank selection and panel width.
+ *   work   [in]  device workspace of work_bytes >= id_workspace_size(...).
+ *   perm   [out] n int32: the column order; J = perm[0:k].
+ *   R      [out] float64, ldr >= kcap where kcap = min(m, n, k_max, k_fixed>0 ?
+ *                k_fixed : inf).  Rows 0..k-1 of the k x n upper-trapezoidal
+ *                factor in pivot order are written (zeros below the diagonal);
+ *                rows k..kcap-1 are left untouched.
+ *   k_out  [host,out] the rank k.
+ *   info   [host,out] 0, or ID_INFO_NONFINITE.
+ *
+ * Pivoting follows the largest remaining column norm with ties going to the
+ * first column in the current (LAPACK swap) order.  The call enqueues work on
+ * "stream" and synchronizes it before returning: the number of pivot steps is
+ * data dependent.  Concurrent calls must use distinct workspaces. */
+int id_factor(const void* A, int32_t dtype, int64_t m, int64_t n, int64_t lda,
+              const id_opts* opts, void* work, size_t work_bytes, int32_t* perm, double* R,
+              int64_t ldr, int64_t* k_out, int32_t* info, void* stream);
+
+/* Interpolation coefficients T = R11^{-1} R12 in float64 (eq. (8); the
+ * coefficient step of Algorithms 1 and 2; Remark 1.1's pseudo-inverse equals
+ * the inverse whenever R11 is nonsingular, which this call checks).
+ *
+ *   R     [in]  k x n upper trapezoidal (as written by id_factor), ldr >= k.
+ *   k, n  [host] rank and column count, 0 <= k <= n.
+ *   T     [out] k x (n-k), ldt >= max(1, k).
+ *   info  [out] device int32: 0, ID_INFO_SINGULAR (T not written) or
+ *               ID_INFO_RANK_FULL (k == n, nothing to write).
+ * Asynchronous on "stream". */
+int id_solve_T(const double* R, int64_t ldr, int64_t k, int64_t n, double* T, int64_t ldt,
+               int32_t* info, void* stream);
+
+/* Reconstruction Y = A(:, J) P in float64 (eq. (4)-(5) with P from eq. (8),
+ * products in double precision as in the remark after Lemma 1):
+ * Y(:, perm[j]) = A(:, perm[j]) for j < k, Y(:, perm[k+c]) = A(:, J) T(:, c).
+ * If "residual" is nonzero, Y receives A - A(:, J) P instead.
+ *
+ *   A    [in]  m x n, lda, storage dtype "dtype".
+ *   perm [in]  n int32 permutation; k [host] rank.
+ *   T    [in]  k x (n-k) float64, ldt >= max(1, k).
+ *   Y    [out] m x n float64, ldy >= max(1, m).
+ * Asynchronous on "stream". */
+int id_reconstruct(const void* A, int32_t dtype, int64_t m, int64_t n, int64_t lda,
+                   const int32_t* perm, int64_t k, const double* T, int64_t ldt, double* Y,
+                   int64_t ldy, int32_t residual, void* stream);
+
+/* Bytes of device workspace id_backward needs [host]. */
+size_t id_backward_workspace_size(int64_t m, int64_t n, int64_t k);
+
+/* Adjoint of the ID with the skeleton J = perm[0:k] held fixed (not in the
+ * paper).  With B = A(:, J), C = A(:, Jc) the coefficients are the least-squares
+ * solution T = B^+ C, which equals R11^{-1} R12 (eq. (6)-(8)).  Given
+ * cotangents gT of T (k x (n-k)) and/or gY of Y = A(:, J) P (m x n), writes
+ * gA = d<gT, T> / dA + d<gY, Y> / dA:
+ *     Tbar = gT + B^T gY(:, Jc),   X = (B^T B)^{-1} Tbar,
+ *     gA(:, Jc) = B X,
+ *     gA(:, J)  = (C - B T) X^T - B X T^T + gY(:, J) + gY(:, Jc) T^T.
+ * (B^T B)^{-1} is applied through the R factor of an FP64 Householder QR of B.
+ *
+ *   A       [in]  m x n, lda, storage dtype "dtype"; perm [in] n int32; k [host].
+ *   T       [in]  k x (n-k) float64, ldt.
+ *   gT      [in]  k x (n-k) float64, ldgt, or NULL.
+ *   gY      [in]  m x n float64, ldgy, or NULL.
+ *   gA      [out] m x n float64, ldga.
+ *   work    [in]  workspace of >= id_backward_workspace_size(m, n, k) bytes.
+ *   info    [host,out] 0 or ID_INFO_SINGULAR (B numerically rank deficient).
+ * Synchronizes "stream" before returning. */
+int id_backward(const void* A, int32_t dtype, int64_t m, int64_t n, int64_t lda,
+                const int32_t* perm, int64_t k, const double* T, int64_t ldt, const double* gT,
+                int64_t ldgt, const double* gY, int64_t ldgy, double* gA, int64_t ldga,
+                void* work, size_t work_bytes, int32_t* info, void* stream);
+
+/* Human-readable text for a return or info code [host]. */
+const char* id_status_string(int code);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MPID_H */

@@ -1,0 +1,76 @@
+// extern "C" entry points of libmpid (declared in include/mpid.h).
+#include <hip/hip_runtime.h>
+
+#include "mpid.h"
+#include "mpid_internal.h"
+
+extern "C" {
+
+size_t id_workspace_size(int64_t m, int64_t n, int32_t dtype, const id_opts* opts) {
+  mpid::FactorPlan p;
+  if (!mpid::make_factor_plan(m, n, dtype, opts, &p)) return 0;
+  return p.bytes;
+}
+
+int id_factor(const void* A, int32_t dtype, int64_t m, int64_t n, int64_t lda,
+              const id_opts* opts, void* work, size_t work_bytes, int32_t* perm, double* R,
+              int64_t ldr, int64_t* k_out, int32_t* info, void* stream) {
+  if (dtype != ID_F32 && dtype != ID_F64) return ID_ERR_DTYPE;
+  if (!opts) return ID_ERR_ARG;
+  if (opts->prec != ID_PREC_F64 && opts->prec != ID_PREC_MIXED_F16 &&
+      opts->prec != ID_PREC_MIXED_BF16)
+    return ID_ERR_DTYPE;
+  return mpid::factor_run(A, dtype, m, n, lda, opts, work, work_bytes, perm, R, ldr, k_out, info,
+                          (hipStream_t)stream);
+}
+
+int id_solve_T(const double* R, int64_t ldr, int64_t k, int64_t n, double* T, int64_t ldt,
+               int32_t* info, void* stream) {
+  return mpid::solve_T_run(R, ldr, k, n, T, ldt, info, (hipStream_t)stream);
+}
+
+int id_reconstruct(const void* A, int32_t dtype, int64_t m, int64_t n, int64_t lda,
+                   const int32_t* perm, int64_t k, const double* T, int64_t ldt, double* Y,
+                   int64_t ldy, int32_t residual, void* stream) {
+  return mpid::reconstruct_run(A, dtype, m, n, lda, perm, k, T, ldt, Y, ldy, residual,
+                               (hipStream_t)stream);
+}
+
+size_t id_backward_workspace_size(int64_t m, int64_t n, int64_t k) {
+  return mpid::backward_workspace(m, n, k);
+}
+
+int id_backward(const void* A, int32_t dtype, int64_t m, int64_t n, int64_t lda,
+                const int32_t* perm, int64_t k, const double* T, int64_t ldt, const double* gT,
+                int64_t ldgt, const double* gY, int64_t ldgy, double* gA, int64_t ldga,
+                void* work, size_t work_bytes, int32_t* info, void* stream) {
+  return mpid::backward_run(A, dtype, m, n, lda, perm, k, T, ldt, gT, ldgt, gY, ldgy, gA, ldga,
+                            work, work_bytes, info, (hipStream_t)stream);
+}
+
+const char* id_status_string(int code) {
+  switch (code) {
+    case ID_OK:
+      return "ok";
+    case ID_ERR_ARG:
+      return "invalid argument";
+    case ID_ERR_DTYPE:
+      return "unknown dtype or precision";
+    case ID_ERR_WORKSPACE:
+      return "workspace too small";
+    case ID_ERR_HIP:
+      return "HIP runtime error";
+    case ID_ERR_UNSUPPORTED:
+      return "unsupported combination";
+    case ID_INFO_NONFINITE:
+      return "input holds NaN or Inf";
+    case ID_INFO_SINGULAR:
+      return "R11 is numerically singular";
+    case ID_INFO_RANK_FULL:
+      return "full rank: k == n";
+    default:
+      return "unknown code";
+  }
+}
+
+}  // extern "C"

@@ -1,0 +1,1045 @@
+// Rank-k column-pivoted Householder QR on gfx950 (MI355X).
+//
+// The method is the truncated column-pivoted QR  A Z = Q R  of the column ID
+// (Section 1.1, eq. (6)-(7); the MGSQR(A, k) step of Algorithms 1 and 2), with
+// Householder reflectors and a lazily blocked ("left-looking within a panel")
+// trailing update: inside a panel of up to nb pivots the trailing columns are
+// not touched; each step only
+//   1. picks the remaining column of largest (downdated) norm,
+//   2. brings that column up to date (w = W(:,p) - V F(p,:)^T),
+//   3. builds its reflector and sweeps the stale trailing block once to get
+//      the new column of F and the new row of R,
+//   4. downdates the remaining column norms,
+// and at the end of the panel one matrix-core update W -= V F^T refreshes the
+// trailing block, recomputes every column norm in FP64 from the refreshed
+// data, and compacts away the columns that were pivoted.
+//
+// Data layout: the working copy W is ROW-major (ld = ldw >= n, multiple of 64)
+// so that the dominant operation -- W^T v over a tall block -- streams rows
+// with fully coalesced 16-byte loads, lanes owning columns and the reflector
+// entry of a row being a broadcast value.  Reflectors are stored unscaled
+// (V(:,c) = Vraw(:,c) * vscale[c]) column-major; F is column-major over the
+// positions of the current layout.  R is accumulated by ORIGINAL column id and
+// gathered into pivot order at the end.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+
+#include "device_util.h"
+#include "mpid_internal.h"
+
+namespace mpid {
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+template <typename S>
+struct Vec16;
+template <>
+struct Vec16<float> {
+  typedef float type __attribute__((ext_vector_type(4)));
+  static constexpr int n = 4;
+};
+template <>
+struct Vec16<double> {
+  typedef double type __attribute__((ext_vector_type(2)));
+  static constexpr int n = 2;
+};
+
+enum { OP_F64 = 0, OP_F16 = 1, OP_BF16 = 2 };
+
+// ----------------------------------------------------------------- plan
+
+bool make_factor_plan(int64_t m, int64_t n, int32_t dtype, const id_opts* o, FactorPlan* p) {
+  if (!o || !p || m < 0 || n < 0) return false;
+  if (dtype != ID_F32 && dtype != ID_F64) return false;
+  if (o->prec != ID_PREC_F64 && o->prec != ID_PREC_MIXED_F16 && o->prec != ID_PREC_MIXED_BF16)
+    return false;
+  if (o->rank_rule != ID_RANK_PIVOT_REL && o->rank_rule != ID_RANK_FROB_REL) return false;
+  if (o->k_fixed < 0 || o->k_max < 0 || !(o->rel_tol >= 0.0)) return false;
+  const int nb = o->nb == 0 ? kNbMax : o->nb;
+  if (nb < 1 || nb > kNbMax) return false;
+  if (m > (int64_t)1 << 31 || n > (int64_t)1 << 30) return false;
+  int64_t kcap = m < n ? m : n;
+  if (o->k_max > 0 && o->k_max < kcap) kcap = o->k_max;
+  if (o->k_fixed > 0 && o->k_fixed < kcap) kcap = o->k_fixed;
+  std::memset(p, 0, sizeof(*p));
+  p->m = m;
+  p->n = n;
+  p->kcap = kcap;
+  p->dtype = dtype;
+  p->prec = o->prec;
+  p->nb = nb;
+  p->wbytes = o->prec == ID_PREC_F64 ? 8 : 4;
+  const int64_t mm = m > 0 ? m : 1, nn = n > 0 ? n : 1, kk = kcap > 0 ? kcap : 1;
+  p->ldw = round_up(nn, 64);
+  p->ldv = round_up(mm, 64);
+  p->ldf = p->ldw;
+  p->ntile_s_max = ceil_div(mm, kRtMin);
+  p->ntile_g = ceil_div(mm, kRowTileG);
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t at = off;
+    off += (bytes + 255) / 256 * 256;
+    return at;
+  };
+  p->off_w0 = take((size_t)mm * p->ldw * p->wbytes);
+  p->off_w1 = take((size_t)mm * p->ldw * p->wbytes);
+  p->off_v = take((size_t)kNbMax * p->ldv * p->wbytes);
+  p->off_f = take((size_t)kNbMax * p->ldf * 8);
+  p->off_zpart = take((size_t)p->ntile_s_max * p->ldf * 8);
+  p->off_auxpart = take((size_t)p->ntile_s_max * kNbMax * 8);
+  p->off_nrm2part = take((size_t)p->ntile_s_max * 8);
+  p->off_colpart = take((size_t)p->ntile_g * p->ldf * 8);
+  p->off_nu = take((size_t)p->ldf * 8);
+  p->off_nuo = take((size_t)p->ldf * 8);
+  p->off_amax = take((size_t)(p->ldf / kFinCols + 8) * sizeof(AmaxPart));
+  p->off_colid0 = take((size_t)p->ldf * 4);
+  p->off_colid1 = take((size_t)p->ldf * 4);
+  p->off_pvflag = take((size_t)p->ldf * 4);
+  p->off_pivpos = take((size_t)kNbMax * 4);
+  p->off_pivid = take((size_t)kk * 4);
+  p->off_permw = take((size_t)nn * 4);
+  p->off_posof = take((size_t)nn * 4);
+  p->off_tau = take((size_t)kk * 8);
+  p->off_vscale = take((size_t)kNbMax * 8);
+  p->off_rorig = take((size_t)kk * nn * 8);
+  p->off_state = take(sizeof(FactorState));
+  p->bytes = off;
+  return true;
+}
+
+// ----------------------------------------------------------------- kernels
+
+__global__ __launch_bounds__(kThreads) void k_init(FactorState* st, int* colid0, int* pvflag,
+                                                   int* permw, int* posof, int64_t n,
+                                                   int64_t ldf) {
+  const int64_t l = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (l < ldf) {
+    colid0[l] = (int)l;
+    pvflag[l] = 0;
+  }
+  if (l < n) {
+    permw[l] = (int)l;
+    posof[l] = (int)l;
+  }
+  if (l == 0) {
+    st->done = 0;
+    st->end_flag = 0;
+    st->jb = 0;
+    st->last_jb = 0;
+    st->info = 0;
+    st->fmax_bits = 0u;
+    st->k = 0;
+    st->r00 = 0.0;
+    st->alpha = 0.0;
+    st->fro2 = 0.0;
+  }
+}
+
+// A (column-major, lda) -> W (row-major, ldw) in the working precision, with
+// the per-row-tile partial sums of squares of every column (FP64) and a
+// NaN/Inf check.  Block: 64 columns x kRowTileG rows, LDS transpose.
+template <typename TA, typename S>
+__global__ __launch_bounds__(kThreads) void k_ingest(const TA* __restrict__ A, int64_t lda,
+                                                     int64_t m, int64_t n, S* __restrict__ W,
+                                                     int64_t ldw, double* __restrict__ colpart,
+                                                     int64_t ldf, FactorState* st) {
+  __shared__ S tile[64][65];
+  __shared__ double ssq[4][64];
+  const int tid = threadIdx.x;
+  const int64_t c0 = (int64_t)blockIdx.x * 64;
+  const int64_t tg = blockIdx.y;
+  const int64_t rb = tg * kRowTileG;
+  const int64_t re = rb + kRowTileG < m ? rb + kRowTileG : m;
+  double ss = 0.0;
+  bool bad = false;
+  for (int64_t rs = rb; rs < re; rs += 64) {
+#pragma unroll 4
+    for (int q = 0; q < 16; ++q) {
+      const int cc = q * 4 + tid / 64, rr = tid % 64;
+      const int64_t r = rs + rr, c = c0 + cc;
+      S v = (S)0;
+      if (r < re && c < n) {
+        const TA x = A[c * lda + r];
+        if (!isfinite((double)x)) bad = true;
+        v = (S)x;
+      }
+      tile[cc][rr] = v;
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int q = 0; q < 16; ++q) {
+      const int rr = tid / 64 + 4 * q, cc = tid % 64;
+      const int64_t r = rs + rr, c = c0 + cc;
+      if (r < re && c < n) {
+        const S v = tile[cc][rr];
+        W[r * ldw + c] = v;
+        ss += (double)v * (double)v;
+      }
+    }
+    __syncthreads();
+  }
+  ssq[tid / 64][tid % 64] = ss;
+  __syncthreads();
+  if (tid < 64) {
+    const int64_t c = c0 + tid;
+    if (c < n) colpart[tg * ldf + c] = ssq[0][tid] + ssq[1][tid] + ssq[2][tid] + ssq[3][tid];
+  }
+  if (bad) st->info = ID_INFO_NONFINITE;
+}
+
+// Column norms from per-row-tile partial sums of squares (FP64): nu = nu_orig
+// = sqrt(sum); clears the per-panel pivot flags; per-block pivot partials.
+// Block: 32 columns x 8 tile lanes.
+__global__ __launch_bounds__(kThreads) void k_colreduce(
+    const double* __restrict__ colpart, int64_t ldf, int64_t tg0, int64_t tg1, int64_t ncols_base,
+    int subtract_jb, double* __restrict__ nu, double* __restrict__ nuo, AmaxPart* __restrict__ amax,
+    const int* __restrict__ colid, const int* __restrict__ posof, int* __restrict__ pvflag,
+    FactorState* st) {
+  __shared__ double red[8][kFinCols + 1];
+  __shared__ AmaxVal ascr[4];
+  __shared__ int s_go;
+  const int tid = threadIdx.x, cl = tid % kFinCols, tl = tid / kFinCols;
+  if (tid == 0) s_go = (st->done == 0);
+  __syncthreads();
+  if (!s_go) return;
+  const int64_t ncols = ncols_base - (subtract_jb ? st->jb : 0);
+  const int64_t l = (int64_t)blockIdx.x * kFinCols + cl;
+  double s = 0.0;
+  if (l < ncols)
+    for (int64_t t = tg0 + tl; t < tg1; t += 8) s += colpart[t * ldf + l];
+  red[tl][cl] = s;
+  __syncthreads();
+  AmaxVal cand = amax_none();
+  if (tl == 0 && l < ncols) {
+    double tot = 0.0;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) tot += red[q][cl];
+    const double v = sqrt(tot);
+    nu[l] = v;
+    nuo[l] = v;
+    pvflag[l] = 0;
+    cand.v = v;
+    cand.s2 = tot;
+    cand.pos = (int)l;
+    cand.key = posof[colid[l]];
+  }
+  cand = block_amax(cand, ascr);
+  if (tid == 0) {
+    AmaxPart o;
+    o.v = cand.v;
+    o.s2 = cand.s2;
+    o.pos = cand.pos;
+    o.key = cand.key;
+    amax[blockIdx.x] = o;
+  }
+}
+
+template <typename S>
+struct StepArgs {
+  const S* W;
+  int64_t ldw, m, n, ncur;
+  S* V;
+  int64_t ldv;
+  double* F;
+  int64_t ldf;
+  double* vscale;
+  double* tau;
+  FactorState* st;
+  AmaxPart* amax;
+  int namax;
+  int* pvflag;
+  const int* colid;
+  int* pivpos;
+  int* pivid;
+  int* permw;
+  int* posof;
+  double* zpart;
+  double* auxpart;
+  double* nrm2part;
+  double* nu;
+  double* nuo;
+  double* rorig;
+  int64_t kcap, k_fixed;
+  double rel_tol, tol3z;
+  int rule, nopivot, nb;
+  // per step
+  int64_t j;
+  int jj;
+  int64_t t0;
+  int ntile, nchunk, Rt, CW;
+};
+
+// One pivot step, part 1.  Grid: (row tiles of Rt rows) x (column chunks of
+// CW positions), padded to a multiple of 8 and remapped so that the chunks of
+// one row tile run on the same XCD (they share the pivot column and the
+// reflector rows through that XCD's L2).
+//  - reduces the pivot partials, applies the rank rule, records the pivot;
+//  - w = W(i,p) - sum_c V(i,c) F(p,c) for the tile's rows i >= j;
+//  - z(l) = sum_{i>j} W(i,l) w(i) for the chunk's columns (the sweep);
+//  - chunk 0 also stores w, its squared norm and sum_{i>j} V(i,c) w(i).
+template <typename S>
+__global__ __launch_bounds__(kThreads) void k_sweep(StepArgs<S> a) {
+  typedef typename Vec16<S>::type VT;
+  constexpr int VEC = Vec16<S>::n;
+  __shared__ double wsh[kRtMax];
+  __shared__ double gsh[kNbMax];
+  __shared__ double red[kThreads * VEC];
+  __shared__ AmaxVal ascr[4];
+  __shared__ double dscr[4];
+  __shared__ int s_go;
+  FactorState* st = a.st;
+  const int tid = threadIdx.x;
+  // One thread reads the flags: block 0 of this kernel may set them while
+  // other blocks start, and every wave of a block must take the same branch.
+  if (tid == 0) s_go = (st->done == 0 && st->end_flag == 0);
+  __syncthreads();
+  if (!s_go) return;
+  const int total = a.ntile * a.nchunk;
+  const int per = gridDim.x / 8;
+  const int v = (blockIdx.x % 8) * per + blockIdx.x / 8;
+  if (v >= total) return;
+  const int64_t tile = a.t0 + v / a.nchunk;
+  const int chunk = v % a.nchunk;
+  const int64_t j = a.j;
+  const int jj = a.jj;
+
+  AmaxVal best = amax_none();
+  for (int q = tid; q < a.namax; q += kThreads) {
+    const AmaxPart pp = a.amax[q];
+    AmaxVal c;
+    c.v = pp.v;
+    c.s2 = pp.s2;
+    c.pos = pp.pos;
+    c.key = pp.key;
+    best = amax_combine(best, c);
+  }
+  best = block_amax(best, ascr);
+  int p = best.pos;
+  double vp = best.v;
+  if (a.nopivot) {
+    p = jj;
+    vp = jj < a.ncur ? a.nu[jj] : 0.0;
+  }
+  bool stop = (j >= a.kcap) || (jj >= a.ncur) || (p < 0) || (st->info != 0);
+  if (!stop && a.k_fixed == 0) {
+    if (!(vp > 0.0)) {
+      stop = true;
+    } else if (a.rule == ID_RANK_PIVOT_REL) {
+      if (j > 0 && vp <= a.rel_tol * st->r00) stop = true;
+    } else {
+      const double fro2 = j == 0 ? best.s2 : st->fro2;
+      if (sqrt(best.s2) <= a.rel_tol * sqrt(fro2)) stop = true;
+    }
+  }
+  if (stop) {
+    if (blockIdx.x == 0 && tid == 0) {
+      st->done = 1;
+      st->k = j;
+      st->end_flag = 1;
+    }
+    return;
+  }
+  if (blockIdx.x == 0 && tid == 0) {
+    a.pivpos[jj] = p;
+    a.pvflag[p] = 1;
+    const int q = a.colid[p];
+    a.pivid[j] = q;
+    const int pa = a.posof[q];
+    const int other = a.permw[j];
+    a.permw[pa] = other;
+    a.posof[other] = pa;
+    a.permw[j] = q;
+    a.posof[q] = (int)j;
+    st->jb = jj + 1;
+    if (j == 0) st->fro2 = best.s2;
+  }
+
+  // current pivot column w for the tile's rows
+  const int64_t r0 = tile * a.Rt;
+  const int64_t r1 = r0 + a.Rt < a.m ? r0 + a.Rt : a.m;
+  if (tid < jj) gsh[tid] = a.vscale[tid] * a.F[(int64_t)tid * a.ldf + p];
+  __syncthreads();
+  for (int rr = tid; rr < a.Rt; rr += kThreads) {
+    const int64_t i = r0 + rr;
+    double w = 0.0;
+    if (i >= j && i < r1) {
+      w = (double)a.W[i * a.ldw + p];
+      for (int c = 0; c < jj; ++c) w -= (double)a.V[(int64_t)c * a.ldv + i] * gsh[c];
+    }
+    wsh[rr] = w;
+  }
+  __syncthreads();
+
+  if (chunk == 0) {
+    double s = 0.0;
+    for (int rr = tid; rr < a.Rt; rr += kThreads) {
+      const int64_t i = r0 + rr;
+      if (i >= j && i < r1) a.V[(int64_t)jj * a.ldv + i] = (S)wsh[rr];
+      if (i > j && i < r1) s += wsh[rr] * wsh[rr];
+    }
+    if (tid == 0 && j >= r0 && j < r1) st->alpha = wsh[j - r0];
+    s = block_sum(s, dscr);
+    if (tid == 0) a.nrm2part[tile] = s;
+    const int lane = tid & 63, wv = tid >> 6;
+    for (int c = wv; c < jj; c += 4) {
+      double acc = 0.0;
+      for (int rr = lane; rr < a.Rt; rr += 64) {
+        const int64_t i = r0 + rr;
+        if (i > j && i < r1) acc += (double)a.V[(int64_t)c * a.ldv + i] * wsh[rr];
+      }
+      acc = wave_sum(acc);
+      if (lane == 0) a.auxpart[tile * kNbMax + c] = acc;
+    }
+  }
+
+  // the sweep: z(l) = sum_{i in tile, i > j} W(i, l) w(i)
+  const int TPR = a.CW / VEC;
+  const int RG = kThreads / TPR;
+  const int rg = tid / TPR, cv = tid % TPR;
+  const int64_t l0 = (int64_t)chunk * a.CW + (int64_t)cv * VEC;
+  double acc[VEC];
+#pragma unroll
+  for (int e = 0; e < VEC; ++e) acc[e] = 0.0;
+  if (l0 < a.ncur) {
+    const int64_t ib = r0 > j + 1 ? r0 : j + 1;
+    const S* base = a.W + l0;
+    int64_t i = ib + rg;
+    for (; i + 3 * RG < r1; i += 4 * RG) {
+      const VT x0 = *(const VT*)(base + i * a.ldw);
+      const VT x1 = *(const VT*)(base + (i + RG) * a.ldw);
+      const VT x2 = *(const VT*)(base + (i + 2 * RG) * a.ldw);
+      const VT x3 = *(const VT*)(base + (i + 3 * RG) * a.ldw);
+      const double w0 = wsh[i - r0], w1 = wsh[i + RG - r0], w2 = wsh[i + 2 * RG - r0],
+                   w3 = wsh[i + 3 * RG - r0];
+#pragma unroll
+      for (int e = 0; e < VEC; ++e) {
+        acc[e] += (double)x0[e] * w0;
+        acc[e] += (double)x1[e] * w1;
+        acc[e] += (double)x2[e] * w2;
+        acc[e] += (double)x3[e] * w3;
+      }
+    }
+    for (; i < r1; i += RG) {
+      const VT x0 = *(const VT*)(base + i * a.ldw);
+      const double w0 = wsh[i - r0];
+#pragma unroll
+      for (int e = 0; e < VEC; ++e) acc[e] += (double)x0[e] * w0;
+    }
+  }
+  if (RG > 1) {
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) red[tid * VEC + e] = acc[e];
+    __syncthreads();
+    if (rg == 0) {
+      for (int g = 1; g < RG; ++g)
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) acc[e] += red[(g * TPR + cv) * VEC + e];
+    }
+  }
+  if (rg == 0 && l0 < a.ncur) {
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) a.zpart[tile * a.ldf + l0 + e] = acc[e];
+  }
+}
+
+// One pivot step, part 2.  Grid: ceil(ncur / 32) blocks of 32 columns x 8
+// tile lanes.  Finishes the reflector (dlarfg conventions), forms the new
+// column of F and the new row of R, downdates the column norms (with the
+// cancellation test that ends the panel), and emits pivot partials.
+template <typename S>
+__global__ __launch_bounds__(kThreads) void k_finalize(StepArgs<S> a) {
+  __shared__ double red[8][kFinCols + 1];
+  __shared__ double aux[kNbMax];
+  __shared__ double vj[kNbMax];
+  __shared__ double dscr[4];
+  __shared__ AmaxVal ascr[4];
+  __shared__ float fscr[4];
+  __shared__ int s_go;
+  FactorState* st = a.st;
+  const int tid = threadIdx.x, cl = tid % kFinCols, tl = tid / kFinCols;
+  if (tid == 0) s_go = (st->jb == a.jj + 1);
+  __syncthreads();
+  if (!s_go) return;
+  const int64_t j = a.j;
+  const int jj = a.jj;
+  const int64_t tend = a.t0 + a.ntile;
+
+  double s = 0.0;
+  for (int64_t t = a.t0 + tid; t < tend; t += kThreads) s += a.nrm2part[t];
+  const double xnorm2 = block_sum(s, dscr);
+  const double alpha = st->alpha;
+  double beta, tau, scale;
+  if (xnorm2 == 0.0) {
+    beta = alpha;
+    tau = 0.0;
+    scale = 0.0;
+  } else {
+    const double h = hypot(alpha, sqrt(xnorm2));
+    beta = alpha >= 0.0 ? -h : h;
+    tau = (beta - alpha) / beta;
+    scale = 1.0 / (alpha - beta);
+  }
+
+  {
+    const int c = tid % kFinCols, sl = tid / kFinCols;
+    double zs = 0.0;
+    if (c < jj)
+      for (int64_t t = a.t0 + sl; t < tend; t += 8) zs += a.auxpart[t * kNbMax + c];
+    red[sl][c] = zs;
+  }
+  __syncthreads();
+  if (tid < jj) {
+    double z = 0.0;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) z += red[q][tid];
+    const double vjc = a.vscale[tid] * (double)a.V[(int64_t)tid * a.ldv + j];
+    vj[tid] = vjc;
+    aux[tid] = vjc + a.vscale[tid] * scale * z;
+  }
+  __syncthreads();
+
+  const int64_t l = (int64_t)blockIdx.x * kFinCols + cl;
+  double z = 0.0;
+  if (l < a.ncur)
+    for (int64_t t = a.t0 + tl; t < tend; t += 8) z += a.zpart[t * a.ldf + l];
+  red[tl][cl] = z;
+  __syncthreads();
+
+  AmaxVal cand = amax_none();
+  float fabsmax = 0.0f;
+  bool flag = false;
+  if (tl == 0 && l < a.ncur) {
+    double zt = 0.0;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) zt += red[q][cl];
+    const double wj = (double)a.W[j * a.ldw + l];
+    const double y = wj + scale * zt;
+    double s1 = 0.0, s2 = 0.0;
+    for (int c = 0; c < jj; ++c) {
+      const double fc = a.F[(int64_t)c * a.ldf + l];
+      s1 += fc * aux[c];
+      s2 += vj[c] * fc;
+    }
+    const double f = tau * (y - s1);
+    a.F[(int64_t)jj * a.ldf + l] = f;
+    if (!a.pvflag[l]) {
+      const double r = wj - s2 - f;
+      const int id = a.colid[l];
+      a.rorig[(int64_t)id * a.kcap + j] = r;
+      double nl = a.nu[l];
+      if (nl != 0.0) {
+        double t = fabs(r) / nl;
+        t = (1.0 + t) * (1.0 - t);
+        if (t < 0.0) t = 0.0;
+        const double ratio = nl / a.nuo[l];
+        if (t * ratio * ratio <= a.tol3z) {
+          flag = true;
+        } else {
+          nl = nl * sqrt(t);
+          a.nu[l] = nl;
+        }
+      }
+      cand.v = nl;
+      cand.s2 = nl * nl;
+      cand.pos = (int)l;
+      cand.key = a.posof[id];
+      fabsmax = (float)fabs(f);
+    }
+  }
+  if (flag) st->end_flag = 1;
+  // largest |F| entry of the panel (for the FP16 operand scaling)
+  {
+    float fm = fabsmax;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) fm = fmaxf(fm, __shfl_xor(fm, off, 64));
+    if ((tid & 63) == 0) fscr[tid >> 6] = fm;
+  }
+  cand = block_amax(cand, ascr);
+  if (tid == 0) {
+    const float fm = fmaxf(fmaxf(fscr[0], fscr[1]), fmaxf(fscr[2], fscr[3]));
+    atomicMax(&st->fmax_bits, __float_as_uint(fm));
+    AmaxPart o;
+    o.v = cand.v;
+    o.s2 = cand.s2;
+    o.pos = cand.pos;
+    o.key = cand.key;
+    a.amax[blockIdx.x] = o;
+  }
+  if (blockIdx.x == 0 && tid == 0) {
+    a.tau[j] = tau;
+    a.vscale[jj] = scale;
+    const int p = a.pivpos[jj];
+    a.rorig[(int64_t)a.colid[p] * a.kcap + j] = beta;
+    if (j == 0) st->r00 = fabs(beta);
+    if (jj + 1 >= a.nb) st->end_flag = 1;
+    if (j + 1 >= a.kcap) {
+      st->done = 1;
+      st->k = j + 1;
+      st->end_flag = 1;
+    }
+  }
+}
+
+template <typename S>
+struct GemmArgs {
+  const S* W;
+  S* Wn;
+  int64_t ldw, m, ncur;
+  const S* V;
+  int64_t ldv;
+  const double* F;
+  int64_t ldf;
+  const double* vscale;
+  FactorState* st;
+  const int* pivpos;
+  const int* colid;
+  int* colid_n;
+  double* colpart;
+  int64_t off, tg0;
+};
+
+// End of a panel: Wn(i, newpos(l)) = W(i, l) - sum_c V(i, c) F(c, l) for rows
+// i >= off + jb, on the matrix cores (FP64 MFMA, or FP16/BF16 MFMA with FP32
+// accumulation), skipping the pivoted positions (compaction), and the FP64
+// sums of squares of every refreshed column per row tile.
+// Block: 64 positions x kRowTileG rows; wave w computes 16 rows x 64 positions
+// per 64-row slice as four 16x16 MFMA blocks with the positions along the MFMA
+// rows, so each lane holds 4 consecutive positions of one row of W.
+template <typename S, int OP>
+__global__ __launch_bounds__(kThreads) void k_panel_gemm(GemmArgs<S> a) {
+  __shared__ int spiv[kNbMax];
+  __shared__ int cidx[64];
+  __shared__ int inv[64];
+  __shared__ int s_count, s_base;
+  __shared__ S tileo[64][64 + (sizeof(S) == 4 ? 1 : 1)];
+  __shared__ double ssq[4][64];
+  __shared__ int s_go;
+  FactorState* st = a.st;
+  const int tid = threadIdx.x;
+  if (tid == 0) s_go = (st->done == 0);
+  __syncthreads();
+  if (!s_go) return;
+  const int jb = st->jb;
+  const int64_t jend = a.off + jb;
+  const int64_t l0 = (int64_t)blockIdx.x * 64;
+  const int64_t tg = a.tg0 + blockIdx.y;
+  const int64_t rbase = tg * kRowTileG;
+  const int64_t rbeg = rbase > jend ? rbase : jend;
+  const int64_t rend = rbase + kRowTileG < a.m ? rbase + kRowTileG : a.m;
+
+  if (tid < jb) spiv[tid] = a.pivpos[tid];
+  __syncthreads();
+  if (tid < 64) {
+    const int64_t l = l0 + tid;
+    int before = 0;
+    bool pv = false;
+    for (int c = 0; c < jb; ++c) {
+      before += spiv[c] < l;
+      pv |= spiv[c] == l;
+    }
+    cidx[tid] = (l < a.ncur && !pv) ? (int)(l - before) : -1;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    int cnt = 0, base = -1;
+    for (int t = 0; t < 64; ++t)
+      if (cidx[t] >= 0) {
+        if (base < 0) base = cidx[t];
+        inv[cnt++] = t;
+      }
+    s_count = cnt;
+    s_base = base;
+  }
+  __syncthreads();
+  const int count = s_count;
+  const int npbase = s_base;
+  if (count == 0) return;
+
+  const int lane = tid & 63, wv = tid >> 6, g = lane >> 4, li = lane & 15;
+  int sF = 0, sV = 0;
+  if (OP == OP_F16) {
+    const float fmax = __uint_as_float(st->fmax_bits);
+    int e = 0;
+    if (fmax > 0.0f) frexpf(fmax, &e);
+    sF = 15 - e;
+    sV = 14;
+  }
+  const double fscl = ldexp(1.0, sF);
+  const float vscl = ldexpf(1.0f, sV);
+  const double descale = ldexp(1.0, -(sF + sV));
+
+  // A operands (F^T rows = positions), held for the whole block
+  f16x8 ah[4];
+  bf16x8 ab[4];
+  double a64[4][8];
+#pragma unroll
+  for (int lb = 0; lb < 4; ++lb) {
+    if (OP == OP_F64) {
+      const int64_t pos = l0 + 16 * lb + (4 * (li % 4) + li / 4);
+#pragma unroll
+      for (int s = 0; s < 8; ++s) {
+        const int c = 4 * s + g;
+        a64[lb][s] = (c < jb && pos < a.ncur) ? a.F[(int64_t)c * a.ldf + pos] : 0.0;
+      }
+    } else {
+      const int64_t pos = l0 + 16 * lb + li;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int c = 8 * g + e;
+        const float x = (c < jb && pos < a.ncur) ? (float)(a.F[(int64_t)c * a.ldf + pos] * fscl)
+                                                 : 0.0f;
+        if (OP == OP_F16)
+          ah[lb][e] = (_Float16)x;
+        else
+          ab[lb][e] = (__bf16)x;
+      }
+    }
+  }
+
+  double ss = 0.0;
+  for (int sb = 0; sb < kRowTileG / 64; ++sb) {
+    const int64_t rs = rbase + 64 * sb;
+    if (rs + 64 <= rbeg || rs >= rend) continue;  // uniform across the block
+    const int64_t row = rs + 16 * wv + li;
+    const bool rowok = row >= rbeg && row < rend;
+    if (OP == OP_F64) {
+      double b64[8];
+#pragma unroll
+      for (int s = 0; s < 8; ++s) {
+        const int c = 4 * s + g;
+        b64[s] = (c < jb && rowok) ? (double)a.V[(int64_t)c * a.ldv + row] * a.vscale[c] : 0.0;
+      }
+#pragma unroll
+      for (int lb = 0; lb < 4; ++lb) {
+        f64x4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int s = 0; s < 8; ++s)
+          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a64[lb][s], b64[s], acc, 0, 0, 0);
+        const int64_t p0 = l0 + 16 * lb + 4 * g;
+        if (rowok) {
+          const S* src = a.W + row * a.ldw + p0;
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int ci = cidx[16 * lb + 4 * g + r];
+            if (ci >= 0) tileo[16 * wv + li][ci - npbase] = (S)((double)src[r] - acc[r]);
+          }
+        }
+      }
+    } else {
+      f16x8 bh;
+      bf16x8 bb;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int c = 8 * g + e;
+        const float x = (c < jb && rowok)
+                            ? (float)a.V[(int64_t)c * a.ldv + row] * (float)a.vscale[c] * vscl
+                            : 0.0f;
+        if (OP == OP_F16)
+          bh[e] = (_Float16)x;
+        else
+          bb[e] = (__bf16)x;
+      }
+#pragma unroll
+      for (int lb = 0; lb < 4; ++lb) {
+        f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+        if (OP == OP_F16)
+          acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah[lb], bh, acc, 0, 0, 0);
+        else
+          acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ab[lb], bb, acc, 0, 0, 0);
+        const int64_t p0 = l0 + 16 * lb + 4 * g;
+        if (rowok) {
+          const S* src = a.W + row * a.ldw + p0;
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int ci = cidx[16 * lb + 4 * g + r];
+            if (ci >= 0)
+              tileo[16 * wv + li][ci - npbase] = (S)((double)src[r] - (double)acc[r] * descale);
+          }
+        }
+      }
+    }
+    __syncthreads();
+    {
+      const int cc = tid % 64;
+#pragma unroll 4
+      for (int q = 0; q < 16; ++q) {
+        const int rr = tid / 64 + 4 * q;
+        const int64_t r = rs + rr;
+        if (cc < count && r >= rbeg && r < rend) {
+          const S v = tileo[rr][cc];
+          a.Wn[r * a.ldw + npbase + cc] = v;
+          ss += (double)v * (double)v;
+        }
+      }
+    }
+    __syncthreads();
+  }
+  ssq[tid / 64][tid % 64] = ss;
+  __syncthreads();
+  if (tid < count) {
+    a.colpart[tg * a.ldf + npbase + tid] =
+        ssq[0][tid] + ssq[1][tid] + ssq[2][tid] + ssq[3][tid];
+    if (blockIdx.y == 0) a.colid_n[npbase + tid] = a.colid[l0 + inv[tid]];
+  }
+}
+
+__global__ void k_advance(FactorState* st) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    if (st->done) return;
+    st->last_jb = st->jb;
+    st->jb = 0;
+    st->end_flag = 0;
+    st->fmax_bits = 0u;
+  }
+}
+
+// perm (swap order) and R gathered into pivot order: R(i, c) = Rorig(i, perm[c])
+// for i < k, zero below the diagonal of the first k columns.
+__global__ __launch_bounds__(kThreads) void k_finish(const int* __restrict__ permw,
+                                                     int32_t* __restrict__ perm_out,
+                                                     const double* __restrict__ rorig,
+                                                     int64_t kcap, int64_t n, int64_t k,
+                                                     double* __restrict__ R, int64_t ldr) {
+  const int64_t c = blockIdx.x;
+  const int64_t i = (int64_t)blockIdx.y * kThreads + threadIdx.x;
+  if (c >= n) return;
+  const int id = permw[c];
+  if (blockIdx.y == 0 && threadIdx.x == 0) perm_out[c] = id;
+  if (i < k) R[c * ldr + i] = (c >= k || i <= c) ? rorig[(int64_t)id * kcap + i] : 0.0;
+}
+
+__global__ void k_iota(int32_t* perm, int64_t n) {
+  const int64_t l = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (l < n) perm[l] = (int32_t)l;
+}
+
+// ----------------------------------------------------------------- host driver
+
+static int env_int(const char* name, int dflt) {
+  const char* s = std::getenv(name);
+  if (!s || !*s) return dflt;
+  return std::atoi(s);
+}
+
+struct SweepShape {
+  int Rt, CW;
+};
+
+static SweepShape choose_sweep_shape(int64_t rows, int64_t ncur, int wbytes) {
+  SweepShape sh;
+  const int vec = 16 / wbytes;
+  const int cw_max = kThreads * vec;  // one row group
+  int cw = env_int("MPID_SWEEP_CW", wbytes == 4 ? 512 : 256);
+  if (cw < 64 * vec) cw = 64 * vec;
+  if (cw > cw_max) cw = cw_max;
+  // round to a power of two number of lanes per row
+  int tpr = cw / vec, t = 1;
+  while (t * 2 <= tpr) t *= 2;
+  sh.CW = t * vec;
+  const int64_t nchunk = ceil_div(ncur, sh.CW);
+  const int target = env_int("MPID_SWEEP_BLOCKS", 1024);
+  int rt = env_int("MPID_SWEEP_RT", 0);
+  if (rt <= 0) {
+    rt = kRtMin;
+    while (rt < kRtMax && ceil_div(rows, rt) * nchunk > target) rt *= 2;
+  }
+  if (rt < kRtMin) rt = kRtMin;
+  if (rt > kRtMax) rt = kRtMax;
+  sh.Rt = rt;
+  return sh;
+}
+
+template <typename TA, typename S, int OP>
+static int factor_impl(const TA* A, int64_t lda, const FactorPlan& pl, const id_opts* o,
+                       char* wb, int32_t* perm, double* R, int64_t ldr, int64_t* k_out,
+                       int32_t* info, hipStream_t s) {
+  const int64_t m = pl.m, n = pl.n, kcap = pl.kcap;
+  S* W[2] = {(S*)(wb + pl.off_w0), (S*)(wb + pl.off_w1)};
+  S* V = (S*)(wb + pl.off_v);
+  double* F = (double*)(wb + pl.off_f);
+  double* zpart = (double*)(wb + pl.off_zpart);
+  double* auxpart = (double*)(wb + pl.off_auxpart);
+  double* nrm2part = (double*)(wb + pl.off_nrm2part);
+  double* colpart = (double*)(wb + pl.off_colpart);
+  double* nu = (double*)(wb + pl.off_nu);
+  double* nuo = (double*)(wb + pl.off_nuo);
+  AmaxPart* amax = (AmaxPart*)(wb + pl.off_amax);
+  int* colid[2] = {(int*)(wb + pl.off_colid0), (int*)(wb + pl.off_colid1)};
+  int* pvflag = (int*)(wb + pl.off_pvflag);
+  int* pivpos = (int*)(wb + pl.off_pivpos);
+  int* pivid = (int*)(wb + pl.off_pivid);
+  int* permw = (int*)(wb + pl.off_permw);
+  int* posof = (int*)(wb + pl.off_posof);
+  double* tau = (double*)(wb + pl.off_tau);
+  double* vscale = (double*)(wb + pl.off_vscale);
+  double* rorig = (double*)(wb + pl.off_rorig);
+  FactorState* st = (FactorState*)(wb + pl.off_state);
+
+  static thread_local FactorState* hst = nullptr;
+  if (!hst) MPID_HIP(hipHostMalloc((void**)&hst, sizeof(FactorState), hipHostMallocDefault));
+
+  const int64_t ldw = pl.ldw, ldf = pl.ldf;
+  const int64_t ntg = ceil_div(m, kRowTileG);
+  k_init<<<dim3((unsigned)ceil_div(ldf > n ? ldf : n, kThreads)), kThreads, 0, s>>>(
+      st, colid[0], pvflag, permw, posof, n, ldf);
+  MPID_LAUNCH_CHECK();
+  k_ingest<TA, S><<<dim3((unsigned)ceil_div(n, 64), (unsigned)ntg), kThreads, 0, s>>>(
+      A, lda, m, n, W[0], ldw, colpart, ldf, st);
+  MPID_LAUNCH_CHECK();
+  int namax = (int)ceil_div(n, kFinCols);
+  k_colreduce<<<dim3((unsigned)namax), kThreads, 0, s>>>(colpart, ldf, 0, ntg, n, 0, nu, nuo,
+                                                          amax, colid[0], posof, pvflag, st);
+  MPID_LAUNCH_CHECK();
+
+  StepArgs<S> a;
+  std::memset(&a, 0, sizeof(a));
+  a.ldw = ldw;
+  a.m = m;
+  a.n = n;
+  a.V = V;
+  a.ldv = pl.ldv;
+  a.F = F;
+  a.ldf = ldf;
+  a.vscale = vscale;
+  a.tau = tau;
+  a.st = st;
+  a.amax = amax;
+  a.pvflag = pvflag;
+  a.pivpos = pivpos;
+  a.pivid = pivid;
+  a.permw = permw;
+  a.posof = posof;
+  a.zpart = zpart;
+  a.auxpart = auxpart;
+  a.nrm2part = nrm2part;
+  a.nu = nu;
+  a.nuo = nuo;
+  a.rorig = rorig;
+  a.kcap = kcap;
+  a.k_fixed = o->k_fixed;
+  a.rel_tol = o->rel_tol;
+  a.tol3z = std::sqrt(pl.wbytes == 8 ? std::ldexp(1.0, -53) : std::ldexp(1.0, -24));
+  a.rule = o->rank_rule;
+  a.nopivot = (o->flags & ID_FLAG_NO_PIVOT) ? 1 : 0;
+  a.nb = pl.nb;
+
+  int64_t off = 0, ncur = n;
+  int cur = 0;
+  for (;;) {
+    a.W = W[cur];
+    a.colid = colid[cur];
+    a.ncur = ncur;
+    for (int jj = 0; jj < pl.nb; ++jj) {
+      const int64_t j = off + jj;
+      if (j >= kcap || jj >= ncur) break;
+      const SweepShape sh = choose_sweep_shape(m - j, ncur, pl.wbytes);
+      a.j = j;
+      a.jj = jj;
+      a.Rt = sh.Rt;
+      a.CW = sh.CW;
+      a.t0 = j / sh.Rt;
+      a.ntile = (int)(ceil_div(m, sh.Rt) - a.t0);
+      a.nchunk = (int)ceil_div(ncur, sh.CW);
+      a.namax = namax;
+      const int64_t total = (int64_t)a.ntile * a.nchunk;
+      k_sweep<S><<<dim3((unsigned)round_up(total, 8)), kThreads, 0, s>>>(a);
+      MPID_LAUNCH_CHECK();
+      namax = (int)ceil_div(ncur, kFinCols);
+      k_finalize<S><<<dim3((unsigned)namax), kThreads, 0, s>>>(a);
+      MPID_LAUNCH_CHECK();
+    }
+    GemmArgs<S> g;
+    g.W = W[cur];
+    g.Wn = W[cur ^ 1];
+    g.ldw = ldw;
+    g.m = m;
+    g.ncur = ncur;
+    g.V = V;
+    g.ldv = pl.ldv;
+    g.F = F;
+    g.ldf = ldf;
+    g.vscale = vscale;
+    g.st = st;
+    g.pivpos = pivpos;
+    g.colid = colid[cur];
+    g.colid_n = colid[cur ^ 1];
+    g.colpart = colpart;
+    g.off = off;
+    g.tg0 = off / kRowTileG;
+    k_panel_gemm<S, OP><<<dim3((unsigned)ceil_div(ncur, 64), (unsigned)(ntg - g.tg0)), kThreads,
+                          0, s>>>(g);
+    MPID_LAUNCH_CHECK();
+    namax = (int)ceil_div(ncur, kFinCols);
+    k_colreduce<<<dim3((unsigned)namax), kThreads, 0, s>>>(colpart, ldf, g.tg0, ntg, ncur, 1,
+                                                            nu, nuo, amax, colid[cur ^ 1], posof,
+                                                            pvflag, st);
+    MPID_LAUNCH_CHECK();
+    k_advance<<<1, 64, 0, s>>>(st);
+    MPID_LAUNCH_CHECK();
+    MPID_HIP(hipMemcpyAsync(hst, st, sizeof(FactorState), hipMemcpyDeviceToHost, s));
+    MPID_HIP(hipStreamSynchronize(s));
+    if (hst->done) break;
+    const int jb = hst->last_jb;
+    if (jb <= 0) return ID_ERR_HIP;  // cannot happen: a live panel makes progress
+    off += jb;
+    ncur -= jb;
+    cur ^= 1;
+  }
+  const int64_t k = hst->k;
+  *k_out = k;
+  *info = hst->info;
+  k_finish<<<dim3((unsigned)n, (unsigned)(k > 0 ? ceil_div(k, kThreads) : 1)), kThreads, 0, s>>>(
+      permw, perm, rorig, kcap, n, k, R, ldr);
+  MPID_LAUNCH_CHECK();
+  return ID_OK;
+}
+
+int factor_run(const void* A, int32_t dtype, int64_t m, int64_t n, int64_t lda,
+               const id_opts* o, void* work, size_t work_bytes, int32_t* perm, double* R,
+               int64_t ldr, int64_t* k_out, int32_t* info, hipStream_t s) {
+  FactorPlan pl;
+  if (!make_factor_plan(m, n, dtype, o, &pl)) return ID_ERR_ARG;
+  if (!k_out || !info) return ID_ERR_ARG;
+  if (n > 0 && !perm) return ID_ERR_ARG;
+  if (m > 0 && n > 0 && !A) return ID_ERR_ARG;
+  if (lda < (m > 1 ? m : 1)) return ID_ERR_ARG;
+  if (pl.kcap > 0 && (!R || ldr < pl.kcap)) return ID_ERR_ARG;
+  if (!work || work_bytes < pl.bytes) return ID_ERR_WORKSPACE;
+  *info = 0;
+  if (m == 0 || n == 0 || pl.kcap == 0) {
+    *k_out = 0;
+    if (n > 0) {
+      k_iota<<<dim3((unsigned)ceil_div(n, kThreads)), kThreads, 0, s>>>(perm, n);
+      MPID_LAUNCH_CHECK();
+    }
+    return ID_OK;
+  }
+  char* wb = (char*)work;
+  if (pl.prec == ID_PREC_F64) {
+    if (dtype == ID_F64)
+      return factor_impl<double, double, OP_F64>((const double*)A, lda, pl, o, wb, perm, R, ldr,
+                                                  k_out, info, s);
+    return factor_impl<float, double, OP_F64>((const float*)A, lda, pl, o, wb, perm, R, ldr, k_out,
+                                              info, s);
+  }
+  if (pl.prec == ID_PREC_MIXED_F16) {
+    if (dtype == ID_F64)
+      return factor_impl<double, float, OP_F16>((const double*)A, lda, pl, o, wb, perm, R, ldr,
+                                                k_out, info, s);
+    return factor_impl<float, float, OP_F16>((const float*)A, lda, pl, o, wb, perm, R, ldr, k_out,
+                                             info, s);
+  }
+  if (dtype == ID_F64)
+    return factor_impl<double, float, OP_BF16>((const double*)A, lda, pl, o, wb, perm, R, ldr,
+                                               k_out, info, s);
+  return factor_impl<float, float, OP_BF16>((const float*)A, lda, pl, o, wb, perm, R, ldr, k_out,
+                                            info, s);
+}
+
+}  // namespace mpid

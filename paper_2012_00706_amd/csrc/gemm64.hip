@@ -1,0 +1,372 @@
+// FP64 matrix-core GEMM and the two consumers of the factorization that are
+// pure products: the reconstruction A(:, J) P (eq. (4)-(5), (8); evaluated in
+// double precision as in the remark after Lemma 1) and the adjoint of T and of
+// the reconstruction with the skeleton held fixed.
+#include <hip/hip_runtime.h>
+
+#include <cstring>
+
+#include "mpid_internal.h"
+
+namespace mpid {
+
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+template <typename TA, typename TC>
+struct G64Args {
+  int ta, tb;
+  int64_t M, N, K;
+  double alpha;
+  const TA* A;  // op(A): M x K; amap maps op(A)'s column index (ta == 0)
+  int64_t lda;
+  const int32_t* amap;
+  const double* B;  // op(B): K x N
+  int64_t ldb;
+  double beta;
+  const TC* Cin;  // Cin(i, cinmap[j])
+  int64_t ldcin;
+  const int32_t* cinmap;
+  double* C;  // C(i, cmap[j])
+  int64_t ldc;
+  const int32_t* cmap;
+};
+
+// C = alpha op(A) op(B) + beta Cin, 64 x 64 tile per block, K chunks of 16
+// staged through LDS, four waves of 2 x 2 FP64 16x16x4 MFMA blocks.
+template <typename TA, typename TC>
+__global__ __launch_bounds__(kThreads) void k_gemm64(G64Args<TA, TC> a) {
+  __shared__ double As[16][64 + 1];  // As[kk][i] = op(A)(m0 + i, k0 + kk)
+  __shared__ double Bs[16][64 + 1];  // Bs[kk][j] = op(B)(k0 + kk, n0 + j)
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wv = tid >> 6, g = lane >> 4, li = lane & 15;
+  const int64_t m0 = (int64_t)blockIdx.x * 64, n0 = (int64_t)blockIdx.y * 64;
+  const int wr = (wv & 1) * 32, wc = (wv >> 1) * 32;
+  f64x4 acc[2][2];
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y) acc[x][y] = (f64x4){0.0, 0.0, 0.0, 0.0};
+
+  for (int64_t k0 = 0; k0 < a.K; k0 += 16) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      if (a.ta == 0) {
+        const int i = tid % 64, kk = tid / 64 + 4 * q;
+        const int64_t gi = m0 + i, gk = k0 + kk;
+        double v = 0.0;
+        if (gi < a.M && gk < a.K) {
+          const int64_t col = a.amap ? (int64_t)a.amap[gk] : gk;
+          v = (double)a.A[col * a.lda + gi];
+        }
+        As[kk][i] = v;
+      } else {
+        const int kk = tid % 16, i = tid / 16 + 16 * q;
+        const int64_t gi = m0 + i, gk = k0 + kk;
+        As[kk][i] = (gi < a.M && gk < a.K) ? (double)a.A[gi * a.lda + gk] : 0.0;
+      }
+      if (a.tb == 0) {
+        const int kk = tid % 16, j = tid / 16 + 16 * q;
+        const int64_t gj = n0 + j, gk = k0 + kk;
+        Bs[kk][j] = (gj < a.N && gk < a.K) ? a.B[gj * a.ldb + gk] : 0.0;
+      } else {
+        const int j = tid % 64, kk = tid / 64 + 4 * q;
+        const int64_t gj = n0 + j, gk = k0 + kk;
+        Bs[kk][j] = (gj < a.N && gk < a.K) ? a.B[gk * a.ldb + gj] : 0.0;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int ks = 0; ks < 4; ++ks) {
+      double af[2], bf[2];
+#pragma unroll
+      for (int x = 0; x < 2; ++x) af[x] = As[4 * ks + g][wr + 16 * x + li];
+#pragma unroll
+      for (int y = 0; y < 2; ++y) bf[y] = Bs[4 * ks + g][wc + 16 * y + li];
+#pragma unroll
+      for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y)
+          acc[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[x], bf[y], acc[x][y], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+  // acc[x][y][r] = C(m0 + wr + 16x + g + 4r, n0 + wc + 16y + li)
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y) {
+      const int64_t j = n0 + wc + 16 * y + li;
+      if (j >= a.N) continue;
+      const int64_t cj = a.cmap ? (int64_t)a.cmap[j] : j;
+      const int64_t ij = a.cinmap ? (int64_t)a.cinmap[j] : j;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t i = m0 + wr + 16 * x + g + 4 * r;
+        if (i >= a.M) continue;
+        double v = a.alpha * acc[x][y][r];
+        if (a.beta != 0.0) v += a.beta * (double)a.Cin[ij * a.ldcin + i];
+        a.C[cj * a.ldc + i] = v;
+      }
+    }
+}
+
+template <typename TA, typename TC>
+static int gemm_launch(const G64Args<TA, TC>& a, hipStream_t s) {
+  if (a.M <= 0 || a.N <= 0) return ID_OK;
+  k_gemm64<TA, TC><<<dim3((unsigned)ceil_div(a.M, 64), (unsigned)ceil_div(a.N, 64)), kThreads, 0,
+                     s>>>(a);
+  MPID_LAUNCH_CHECK();
+  return ID_OK;
+}
+
+int gemm64_run(int ta, int tb, int64_t M, int64_t N, int64_t K, double alpha, const double* A,
+               int64_t lda, const double* B, int64_t ldb, double beta, double* C, int64_t ldc,
+               hipStream_t s) {
+  G64Args<double, double> a;
+  std::memset(&a, 0, sizeof(a));
+  a.ta = ta;
+  a.tb = tb;
+  a.M = M;
+  a.N = N;
+  a.K = K;
+  a.alpha = alpha;
+  a.A = A;
+  a.lda = lda;
+  a.B = B;
+  a.ldb = ldb;
+  a.beta = beta;
+  a.Cin = C;
+  a.ldcin = ldc;
+  a.C = C;
+  a.ldc = ldc;
+  return gemm_launch(a, s);
+}
+
+// Y(:, cols[j]) = zero ? 0 : (double) A(:, cols[j]), j < ncols (cols may be null = identity);
+// the destination column is dcols[j] (null = j).
+template <typename TA>
+__global__ __launch_bounds__(kThreads) void k_gather_cols(const TA* __restrict__ A, int64_t lda,
+                                                          int64_t m, const int32_t* cols,
+                                                          double* __restrict__ Y, int64_t ldy,
+                                                          const int32_t* dcols, int zero) {
+  const int64_t j = blockIdx.y;
+  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (i >= m) return;
+  const int64_t sc = cols ? (int64_t)cols[j] : j;
+  const int64_t dc = dcols ? (int64_t)dcols[j] : j;
+  Y[dc * ldy + i] = zero ? 0.0 : (double)A[sc * lda + i];
+}
+
+template <typename TA>
+static int gather(const TA* A, int64_t lda, int64_t m, const int32_t* cols, int64_t ncols,
+                  double* Y, int64_t ldy, const int32_t* dcols, int zero, hipStream_t s) {
+  if (m <= 0 || ncols <= 0) return ID_OK;
+  k_gather_cols<TA><<<dim3((unsigned)ceil_div(m, kThreads), (unsigned)ncols), kThreads, 0, s>>>(
+      A, lda, m, cols, Y, ldy, dcols, zero);
+  MPID_LAUNCH_CHECK();
+  return ID_OK;
+}
+
+__global__ __launch_bounds__(kThreads) void k_axpy_cols(double* __restrict__ X, int64_t ldx,
+                                                        const double* __restrict__ Y, int64_t ldy,
+                                                        int64_t m, double alpha) {
+  const int64_t j = blockIdx.y;
+  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (i < m) X[j * ldx + i] += alpha * Y[j * ldy + i];
+}
+
+template <typename TA>
+static int reconstruct_impl(const TA* A, int64_t m, int64_t n, int64_t lda, const int32_t* perm,
+                            int64_t k, const double* T, int64_t ldt, double* Y, int64_t ldy,
+                            int32_t residual, hipStream_t s) {
+  int rc = gather<TA>(A, lda, m, perm, k, Y, ldy, perm, residual ? 1 : 0, s);
+  if (rc) return rc;
+  if (n - k <= 0) return ID_OK;
+  G64Args<TA, TA> a;
+  std::memset(&a, 0, sizeof(a));
+  a.ta = 0;
+  a.tb = 0;
+  a.M = m;
+  a.N = n - k;
+  a.K = k;
+  a.alpha = residual ? -1.0 : 1.0;
+  a.A = A;
+  a.lda = lda;
+  a.amap = perm;
+  a.B = T;
+  a.ldb = ldt;
+  a.beta = residual ? 1.0 : 0.0;
+  a.Cin = A;
+  a.ldcin = lda;
+  a.cinmap = perm + k;
+  a.C = Y;
+  a.ldc = ldy;
+  a.cmap = perm + k;
+  return gemm_launch(a, s);
+}
+
+int reconstruct_run(const void* A, int32_t dtype, int64_t m, int64_t n, int64_t lda,
+                    const int32_t* perm, int64_t k, const double* T, int64_t ldt, double* Y,
+                    int64_t ldy, int32_t residual, hipStream_t s) {
+  if (dtype != ID_F32 && dtype != ID_F64) return ID_ERR_DTYPE;
+  if (m < 0 || n < 0 || k < 0 || k > n) return ID_ERR_ARG;
+  if (m == 0 || n == 0) return ID_OK;
+  if (!A || !perm || !Y || lda < m || ldy < m) return ID_ERR_ARG;
+  if (k > 0 && n - k > 0 && (!T || ldt < k)) return ID_ERR_ARG;
+  if (dtype == ID_F64)
+    return reconstruct_impl<double>((const double*)A, m, n, lda, perm, k, T, ldt, Y, ldy,
+                                    residual, s);
+  return reconstruct_impl<float>((const float*)A, m, n, lda, perm, k, T, ldt, Y, ldy, residual,
+                                 s);
+}
+
+// ---------------------------------------------------------------- adjoint
+
+struct BwdPlan {
+  size_t off_b, off_c, off_gyj, off_gyc, off_tbar, off_wt, off_rq, off_permq, off_info, off_fws;
+  size_t fws_bytes, bytes;
+};
+
+static bool make_bwd_plan(int64_t m, int64_t n, int64_t k, BwdPlan* p) {
+  if (m < 0 || n < 0 || k < 0 || k > n) return false;
+  const int64_t mm = m > 0 ? m : 1, kk = k > 0 ? k : 1, cc = (n - k) > 0 ? (n - k) : 1;
+  std::memset(p, 0, sizeof(*p));
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t at = off;
+    off += (bytes + 255) / 256 * 256;
+    return at;
+  };
+  p->off_b = take((size_t)mm * kk * 8);
+  p->off_c = take((size_t)mm * cc * 8);
+  p->off_gyj = take((size_t)mm * kk * 8);
+  p->off_gyc = take((size_t)mm * cc * 8);
+  p->off_tbar = take((size_t)kk * cc * 8);
+  p->off_wt = take((size_t)mm * cc * 8);
+  p->off_rq = take((size_t)kk * kk * 8);
+  p->off_permq = take((size_t)kk * 4);
+  p->off_info = take(64);
+  id_opts o;
+  std::memset(&o, 0, sizeof(o));
+  o.prec = ID_PREC_F64;
+  o.k_fixed = kk;
+  o.flags = ID_FLAG_NO_PIVOT;
+  FactorPlan fp;
+  if (!make_factor_plan(mm, kk, ID_F64, &o, &fp)) return false;
+  p->fws_bytes = fp.bytes;
+  p->off_fws = take(fp.bytes);
+  p->bytes = off;
+  return true;
+}
+
+size_t backward_workspace(int64_t m, int64_t n, int64_t k) {
+  BwdPlan p;
+  return make_bwd_plan(m, n, k, &p) ? p.bytes : 0;
+}
+
+template <typename TA>
+static int backward_impl(const TA* A, int64_t m, int64_t n, int64_t lda, const int32_t* perm,
+                         int64_t k, const double* T, int64_t ldt, const double* gT, int64_t ldgt,
+                         const double* gY, int64_t ldgy, double* gA, int64_t ldga, char* wb,
+                         const BwdPlan& p, int32_t* info, hipStream_t s) {
+  const int64_t nc = n - k;
+  double* Bm = (double*)(wb + p.off_b);
+  double* Cm = (double*)(wb + p.off_c);
+  double* gYJ = (double*)(wb + p.off_gyj);
+  double* gYc = (double*)(wb + p.off_gyc);
+  double* Tb = (double*)(wb + p.off_tbar);
+  double* Wt = (double*)(wb + p.off_wt);
+  double* Rq = (double*)(wb + p.off_rq);
+  int32_t* permq = (int32_t*)(wb + p.off_permq);
+  int32_t* dinfo = (int32_t*)(wb + p.off_info);
+  int rc;
+  *info = 0;
+  // gA = 0 when there is no skeleton
+  if (k == 0) return gather<double>(nullptr, 1, m, nullptr, n, gA, ldga, nullptr, 1, s);
+  if ((rc = gather<TA>(A, lda, m, perm, k, Bm, m, nullptr, 0, s))) return rc;
+  if (nc > 0 && (rc = gather<TA>(A, lda, m, perm + k, nc, Cm, m, nullptr, 0, s))) return rc;
+  if (gY) {
+    if ((rc = gather<double>(gY, ldgy, m, perm, k, gYJ, m, nullptr, 0, s))) return rc;
+    if (nc > 0 && (rc = gather<double>(gY, ldgy, m, perm + k, nc, gYc, m, nullptr, 0, s)))
+      return rc;
+  } else {
+    if ((rc = gather<double>(nullptr, 1, m, nullptr, k, gYJ, m, nullptr, 1, s))) return rc;
+  }
+  if (nc > 0) {
+    // R factor of B (unpivoted FP64 Householder QR)
+    id_opts o;
+    std::memset(&o, 0, sizeof(o));
+    o.prec = ID_PREC_F64;
+    o.k_fixed = k;
+    o.flags = ID_FLAG_NO_PIVOT;
+    int64_t kq = 0;
+    int32_t iq = 0;
+    rc = factor_run(Bm, ID_F64, m, k, m, &o, wb + p.off_fws, p.fws_bytes, permq, Rq, k, &kq, &iq,
+                    s);
+    if (rc) return rc;
+    if (iq != 0 || kq != k) {
+      *info = ID_INFO_SINGULAR;
+      return ID_OK;
+    }
+    if ((rc = solve_T_run(Rq, k, k, k, nullptr, 1, dinfo, s))) return rc;
+    int32_t hinfo = 0;
+    MPID_HIP(hipMemcpyAsync(&hinfo, dinfo, 4, hipMemcpyDeviceToHost, s));
+    MPID_HIP(hipStreamSynchronize(s));
+    if (hinfo == ID_INFO_SINGULAR) {
+      *info = ID_INFO_SINGULAR;
+      return ID_OK;
+    }
+    // Tbar = gT + B^T gY(:, Jc)
+    if (gT) {
+      if ((rc = gather<double>(gT, ldgt, k, nullptr, nc, Tb, k, nullptr, 0, s))) return rc;
+    } else {
+      if ((rc = gather<double>(nullptr, 1, k, nullptr, nc, Tb, k, nullptr, 1, s))) return rc;
+    }
+    if (gY && (rc = gemm64_run(1, 0, k, nc, m, 1.0, Bm, m, gYc, m, 1.0, Tb, k, s))) return rc;
+    // X = (B^T B)^{-1} Tbar = R^{-1} R^{-T} Tbar
+    if ((rc = trsm_upper_run(Rq, k, k, Tb, k, nc, Tb, k, 1, s))) return rc;
+    if ((rc = trsm_upper_run(Rq, k, k, Tb, k, nc, Tb, k, 0, s))) return rc;
+    // Wt = B X  (= dL/dC)
+    if ((rc = gemm64_run(0, 0, m, nc, k, 1.0, Bm, m, Tb, k, 0.0, Wt, m, s))) return rc;
+    // Rres = C - B T (in place in Cm)
+    if ((rc = gemm64_run(0, 0, m, nc, k, -1.0, Bm, m, T, ldt, 1.0, Cm, m, s))) return rc;
+    // Bbar = gY(:, J) + Rres X^T + (gY(:, Jc) - Wt) T^T
+    if ((rc = gemm64_run(0, 1, m, k, nc, 1.0, Cm, m, Tb, k, 1.0, gYJ, m, s))) return rc;
+    if (gY) {
+      k_axpy_cols<<<dim3((unsigned)ceil_div(m, kThreads), (unsigned)nc), kThreads, 0, s>>>(
+          gYc, m, Wt, m, m, -1.0);
+      MPID_LAUNCH_CHECK();
+      if ((rc = gemm64_run(0, 1, m, k, nc, 1.0, gYc, m, T, ldt, 1.0, gYJ, m, s))) return rc;
+    } else {
+      if ((rc = gemm64_run(0, 1, m, k, nc, -1.0, Wt, m, T, ldt, 1.0, gYJ, m, s))) return rc;
+    }
+    if ((rc = gather<double>(Wt, m, m, nullptr, nc, gA, ldga, perm + k, 0, s))) return rc;
+  }
+  if ((rc = gather<double>(gYJ, m, m, nullptr, k, gA, ldga, perm, 0, s))) return rc;
+  MPID_HIP(hipStreamSynchronize(s));
+  return ID_OK;
+}
+
+int backward_run(const void* A, int32_t dtype, int64_t m, int64_t n, int64_t lda,
+                 const int32_t* perm, int64_t k, const double* T, int64_t ldt, const double* gT,
+                 int64_t ldgt, const double* gY, int64_t ldgy, double* gA, int64_t ldga,
+                 void* work, size_t work_bytes, int32_t* info, hipStream_t s) {
+  if (dtype != ID_F32 && dtype != ID_F64) return ID_ERR_DTYPE;
+  if (!info || m < 0 || n < 0 || k < 0 || k > n) return ID_ERR_ARG;
+  *info = 0;
+  if (m == 0 || n == 0) return ID_OK;
+  if (!A || !perm || !gA || lda < m || ldga < m) return ID_ERR_ARG;
+  if (k > 0 && n - k > 0 && (!T || ldt < k)) return ID_ERR_ARG;
+  if (gT && ldgt < (k > 0 ? k : 1)) return ID_ERR_ARG;
+  if (gY && ldgy < m) return ID_ERR_ARG;
+  BwdPlan p;
+  if (!make_bwd_plan(m, n, k, &p)) return ID_ERR_ARG;
+  if (!work || work_bytes < p.bytes) return ID_ERR_WORKSPACE;
+  if (dtype == ID_F64)
+    return backward_impl<double>((const double*)A, m, n, lda, perm, k, T, ldt, gT, ldgt, gY, ldgy,
+                                 gA, ldga, (char*)work, p, info, s);
+  return backward_impl<float>((const float*)A, m, n, lda, perm, k, T, ldt, gT, ldgt, gY, ldgy, gA,
+                              ldga, (char*)work, p, info, s);
+}
+
+}  // namespace mpid

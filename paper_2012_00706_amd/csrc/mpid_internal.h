@@ -1,0 +1,100 @@
+// Internal declarations shared by the HIP translation units of libmpid.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "mpid.h"
+
+namespace mpid {
+
+constexpr int kThreads = 256;   // block size of every kernel
+constexpr int kNbMax = 32;      // largest panel width (K of the blocked update)
+constexpr int kRtMax = 2048;    // largest row tile of the reflector sweep
+constexpr int kRtMin = 64;      // smallest row tile of the reflector sweep
+constexpr int kRowTileG = 256;  // row tile of the ingest / blocked-update kernels
+constexpr int kColTileG = 64;   // column tile of the blocked update
+constexpr int kFinCols = 32;    // columns per block of the reduction kernels
+
+// Device-resident control block of one factorization.  Every field is written
+// by exactly one kind of kernel and read only by later kernels on the stream.
+struct FactorState {
+  int32_t done;      // factorization finished (k valid)
+  int32_t end_flag;  // current panel ends after the step that set it
+  int32_t jb;        // reflectors generated in the current panel
+  int32_t last_jb;   // jb of the panel that just ended (for the host)
+  int32_t info;      // ID_INFO_NONFINITE when the input holds NaN/Inf
+  uint32_t fmax_bits;  // max |F| of the current panel, as float bits
+  int64_t k;         // rank (valid when done)
+  double r00;        // |R_00|
+  double alpha;      // leading entry of the current pivot column
+  double fro2;       // ||A||_F^2
+  double pad[2];
+};
+
+// Per-block partial of the pivot search.
+struct AmaxPart {
+  double v;     // largest column norm of the block (-1 if none)
+  double s2;    // sum of squared column norms of the block
+  int32_t pos;  // position of the largest column in the working layout
+  int32_t key;  // its position in the swap order (tie-break: smaller wins)
+};
+
+// Layout of the factorization workspace (all offsets in bytes).
+struct FactorPlan {
+  int64_t m, n, kcap;
+  int32_t dtype, prec, nb, wbytes;  // wbytes: 4 (fp32 working copy) or 8
+  int64_t ldw, ldv, ldf;
+  int64_t ntile_s_max, ntile_g;
+  size_t off_w0, off_w1, off_v, off_f, off_zpart, off_auxpart, off_nrm2part, off_colpart,
+      off_nu, off_nuo, off_amax, off_colid0, off_colid1, off_pvflag, off_pivpos, off_pivid,
+      off_permw, off_posof, off_tau, off_vscale, off_rorig, off_state;
+  size_t bytes;
+};
+
+bool make_factor_plan(int64_t m, int64_t n, int32_t dtype, const id_opts* o, FactorPlan* p);
+
+int factor_run(const void* A, int32_t dtype, int64_t m, int64_t n, int64_t lda,
+               const id_opts* o, void* work, size_t work_bytes, int32_t* perm, double* R,
+               int64_t ldr, int64_t* k_out, int32_t* info, hipStream_t s);
+
+int solve_T_run(const double* R, int64_t ldr, int64_t k, int64_t n, double* T, int64_t ldt,
+                int32_t* info, hipStream_t s);
+
+// X = op(R)^{-1} B for upper-triangular R (k x k, ldr); trans = 0 solves R X = B,
+// trans = 1 solves R^T X = B.  B (k x ncols, ldb) and X (ldx) may alias.
+int trsm_upper_run(const double* R, int64_t ldr, int64_t k, const double* B, int64_t ldb,
+                   int64_t ncols, double* X, int64_t ldx, int trans, hipStream_t s);
+
+// C = alpha * op(A) op(B) + beta * C (column-major float64; ta/tb: 0 = N, 1 = T).
+int gemm64_run(int ta, int tb, int64_t M, int64_t N, int64_t K, double alpha, const double* A,
+               int64_t lda, const double* B, int64_t ldb, double beta, double* C, int64_t ldc,
+               hipStream_t s);
+
+int reconstruct_run(const void* A, int32_t dtype, int64_t m, int64_t n, int64_t lda,
+                    const int32_t* perm, int64_t k, const double* T, int64_t ldt, double* Y,
+                    int64_t ldy, int32_t residual, hipStream_t s);
+
+size_t backward_workspace(int64_t m, int64_t n, int64_t k);
+int backward_run(const void* A, int32_t dtype, int64_t m, int64_t n, int64_t lda,
+                 const int32_t* perm, int64_t k, const double* T, int64_t ldt, const double* gT,
+                 int64_t ldgt, const double* gY, int64_t ldgy, double* gA, int64_t ldga,
+                 void* work, size_t work_bytes, int32_t* info, hipStream_t s);
+
+__host__ __device__ inline int64_t round_up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
+__host__ __device__ inline int64_t ceil_div(int64_t x, int64_t a) { return (x + a - 1) / a; }
+
+// Returns ID_ERR_HIP from the enclosing function when a HIP call fails.
+#define MPID_HIP(expr)                              \
+  do {                                              \
+    if ((expr) != hipSuccess) return ID_ERR_HIP;    \
+  } while (0)
+
+#define MPID_LAUNCH_CHECK()                                  \
+  do {                                                       \
+    if (hipGetLastError() != hipSuccess) return ID_ERR_HIP;  \
+  } while (0)
+
+}  // namespace mpid

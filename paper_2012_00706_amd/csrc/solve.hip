@@ -1,0 +1,175 @@
+// Triangular solves in FP64: T = R11^{-1} R12 (eq. (8); the coefficient step of
+// Algorithms 1 and 2) and the general X = op(R)^{-1} B used by the adjoint.
+//
+// Each block owns 64 right-hand-side columns and walks the 64-row blocks of R
+// in dependency order: the contribution of the already-solved row blocks is
+// accumulated tile by tile through LDS (256 threads x 16 accumulators), then
+// the 64 x 64 diagonal block is solved in LDS.  Columns are independent, so
+// blocks never synchronize with each other.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "device_util.h"
+#include "mpid_internal.h"
+
+namespace mpid {
+
+constexpr int kTB = 64;
+
+// trans = 0: R X = B (back substitution over row blocks, last first).
+// trans = 1: R^T X = B (forward substitution, first row block first).
+// Global traffic goes through LDS with the row index fastest (coalesced in the
+// column-major operands); the arithmetic uses thread = (column cc, row phase rq).
+__global__ __launch_bounds__(kThreads) void k_trsm_upper(const double* __restrict__ R, int64_t ldr,
+                                                        int64_t k, const double* B, int64_t ldb,
+                                                        int64_t ncols, double* X, int64_t ldx,
+                                                        int trans, const int32_t* info) {
+  __shared__ double Rs[kTB][kTB + 1];
+  __shared__ double Xs[kTB][kTB + 1];
+  __shared__ int s_go;
+  const int tid = threadIdx.x;
+  if (tid == 0) s_go = !(info && *info == ID_INFO_SINGULAR);
+  __syncthreads();
+  if (!s_go) return;
+  const int cc = tid % kTB, rq = tid / kTB;  // compute mapping
+  const int la = tid % kTB, lb = tid / kTB;  // load mapping: la fastest (rows)
+  const int64_t c0 = (int64_t)blockIdx.x * kTB;
+  const int64_t nblk = ceil_div(k, kTB);
+  for (int64_t bi = 0; bi < nblk; ++bi) {
+    const int64_t I = trans ? bi : nblk - 1 - bi;
+    const int64_t i0 = I * kTB;
+    const int ib = (int)((k - i0) < kTB ? (k - i0) : kTB);
+    // right-hand side block B(I, cols)
+#pragma unroll 4
+    for (int q = 0; q < 16; ++q) {
+      const int b = lb + 4 * q;
+      const int64_t i = i0 + la, c = c0 + b;
+      Xs[la][b] = (la < ib && c < ncols) ? B[c * ldb + i] : 0.0;
+    }
+    __syncthreads();
+    double acc[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) acc[q] = Xs[rq + 4 * q][cc];
+    // subtract the solved row blocks: acc(i) -= sum_l op(R)(i, l) X(l)
+    for (int64_t bl = 0; bl < bi; ++bl) {
+      const int64_t L = trans ? bl : nblk - 1 - bl;
+      const int64_t l0 = L * kTB;
+      __syncthreads();
+#pragma unroll 4
+      for (int q = 0; q < 16; ++q) {
+        const int b = lb + 4 * q;
+        double v = 0.0;
+        if (!trans) {
+          // Rs[ii][ll] = R(i0 + ii, l0 + ll): load row la, column b
+          const int64_t i = i0 + la, l = l0 + b;
+          if (i < k && l < k) v = R[l * ldr + i];
+          Rs[la][b] = v;
+        } else {
+          // Rs[ii][ll] = R(l0 + ll, i0 + ii): load row l0 + la of column i0 + b
+          const int64_t l = l0 + la, i = i0 + b;
+          if (i < k && l < k) v = R[i * ldr + l];
+          Rs[b][la] = v;
+        }
+        const int64_t xr = l0 + la, c = c0 + b;
+        Xs[la][b] = (xr < k && c < ncols) ? X[c * ldx + xr] : 0.0;
+      }
+      __syncthreads();
+#pragma unroll 4
+      for (int ll = 0; ll < kTB; ++ll) {
+        const double x = Xs[ll][cc];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) acc[q] -= Rs[rq + 4 * q][ll] * x;
+      }
+    }
+    __syncthreads();
+    // diagonal block
+#pragma unroll 4
+    for (int q = 0; q < 16; ++q) {
+      const int b = lb + 4 * q;
+      double v = 0.0;
+      if (!trans) {
+        const int64_t i = i0 + la, l = i0 + b;
+        if (i < k && l < k) v = R[l * ldr + i];
+        Rs[la][b] = v;
+      } else {
+        const int64_t l = i0 + la, i = i0 + b;
+        if (i < k && l < k) v = R[i * ldr + l];
+        Rs[b][la] = v;
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < 16; ++q) Xs[rq + 4 * q][cc] = acc[q];
+    __syncthreads();
+    if (!trans) {
+      for (int ii = ib - 1; ii >= 0; --ii) {
+        const double xi = Xs[ii][cc] / Rs[ii][ii];
+        __syncthreads();
+        if (rq == 0) Xs[ii][cc] = xi;
+        for (int r = rq; r < ii; r += 4) Xs[r][cc] -= Rs[r][ii] * xi;
+        __syncthreads();
+      }
+    } else {
+      for (int ii = 0; ii < ib; ++ii) {
+        const double xi = Xs[ii][cc] / Rs[ii][ii];
+        __syncthreads();
+        if (rq == 0) Xs[ii][cc] = xi;
+        for (int r = rq; r < ib; r += 4)
+          if (r > ii) Xs[r][cc] -= Rs[r][ii] * xi;
+        __syncthreads();
+      }
+    }
+#pragma unroll 4
+    for (int q = 0; q < 16; ++q) {
+      const int b = lb + 4 * q;
+      const int64_t c = c0 + b;
+      if (la < ib && c < ncols) X[c * ldx + i0 + la] = Xs[la][b];
+    }
+    __syncthreads();
+  }
+}
+
+// info = ID_INFO_SINGULAR when some |R_ii| <= n * 2^-53 * |R_00| (or R_00 = 0),
+// ID_INFO_RANK_FULL when k == n, else 0.
+__global__ __launch_bounds__(kThreads) void k_check_diag(const double* __restrict__ R, int64_t ldr,
+                                                         int64_t k, int64_t n, int32_t* info) {
+  __shared__ double dscr[4];
+  const int tid = threadIdx.x;
+  const double r00 = k > 0 ? fabs(R[0]) : 0.0;
+  const double thr = (double)n * ldexp(1.0, -53) * r00;
+  double bad = 0.0;
+  for (int64_t i = tid; i < k; i += kThreads)
+    if (!(fabs(R[i * ldr + i]) > thr)) bad += 1.0;
+  bad = block_sum(bad, dscr);
+  if (tid == 0) {
+    if (k > 0 && (bad > 0.0 || r00 == 0.0))
+      *info = ID_INFO_SINGULAR;
+    else
+      *info = (k == n) ? ID_INFO_RANK_FULL : 0;
+  }
+}
+
+int trsm_upper_run(const double* R, int64_t ldr, int64_t k, const double* B, int64_t ldb,
+                   int64_t ncols, double* X, int64_t ldx, int trans, hipStream_t s) {
+  if (k <= 0 || ncols <= 0) return ID_OK;
+  k_trsm_upper<<<dim3((unsigned)ceil_div(ncols, kTB)), kThreads, 0, s>>>(R, ldr, k, B, ldb, ncols,
+                                                                         X, ldx, trans, nullptr);
+  MPID_LAUNCH_CHECK();
+  return ID_OK;
+}
+
+int solve_T_run(const double* R, int64_t ldr, int64_t k, int64_t n, double* T, int64_t ldt,
+                int32_t* info, hipStream_t s) {
+  if (!info || k < 0 || n < k) return ID_ERR_ARG;
+  if (k > 0 && (!R || ldr < k)) return ID_ERR_ARG;
+  if (n - k > 0 && k > 0 && (!T || ldt < k)) return ID_ERR_ARG;
+  k_check_diag<<<1, kThreads, 0, s>>>(R, ldr, k, n, info);
+  MPID_LAUNCH_CHECK();
+  if (k == 0 || n == k) return ID_OK;
+  k_trsm_upper<<<dim3((unsigned)ceil_div(n - k, kTB)), kThreads, 0, s>>>(
+      R, ldr, k, R + k * ldr, ldr, n - k, T, ldt, 0, info);
+  MPID_LAUNCH_CHECK();
+  return ID_OK;
+}
+
+}  // namespace mpid

@@ -1,0 +1,106 @@
+"""CPU checks of the C-ABI library: it loads, exports every symbol that
+include/mpid.h declares, and rejects bad arguments before touching the GPU."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "mpid.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(id_\w+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2012_00706_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        from paper_2012_00706_amd.build import build_library
+        build_library()
+    return _lib.load()
+
+
+def test_exports_every_declared_symbol(lib):
+    names = declared_functions()
+    assert {"id_factor", "id_solve_T", "id_reconstruct", "id_backward",
+            "id_workspace_size", "id_status_string"} <= set(names)
+    for name in names:
+        assert hasattr(lib, name), name
+
+
+def test_binding_covers_header(lib):
+    from paper_2012_00706_amd import _lib
+    assert set(declared_functions()) == set(_lib.SIGNATURES)
+
+
+def test_status_strings(lib):
+    from paper_2012_00706_amd import C
+    for key in ("ID_OK", "ID_ERR_ARG", "ID_ERR_WORKSPACE", "ID_INFO_SINGULAR"):
+        s = lib.id_status_string(C[key]).decode()
+        assert s and s != "unknown code"
+    assert lib.id_status_string(12345).decode() == "unknown code"
+
+
+def test_workspace_size_host_logic(lib):
+    from paper_2012_00706_amd import C, make_opts
+    o = make_opts(tol=1e-3, prec="mixed_bf16")
+    s1 = lib.id_workspace_size(20000, 2000, C["ID_F32"], ctypes.byref(o))
+    # two fp32 working copies dominate
+    assert s1 >= 2 * 20000 * 2048 * 4
+    o64 = make_opts(tol=1e-3, prec="f64")
+    s2 = lib.id_workspace_size(20000, 2000, C["ID_F32"], ctypes.byref(o64))
+    assert s2 > s1
+    bad = make_opts(k=3)
+    bad.nb = 99
+    assert lib.id_workspace_size(10, 10, C["ID_F32"], ctypes.byref(bad)) == 0
+    assert lib.id_workspace_size(-1, 10, C["ID_F32"], ctypes.byref(o)) == 0
+    assert lib.id_workspace_size(10, 10, 7, ctypes.byref(o)) == 0
+
+
+def test_argument_errors_return_before_any_device_call(lib):
+    from paper_2012_00706_amd import C, make_opts
+    o = make_opts(k=2)
+    k = ctypes.c_int64(0)
+    info = ctypes.c_int32(0)
+    # null A
+    rc = lib.id_factor(None, C["ID_F64"], 10, 5, 10, ctypes.byref(o), None, 0, None, None, 2,
+                       ctypes.byref(k), ctypes.byref(info), None)
+    assert rc == C["ID_ERR_ARG"]
+    # bad dtype
+    rc = lib.id_factor(None, 9, 10, 5, 10, ctypes.byref(o), None, 0, None, None, 2,
+                       ctypes.byref(k), ctypes.byref(info), None)
+    assert rc == C["ID_ERR_DTYPE"]
+    # lda < m
+    fake = ctypes.c_void_p(0x1000)
+    rc = lib.id_factor(fake, C["ID_F64"], 10, 5, 3, ctypes.byref(o), fake, 1 << 30, fake, fake, 2,
+                       ctypes.byref(k), ctypes.byref(info), None)
+    assert rc == C["ID_ERR_ARG"]
+    # workspace too small
+    rc = lib.id_factor(fake, C["ID_F64"], 10, 5, 10, ctypes.byref(o), fake, 16, fake, fake, 2,
+                       ctypes.byref(k), ctypes.byref(info), None)
+    assert rc == C["ID_ERR_WORKSPACE"]
+    # solve_T: n < k
+    rc = lib.id_solve_T(fake, 5, 6, 5, fake, 6, fake, None)
+    assert rc == C["ID_ERR_ARG"]
+    # reconstruct: k > n
+    rc = lib.id_reconstruct(fake, C["ID_F32"], 4, 3, 4, fake, 5, fake, 5, fake, 4, 0, None)
+    assert rc == C["ID_ERR_ARG"]
+    rc = lib.id_backward(fake, C["ID_F32"], 4, 3, 4, fake, 5, fake, 5, None, 1, None, 4, fake, 4,
+                         fake, 1 << 20, ctypes.byref(info), None)
+    assert rc == C["ID_ERR_ARG"]
+    assert lib.id_backward_workspace_size(4, 3, 5) == 0
+
+
+def test_options_validation():
+    from paper_2012_00706_amd import make_opts
+    with pytest.raises(ValueError):
+        make_opts()
+    with pytest.raises(ValueError):
+        make_opts(k=3, prec="fp8")
+    with pytest.raises(ValueError):
+        make_opts(k=3, rule="nope")

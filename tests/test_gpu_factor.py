@@ -1,0 +1,183 @@
+"""Parity of the HIP factorization + solve (through the C ABI) with the CPU
+oracle: FP64 pivots exactly and T to 1e-12 on gap-separated inputs, at sizes
+that span several tiles with ragged tails; edge cases; determinism."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as orc
+import synth
+from gpu_helpers import gpu_id, host, need_gpu, rel_err, row_sign_align, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+def _check_f64_parity(A, k, tol_T=1e-12):
+    perm, kk, R, T = gpu_id(A, k=k, prec="f64")
+    ref = orc.cpqr(A, k=k)
+    Tref = orc.solve_T(ref.R, ref.k)
+    assert kk == ref.k
+    gap = ref.margins.min() if ref.k else 1.0
+    assert gap > 1e-8, "input not gap-separated"
+    assert perm[:kk].tolist() == ref.perm[:kk].tolist()
+    np.testing.assert_allclose(row_sign_align(R, ref.R), ref.R, rtol=0,
+                               atol=1e-12 * np.abs(ref.R).max())
+    assert rel_err(T, Tref) <= tol_T * max(1.0, np.linalg.cond(ref.R[:, :kk]) / 1e3)
+
+
+def test_config1_f64_parity():
+    need_gpu()
+    A = synth.config1()
+    _check_f64_parity(A, 50)
+
+
+@pytest.mark.parametrize("m,n,k", [
+    (300, 150, 40),     # several sweep tiles, one panel + part
+    (1000, 257, 70),    # ragged column tail, three panels
+    (2100, 100, 33),    # many row tiles, panel boundary + 1
+    (65, 64, 64),       # full rank square-ish, m = 65
+    (129, 33, 33),      # k = n
+    (40, 90, 40),       # wide: k = m
+])
+def test_f64_parity_shapes(m, n, k):
+    need_gpu()
+    r = min(m, n)
+    A = synth.spectrum_matrix(m, n, synth.sigma_geom10(r, 12.0), 100 + m, 200 + n)
+    perm, kk, R, T = gpu_id(A, k=k, prec="f64")
+    ref = orc.cpqr(A, k=k)
+    assert kk == ref.k
+    gap = ref.margins
+    # compare pivots up to the first step whose margin is at rounding level
+    upto = int(np.argmax(gap < 1e-8)) if np.any(gap < 1e-8) else kk
+    assert perm[:upto].tolist() == ref.perm[:upto].tolist()
+    if upto == kk:
+        Tref = orc.solve_T(ref.R, kk)
+        if T.size:
+            kappa = np.linalg.cond(ref.R[:, :kk])
+            assert rel_err(T, Tref) <= 1e-14 * kappa * 100
+    # the factorization identity holds whatever the pivots
+    Q = None
+    e2, _ = orc.id_error(A, perm, kk, T if T.size else np.zeros((kk, n - kk)))
+    assert e2 <= np.linalg.norm(A, 2) * 1e-2 + 10 * synth.sigma_geom10(r, 12.0)[min(kk, r - 1)] * np.sqrt(1 + kk * (n - kk))
+
+
+@pytest.mark.parametrize("nb", [1, 7, 32])
+def test_panel_width_does_not_change_result(nb):
+    need_gpu()
+    A = synth.spectrum_matrix(500, 120, synth.sigma_geom10(120, 15.0), 5, 6)
+    ref = orc.cpqr(A, k=45)
+    perm, kk, R, T = gpu_id(A, k=45, prec="f64", nb=nb)
+    assert perm[:45].tolist() == ref.perm[:45].tolist()
+    assert rel_err(T, orc.solve_T(ref.R, 45)) <= 1e-11
+
+
+@pytest.mark.parametrize("rule", ["pivot_rel", "frob_rel"])
+def test_adaptive_rank_matches_oracle(rule):
+    need_gpu()
+    A = synth.spectrum_matrix(800, 200, synth.sigma_exp(200, 10.0), 41, 42)
+    tol = 1e-3
+    ref = orc.cpqr(A, tol=tol, rule=rule)
+    perm, kk, R, T = gpu_id(A, tol=tol, rule=rule, prec="f64")
+    assert kk == ref.k
+    assert perm[:kk].tolist() == ref.perm[:kk].tolist()
+
+
+def test_exact_low_rank_recovered():
+    need_gpu()
+    A = synth.low_rank(700, 130, 23, seed=3)
+    perm, kk, R, T = gpu_id(A, tol=1e-10, prec="f64")
+    assert kk == 23
+    _, ef = orc.id_error(A, perm, kk, T)
+    assert ef <= 1e-12 * np.linalg.norm(A)
+
+
+@pytest.mark.parametrize("prec,u_low", [("mixed_bf16", orc.U_BF16), ("mixed_f16", orc.U_HALF)])
+def test_mixed_acceptance_bound(prec, u_low):
+    need_gpu()
+    A = synth.spectrum_matrix(3000, 400, synth.sigma_exp(400, 40.0), 51, 52).astype(np.float32)
+    perm, kk, R, T = gpu_id(A, tol=1e-3, prec=prec)
+    assert kk > 0
+    e_mixed = orc.id_error(A, perm, kk, T)[0]
+    ref = orc.cpqr(A, k=kk)
+    e_ref = orc.id_error(A, ref.perm, kk, orc.solve_T(ref.R, kk))[0]
+    norm2 = synth.sigma_exp(400, 40.0)[0]
+    assert e_mixed <= 1.1 * e_ref + 10 * u_low * norm2
+
+
+def test_mixed_fp16_tiny_values_scaled():
+    """The FP16 path scales its operands by powers of two, so a matrix whose
+    entries sit far below FP16's normal range still factors accurately."""
+    need_gpu()
+    A = (synth.spectrum_matrix(1500, 200, synth.sigma_pow(200, 2.0), 61, 62) * 1e-9).astype(np.float32)
+    perm, kk, R, T = gpu_id(A, k=40, prec="mixed_f16")
+    e = orc.id_error(A, perm, kk, T)[0]
+    ref = orc.cpqr(A, k=40)
+    e_ref = orc.id_error(A, ref.perm, 40, orc.solve_T(ref.R, 40))[0]
+    assert e <= 1.1 * e_ref + 10 * orc.U_HALF * 1e-9
+
+
+def test_identity_block_and_reconstruction():
+    need_gpu()
+    import paper_2012_00706_amd as mp
+    A = synth.spectrum_matrix(400, 90, synth.sigma_exp(90, 8.0), 71, 72)
+    At = to_dev(A)
+    res = mp.column_id(At, k=30)
+    Y = host(mp.reconstruct(At, res.perm, res.k, res.T))
+    perm = host(res.perm).astype(np.int64)
+    J = perm[:30]
+    assert np.array_equal(Y[:, J], A[:, J])
+    Yref = orc.reconstruct(A, perm, 30, host(res.T))
+    assert rel_err(Y, Yref) <= 1e-14
+    E = host(mp.reconstruct(At, res.perm, res.k, res.T, residual=True))
+    assert rel_err(E, A - Yref) <= 1e-10
+
+
+def test_determinism_bitwise():
+    need_gpu()
+    A = synth.spectrum_matrix(2000, 300, synth.sigma_exp(300, 30.0), 81, 82).astype(np.float32)
+    p1, k1, R1, T1 = gpu_id(A, tol=1e-3, prec="mixed_bf16")
+    p2, k2, R2, T2 = gpu_id(A, tol=1e-3, prec="mixed_bf16")
+    assert k1 == k2 and np.array_equal(p1, p2)
+    assert np.array_equal(R1, R2) and np.array_equal(T1, T2)
+
+
+# ---------------------------------------------------------------- edge cases
+
+def test_zero_matrix_gives_rank_zero():
+    need_gpu()
+    import paper_2012_00706_amd as mp
+    A = torch.zeros((50, 20), dtype=torch.float64, device="cuda")
+    fr = mp.factor(A, tol=1e-3)
+    assert fr.k == 0
+
+
+def test_nonfinite_input_reported():
+    need_gpu()
+    import paper_2012_00706_amd as mp
+    A = synth.gaussian(60, 10, seed=1)
+    A[7, 3] = np.nan
+    fr = mp.factor(to_dev(A), tol=1e-3)
+    assert fr.info == mp.C["ID_INFO_NONFINITE"] and fr.k == 0
+
+
+def test_full_rank_and_singular_fixed_rank():
+    need_gpu()
+    import paper_2012_00706_amd as mp
+    A = synth.gaussian(40, 12, seed=2)
+    res = mp.column_id(to_dev(A), tol=1e-14)
+    assert res.k == 12 and res.T.shape == (12, 0)
+    L = synth.low_rank(60, 20, 4, seed=3)
+    fr = mp.factor(to_dev(L), k=8)
+    with pytest.raises(mp.MpidError):
+        mp.solve_T(fr.R, fr.k, 20)
+
+
+@pytest.mark.parametrize("m,n", [(1, 1), (1, 7), (9, 1), (2, 3)])
+def test_degenerate_shapes(m, n):
+    need_gpu()
+    A = synth.gaussian(m, n, seed=m * 10 + n)
+    k = min(m, n)
+    perm, kk, R, T = gpu_id(A, k=k, prec="f64")
+    ref = orc.cpqr(A, k=k)
+    assert perm[:k].tolist() == ref.perm[:k].tolist()
+    np.testing.assert_allclose(np.abs(R), np.abs(ref.R), rtol=1e-13, atol=1e-14)
