@@ -52,10 +52,17 @@ extern "C" {
  *                     by powers of two, which is exact, so they stay in FP16
  *                     range); column norms, R, the recomputation of norms and the
  *                     triangular solve in float64 (Algorithm 2, mixed variant).
- * ID_PREC_MIXED_BF16: as above with BF16 operands (no scaling needed).      */
+ * ID_PREC_MIXED_BF16: as above with BF16 operands (no scaling needed).
+ * ID_PREC_MIXED_BF16X3: as ID_PREC_MIXED_BF16, each operand split into a sum of
+ *                     two BF16 numbers (x = hi + lo) and the product formed as
+ *                     hi*hi + hi*lo + lo*hi on BF16 matrix cores with FP32
+ *                     accumulation: the update error drops from about 2^-8 to
+ *                     about 2^-16 of its size at three times the (idle) matrix
+ *                     work of the bandwidth-bound update.                    */
 #define ID_PREC_F64 0
 #define ID_PREC_MIXED_F16 1
 #define ID_PREC_MIXED_BF16 2
+#define ID_PREC_MIXED_BF16X3 3
 
 /* ---- adaptive rank rules (used when k_fixed == 0) ------------------------
  * ID_RANK_PIVOT_REL: stop before step j >= 1 once the largest remaining column
@@ -68,6 +75,7 @@ extern "C" {
 
 /* ---- flags --------------------------------------------------------------- */
 #define ID_FLAG_NO_PIVOT 1 /* unpivoted Householder QR (perm = identity) */
+#define ID_FLAG_PROFILE 2  /* time every kernel with HIP events (see id_last_profile) */
 
 typedef struct {
   int32_t prec;      /* ID_PREC_* */
@@ -159,6 +167,29 @@ int id_backward(const void* A, int32_t dtype, int64_t m, int64_t n, int64_t lda,
                 const int32_t* perm, int64_t k, const double* T, int64_t ldt, const double* gT,
                 int64_t ldgt, const double* gY, int64_t ldgy, double* gA, int64_t ldga,
                 void* work, size_t work_bytes, int32_t* info, void* stream);
+
+/* Per-kernel timing of the calling thread's last id_factor call made with
+ * ID_FLAG_PROFILE (instrumentation, not part of the method).  Times come from
+ * HIP events recorded around each launch on the call's stream; "bytes" are the
+ * algorithmic bytes of the work the kernels did:
+ *   sweep: one read of the trailing block per pivot step j,
+ *          (m - j) * (n - j - 1) * s bytes, s = 4 (fp32 working copy) or 8;
+ *   gemm:  one read and one write of the refreshed block per panel,
+ *          2 * (m - j_end) * (n - j_end) * s bytes.
+ * Launches that found nothing to do (after the rank was reached or a panel
+ * ended early) are not counted. */
+typedef struct {
+  int64_t sweep_launches;
+  double sweep_ms, sweep_bytes;
+  int64_t finalize_launches;
+  double finalize_ms;
+  int64_t gemm_launches;
+  double gemm_ms, gemm_bytes;
+  double other_ms; /* ingest, norm reductions, bookkeeping */
+  double total_ms; /* first to last event of the call */
+} id_profile;
+
+int id_last_profile(id_profile* out);
 
 /* Human-readable text for a return or info code [host]. */
 const char* id_status_string(int code);

@@ -17,6 +17,7 @@ from .api import (  # noqa: F401
     empty_colmajor,
     factor,
     kcap_of,
+    last_profile,
     make_opts,
     reconstruct,
     solve_T,

@@ -26,6 +26,24 @@ class IdOpts(ctypes.Structure):
     ]
 
 
+class IdProfile(ctypes.Structure):
+    _fields_ = [
+        ("sweep_launches", ctypes.c_int64),
+        ("sweep_ms", ctypes.c_double),
+        ("sweep_bytes", ctypes.c_double),
+        ("finalize_launches", ctypes.c_int64),
+        ("finalize_ms", ctypes.c_double),
+        ("gemm_launches", ctypes.c_int64),
+        ("gemm_ms", ctypes.c_double),
+        ("gemm_bytes", ctypes.c_double),
+        ("other_ms", ctypes.c_double),
+        ("total_ms", ctypes.c_double),
+    ]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
 def _constants():
     """#define ID_* integer constants parsed from the public header."""
     out = {}
@@ -53,6 +71,7 @@ SIGNATURES = {
     "id_backward_workspace_size": (_sz, [_i64, _i64, _i64]),
     "id_backward": (ctypes.c_int, [_vp, _i32, _i64, _i64, _i64, _vp, _i64, _vp, _i64, _vp, _i64,
                                    _vp, _i64, _vp, _i64, _vp, _sz, _P(_i32), _vp]),
+    "id_last_profile": (ctypes.c_int, [_P(IdProfile)]),
     "id_status_string": (ctypes.c_char_p, [ctypes.c_int]),
 }
 

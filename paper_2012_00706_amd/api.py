@@ -19,6 +19,7 @@ PREC = {
     "f64": C["ID_PREC_F64"],
     "mixed_f16": C["ID_PREC_MIXED_F16"],
     "mixed_bf16": C["ID_PREC_MIXED_BF16"],
+    "mixed_bf16x3": C["ID_PREC_MIXED_BF16X3"],
 }
 RULE = {"pivot_rel": C["ID_RANK_PIVOT_REL"], "frob_rel": C["ID_RANK_FROB_REL"]}
 DTYPE = {torch.float32: C["ID_F32"], torch.float64: C["ID_F64"]}
@@ -47,7 +48,8 @@ def _stream(device=None):
     return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
 
 
-def make_opts(k=None, tol=None, prec="f64", rule="pivot_rel", k_max=0, nb=0, no_pivot=False):
+def make_opts(k=None, tol=None, prec="f64", rule="pivot_rel", k_max=0, nb=0, no_pivot=False,
+              profile=False):
     if prec not in PREC:
         raise ValueError(f"prec must be one of {sorted(PREC)}")
     if rule not in RULE:
@@ -61,7 +63,7 @@ def make_opts(k=None, tol=None, prec="f64", rule="pivot_rel", k_max=0, nb=0, no_
     o.rel_tol = float(tol) if tol is not None else 0.0
     o.k_max = int(k_max)
     o.nb = int(nb)
-    o.flags = C["ID_FLAG_NO_PIVOT"] if no_pivot else 0
+    o.flags = (C["ID_FLAG_NO_PIVOT"] if no_pivot else 0) | (C["ID_FLAG_PROFILE"] if profile else 0)
     if k is not None and int(k) == 0:
         o.k_max = 0
     return o
@@ -90,7 +92,7 @@ class FactorResult:
 
 def factor(A: torch.Tensor, k=None, tol=None, prec="f64", rule="pivot_rel", k_max=0, nb=0,
            no_pivot=False, work: torch.Tensor | None = None, R_buf: torch.Tensor | None = None,
-           perm_buf: torch.Tensor | None = None) -> FactorResult:
+           perm_buf: torch.Tensor | None = None, profile: bool = False) -> FactorResult:
     """Rank-k column-pivoted QR (id_factor).  k=0 gives k = 0."""
     lib = _lib.load()
     A, lda = colmajor(A)
@@ -98,7 +100,7 @@ def factor(A: torch.Tensor, k=None, tol=None, prec="f64", rule="pivot_rel", k_ma
     if k is not None and int(k) == 0:
         return FactorResult(torch.arange(n, dtype=torch.int32, device=A.device),
                             empty_colmajor(0, n, device=A.device), 0, 0)
-    o = make_opts(k, tol, prec, rule, k_max, nb, no_pivot)
+    o = make_opts(k, tol, prec, rule, k_max, nb, no_pivot, profile)
     ws = workspace_size(m, n, A.dtype, o)
     if ws == 0:
         raise ValueError("invalid factorization arguments")
@@ -194,6 +196,13 @@ def backward(A: torch.Tensor, perm: torch.Tensor, k: int, T: torch.Tensor, gT=No
     if info.value == C["ID_INFO_SINGULAR"]:
         raise _lib.MpidError(info.value, "id_backward")
     return gA
+
+
+def last_profile() -> dict:
+    """Per-kernel event timings of this thread's last factor(..., profile=True)."""
+    p = _lib.IdProfile()
+    _lib.check(_lib.load().id_last_profile(ctypes.byref(p)), "id_last_profile")
+    return p.as_dict()
 
 
 @dataclass

@@ -18,7 +18,7 @@ int id_factor(const void* A, int32_t dtype, int64_t m, int64_t n, int64_t lda,
   if (dtype != ID_F32 && dtype != ID_F64) return ID_ERR_DTYPE;
   if (!opts) return ID_ERR_ARG;
   if (opts->prec != ID_PREC_F64 && opts->prec != ID_PREC_MIXED_F16 &&
-      opts->prec != ID_PREC_MIXED_BF16)
+      opts->prec != ID_PREC_MIXED_BF16 && opts->prec != ID_PREC_MIXED_BF16X3)
     return ID_ERR_DTYPE;
   return mpid::factor_run(A, dtype, m, n, lda, opts, work, work_bytes, perm, R, ldr, k_out, info,
                           (hipStream_t)stream);
@@ -46,6 +46,12 @@ int id_backward(const void* A, int32_t dtype, int64_t m, int64_t n, int64_t lda,
                 void* work, size_t work_bytes, int32_t* info, void* stream) {
   return mpid::backward_run(A, dtype, m, n, lda, perm, k, T, ldt, gT, ldgt, gY, ldgy, gA, ldga,
                             work, work_bytes, info, (hipStream_t)stream);
+}
+
+int id_last_profile(id_profile* out) {
+  if (!out) return ID_ERR_ARG;
+  mpid::last_profile(out);
+  return ID_OK;
 }
 
 const char* id_status_string(int code) {

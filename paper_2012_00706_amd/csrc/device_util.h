@@ -25,6 +25,22 @@ __device__ __forceinline__ double block_sum(double v, double* scratch) {
   return t;
 }
 
+// sum over t = start, start + step, ... < end of p[t * stride], keeping eight
+// independent loads in flight; fixed summation order (deterministic).
+__device__ __forceinline__ double strided_sum(const double* __restrict__ p, int64_t stride,
+                                              int64_t start, int64_t end, int step) {
+  double s[8];
+#pragma unroll
+  for (int u = 0; u < 8; ++u) s[u] = 0.0;
+  int64_t t = start;
+  for (; t + 7 * (int64_t)step < end; t += 8 * (int64_t)step) {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) s[u] += p[(t + (int64_t)u * step) * stride];
+  }
+  for (; t < end; t += step) s[0] += p[t * stride];
+  return ((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7]));
+}
+
 // Pivot order: larger norm first; equal norms go to the smaller swap-order key.
 __device__ __forceinline__ bool amax_better(double va, int ka, double vb, int kb) {
   return va > vb || (va == vb && ka < kb);

@@ -26,6 +26,7 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <vector>
 
 #include "device_util.h"
 #include "mpid_internal.h"
@@ -50,14 +51,17 @@ struct Vec16<double> {
   static constexpr int n = 2;
 };
 
-enum { OP_F64 = 0, OP_F16 = 1, OP_BF16 = 2 };
+enum { OP_F64 = 0, OP_F16 = 1, OP_BF16 = 2, OP_BF16X3 = 3 };
+
+constexpr int kPrefetch = 4;  // sweep rows per thread loaded ahead of the pivot search
 
 // ----------------------------------------------------------------- plan
 
 bool make_factor_plan(int64_t m, int64_t n, int32_t dtype, const id_opts* o, FactorPlan* p) {
   if (!o || !p || m < 0 || n < 0) return false;
   if (dtype != ID_F32 && dtype != ID_F64) return false;
-  if (o->prec != ID_PREC_F64 && o->prec != ID_PREC_MIXED_F16 && o->prec != ID_PREC_MIXED_BF16)
+  if (o->prec != ID_PREC_F64 && o->prec != ID_PREC_MIXED_F16 && o->prec != ID_PREC_MIXED_BF16 &&
+      o->prec != ID_PREC_MIXED_BF16X3)
     return false;
   if (o->rank_rule != ID_RANK_PIVOT_REL && o->rank_rule != ID_RANK_FROB_REL) return false;
   if (o->k_fixed < 0 || o->k_max < 0 || !(o->rel_tol >= 0.0)) return false;
@@ -97,7 +101,7 @@ bool make_factor_plan(int64_t m, int64_t n, int32_t dtype, const id_opts* o, Fac
   p->off_colpart = take((size_t)p->ntile_g * p->ldf * 8);
   p->off_nu = take((size_t)p->ldf * 8);
   p->off_nuo = take((size_t)p->ldf * 8);
-  p->off_amax = take((size_t)(p->ldf / kFinCols + 8) * sizeof(AmaxPart));
+  p->off_amax = take((size_t)(p->ldf / kFC + 8) * sizeof(AmaxPart));
   p->off_colid0 = take((size_t)p->ldf * 4);
   p->off_colid1 = take((size_t)p->ldf * 4);
   p->off_pvflag = take((size_t)p->ldf * 4);
@@ -210,10 +214,7 @@ __global__ __launch_bounds__(kThreads) void k_colreduce(
   if (!s_go) return;
   const int64_t ncols = ncols_base - (subtract_jb ? st->jb : 0);
   const int64_t l = (int64_t)blockIdx.x * kFinCols + cl;
-  double s = 0.0;
-  if (l < ncols)
-    for (int64_t t = tg0 + tl; t < tg1; t += 8) s += colpart[t * ldf + l];
-  red[tl][cl] = s;
+  red[tl][cl] = l < ncols ? strided_sum(colpart + l, ldf, tg0 + tl, tg1, 8) : 0.0;
   __syncthreads();
   AmaxVal cand = amax_none();
   if (tl == 0 && l < ncols) {
@@ -290,16 +291,12 @@ __global__ __launch_bounds__(kThreads) void k_sweep(StepArgs<S> a) {
   __shared__ double wsh[kRtMax];
   __shared__ double gsh[kNbMax];
   __shared__ double red[kThreads * VEC];
+  __shared__ double zred[8][kNbMax + 1];
   __shared__ AmaxVal ascr[4];
   __shared__ double dscr[4];
   __shared__ int s_go;
   FactorState* st = a.st;
   const int tid = threadIdx.x;
-  // One thread reads the flags: block 0 of this kernel may set them while
-  // other blocks start, and every wave of a block must take the same branch.
-  if (tid == 0) s_go = (st->done == 0 && st->end_flag == 0);
-  __syncthreads();
-  if (!s_go) return;
   const int total = a.ntile * a.nchunk;
   const int per = gridDim.x / 8;
   const int v = (blockIdx.x % 8) * per + blockIdx.x / 8;
@@ -308,6 +305,28 @@ __global__ __launch_bounds__(kThreads) void k_sweep(StepArgs<S> a) {
   const int chunk = v % a.nchunk;
   const int64_t j = a.j;
   const int jj = a.jj;
+  const int64_t r0 = tile * a.Rt;
+  const int64_t r1 = r0 + a.Rt < a.m ? r0 + a.Rt : a.m;
+  // sweep geometry; the block's first rows are loaded now, before the pivot
+  // search, since they do not depend on it
+  const int TPR = a.CW / VEC;
+  const int RG = kThreads / TPR;
+  const int rg = tid / TPR, cv = tid % TPR;
+  const int64_t l0 = (int64_t)chunk * a.CW + (int64_t)cv * VEC;
+  const bool colok = l0 < a.ncur;
+  const int64_t ib = (r0 > j + 1 ? r0 : j + 1) + rg;
+  const S* base = a.W + l0;
+  VT pf[kPrefetch];
+#pragma unroll
+  for (int u = 0; u < kPrefetch; ++u) {
+    const int64_t i = ib + (int64_t)u * RG;
+    if (colok && i < r1) pf[u] = *(const VT*)(base + i * a.ldw);
+  }
+  // One thread reads the flags: block 0 of this kernel may set them while
+  // other blocks start, and every wave of a block must take the same branch.
+  if (tid == 0) s_go = (st->done == 0 && st->end_flag == 0);
+  __syncthreads();
+  if (!s_go) return;
 
   AmaxVal best = amax_none();
   for (int q = tid; q < a.namax; q += kThreads) {
@@ -360,56 +379,82 @@ __global__ __launch_bounds__(kThreads) void k_sweep(StepArgs<S> a) {
     if (j == 0) st->fro2 = best.s2;
   }
 
-  // current pivot column w for the tile's rows
-  const int64_t r0 = tile * a.Rt;
-  const int64_t r1 = r0 + a.Rt < a.m ? r0 + a.Rt : a.m;
-  if (tid < jj) gsh[tid] = a.vscale[tid] * a.F[(int64_t)tid * a.ldf + p];
+  // Current pivot column w on the tile's rows: the stale column minus the
+  // panel's reflectors times F(p, :).  Each thread owns rows; the reflector
+  // entries of a row are loaded together (independent loads) and kept in
+  // registers, so chunk 0 can also form sum_{i>j} V(i,c) w(i) from them.
+  if (tid < kNbMax) gsh[tid] = tid < jj ? a.vscale[tid] * a.F[(int64_t)tid * a.ldf + p] : 0.0;
   __syncthreads();
+  const bool lead = chunk == 0;
   for (int rr = tid; rr < a.Rt; rr += kThreads) {
     const int64_t i = r0 + rr;
     double w = 0.0;
     if (i >= j && i < r1) {
+      const S* vcol = a.V + i;
       w = (double)a.W[i * a.ldw + p];
-      for (int c = 0; c < jj; ++c) w -= (double)a.V[(int64_t)c * a.ldv + i] * gsh[c];
+      for (int cb = 0; cb < jj; cb += 8) {
+        S vr[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) vr[u] = cb + u < jj ? vcol[(int64_t)(cb + u) * a.ldv] : (S)0;
+#pragma unroll
+        for (int u = 0; u < 8; ++u) w -= (double)vr[u] * gsh[cb + u];
+      }
+      if (lead) {
+        a.V[(int64_t)jj * a.ldv + i] = (S)w;
+        if (i == j) st->alpha = w;
+      }
     }
-    wsh[rr] = w;
+    // row j holds alpha, kept apart: every sum below runs over rows i > j
+    wsh[rr] = i == j ? 0.0 : w;
   }
   __syncthreads();
-
-  if (chunk == 0) {
-    double s = 0.0;
-    for (int rr = tid; rr < a.Rt; rr += kThreads) {
-      const int64_t i = r0 + rr;
-      if (i >= j && i < r1) a.V[(int64_t)jj * a.ldv + i] = (S)wsh[rr];
-      if (i > j && i < r1) s += wsh[rr] * wsh[rr];
-    }
-    if (tid == 0 && j >= r0 && j < r1) st->alpha = wsh[j - r0];
-    s = block_sum(s, dscr);
-    if (tid == 0) a.nrm2part[tile] = s;
-    const int lane = tid & 63, wv = tid >> 6;
-    for (int c = wv; c < jj; c += 4) {
-      double acc = 0.0;
-      for (int rr = lane; rr < a.Rt; rr += 64) {
-        const int64_t i = r0 + rr;
-        if (i > j && i < r1) acc += (double)a.V[(int64_t)c * a.ldv + i] * wsh[rr];
+  if (lead) {
+    // sum_{i>j} V(i,c) w(i) for c < jj (thread = column c x row group) and
+    // sum_{i>j} w(i)^2; the V rows were just read, so these loads hit cache
+    const int c = tid % kNbMax, rg = tid / kNbMax;
+    double z = 0.0;
+    if (c < jj) {
+      const S* vc = a.V + (int64_t)c * a.ldv + r0;
+      const int64_t rend = r1 - r0;
+      int64_t rr = rg;
+      double z1 = 0.0, z2 = 0.0, z3 = 0.0;
+      for (; rr + 24 < rend; rr += 32) {
+        z += (double)vc[rr] * wsh[rr];
+        z1 += (double)vc[rr + 8] * wsh[rr + 8];
+        z2 += (double)vc[rr + 16] * wsh[rr + 16];
+        z3 += (double)vc[rr + 24] * wsh[rr + 24];
       }
-      acc = wave_sum(acc);
-      if (lane == 0) a.auxpart[tile * kNbMax + c] = acc;
+      for (; rr < rend; rr += 8) z += (double)vc[rr] * wsh[rr];
+      z = (z + z1) + (z2 + z3);
     }
+    zred[rg][c] = z;
+    double nn = 0.0;
+    for (int64_t rr = tid; rr < r1 - r0; rr += kThreads) nn += wsh[rr] * wsh[rr];
+    nn = block_sum(nn, dscr);
+    if (tid < jj) {
+      double t = 0.0;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) t += zred[q][tid];
+      a.auxpart[tile * kNbMax + tid] = t;
+    }
+    if (tid == 0) a.nrm2part[tile] = nn;
   }
 
   // the sweep: z(l) = sum_{i in tile, i > j} W(i, l) w(i)
-  const int TPR = a.CW / VEC;
-  const int RG = kThreads / TPR;
-  const int rg = tid / TPR, cv = tid % TPR;
-  const int64_t l0 = (int64_t)chunk * a.CW + (int64_t)cv * VEC;
   double acc[VEC];
 #pragma unroll
   for (int e = 0; e < VEC; ++e) acc[e] = 0.0;
-  if (l0 < a.ncur) {
-    const int64_t ib = r0 > j + 1 ? r0 : j + 1;
-    const S* base = a.W + l0;
-    int64_t i = ib + rg;
+  if (colok) {
+#pragma unroll
+    for (int u = 0; u < kPrefetch; ++u) {
+      const int64_t i = ib + (int64_t)u * RG;
+      if (i < r1) {
+        const double w0 = wsh[i - r0];
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) acc[e] += (double)pf[u][e] * w0;
+      }
+    }
+    int64_t i = ib + (int64_t)kPrefetch * RG;
     for (; i + 3 * RG < r1; i += 4 * RG) {
       const VT x0 = *(const VT*)(base + i * a.ldw);
       const VT x1 = *(const VT*)(base + (i + RG) * a.ldw);
@@ -448,32 +493,67 @@ __global__ __launch_bounds__(kThreads) void k_sweep(StepArgs<S> a) {
   }
 }
 
-// One pivot step, part 2.  Grid: ceil(ncur / 32) blocks of 32 columns x 8
+// One pivot step, part 2.  Grid: ceil(ncur / kFC) blocks of kFC columns x kFL
 // tile lanes.  Finishes the reflector (dlarfg conventions), forms the new
 // column of F and the new row of R, downdates the column norms (with the
 // cancellation test that ends the panel), and emits pivot partials.
+// Every load that does not depend on another one is issued before the first
+// barrier, so the kernel costs about two memory round trips.
 template <typename S>
 __global__ __launch_bounds__(kThreads) void k_finalize(StepArgs<S> a) {
-  __shared__ double red[8][kFinCols + 1];
+  __shared__ double red[kFL][kFC + 1];
+  __shared__ double ared[8][kNbMax + 1];
+  __shared__ double Fsh[kNbMax][kFC + 1];
   __shared__ double aux[kNbMax];
   __shared__ double vj[kNbMax];
   __shared__ double dscr[4];
   __shared__ AmaxVal ascr[4];
   __shared__ float fscr[4];
   __shared__ int s_go;
+  __shared__ double s_alpha;
   FactorState* st = a.st;
-  const int tid = threadIdx.x, cl = tid % kFinCols, tl = tid / kFinCols;
-  if (tid == 0) s_go = (st->jb == a.jj + 1);
-  __syncthreads();
-  if (!s_go) return;
+  const int tid = threadIdx.x, cl = tid % kFC, tl = tid / kFC;
   const int64_t j = a.j;
   const int jj = a.jj;
   const int64_t tend = a.t0 + a.ntile;
+  const int64_t l = (int64_t)blockIdx.x * kFC + cl;
+  const bool lv = l < a.ncur;
 
-  double s = 0.0;
-  for (int64_t t = a.t0 + tid; t < tend; t += kThreads) s += a.nrm2part[t];
-  const double xnorm2 = block_sum(s, dscr);
-  const double alpha = st->alpha;
+  // independent loads (buffers hold valid if stale data when the step is off)
+  if (tid == 0) {
+    s_go = (st->jb == jj + 1);
+    s_alpha = st->alpha;
+  }
+  double wj = 0.0, nl = 0.0, nlo = 1.0;
+  int pv = 1, id = 0;
+  if (tl == 0 && lv) {
+    wj = (double)a.W[j * a.ldw + l];
+    nl = a.nu[l];
+    nlo = a.nuo[l];
+    pv = a.pvflag[l];
+    id = a.colid[l];
+  }
+#pragma unroll
+  for (int q = 0; q < kNbMax / kFL; ++q) {
+    const int cf = tl + kFL * q;
+    Fsh[cf][cl] = (cf < jj && lv) ? a.F[(int64_t)cf * a.ldf + l] : 0.0;
+  }
+  double vjr = 0.0, vsc = 0.0;
+  if (tid < jj) {
+    vjr = (double)a.V[(int64_t)tid * a.ldv + j];
+    vsc = a.vscale[tid];
+  }
+  const double pn = strided_sum(a.nrm2part, 1, a.t0 + tid, tend, kThreads);
+  {
+    const int c = tid % kNbMax, sl = tid / kNbMax;
+    ared[sl][c] = c < jj ? strided_sum(a.auxpart + c, kNbMax, a.t0 + sl, tend, 8) : 0.0;
+  }
+  red[tl][cl] = lv ? strided_sum(a.zpart + l, a.ldf, a.t0 + tl, tend, kFL) : 0.0;
+  const int key = (tl == 0 && lv) ? a.posof[id] : 0;
+
+  const double xnorm2 = block_sum(pn, dscr);  // also publishes the LDS writes above
+  if (!s_go) return;
+  const double alpha = s_alpha;
   double beta, tau, scale;
   if (xnorm2 == 0.0) {
     beta = alpha;
@@ -485,59 +565,40 @@ __global__ __launch_bounds__(kThreads) void k_finalize(StepArgs<S> a) {
     tau = (beta - alpha) / beta;
     scale = 1.0 / (alpha - beta);
   }
-
-  {
-    const int c = tid % kFinCols, sl = tid / kFinCols;
-    double zs = 0.0;
-    if (c < jj)
-      for (int64_t t = a.t0 + sl; t < tend; t += 8) zs += a.auxpart[t * kNbMax + c];
-    red[sl][c] = zs;
-  }
-  __syncthreads();
   if (tid < jj) {
     double z = 0.0;
 #pragma unroll
-    for (int q = 0; q < 8; ++q) z += red[q][tid];
-    const double vjc = a.vscale[tid] * (double)a.V[(int64_t)tid * a.ldv + j];
+    for (int q = 0; q < 8; ++q) z += ared[q][tid];
+    const double vjc = vsc * vjr;
     vj[tid] = vjc;
-    aux[tid] = vjc + a.vscale[tid] * scale * z;
+    aux[tid] = vjc + vsc * scale * z;
   }
-  __syncthreads();
-
-  const int64_t l = (int64_t)blockIdx.x * kFinCols + cl;
-  double z = 0.0;
-  if (l < a.ncur)
-    for (int64_t t = a.t0 + tl; t < tend; t += 8) z += a.zpart[t * a.ldf + l];
-  red[tl][cl] = z;
   __syncthreads();
 
   AmaxVal cand = amax_none();
   float fabsmax = 0.0f;
   bool flag = false;
-  if (tl == 0 && l < a.ncur) {
+  if (tl == 0 && lv) {
     double zt = 0.0;
 #pragma unroll
-    for (int q = 0; q < 8; ++q) zt += red[q][cl];
-    const double wj = (double)a.W[j * a.ldw + l];
+    for (int q = 0; q < kFL; ++q) zt += red[q][cl];
     const double y = wj + scale * zt;
     double s1 = 0.0, s2 = 0.0;
     for (int c = 0; c < jj; ++c) {
-      const double fc = a.F[(int64_t)c * a.ldf + l];
+      const double fc = Fsh[c][cl];
       s1 += fc * aux[c];
       s2 += vj[c] * fc;
     }
     const double f = tau * (y - s1);
     a.F[(int64_t)jj * a.ldf + l] = f;
-    if (!a.pvflag[l]) {
+    if (!pv) {
       const double r = wj - s2 - f;
-      const int id = a.colid[l];
       a.rorig[(int64_t)id * a.kcap + j] = r;
-      double nl = a.nu[l];
       if (nl != 0.0) {
         double t = fabs(r) / nl;
         t = (1.0 + t) * (1.0 - t);
         if (t < 0.0) t = 0.0;
-        const double ratio = nl / a.nuo[l];
+        const double ratio = nl / nlo;
         if (t * ratio * ratio <= a.tol3z) {
           flag = true;
         } else {
@@ -548,7 +609,7 @@ __global__ __launch_bounds__(kThreads) void k_finalize(StepArgs<S> a) {
       cand.v = nl;
       cand.s2 = nl * nl;
       cand.pos = (int)l;
-      cand.key = a.posof[id];
+      cand.key = key;
       fabsmax = (float)fabs(f);
     }
   }
@@ -676,7 +737,7 @@ __global__ __launch_bounds__(kThreads) void k_panel_gemm(GemmArgs<S> a) {
 
   // A operands (F^T rows = positions), held for the whole block
   f16x8 ah[4];
-  bf16x8 ab[4];
+  bf16x8 ab[4], abl[4];
   double a64[4][8];
 #pragma unroll
   for (int lb = 0; lb < 4; ++lb) {
@@ -694,10 +755,13 @@ __global__ __launch_bounds__(kThreads) void k_panel_gemm(GemmArgs<S> a) {
         const int c = 8 * g + e;
         const float x = (c < jb && pos < a.ncur) ? (float)(a.F[(int64_t)c * a.ldf + pos] * fscl)
                                                  : 0.0f;
-        if (OP == OP_F16)
+        if (OP == OP_F16) {
           ah[lb][e] = (_Float16)x;
-        else
-          ab[lb][e] = (__bf16)x;
+        } else {
+          const __bf16 h = (__bf16)x;
+          ab[lb][e] = h;
+          if (OP == OP_BF16X3) abl[lb][e] = (__bf16)(x - (float)h);
+        }
       }
     }
   }
@@ -733,25 +797,34 @@ __global__ __launch_bounds__(kThreads) void k_panel_gemm(GemmArgs<S> a) {
       }
     } else {
       f16x8 bh;
-      bf16x8 bb;
+      bf16x8 bb, bbl;
 #pragma unroll
       for (int e = 0; e < 8; ++e) {
         const int c = 8 * g + e;
         const float x = (c < jb && rowok)
-                            ? (float)a.V[(int64_t)c * a.ldv + row] * (float)a.vscale[c] * vscl
+                            ? (float)((double)a.V[(int64_t)c * a.ldv + row] * a.vscale[c]) * vscl
                             : 0.0f;
-        if (OP == OP_F16)
+        if (OP == OP_F16) {
           bh[e] = (_Float16)x;
-        else
-          bb[e] = (__bf16)x;
+        } else {
+          const __bf16 h = (__bf16)x;
+          bb[e] = h;
+          if (OP == OP_BF16X3) bbl[e] = (__bf16)(x - (float)h);
+        }
       }
 #pragma unroll
       for (int lb = 0; lb < 4; ++lb) {
         f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
-        if (OP == OP_F16)
+        if (OP == OP_F16) {
           acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah[lb], bh, acc, 0, 0, 0);
-        else
+        } else if (OP == OP_BF16) {
           acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ab[lb], bb, acc, 0, 0, 0);
+        } else {
+          // small terms first, then the leading product
+          acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(abl[lb], bb, acc, 0, 0, 0);
+          acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ab[lb], bbl, acc, 0, 0, 0);
+          acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ab[lb], bb, acc, 0, 0, 0);
+        }
         const int64_t p0 = l0 + 16 * lb + 4 * g;
         if (rowok) {
           const S* src = a.W + row * a.ldw + p0;
@@ -855,6 +928,51 @@ static SweepShape choose_sweep_shape(int64_t rows, int64_t ncur, int wbytes) {
   return sh;
 }
 
+// ---- opt-in per-kernel event timing (ID_FLAG_PROFILE)
+
+static thread_local id_profile g_last_profile;
+
+void last_profile(id_profile* out) { *out = g_last_profile; }
+
+namespace {
+enum { PK_SWEEP = 0, PK_FINALIZE, PK_GEMM, PK_OTHER };
+struct ProfRec {
+  int kind;
+  int64_t j;  // pivot step (sweep/finalize) or panel end row (gemm)
+  size_t e0;  // index of the start event; the end event is e0 + 1
+};
+struct Profiler {
+  bool on = false;
+  std::vector<hipEvent_t>* pool = nullptr;
+  std::vector<ProfRec> recs;
+  size_t used = 0;
+  hipEvent_t ev(size_t i) {
+    while (pool->size() <= i) {
+      hipEvent_t e;
+      if (hipEventCreate(&e) != hipSuccess) return nullptr;
+      pool->push_back(e);
+    }
+    return (*pool)[i];
+  }
+  void begin(int kind, int64_t j, hipStream_t s) {
+    if (!on) return;
+    recs.push_back({kind, j, used});
+    (void)hipEventRecord(ev(used), s);
+    ++used;
+  }
+  void end(hipStream_t s) {
+    if (!on) return;
+    (void)hipEventRecord(ev(used), s);
+    ++used;
+  }
+  float ms(const ProfRec& r) {
+    float t = 0.0f;
+    if (hipEventElapsedTime(&t, (*pool)[r.e0], (*pool)[r.e0 + 1]) != hipSuccess) return 0.0f;
+    return t;
+  }
+};
+}  // namespace
+
 template <typename TA, typename S, int OP>
 static int factor_impl(const TA* A, int64_t lda, const FactorPlan& pl, const id_opts* o,
                        char* wb, int32_t* perm, double* R, int64_t ldr, int64_t* k_out,
@@ -886,6 +1004,21 @@ static int factor_impl(const TA* A, int64_t lda, const FactorPlan& pl, const id_
 
   const int64_t ldw = pl.ldw, ldf = pl.ldf;
   const int64_t ntg = ceil_div(m, kRowTileG);
+  static thread_local std::vector<hipEvent_t> ev_pool;
+  Profiler prof;
+  prof.on = (o->flags & ID_FLAG_PROFILE) != 0;
+  prof.pool = &ev_pool;
+  id_profile acc;
+  std::memset(&acc, 0, sizeof(acc));
+  hipEvent_t ev_t0 = nullptr, ev_t1 = nullptr;
+  if (prof.on) {
+    ev_t0 = prof.ev(0);
+    ev_t1 = prof.ev(1);
+    prof.used = 2;
+    MPID_HIP(hipEventRecord(ev_t0, s));
+  }
+  const double sbytes = (double)pl.wbytes;
+  prof.begin(PK_OTHER, 0, s);
   k_init<<<dim3((unsigned)ceil_div(ldf > n ? ldf : n, kThreads)), kThreads, 0, s>>>(
       st, colid[0], pvflag, permw, posof, n, ldf);
   MPID_LAUNCH_CHECK();
@@ -896,6 +1029,7 @@ static int factor_impl(const TA* A, int64_t lda, const FactorPlan& pl, const id_
   k_colreduce<<<dim3((unsigned)namax), kThreads, 0, s>>>(colpart, ldf, 0, ntg, n, 0, nu, nuo,
                                                           amax, colid[0], posof, pvflag, st);
   MPID_LAUNCH_CHECK();
+  prof.end(s);
 
   StepArgs<S> a;
   std::memset(&a, 0, sizeof(a));
@@ -948,11 +1082,15 @@ static int factor_impl(const TA* A, int64_t lda, const FactorPlan& pl, const id_
       a.nchunk = (int)ceil_div(ncur, sh.CW);
       a.namax = namax;
       const int64_t total = (int64_t)a.ntile * a.nchunk;
+      prof.begin(PK_SWEEP, j, s);
       k_sweep<S><<<dim3((unsigned)round_up(total, 8)), kThreads, 0, s>>>(a);
       MPID_LAUNCH_CHECK();
-      namax = (int)ceil_div(ncur, kFinCols);
+      prof.end(s);
+      namax = (int)ceil_div(ncur, kFC);
+      prof.begin(PK_FINALIZE, j, s);
       k_finalize<S><<<dim3((unsigned)namax), kThreads, 0, s>>>(a);
       MPID_LAUNCH_CHECK();
+      prof.end(s);
     }
     GemmArgs<S> g;
     g.W = W[cur];
@@ -972,18 +1110,52 @@ static int factor_impl(const TA* A, int64_t lda, const FactorPlan& pl, const id_
     g.colpart = colpart;
     g.off = off;
     g.tg0 = off / kRowTileG;
+    prof.begin(PK_GEMM, off, s);
     k_panel_gemm<S, OP><<<dim3((unsigned)ceil_div(ncur, 64), (unsigned)(ntg - g.tg0)), kThreads,
                           0, s>>>(g);
     MPID_LAUNCH_CHECK();
+    prof.end(s);
     namax = (int)ceil_div(ncur, kFinCols);
+    prof.begin(PK_OTHER, 0, s);
     k_colreduce<<<dim3((unsigned)namax), kThreads, 0, s>>>(colpart, ldf, g.tg0, ntg, ncur, 1,
                                                             nu, nuo, amax, colid[cur ^ 1], posof,
                                                             pvflag, st);
     MPID_LAUNCH_CHECK();
     k_advance<<<1, 64, 0, s>>>(st);
     MPID_LAUNCH_CHECK();
+    prof.end(s);
     MPID_HIP(hipMemcpyAsync(hst, st, sizeof(FactorState), hipMemcpyDeviceToHost, s));
     MPID_HIP(hipStreamSynchronize(s));
+    if (prof.on) {
+      // count only the launches that did work in this panel
+      const int64_t live_end = hst->done ? hst->k : off + hst->last_jb;
+      for (const ProfRec& r : prof.recs) {
+        const double t = prof.ms(r);
+        if (r.kind == PK_SWEEP) {
+          if (r.j < live_end) {
+            acc.sweep_launches += 1;
+            acc.sweep_ms += t;
+            acc.sweep_bytes += (double)(m - r.j) * (double)(n - r.j - 1) * sbytes;
+          }
+        } else if (r.kind == PK_FINALIZE) {
+          if (r.j < live_end) {
+            acc.finalize_launches += 1;
+            acc.finalize_ms += t;
+          }
+        } else if (r.kind == PK_GEMM) {
+          if (!hst->done) {
+            const int64_t je = off + hst->last_jb;
+            acc.gemm_launches += 1;
+            acc.gemm_ms += t;
+            acc.gemm_bytes += 2.0 * (double)(m - je) * (double)(n - je) * sbytes;
+          }
+        } else {
+          acc.other_ms += t;
+        }
+      }
+      prof.recs.clear();
+      prof.used = 2;
+    }
     if (hst->done) break;
     const int jb = hst->last_jb;
     if (jb <= 0) return ID_ERR_HIP;  // cannot happen: a live panel makes progress
@@ -997,6 +1169,14 @@ static int factor_impl(const TA* A, int64_t lda, const FactorPlan& pl, const id_
   k_finish<<<dim3((unsigned)n, (unsigned)(k > 0 ? ceil_div(k, kThreads) : 1)), kThreads, 0, s>>>(
       permw, perm, rorig, kcap, n, k, R, ldr);
   MPID_LAUNCH_CHECK();
+  if (prof.on) {
+    MPID_HIP(hipEventRecord(ev_t1, s));
+    MPID_HIP(hipEventSynchronize(ev_t1));
+    float t = 0.0f;
+    MPID_HIP(hipEventElapsedTime(&t, ev_t0, ev_t1));
+    acc.total_ms = t;
+    g_last_profile = acc;
+  }
   return ID_OK;
 }
 
@@ -1034,6 +1214,13 @@ int factor_run(const void* A, int32_t dtype, int64_t m, int64_t n, int64_t lda,
                                                 k_out, info, s);
     return factor_impl<float, float, OP_F16>((const float*)A, lda, pl, o, wb, perm, R, ldr, k_out,
                                              info, s);
+  }
+  if (pl.prec == ID_PREC_MIXED_BF16X3) {
+    if (dtype == ID_F64)
+      return factor_impl<double, float, OP_BF16X3>((const double*)A, lda, pl, o, wb, perm, R, ldr,
+                                                   k_out, info, s);
+    return factor_impl<float, float, OP_BF16X3>((const float*)A, lda, pl, o, wb, perm, R, ldr,
+                                                k_out, info, s);
   }
   if (dtype == ID_F64)
     return factor_impl<double, float, OP_BF16>((const double*)A, lda, pl, o, wb, perm, R, ldr,

@@ -16,7 +16,9 @@ constexpr int kRtMax = 2048;    // largest row tile of the reflector sweep
 constexpr int kRtMin = 64;      // smallest row tile of the reflector sweep
 constexpr int kRowTileG = 256;  // row tile of the ingest / blocked-update kernels
 constexpr int kColTileG = 64;   // column tile of the blocked update
-constexpr int kFinCols = 32;    // columns per block of the reduction kernels
+constexpr int kFinCols = 32;    // columns per block of the norm reduction
+constexpr int kFC = 16;         // columns per block of the step finalization
+constexpr int kFL = kThreads / kFC;  // its tile lanes
 
 // Device-resident control block of one factorization.  Every field is written
 // by exactly one kind of kernel and read only by later kernels on the stream.
@@ -59,6 +61,8 @@ bool make_factor_plan(int64_t m, int64_t n, int32_t dtype, const id_opts* o, Fac
 int factor_run(const void* A, int32_t dtype, int64_t m, int64_t n, int64_t lda,
                const id_opts* o, void* work, size_t work_bytes, int32_t* perm, double* R,
                int64_t ldr, int64_t* k_out, int32_t* info, hipStream_t s);
+
+void last_profile(id_profile* out);
 
 int solve_T_run(const double* R, int64_t ldr, int64_t k, int64_t n, double* T, int64_t ldt,
                 int32_t* info, hipStream_t s);
