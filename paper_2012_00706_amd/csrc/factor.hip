@@ -26,6 +26,7 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <type_traits>
 #include <vector>
 
 #include "device_util.h"
@@ -669,24 +670,31 @@ struct GemmArgs {
 // i >= off + jb, on the matrix cores (FP64 MFMA, or FP16/BF16 MFMA with FP32
 // accumulation), skipping the pivoted positions (compaction), and the FP64
 // sums of squares of every refreshed column per row tile.
-// Block: 64 positions x kRowTileG rows; wave w computes 16 rows x 64 positions
-// per 64-row slice as four 16x16 MFMA blocks with the positions along the MFMA
-// rows, so each lane holds 4 consecutive positions of one row of W.
+// Block: 64 positions x kRowTileG rows, processed in 64-row slices.  Per
+// slice each thread first issues its 16 loads of the W tile (coalesced rows),
+// the waves form the 64 x 64 product as 16x16 MFMA blocks (positions along
+// the MFMA rows) and park it in LDS, then each thread writes its column of the
+// refreshed tile to the compacted position.
 template <typename S, int OP>
 __global__ __launch_bounds__(kThreads) void k_panel_gemm(GemmArgs<S> a) {
+  typedef typename std::conditional<OP == OP_F64, double, float>::type AccT;
   __shared__ int spiv[kNbMax];
   __shared__ int cidx[64];
-  __shared__ int inv[64];
-  __shared__ int s_count, s_base;
-  __shared__ S tileo[64][64 + (sizeof(S) == 4 ? 1 : 1)];
+  __shared__ AccT accs[64][64 + 1];
   __shared__ double ssq[4][64];
-  __shared__ int s_go;
+  __shared__ int s_go, s_jb;
+  __shared__ uint32_t s_fmax;
   FactorState* st = a.st;
   const int tid = threadIdx.x;
-  if (tid == 0) s_go = (st->done == 0);
+  if (tid == 0) {
+    s_go = (st->done == 0);
+    s_jb = st->jb;
+    s_fmax = st->fmax_bits;
+  }
+  if (tid < kNbMax) spiv[tid] = a.pivpos[tid];
   __syncthreads();
   if (!s_go) return;
-  const int jb = st->jb;
+  const int jb = s_jb;
   const int64_t jend = a.off + jb;
   const int64_t l0 = (int64_t)blockIdx.x * 64;
   const int64_t tg = a.tg0 + blockIdx.y;
@@ -694,8 +702,6 @@ __global__ __launch_bounds__(kThreads) void k_panel_gemm(GemmArgs<S> a) {
   const int64_t rbeg = rbase > jend ? rbase : jend;
   const int64_t rend = rbase + kRowTileG < a.m ? rbase + kRowTileG : a.m;
 
-  if (tid < jb) spiv[tid] = a.pivpos[tid];
-  __syncthreads();
   if (tid < 64) {
     const int64_t l = l0 + tid;
     int before = 0;
@@ -707,25 +713,13 @@ __global__ __launch_bounds__(kThreads) void k_panel_gemm(GemmArgs<S> a) {
     cidx[tid] = (l < a.ncur && !pv) ? (int)(l - before) : -1;
   }
   __syncthreads();
-  if (tid == 0) {
-    int cnt = 0, base = -1;
-    for (int t = 0; t < 64; ++t)
-      if (cidx[t] >= 0) {
-        if (base < 0) base = cidx[t];
-        inv[cnt++] = t;
-      }
-    s_count = cnt;
-    s_base = base;
-  }
-  __syncthreads();
-  const int count = s_count;
-  const int npbase = s_base;
-  if (count == 0) return;
 
   const int lane = tid & 63, wv = tid >> 6, g = lane >> 4, li = lane & 15;
+  const int cc = tid % 64, rq = tid / 64;  // write-out mapping: column cc, rows rq + 4q
+  const int myout = cidx[cc];
   int sF = 0, sV = 0;
   if (OP == OP_F16) {
-    const float fmax = __uint_as_float(st->fmax_bits);
+    const float fmax = __uint_as_float(s_fmax);
     int e = 0;
     if (fmax > 0.0f) frexpf(fmax, &e);
     sF = 15 - e;
@@ -770,6 +764,14 @@ __global__ __launch_bounds__(kThreads) void k_panel_gemm(GemmArgs<S> a) {
   for (int sb = 0; sb < kRowTileG / 64; ++sb) {
     const int64_t rs = rbase + 64 * sb;
     if (rs + 64 <= rbeg || rs >= rend) continue;  // uniform across the block
+    // 1. this thread's 16 elements of the stale W tile, loads issued first
+    S wtile[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int64_t r = rs + rq + 4 * q;
+      wtile[q] = (myout >= 0 && r >= rbeg && r < rend) ? a.W[r * a.ldw + l0 + cc] : (S)0;
+    }
+    // 2. the product tile on the matrix cores, parked in LDS
     const int64_t row = rs + 16 * wv + li;
     const bool rowok = row >= rbeg && row < rend;
     if (OP == OP_F64) {
@@ -785,15 +787,8 @@ __global__ __launch_bounds__(kThreads) void k_panel_gemm(GemmArgs<S> a) {
 #pragma unroll
         for (int s = 0; s < 8; ++s)
           acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a64[lb][s], b64[s], acc, 0, 0, 0);
-        const int64_t p0 = l0 + 16 * lb + 4 * g;
-        if (rowok) {
-          const S* src = a.W + row * a.ldw + p0;
 #pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            const int ci = cidx[16 * lb + 4 * g + r];
-            if (ci >= 0) tileo[16 * wv + li][ci - npbase] = (S)((double)src[r] - acc[r]);
-          }
-        }
+        for (int r = 0; r < 4; ++r) accs[16 * wv + li][16 * lb + 4 * g + r] = (AccT)acc[r];
       }
     } else {
       f16x8 bh;
@@ -825,40 +820,31 @@ __global__ __launch_bounds__(kThreads) void k_panel_gemm(GemmArgs<S> a) {
           acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ab[lb], bbl, acc, 0, 0, 0);
           acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ab[lb], bb, acc, 0, 0, 0);
         }
-        const int64_t p0 = l0 + 16 * lb + 4 * g;
-        if (rowok) {
-          const S* src = a.W + row * a.ldw + p0;
 #pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            const int ci = cidx[16 * lb + 4 * g + r];
-            if (ci >= 0)
-              tileo[16 * wv + li][ci - npbase] = (S)((double)src[r] - (double)acc[r] * descale);
-          }
-        }
+        for (int r = 0; r < 4; ++r) accs[16 * wv + li][16 * lb + 4 * g + r] = (AccT)acc[r];
       }
     }
     __syncthreads();
-    {
-      const int cc = tid % 64;
-#pragma unroll 4
+    // 3. refreshed column cc of the tile, written to its compacted position
+    if (myout >= 0) {
+#pragma unroll
       for (int q = 0; q < 16; ++q) {
-        const int rr = tid / 64 + 4 * q;
+        const int rr = rq + 4 * q;
         const int64_t r = rs + rr;
-        if (cc < count && r >= rbeg && r < rend) {
-          const S v = tileo[rr][cc];
-          a.Wn[r * a.ldw + npbase + cc] = v;
+        if (r >= rbeg && r < rend) {
+          const S v = (S)((double)wtile[q] - (double)accs[rr][cc] * descale);
+          a.Wn[r * a.ldw + myout] = v;
           ss += (double)v * (double)v;
         }
       }
     }
     __syncthreads();
   }
-  ssq[tid / 64][tid % 64] = ss;
+  ssq[rq][cc] = ss;
   __syncthreads();
-  if (tid < count) {
-    a.colpart[tg * a.ldf + npbase + tid] =
-        ssq[0][tid] + ssq[1][tid] + ssq[2][tid] + ssq[3][tid];
-    if (blockIdx.y == 0) a.colid_n[npbase + tid] = a.colid[l0 + inv[tid]];
+  if (tid < 64 && cidx[tid] >= 0) {
+    a.colpart[tg * a.ldf + cidx[tid]] = ssq[0][tid] + ssq[1][tid] + ssq[2][tid] + ssq[3][tid];
+    if (blockIdx.y == 0) a.colid_n[cidx[tid]] = a.colid[l0 + tid];
   }
 }
 

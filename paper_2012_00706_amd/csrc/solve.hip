@@ -1,11 +1,11 @@
 // Triangular solves in FP64: T = R11^{-1} R12 (eq. (8); the coefficient step of
 // Algorithms 1 and 2) and the general X = op(R)^{-1} B used by the adjoint.
 //
-// Each block owns 64 right-hand-side columns and walks the 64-row blocks of R
+// Each block owns 16 right-hand-side columns and walks the 64-row blocks of R
 // in dependency order: the contribution of the already-solved row blocks is
-// accumulated tile by tile through LDS (256 threads x 16 accumulators), then
-// the 64 x 64 diagonal block is solved in LDS.  Columns are independent, so
-// blocks never synchronize with each other.
+// accumulated tile by tile on the FP64 matrix cores, then the 64 x 64 diagonal
+// block is solved in LDS.  Columns are independent, so blocks never
+// synchronize with each other.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -17,115 +17,107 @@ namespace mpid {
 
 constexpr int kTB = 64;
 
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+constexpr int kTC = 16;  // right-hand-side columns per block
+
 // trans = 0: R X = B (back substitution over row blocks, last first).
 // trans = 1: R^T X = B (forward substitution, first row block first).
-// Global traffic goes through LDS with the row index fastest (coalesced in the
-// column-major operands); the arithmetic uses thread = (column cc, row phase rq).
+// Per row block I: As = B(I, cols) - sum_L op(R)(I, L) X(L, cols) on the FP64
+// matrix cores (wave w owns rows 16w..16w+15), then op(R)(I, I) As = rhs is
+// solved with each wave owning four columns -- the 64 dependent steps run
+// inside one wavefront, without block barriers.
 __global__ __launch_bounds__(kThreads) void k_trsm_upper(const double* __restrict__ R, int64_t ldr,
                                                         int64_t k, const double* B, int64_t ldb,
                                                         int64_t ncols, double* X, int64_t ldx,
                                                         int trans, const int32_t* info) {
   __shared__ double Rs[kTB][kTB + 1];
-  __shared__ double Xs[kTB][kTB + 1];
+  __shared__ double Xs[kTB][kTC + 1];
+  __shared__ double As[kTB][kTC + 1];
+  __shared__ double rinv[kTB];
   __shared__ int s_go;
   const int tid = threadIdx.x;
   if (tid == 0) s_go = !(info && *info == ID_INFO_SINGULAR);
   __syncthreads();
   if (!s_go) return;
-  const int cc = tid % kTB, rq = tid / kTB;  // compute mapping
-  const int la = tid % kTB, lb = tid / kTB;  // load mapping: la fastest (rows)
-  const int64_t c0 = (int64_t)blockIdx.x * kTB;
+  const int lane = tid & 63, wv = tid >> 6, g = lane >> 4, li = lane & 15;
+  const int la = tid % kTB, lb = tid / kTB;  // load mapping, rows fastest
+  const int64_t c0 = (int64_t)blockIdx.x * kTC;
   const int64_t nblk = ceil_div(k, kTB);
-  for (int64_t bi = 0; bi < nblk; ++bi) {
-    const int64_t I = trans ? bi : nblk - 1 - bi;
-    const int64_t i0 = I * kTB;
-    const int ib = (int)((k - i0) < kTB ? (k - i0) : kTB);
-    // right-hand side block B(I, cols)
-#pragma unroll 4
-    for (int q = 0; q < 16; ++q) {
-      const int b = lb + 4 * q;
-      const int64_t i = i0 + la, c = c0 + b;
-      Xs[la][b] = (la < ib && c < ncols) ? B[c * ldb + i] : 0.0;
-    }
-    __syncthreads();
-    double acc[16];
-#pragma unroll
-    for (int q = 0; q < 16; ++q) acc[q] = Xs[rq + 4 * q][cc];
-    // subtract the solved row blocks: acc(i) -= sum_l op(R)(i, l) X(l)
-    for (int64_t bl = 0; bl < bi; ++bl) {
-      const int64_t L = trans ? bl : nblk - 1 - bl;
-      const int64_t l0 = L * kTB;
-      __syncthreads();
-#pragma unroll 4
-      for (int q = 0; q < 16; ++q) {
-        const int b = lb + 4 * q;
-        double v = 0.0;
-        if (!trans) {
-          // Rs[ii][ll] = R(i0 + ii, l0 + ll): load row la, column b
-          const int64_t i = i0 + la, l = l0 + b;
-          if (i < k && l < k) v = R[l * ldr + i];
-          Rs[la][b] = v;
-        } else {
-          // Rs[ii][ll] = R(l0 + ll, i0 + ii): load row l0 + la of column i0 + b
-          const int64_t l = l0 + la, i = i0 + b;
-          if (i < k && l < k) v = R[i * ldr + l];
-          Rs[b][la] = v;
-        }
-        const int64_t xr = l0 + la, c = c0 + b;
-        Xs[la][b] = (xr < k && c < ncols) ? X[c * ldx + xr] : 0.0;
-      }
-      __syncthreads();
-#pragma unroll 4
-      for (int ll = 0; ll < kTB; ++ll) {
-        const double x = Xs[ll][cc];
-#pragma unroll
-        for (int q = 0; q < 16; ++q) acc[q] -= Rs[rq + 4 * q][ll] * x;
-      }
-    }
-    __syncthreads();
-    // diagonal block
+  auto load_R_tile = [&](int64_t i0, int64_t l0) {
+    // Rs[ii][ll] = op(R)(i0 + ii, l0 + ll)
 #pragma unroll 4
     for (int q = 0; q < 16; ++q) {
       const int b = lb + 4 * q;
       double v = 0.0;
       if (!trans) {
-        const int64_t i = i0 + la, l = i0 + b;
+        const int64_t i = i0 + la, l = l0 + b;
         if (i < k && l < k) v = R[l * ldr + i];
         Rs[la][b] = v;
       } else {
-        const int64_t l = i0 + la, i = i0 + b;
+        const int64_t l = l0 + la, i = i0 + b;
         if (i < k && l < k) v = R[i * ldr + l];
         Rs[b][la] = v;
       }
     }
+  };
+  for (int64_t bi = 0; bi < nblk; ++bi) {
+    const int64_t I = trans ? bi : nblk - 1 - bi;
+    const int64_t i0 = I * kTB;
+    const int ib = (int)((k - i0) < kTB ? (k - i0) : kTB);
 #pragma unroll
-    for (int q = 0; q < 16; ++q) Xs[rq + 4 * q][cc] = acc[q];
-    __syncthreads();
-    if (!trans) {
-      for (int ii = ib - 1; ii >= 0; --ii) {
-        const double xi = Xs[ii][cc] / Rs[ii][ii];
-        __syncthreads();
-        if (rq == 0) Xs[ii][cc] = xi;
-        for (int r = rq; r < ii; r += 4) Xs[r][cc] -= Rs[r][ii] * xi;
-        __syncthreads();
-      }
-    } else {
-      for (int ii = 0; ii < ib; ++ii) {
-        const double xi = Xs[ii][cc] / Rs[ii][ii];
-        __syncthreads();
-        if (rq == 0) Xs[ii][cc] = xi;
-        for (int r = rq; r < ib; r += 4)
-          if (r > ii) Xs[r][cc] -= Rs[r][ii] * xi;
-        __syncthreads();
-      }
-    }
-#pragma unroll 4
-    for (int q = 0; q < 16; ++q) {
+    for (int q = 0; q < kTC / 4; ++q) {
       const int b = lb + 4 * q;
       const int64_t c = c0 + b;
-      if (la < ib && c < ncols) X[c * ldx + i0 + la] = Xs[la][b];
+      As[la][b] = (la < ib && c < ncols) ? B[c * ldb + i0 + la] : 0.0;
+    }
+    if (tid < kTB) rinv[tid] = tid < ib ? 1.0 / R[(i0 + tid) * ldr + i0 + tid] : 0.0;
+    f64x4 acc = {0.0, 0.0, 0.0, 0.0};
+    for (int64_t bl = 0; bl < bi; ++bl) {
+      const int64_t L = trans ? bl : nblk - 1 - bl;
+      const int64_t l0 = L * kTB;
+      __syncthreads();
+      load_R_tile(i0, l0);
+#pragma unroll
+      for (int q = 0; q < kTC / 4; ++q) {
+        const int b = lb + 4 * q;
+        const int64_t c = c0 + b, xr = l0 + la;
+        Xs[la][b] = (xr < k && c < ncols) ? X[c * ldx + xr] : 0.0;
+      }
+      __syncthreads();
+#pragma unroll
+      for (int ks = 0; ks < kTB / 4; ++ks)
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(Rs[16 * wv + li][4 * ks + g], Xs[4 * ks + g][li],
+                                                   acc, 0, 0, 0);
     }
     __syncthreads();
+#pragma unroll
+    for (int r = 0; r < 4; ++r) As[16 * wv + g + 4 * r][li] -= acc[r];
+    load_R_tile(i0, i0);
+    __syncthreads();
+    {
+      const int col = 4 * wv + (lane & 3), rg = lane >> 2;  // 4 columns x 16 row groups
+      if (!trans) {
+        for (int ii = ib - 1; ii >= 0; --ii) {
+          const double xi = As[ii][col] * rinv[ii];
+          for (int r = rg; r < ii; r += 16) As[r][col] -= Rs[r][ii] * xi;
+          if (rg == (ii & 15)) As[ii][col] = xi;
+        }
+      } else {
+        for (int ii = 0; ii < ib; ++ii) {
+          const double xi = As[ii][col] * rinv[ii];
+          for (int r = rg; r < ib; r += 16)
+            if (r > ii) As[r][col] -= Rs[r][ii] * xi;
+          if (rg == (ii & 15)) As[ii][col] = xi;
+        }
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < kTC / 4; ++q) {
+      const int b = lb + 4 * q;
+      const int64_t c = c0 + b;
+      if (la < ib && c < ncols) X[c * ldx + i0 + la] = As[la][b];
+    }
   }
 }
 
@@ -152,7 +144,7 @@ __global__ __launch_bounds__(kThreads) void k_check_diag(const double* __restric
 int trsm_upper_run(const double* R, int64_t ldr, int64_t k, const double* B, int64_t ldb,
                    int64_t ncols, double* X, int64_t ldx, int trans, hipStream_t s) {
   if (k <= 0 || ncols <= 0) return ID_OK;
-  k_trsm_upper<<<dim3((unsigned)ceil_div(ncols, kTB)), kThreads, 0, s>>>(R, ldr, k, B, ldb, ncols,
+  k_trsm_upper<<<dim3((unsigned)ceil_div(ncols, kTC)), kThreads, 0, s>>>(R, ldr, k, B, ldb, ncols,
                                                                          X, ldx, trans, nullptr);
   MPID_LAUNCH_CHECK();
   return ID_OK;
@@ -166,7 +158,7 @@ int solve_T_run(const double* R, int64_t ldr, int64_t k, int64_t n, double* T, i
   k_check_diag<<<1, kThreads, 0, s>>>(R, ldr, k, n, info);
   MPID_LAUNCH_CHECK();
   if (k == 0 || n == k) return ID_OK;
-  k_trsm_upper<<<dim3((unsigned)ceil_div(n - k, kTB)), kThreads, 0, s>>>(
+  k_trsm_upper<<<dim3((unsigned)ceil_div(n - k, kTC)), kThreads, 0, s>>>(
       R, ldr, k, R + k * ldr, ldr, n - k, T, ldt, 0, info);
   MPID_LAUNCH_CHECK();
   return ID_OK;
