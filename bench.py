@@ -135,6 +135,89 @@ def cpu_baseline(A_np, steps: int, k_full: int):
     }
 
 
+COPY_BYTES = 256 << 20
+TRAFFIC_JSON = os.path.join(ROOT, "profiles", "sweep_traffic.json")
+SWEEP_SOURCES = [os.path.join(ROOT, "paper_2012_00706_amd", "csrc", f)
+                 for f in ("factor.hip", "device_util.h", "mpid_internal.h")]
+
+
+def sweep_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in SWEEP_SOURCES:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def copy_calibration():
+    """One plain device-to-device copy of COPY_BYTES (known traffic: that many
+    bytes read and written), for scaling the HBM byte counters."""
+    import torch
+    src = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+
+
+def _read_counter_csv(path):
+    """{(dispatch_id, kernel_name): value} for the single counter in the file."""
+    import csv
+    out = {}
+    with open(path) as fh:
+        for row in csv.DictReader(fh):
+            name = row.get("Kernel_Name") or row.get("Kernel-Name") or ""
+            did = row.get("Dispatch_Id") or row.get("Dispatch-Id")
+            val = float(row.get("Counter_Value") or row.get("Counter-Value") or 0.0)
+            out[(int(did), name)] = out.get((int(did), name), 0.0) + val
+    return out
+
+
+def summarize_pmc(fetch_csv, write_csv):
+    """Average HBM fetch/write per live k_sweep dispatch (KiB counters x 1024),
+    scaled by the same counters' reading on the calibration copy; written to
+    profiles/sweep_traffic.json with the hash of the sweep's sources."""
+    fetch = _read_counter_csv(fetch_csv)
+    write = _read_counter_csv(write_csv)
+
+    def sweep_live(d):
+        vals = [v for (did, name), v in d.items() if "k_sweep" in name]
+        big = max(vals) if vals else 0.0
+        return [v for v in vals if v > 0.05 * big]  # launches that did work
+
+    def copy_kib(d):
+        vals = [v for (did, name), v in d.items()
+                if "k_" not in name and ("copy" in name.lower() or "elementwise" in name)]
+        return max(vals) if vals else 0.0
+
+    f_scale = COPY_BYTES / (copy_kib(fetch) * 1024.0) if copy_kib(fetch) > 0 else 1.0
+    w_scale = COPY_BYTES / (copy_kib(write) * 1024.0) if copy_kib(write) > 0 else 1.0
+    sf, sw = sweep_live(fetch), sweep_live(write)
+    fetch_b = sum(sf) / len(sf) * 1024.0 * f_scale if sf else 0.0
+    write_b = sum(sw) / len(sw) * 1024.0 * w_scale if sw else 0.0
+    res = {"kernel": "k_sweep", "launches": len(sf), "fetch_bytes_per_launch": fetch_b,
+           "write_bytes_per_launch": write_b, "traffic_bytes_per_launch": fetch_b + write_b,
+           "copy_fetch_scale": f_scale, "copy_write_scale": w_scale,
+           "copy_bytes": COPY_BYTES, "source_hash": sweep_source_hash()}
+    os.makedirs(os.path.dirname(TRAFFIC_JSON), exist_ok=True)
+    with open(TRAFFIC_JSON, "w") as fh:
+        json.dump(res, fh, indent=1)
+    print(json.dumps(res))
+
+
+def measured_traffic():
+    """Per-launch HBM bytes of the sweep from the committed counter summary,
+    or None when it is missing or was taken on different kernel sources."""
+    try:
+        with open(TRAFFIC_JSON) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if t.get("source_hash") != sweep_source_hash():
+        return None
+    return t.get("traffic_bytes_per_launch")
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawTextHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -149,8 +232,19 @@ def main():
     ap.add_argument("--n", type=int, default=2000)
     ap.add_argument("--cpu-steps", type=int, default=30)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--profile-reps", type=int, default=3)
+    ap.add_argument("--profile-reps", type=int, default=3,
+                    help="instrumented runs per precision (>= 1)")
+    ap.add_argument("--headline-only", action="store_true",
+                    help="time only the headline precision (no FP64 comparison, no errors)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run one plain 256 MiB device copy (HBM counter calibration)")
+    ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="turn two rocprofv3 --pmc counter files into the sweep traffic summary")
     args = ap.parse_args()
+    if args.summarize_pmc:
+        summarize_pmc(*args.summarize_pmc)
+        return
+    args.profile_reps = max(args.profile_reps, 1)
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build measures one GPU only (the column ID runs on a single "
@@ -173,8 +267,15 @@ def main():
     A = torch.from_numpy(np.ascontiguousarray(A_np.T)).cuda().t()
     torch.cuda.synchronize()
 
+    if args.copy_calibration:
+        copy_calibration()
     res = {}
     extra = [p for p in args.compare.split(",") if p and p not in (args.prec, "f64")]
+    if args.headline_only:
+        pt = PathTimer(A, args.prec, tol=tol)
+        ms, wall, fr, T = pt.timed(args.steps, args.warmup)
+        print(json.dumps({"headline_only": True, "prec": args.prec, "k": fr.k, "ms_per_id": ms}))
+        return
     for prec in [args.prec, "f64"] + extra:
         pt = PathTimer(A, prec, tol=tol)
         ms, wall, fr, T = pt.timed(args.steps, args.warmup)
@@ -246,7 +347,7 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": sweep_gbs / HBM_PEAK_GBS,
-            "traffic": None,
+            "traffic": measured_traffic(),
             "bytes_per_launch": per_launch_bytes,
             "us_per_launch": per_launch_us,
             "launches_per_id": prof["sweep_launches"] / args.profile_reps,

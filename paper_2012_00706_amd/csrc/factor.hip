@@ -21,6 +21,7 @@
 // (V(:,c) = Vraw(:,c) * vscale[c]) column-major; F is column-major over the
 // positions of the current layout.  R is accumulated by ORIGINAL column id and
 // gathered into pivot order at the end.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -139,10 +140,13 @@ __global__ __launch_bounds__(kThreads) void k_init(FactorState* st, int* colid0,
     st->last_jb = 0;
     st->info = 0;
     st->fmax_bits = 0u;
+    st->vmax_bits = 0u;
     st->k = 0;
     st->r00 = 0.0;
     st->alpha = 0.0;
     st->fro2 = 0.0;
+    st->off = 0;
+    st->ncur = n;
   }
 }
 
@@ -213,7 +217,7 @@ __global__ __launch_bounds__(kThreads) void k_colreduce(
   if (tid == 0) s_go = (st->done == 0);
   __syncthreads();
   if (!s_go) return;
-  const int64_t ncols = ncols_base - (subtract_jb ? st->jb : 0);
+  const int64_t ncols = subtract_jb ? st->ncur - st->jb : ncols_base;
   const int64_t l = (int64_t)blockIdx.x * kFinCols + cl;
   red[tl][cl] = l < ncols ? strided_sum(colpart + l, ldf, tg0 + tl, tg1, 8) : 0.0;
   __syncthreads();
@@ -239,6 +243,8 @@ __global__ __launch_bounds__(kThreads) void k_colreduce(
     o.pos = cand.pos;
     o.key = cand.key;
     amax[blockIdx.x] = o;
+    // the host's view of how close the rank rule is (norms are >= 0)
+    if (cand.v > 0.0) atomicMax(&st->vmax_bits, __float_as_uint((float)cand.v));
   }
 }
 
@@ -270,32 +276,40 @@ struct StepArgs {
   int64_t kcap, k_fixed;
   double rel_tol, tol3z;
   int rule, nopivot, nb;
-  // per step
+  // per step; j and ncur above are the host's bounds (j <= the step's row,
+  // ncur >= the live column count), the exact values live in the state
   int64_t j;
   int jj;
   int64_t t0;
   int ntile, nchunk, Rt, CW;
 };
 
-// One pivot step, part 1.  Grid: (row tiles of Rt rows) x (column chunks of
-// CW positions), padded to a multiple of 8 and remapped so that the chunks of
-// one row tile run on the same XCD (they share the pivot column and the
-// reflector rows through that XCD's L2).
+// One pivot step, part 1.  Grid: (row tiles of Rt <= 256 rows) x (column
+// chunks of CW positions), padded to a multiple of 8 and remapped so that the
+// chunks of one row tile run on the same XCD (they share the pivot column and
+// the reflector rows through that XCD's L2).  G = 256 / Rt threads share a row.
 //  - reduces the pivot partials, applies the rank rule, records the pivot;
 //  - w = W(i,p) - sum_c V(i,c) F(p,c) for the tile's rows i >= j;
 //  - z(l) = sum_{i>j} W(i,l) w(i) for the chunk's columns (the sweep);
-//  - chunk 0 also stores w, its squared norm and sum_{i>j} V(i,c) w(i).
-template <typename S>
+//  - partial sums over the tile of V(i,c) w(i) (c split across the chunks)
+//    and, in chunk 0, of w(i)^2; chunk 0 also stores w as reflector jj.
+// Everything that does not depend on the pivot -- flags, pivot partials, the
+// reflector entries of the tile and the first rows of the sweep -- is loaded
+// in one round trip before the pivot is known.
+template <typename S, int G>
 __global__ __launch_bounds__(kThreads) void k_sweep(StepArgs<S> a) {
   typedef typename Vec16<S>::type VT;
   constexpr int VEC = Vec16<S>::n;
-  __shared__ double wsh[kRtMax];
+  constexpr int SLOTS = kNbMax / G;
+  __shared__ double wsh[kThreads];
   __shared__ double gsh[kNbMax];
   __shared__ double red[kThreads * VEC];
-  __shared__ double zred[8][kNbMax + 1];
+  __shared__ double zred[4][kNbMax];
   __shared__ AmaxVal ascr[4];
   __shared__ double dscr[4];
-  __shared__ int s_go;
+  __shared__ int s_go, s_info;
+  __shared__ double s_r00, s_fro2;
+  __shared__ int64_t s_off, s_ncur;
   FactorState* st = a.st;
   const int tid = threadIdx.x;
   const int total = a.ntile * a.nchunk;
@@ -304,31 +318,44 @@ __global__ __launch_bounds__(kThreads) void k_sweep(StepArgs<S> a) {
   if (v >= total) return;
   const int64_t tile = a.t0 + v / a.nchunk;
   const int chunk = v % a.nchunk;
-  const int64_t j = a.j;
   const int jj = a.jj;
+  const int64_t jlb = a.j;  // lower bound of this step's row
   const int64_t r0 = tile * a.Rt;
   const int64_t r1 = r0 + a.Rt < a.m ? r0 + a.Rt : a.m;
-  // sweep geometry; the block's first rows are loaded now, before the pivot
-  // search, since they do not depend on it
+
+  // ---- round trip 1: nothing here depends on the pivot (or on the exact
+  // panel offset: the rows loaded from the bound jlb on are a superset)
+  if (tid == 0) {
+    s_go = (st->done == 0 && st->end_flag == 0);
+    s_info = st->info;
+    s_r00 = st->r00;
+    s_fro2 = st->fro2;
+    s_off = st->off;
+    s_ncur = st->ncur;
+  }
+  // sweep geometry and the first rows of the sweep
   const int TPR = a.CW / VEC;
   const int RG = kThreads / TPR;
   const int rg = tid / TPR, cv = tid % TPR;
   const int64_t l0 = (int64_t)chunk * a.CW + (int64_t)cv * VEC;
-  const bool colok = l0 < a.ncur;
-  const int64_t ib = (r0 > j + 1 ? r0 : j + 1) + rg;
+  const int64_t ib = (r0 > jlb + 1 ? r0 : jlb + 1) + rg;
   const S* base = a.W + l0;
   VT pf[kPrefetch];
 #pragma unroll
   for (int u = 0; u < kPrefetch; ++u) {
     const int64_t i = ib + (int64_t)u * RG;
-    if (colok && i < r1) pf[u] = *(const VT*)(base + i * a.ldw);
+    if (l0 < a.ncur && i < r1) pf[u] = *(const VT*)(base + i * a.ldw);
   }
-  // One thread reads the flags: block 0 of this kernel may set them while
-  // other blocks start, and every wave of a block must take the same branch.
-  if (tid == 0) s_go = (st->done == 0 && st->end_flag == 0);
-  __syncthreads();
-  if (!s_go) return;
-
+  // reflector entries of this thread's row: c = gi, gi + G, ...
+  const int rsub = tid / G, gi = tid % G;
+  const int64_t iw = r0 + rsub;
+  S vr[SLOTS];
+#pragma unroll
+  for (int q = 0; q < SLOTS; ++q) {
+    const int c = gi + G * q;
+    vr[q] = (iw >= jlb && iw < r1 && c < jj) ? a.V[(int64_t)c * a.ldv + iw] : (S)0;
+  }
+  // pivot partials
   AmaxVal best = amax_none();
   for (int q = tid; q < a.namax; q += kThreads) {
     const AmaxPart pp = a.amax[q];
@@ -339,21 +366,27 @@ __global__ __launch_bounds__(kThreads) void k_sweep(StepArgs<S> a) {
     c.key = pp.key;
     best = amax_combine(best, c);
   }
-  best = block_amax(best, ascr);
+  best = block_amax(best, ascr);  // its barriers also publish the flags
+  if (!s_go) return;
+  const int64_t j = s_off + jj;
+  const int64_t ncur = s_ncur;
+  const int nchunk = (int)ceil_div(ncur, a.CW);
+  const bool colok = l0 < ncur;
+  const bool rowok = iw >= j && iw < r1;
   int p = best.pos;
   double vp = best.v;
   if (a.nopivot) {
     p = jj;
-    vp = jj < a.ncur ? a.nu[jj] : 0.0;
+    vp = jj < ncur ? a.nu[jj] : 0.0;
   }
-  bool stop = (j >= a.kcap) || (jj >= a.ncur) || (p < 0) || (st->info != 0);
+  bool stop = (j >= a.kcap) || (jj >= ncur) || (p < 0) || (s_info != 0);
   if (!stop && a.k_fixed == 0) {
     if (!(vp > 0.0)) {
       stop = true;
     } else if (a.rule == ID_RANK_PIVOT_REL) {
-      if (j > 0 && vp <= a.rel_tol * st->r00) stop = true;
+      if (j > 0 && vp <= a.rel_tol * s_r00) stop = true;
     } else {
-      const double fro2 = j == 0 ? best.s2 : st->fro2;
+      const double fro2 = j == 0 ? best.s2 : s_fro2;
       if (sqrt(best.s2) <= a.rel_tol * sqrt(fro2)) stop = true;
     }
   }
@@ -379,83 +412,87 @@ __global__ __launch_bounds__(kThreads) void k_sweep(StepArgs<S> a) {
     st->jb = jj + 1;
     if (j == 0) st->fro2 = best.s2;
   }
+  if (r1 <= j || chunk >= nchunk) {
+    // below the step's row or past the live columns: the bound-sized grid
+    // leaves zero partials wherever the finalization sums
+    if (r1 <= j) {
+      if (rg == 0 && l0 < a.ncur)
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) a.zpart[tile * a.ldf + l0 + e] = 0.0;
+      if (tid < jj && chunk < nchunk && tid % nchunk == chunk)
+        a.auxpart[tile * kNbMax + tid] = 0.0;
+      if (chunk == 0 && tid == 0) a.nrm2part[tile] = 0.0;
+    }
+    return;
+  }
 
-  // Current pivot column w on the tile's rows: the stale column minus the
-  // panel's reflectors times F(p, :).  Each thread owns rows; the reflector
-  // entries of a row are loaded together (independent loads) and kept in
-  // registers, so chunk 0 can also form sum_{i>j} V(i,c) w(i) from them.
+  // rows loaded from the lower bound jlb on but below the step hold stale
+  // workspace data (possibly not even finite): drop them, never scale by 0
+  if (!rowok) {
+#pragma unroll
+    for (int q = 0; q < SLOTS; ++q) vr[q] = (S)0;
+  }
+
+  // ---- round trip 2: F(c, p) and the pivot column itself
   if (tid < kNbMax) gsh[tid] = tid < jj ? a.vscale[tid] * a.F[(int64_t)tid * a.ldf + p] : 0.0;
+  const double wp = rowok ? (double)a.W[iw * a.ldw + p] : 0.0;  // same address on the G lanes
   __syncthreads();
+  double part = 0.0;
+#pragma unroll
+  for (int q = 0; q < SLOTS; ++q) part += (double)vr[q] * gsh[gi + G * q];
+#pragma unroll
+  for (int off = 1; off < G; off <<= 1) part += __shfl_xor(part, off, 64);
+  // valid on all G lanes of the row; rows below the step (loaded from the
+  // lower bound jlb on) and past the matrix contribute nothing
+  const double w = rowok ? wp - part : 0.0;
   const bool lead = chunk == 0;
-  for (int rr = tid; rr < a.Rt; rr += kThreads) {
-    const int64_t i = r0 + rr;
-    double w = 0.0;
-    if (i >= j && i < r1) {
-      const S* vcol = a.V + i;
-      w = (double)a.W[i * a.ldw + p];
-      for (int cb = 0; cb < jj; cb += 8) {
-        S vr[8];
+  if (gi == 0 && rsub < a.Rt) {
+    wsh[rsub] = iw == j ? 0.0 : w;  // row j holds alpha, kept apart
+    if (rowok && lead) {
+      a.V[(int64_t)jj * a.ldv + iw] = (S)w;
+      if (iw == j) st->alpha = w;
+    }
+  }
+  // tile partials of sum_{i>j} V(i,c) w(i) for c = chunk, chunk + nchunk, ...
+  {
+    const double wz = (rowok && iw > j) ? w : 0.0;
+    const int lane = tid & 63, wv = tid >> 6;
 #pragma unroll
-        for (int u = 0; u < 8; ++u) vr[u] = cb + u < jj ? vcol[(int64_t)(cb + u) * a.ldv] : (S)0;
+    for (int q = 0; q < SLOTS; ++q) {
+      const int c0 = G * q;  // the slot's columns are c0 .. c0 + G - 1
+      if (c0 < jj) {
+        double z = (double)vr[q] * wz;
 #pragma unroll
-        for (int u = 0; u < 8; ++u) w -= (double)vr[u] * gsh[cb + u];
-      }
-      if (lead) {
-        a.V[(int64_t)jj * a.ldv + i] = (S)w;
-        if (i == j) st->alpha = w;
+        for (int off = G; off < 64; off <<= 1) z += __shfl_xor(z, off, 64);
+        const int c = c0 + gi;
+        if (lane < G && c < jj && c % nchunk == chunk) zred[wv][c] = z;
       }
     }
-    // row j holds alpha, kept apart: every sum below runs over rows i > j
-    wsh[rr] = i == j ? 0.0 : w;
   }
+  double nn = (lead && rowok && iw > j && gi == 0) ? w * w : 0.0;
+  if (lead) nn = block_sum(nn, dscr);
   __syncthreads();
-  if (lead) {
-    // sum_{i>j} V(i,c) w(i) for c < jj (thread = column c x row group) and
-    // sum_{i>j} w(i)^2; the V rows were just read, so these loads hit cache
-    const int c = tid % kNbMax, rg = tid / kNbMax;
-    double z = 0.0;
-    if (c < jj) {
-      const S* vc = a.V + (int64_t)c * a.ldv + r0;
-      const int64_t rend = r1 - r0;
-      int64_t rr = rg;
-      double z1 = 0.0, z2 = 0.0, z3 = 0.0;
-      for (; rr + 24 < rend; rr += 32) {
-        z += (double)vc[rr] * wsh[rr];
-        z1 += (double)vc[rr + 8] * wsh[rr + 8];
-        z2 += (double)vc[rr + 16] * wsh[rr + 16];
-        z3 += (double)vc[rr + 24] * wsh[rr + 24];
-      }
-      for (; rr < rend; rr += 8) z += (double)vc[rr] * wsh[rr];
-      z = (z + z1) + (z2 + z3);
-    }
-    zred[rg][c] = z;
-    double nn = 0.0;
-    for (int64_t rr = tid; rr < r1 - r0; rr += kThreads) nn += wsh[rr] * wsh[rr];
-    nn = block_sum(nn, dscr);
-    if (tid < jj) {
-      double t = 0.0;
-#pragma unroll
-      for (int q = 0; q < 8; ++q) t += zred[q][tid];
-      a.auxpart[tile * kNbMax + tid] = t;
-    }
-    if (tid == 0) a.nrm2part[tile] = nn;
-  }
+  if (tid < jj && tid % nchunk == chunk)
+    a.auxpart[tile * kNbMax + tid] = zred[0][tid] + zred[1][tid] + zred[2][tid] + zred[3][tid];
+  if (lead && tid == 0) a.nrm2part[tile] = nn;
 
-  // the sweep: z(l) = sum_{i in tile, i > j} W(i, l) w(i)
+  // ---- the sweep: z(l) = sum_{i in tile, i > j} W(i, l) w(i)
   double acc[VEC];
 #pragma unroll
   for (int e = 0; e < VEC; ++e) acc[e] = 0.0;
   if (colok) {
+    // only rows i > j: rows from the bound jlb up to j may hold stale data
 #pragma unroll
     for (int u = 0; u < kPrefetch; ++u) {
       const int64_t i = ib + (int64_t)u * RG;
-      if (i < r1) {
+      if (i > j && i < r1) {
         const double w0 = wsh[i - r0];
 #pragma unroll
         for (int e = 0; e < VEC; ++e) acc[e] += (double)pf[u][e] * w0;
       }
     }
     int64_t i = ib + (int64_t)kPrefetch * RG;
+    if (i <= j) i += (j + 1 - i + RG - 1) / RG * RG;
     for (; i + 3 * RG < r1; i += 4 * RG) {
       const VT x0 = *(const VT*)(base + i * a.ldw);
       const VT x1 = *(const VT*)(base + (i + RG) * a.ldw);
@@ -483,12 +520,12 @@ __global__ __launch_bounds__(kThreads) void k_sweep(StepArgs<S> a) {
     for (int e = 0; e < VEC; ++e) red[tid * VEC + e] = acc[e];
     __syncthreads();
     if (rg == 0) {
-      for (int g = 1; g < RG; ++g)
+      for (int gq = 1; gq < RG; ++gq)
 #pragma unroll
-        for (int e = 0; e < VEC; ++e) acc[e] += red[(g * TPR + cv) * VEC + e];
+        for (int e = 0; e < VEC; ++e) acc[e] += red[(gq * TPR + cv) * VEC + e];
     }
   }
-  if (rg == 0 && l0 < a.ncur) {
+  if (rg == 0 && colok) {
 #pragma unroll
     for (int e = 0; e < VEC; ++e) a.zpart[tile * a.ldf + l0 + e] = acc[e];
   }
@@ -512,23 +549,25 @@ __global__ __launch_bounds__(kThreads) void k_finalize(StepArgs<S> a) {
   __shared__ float fscr[4];
   __shared__ int s_go;
   __shared__ double s_alpha;
+  __shared__ int64_t s_off, s_ncur;
   FactorState* st = a.st;
   const int tid = threadIdx.x, cl = tid % kFC, tl = tid / kFC;
-  const int64_t j = a.j;
   const int jj = a.jj;
   const int64_t tend = a.t0 + a.ntile;
   const int64_t l = (int64_t)blockIdx.x * kFC + cl;
-  const bool lv = l < a.ncur;
+  const bool lb = l < a.ncur;  // within the host's column bound
 
-  // independent loads (buffers hold valid if stale data when the step is off)
+  // round trip 1: loads that depend neither on each other nor on the exact
+  // step (partials below the step's row were zeroed by the sweep)
   if (tid == 0) {
     s_go = (st->jb == jj + 1);
     s_alpha = st->alpha;
+    s_off = st->off;
+    s_ncur = st->ncur;
   }
-  double wj = 0.0, nl = 0.0, nlo = 1.0;
+  double nl = 0.0, nlo = 1.0;
   int pv = 1, id = 0;
-  if (tl == 0 && lv) {
-    wj = (double)a.W[j * a.ldw + l];
+  if (tl == 0 && lb) {
     nl = a.nu[l];
     nlo = a.nuo[l];
     pv = a.pvflag[l];
@@ -537,23 +576,24 @@ __global__ __launch_bounds__(kThreads) void k_finalize(StepArgs<S> a) {
 #pragma unroll
   for (int q = 0; q < kNbMax / kFL; ++q) {
     const int cf = tl + kFL * q;
-    Fsh[cf][cl] = (cf < jj && lv) ? a.F[(int64_t)cf * a.ldf + l] : 0.0;
+    Fsh[cf][cl] = (cf < jj && lb) ? a.F[(int64_t)cf * a.ldf + l] : 0.0;
   }
-  double vjr = 0.0, vsc = 0.0;
-  if (tid < jj) {
-    vjr = (double)a.V[(int64_t)tid * a.ldv + j];
-    vsc = a.vscale[tid];
-  }
+  const double vsc = tid < jj ? a.vscale[tid] : 0.0;
   const double pn = strided_sum(a.nrm2part, 1, a.t0 + tid, tend, kThreads);
   {
     const int c = tid % kNbMax, sl = tid / kNbMax;
     ared[sl][c] = c < jj ? strided_sum(a.auxpart + c, kNbMax, a.t0 + sl, tend, 8) : 0.0;
   }
-  red[tl][cl] = lv ? strided_sum(a.zpart + l, a.ldf, a.t0 + tl, tend, kFL) : 0.0;
-  const int key = (tl == 0 && lv) ? a.posof[id] : 0;
+  red[tl][cl] = lb ? strided_sum(a.zpart + l, a.ldf, a.t0 + tl, tend, kFL) : 0.0;
 
   const double xnorm2 = block_sum(pn, dscr);  // also publishes the LDS writes above
   if (!s_go) return;
+  // round trip 2: the step's row
+  const int64_t j = s_off + jj;
+  const bool lv = l < s_ncur;
+  const double wj = (tl == 0 && lv) ? (double)a.W[j * a.ldw + l] : 0.0;
+  const double vjr = tid < jj ? (double)a.V[(int64_t)tid * a.ldv + j] : 0.0;
+  const int key = (tl == 0 && lv) ? a.posof[id] : 0;
   const double alpha = s_alpha;
   double beta, tau, scale;
   if (xnorm2 == 0.0) {
@@ -684,18 +724,23 @@ __global__ __launch_bounds__(kThreads) void k_panel_gemm(GemmArgs<S> a) {
   __shared__ double ssq[4][64];
   __shared__ int s_go, s_jb;
   __shared__ uint32_t s_fmax;
+  __shared__ int64_t s_off, s_ncur;
   FactorState* st = a.st;
   const int tid = threadIdx.x;
   if (tid == 0) {
     s_go = (st->done == 0);
     s_jb = st->jb;
     s_fmax = st->fmax_bits;
+    s_off = st->off;
+    s_ncur = st->ncur;
   }
   if (tid < kNbMax) spiv[tid] = a.pivpos[tid];
   __syncthreads();
   if (!s_go) return;
+  if (tid == 0 && blockIdx.x == 0 && blockIdx.y == 0) st->vmax_bits = 0u;  // refilled after
   const int jb = s_jb;
-  const int64_t jend = a.off + jb;
+  const int64_t ncur = s_ncur;  // a.ncur is the host's bound that sized the grid
+  const int64_t jend = s_off + jb;
   const int64_t l0 = (int64_t)blockIdx.x * 64;
   const int64_t tg = a.tg0 + blockIdx.y;
   const int64_t rbase = tg * kRowTileG;
@@ -710,7 +755,7 @@ __global__ __launch_bounds__(kThreads) void k_panel_gemm(GemmArgs<S> a) {
       before += spiv[c] < l;
       pv |= spiv[c] == l;
     }
-    cidx[tid] = (l < a.ncur && !pv) ? (int)(l - before) : -1;
+    cidx[tid] = (l < ncur && !pv) ? (int)(l - before) : -1;
   }
   __syncthreads();
 
@@ -740,14 +785,14 @@ __global__ __launch_bounds__(kThreads) void k_panel_gemm(GemmArgs<S> a) {
 #pragma unroll
       for (int s = 0; s < 8; ++s) {
         const int c = 4 * s + g;
-        a64[lb][s] = (c < jb && pos < a.ncur) ? a.F[(int64_t)c * a.ldf + pos] : 0.0;
+        a64[lb][s] = (c < jb && pos < ncur) ? a.F[(int64_t)c * a.ldf + pos] : 0.0;
       }
     } else {
       const int64_t pos = l0 + 16 * lb + li;
 #pragma unroll
       for (int e = 0; e < 8; ++e) {
         const int c = 8 * g + e;
-        const float x = (c < jb && pos < a.ncur) ? (float)(a.F[(int64_t)c * a.ldf + pos] * fscl)
+        const float x = (c < jb && pos < ncur) ? (float)(a.F[(int64_t)c * a.ldf + pos] * fscl)
                                                  : 0.0f;
         if (OP == OP_F16) {
           ah[lb][e] = (_Float16)x;
@@ -850,8 +895,14 @@ __global__ __launch_bounds__(kThreads) void k_panel_gemm(GemmArgs<S> a) {
 
 __global__ void k_advance(FactorState* st) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
-    if (st->done) return;
+    if (st->done) {
+      // panels enqueued after the stop must not match any step's jb
+      st->jb = 0;
+      return;
+    }
     st->last_jb = st->jb;
+    st->off += st->jb;
+    st->ncur -= st->jb;
     st->jb = 0;
     st->end_flag = 0;
     st->fmax_bits = 0u;
@@ -908,9 +959,8 @@ static SweepShape choose_sweep_shape(int64_t rows, int64_t ncur, int wbytes) {
     rt = kRtMin;
     while (rt < kRtMax && ceil_div(rows, rt) * nchunk > target) rt *= 2;
   }
-  if (rt < kRtMin) rt = kRtMin;
-  if (rt > kRtMax) rt = kRtMax;
-  sh.Rt = rt;
+  // the sweep kernel supports row tiles of 64, 128 or 256 rows
+  sh.Rt = rt <= 64 ? 64 : (rt <= 128 ? 128 : 256);
   return sh;
 }
 
@@ -951,6 +1001,19 @@ struct Profiler {
     (void)hipEventRecord(ev(used), s);
     ++used;
   }
+  // Launches a kernel; when profiling, its start and stop events are taken at
+  // the kernel's own execution boundaries (hipExtLaunchKernelGGL).
+  template <typename K, typename... Args>
+  void launch(int kind, int64_t j, K kernel, dim3 grid, hipStream_t s, Args... args) {
+    if (!on) {
+      kernel<<<grid, kThreads, 0, s>>>(args...);
+      return;
+    }
+    recs.push_back({kind, j, used});
+    hipEvent_t e0 = ev(used), e1 = ev(used + 1);
+    used += 2;
+    hipExtLaunchKernelGGL(kernel, grid, dim3(kThreads), 0, s, e0, e1, 0, args...);
+  }
   float ms(const ProfRec& r) {
     float t = 0.0f;
     if (hipEventElapsedTime(&t, (*pool)[r.e0], (*pool)[r.e0 + 1]) != hipSuccess) return 0.0f;
@@ -985,8 +1048,6 @@ static int factor_impl(const TA* A, int64_t lda, const FactorPlan& pl, const id_
   double* rorig = (double*)(wb + pl.off_rorig);
   FactorState* st = (FactorState*)(wb + pl.off_state);
 
-  static thread_local FactorState* hst = nullptr;
-  if (!hst) MPID_HIP(hipHostMalloc((void**)&hst, sizeof(FactorState), hipHostMallocDefault));
 
   const int64_t ldw = pl.ldw, ldf = pl.ldf;
   const int64_t ntg = ceil_div(m, kRowTileG);
@@ -1049,41 +1110,127 @@ static int factor_impl(const TA* A, int64_t lda, const FactorPlan& pl, const id_
   a.nopivot = (o->flags & ID_FLAG_NO_PIVOT) ? 1 : 0;
   a.nb = pl.nb;
 
-  int64_t off = 0, ncur = n;
-  int cur = 0;
-  for (;;) {
+  // Panels are enqueued one ahead of what the host knows: before panel P is
+  // enqueued the host has read the state after panel P - 2, whose offset is a
+  // lower bound for the panel's real offset (each panel advances it by its
+  // data-dependent jb <= nb).  Grids are sized from these bounds and the
+  // kernels take the exact offset and column count from the device state.
+  // Every live panel compacts into the other buffer, so panel P works on
+  // buffer P & 1.
+  static thread_local FactorState* hslot = nullptr;
+  static thread_local hipEvent_t pev[2] = {nullptr, nullptr};
+  if (!hslot) MPID_HIP(hipHostMalloc((void**)&hslot, 2 * sizeof(FactorState), hipHostMallocDefault));
+  for (int q = 0; q < 2; ++q)
+    if (!pev[q]) MPID_HIP(hipEventCreateWithFlags(&pev[q], hipEventDisableTiming));
+  int64_t off_lb = 0;     // lower bound of the offset of the panel being enqueued
+  int64_t known_off = 0;  // exact offset at the start of the first unsettled panel
+  const FactorState* fin = nullptr;
+  // resolves profiler records of one panel once its end state is known
+  auto settle = [&](int panel_id, int64_t start_off, const FactorState& h) {
+    if (!prof.on) return;
+    const int64_t live_end = h.done ? h.k : start_off + h.last_jb;
+    for (const ProfRec& r : prof.recs) {
+      if (r.j / 1024 != panel_id) continue;  // j packs (panel, step)
+      const int64_t jj = r.j % 1024;
+      const double t = prof.ms(r);
+      const int64_t jd = start_off + jj;
+      if (r.kind == PK_SWEEP) {
+        if (jd < live_end) {
+          acc.sweep_launches += 1;
+          acc.sweep_ms += t;
+          acc.sweep_bytes += (double)(m - jd) * (double)(n - jd - 1) * sbytes;
+        }
+      } else if (r.kind == PK_FINALIZE) {
+        if (jd < live_end) {
+          acc.finalize_launches += 1;
+          acc.finalize_ms += t;
+        }
+      } else if (r.kind == PK_GEMM) {
+        if (!h.done) {
+          const int64_t je = start_off + h.last_jb;
+          acc.gemm_launches += 1;
+          acc.gemm_ms += t;
+          acc.gemm_bytes += 2.0 * (double)(m - je) * (double)(n - je) * sbytes;
+        }
+      } else {
+        acc.other_ms += t;
+      }
+    }
+  };
+  int settled = 0;           // panels whose end state has been processed
+  bool drain = false;        // near the end: settle every panel before the next
+  const FactorState* fin_drain = nullptr;
+  auto settle_upto = [&](int target, const FactorState** done_state) -> int {
+    while (settled <= target) {
+      MPID_HIP(hipEventSynchronize(pev[settled & 1]));
+      const FactorState& h = hslot[settled & 1];
+      settle(settled, known_off, h);
+      ++settled;
+      if (h.done) {
+        *done_state = &h;
+        return ID_OK;
+      }
+      if (h.last_jb <= 0) return ID_ERR_HIP;  // a live panel always makes progress
+      known_off += h.last_jb;
+      // the rank rule is near: largest norm within a few panels' decay of the
+      // threshold, or kcap within two panels
+      float vmaxf;
+      std::memcpy(&vmaxf, &h.vmax_bits, sizeof(float));
+      const double vmax = (double)vmaxf;
+      if (known_off + 2 * pl.nb >= kcap ||
+          (o->k_fixed == 0 &&
+           (o->rank_rule != ID_RANK_PIVOT_REL || vmax <= 16.0 * o->rel_tol * h.r00)))
+        drain = true;
+    }
+    return ID_OK;
+  };
+  for (int panel = 0;; ++panel) {
+    if (drain && settled < panel) {
+      const int rc = settle_upto(panel - 1, &fin_drain);
+      if (rc) return rc;
+      if (fin_drain) {
+        fin = fin_drain;
+        break;
+      }
+      off_lb = known_off;
+    }
+    const int cur = panel & 1;
+    const int64_t ncur_ub = n - off_lb;
     a.W = W[cur];
     a.colid = colid[cur];
-    a.ncur = ncur;
+    a.ncur = ncur_ub;
     for (int jj = 0; jj < pl.nb; ++jj) {
-      const int64_t j = off + jj;
-      if (j >= kcap || jj >= ncur) break;
-      const SweepShape sh = choose_sweep_shape(m - j, ncur, pl.wbytes);
-      a.j = j;
+      const int64_t jlb = off_lb + jj;
+      if (jlb >= kcap || jj >= ncur_ub) break;
+      const SweepShape sh = choose_sweep_shape(m - jlb, ncur_ub, pl.wbytes);
+      a.j = jlb;
       a.jj = jj;
       a.Rt = sh.Rt;
       a.CW = sh.CW;
-      a.t0 = j / sh.Rt;
+      a.t0 = jlb / sh.Rt;
       a.ntile = (int)(ceil_div(m, sh.Rt) - a.t0);
-      a.nchunk = (int)ceil_div(ncur, sh.CW);
+      a.nchunk = (int)ceil_div(ncur_ub, sh.CW);
       a.namax = namax;
       const int64_t total = (int64_t)a.ntile * a.nchunk;
-      prof.begin(PK_SWEEP, j, s);
-      k_sweep<S><<<dim3((unsigned)round_up(total, 8)), kThreads, 0, s>>>(a);
+      const dim3 sgrid((unsigned)round_up(total, 8));
+      const int64_t tag = (int64_t)panel * 1024 + jj;
+      if (sh.Rt >= 256)
+        prof.launch(PK_SWEEP, tag, k_sweep<S, 1>, sgrid, s, a);
+      else if (sh.Rt >= 128)
+        prof.launch(PK_SWEEP, tag, k_sweep<S, 2>, sgrid, s, a);
+      else
+        prof.launch(PK_SWEEP, tag, k_sweep<S, 4>, sgrid, s, a);
       MPID_LAUNCH_CHECK();
-      prof.end(s);
-      namax = (int)ceil_div(ncur, kFC);
-      prof.begin(PK_FINALIZE, j, s);
-      k_finalize<S><<<dim3((unsigned)namax), kThreads, 0, s>>>(a);
+      namax = (int)ceil_div(ncur_ub, kFC);
+      prof.launch(PK_FINALIZE, tag, k_finalize<S>, dim3((unsigned)namax), s, a);
       MPID_LAUNCH_CHECK();
-      prof.end(s);
     }
     GemmArgs<S> g;
     g.W = W[cur];
     g.Wn = W[cur ^ 1];
     g.ldw = ldw;
     g.m = m;
-    g.ncur = ncur;
+    g.ncur = ncur_ub;
     g.V = V;
     g.ldv = pl.ldv;
     g.F = F;
@@ -1094,70 +1241,50 @@ static int factor_impl(const TA* A, int64_t lda, const FactorPlan& pl, const id_
     g.colid = colid[cur];
     g.colid_n = colid[cur ^ 1];
     g.colpart = colpart;
-    g.off = off;
-    g.tg0 = off / kRowTileG;
-    prof.begin(PK_GEMM, off, s);
-    k_panel_gemm<S, OP><<<dim3((unsigned)ceil_div(ncur, 64), (unsigned)(ntg - g.tg0)), kThreads,
-                          0, s>>>(g);
+    g.off = off_lb;
+    g.tg0 = off_lb / kRowTileG;
+    prof.launch(PK_GEMM, (int64_t)panel * 1024, k_panel_gemm<S, OP>,
+                dim3((unsigned)ceil_div(ncur_ub, 64), (unsigned)(ntg - g.tg0)), s, g);
     MPID_LAUNCH_CHECK();
-    prof.end(s);
-    namax = (int)ceil_div(ncur, kFinCols);
-    prof.begin(PK_OTHER, 0, s);
-    k_colreduce<<<dim3((unsigned)namax), kThreads, 0, s>>>(colpart, ldf, g.tg0, ntg, ncur, 1,
+    namax = (int)ceil_div(ncur_ub, kFinCols);
+    prof.begin(PK_OTHER, (int64_t)panel * 1024, s);
+    k_colreduce<<<dim3((unsigned)namax), kThreads, 0, s>>>(colpart, ldf, g.tg0, ntg, ncur_ub, 1,
                                                             nu, nuo, amax, colid[cur ^ 1], posof,
                                                             pvflag, st);
     MPID_LAUNCH_CHECK();
     k_advance<<<1, 64, 0, s>>>(st);
     MPID_LAUNCH_CHECK();
     prof.end(s);
-    MPID_HIP(hipMemcpyAsync(hst, st, sizeof(FactorState), hipMemcpyDeviceToHost, s));
-    MPID_HIP(hipStreamSynchronize(s));
-    if (prof.on) {
-      // count only the launches that did work in this panel
-      const int64_t live_end = hst->done ? hst->k : off + hst->last_jb;
-      for (const ProfRec& r : prof.recs) {
-        const double t = prof.ms(r);
-        if (r.kind == PK_SWEEP) {
-          if (r.j < live_end) {
-            acc.sweep_launches += 1;
-            acc.sweep_ms += t;
-            acc.sweep_bytes += (double)(m - r.j) * (double)(n - r.j - 1) * sbytes;
-          }
-        } else if (r.kind == PK_FINALIZE) {
-          if (r.j < live_end) {
-            acc.finalize_launches += 1;
-            acc.finalize_ms += t;
-          }
-        } else if (r.kind == PK_GEMM) {
-          if (!hst->done) {
-            const int64_t je = off + hst->last_jb;
-            acc.gemm_launches += 1;
-            acc.gemm_ms += t;
-            acc.gemm_bytes += 2.0 * (double)(m - je) * (double)(n - je) * sbytes;
-          }
-        } else {
-          acc.other_ms += t;
-        }
+    MPID_HIP(hipMemcpyAsync(&hslot[cur], st, sizeof(FactorState), hipMemcpyDeviceToHost, s));
+    MPID_HIP(hipEventRecord(pev[cur], s));
+    // Settle panels up to the previous one (the panel just enqueued keeps the
+    // GPU busy meanwhile).  Near the end (drain) the next iteration settles
+    // this panel before enqueueing another, so no idle panel follows the stop.
+    // A panel's slot and event are reused two panels later, after settling.
+    if (!drain) {
+      const FactorState* d = nullptr;
+      const int rc = settle_upto(panel - 1, &d);
+      if (rc) return rc;
+      if (d) {
+        fin = d;
+        break;
       }
-      prof.recs.clear();
-      prof.used = 2;
+      off_lb = known_off;
     }
-    if (hst->done) break;
-    const int jb = hst->last_jb;
-    if (jb <= 0) return ID_ERR_HIP;  // cannot happen: a live panel makes progress
-    off += jb;
-    ncur -= jb;
-    cur ^= 1;
   }
-  const int64_t k = hst->k;
+  if (!fin->done) return ID_ERR_HIP;
+  // the panel enqueued after the stop (if any) only found the done flag
+  MPID_HIP(hipStreamSynchronize(s));
+  const int64_t k = fin->k;
   *k_out = k;
-  *info = hst->info;
+  *info = fin->info;
   k_finish<<<dim3((unsigned)n, (unsigned)(k > 0 ? ceil_div(k, kThreads) : 1)), kThreads, 0, s>>>(
       permw, perm, rorig, kcap, n, k, R, ldr);
   MPID_LAUNCH_CHECK();
   if (prof.on) {
     MPID_HIP(hipEventRecord(ev_t1, s));
     MPID_HIP(hipEventSynchronize(ev_t1));
+    // records of a panel enqueued after the stop are never settled
     float t = 0.0f;
     MPID_HIP(hipEventElapsedTime(&t, ev_t0, ev_t1));
     acc.total_ms = t;

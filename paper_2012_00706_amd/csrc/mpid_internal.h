@@ -12,7 +12,7 @@ namespace mpid {
 
 constexpr int kThreads = 256;   // block size of every kernel
 constexpr int kNbMax = 32;      // largest panel width (K of the blocked update)
-constexpr int kRtMax = 2048;    // largest row tile of the reflector sweep
+constexpr int kRtMax = 256;     // largest row tile of the reflector sweep
 constexpr int kRtMin = 64;      // smallest row tile of the reflector sweep
 constexpr int kRowTileG = 256;  // row tile of the ingest / blocked-update kernels
 constexpr int kColTileG = 64;   // column tile of the blocked update
@@ -29,11 +29,14 @@ struct FactorState {
   int32_t last_jb;   // jb of the panel that just ended (for the host)
   int32_t info;      // ID_INFO_NONFINITE when the input holds NaN/Inf
   uint32_t fmax_bits;  // max |F| of the current panel, as float bits
+  uint32_t vmax_bits;  // largest column norm after the last recomputation (float bits)
+  int32_t pad0;
   int64_t k;         // rank (valid when done)
   double r00;        // |R_00|
   double alpha;      // leading entry of the current pivot column
   double fro2;       // ||A||_F^2
-  double pad[2];
+  int64_t off;       // first step of the current panel
+  int64_t ncur;      // columns of the current (compacted) working copy
 };
 
 // Per-block partial of the pivot search.

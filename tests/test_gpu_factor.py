@@ -181,3 +181,20 @@ def test_degenerate_shapes(m, n):
     ref = orc.cpqr(A, k=k)
     assert perm[:k].tolist() == ref.perm[:k].tolist()
     np.testing.assert_allclose(np.abs(R), np.abs(ref.R), rtol=1e-13, atol=1e-14)
+
+
+@pytest.mark.parametrize("m,n,k", [(2000, 200, 120), (3000, 150, 70), (700, 300, 97)])
+def test_fixed_rank_below_n_multi_panel(m, n, k):
+    """Fixed k < n over several panels: the last rows of R (and so T) match the
+    oracle; steps enqueued after the last one must leave them alone."""
+    need_gpu()
+    A = synth.spectrum_matrix(m, n, synth.sigma_geom10(min(m, n), 40.0), m + 1, n + 1)
+    perm, kk, R, T = gpu_id(A, k=k, prec="f64")
+    ref = orc.cpqr(A, k=k)
+    assert kk == k
+    upto = int(np.argmax(ref.margins < 1e-8)) if np.any(ref.margins < 1e-8) else k
+    assert perm[:upto].tolist() == ref.perm[:upto].tolist()
+    if upto == k:
+        np.testing.assert_allclose(row_sign_align(R, ref.R), ref.R, rtol=0,
+                                   atol=1e-11 * np.abs(ref.R).max())
+        assert rel_err(T, orc.solve_T(ref.R, k)) <= 1e-10
