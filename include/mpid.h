@@ -168,6 +168,52 @@ int id_backward(const void* A, int32_t dtype, int64_t m, int64_t n, int64_t lda,
                 int64_t ldgt, const double* gY, int64_t ldgy, double* gA, int64_t ldga,
                 void* work, size_t work_bytes, int32_t* info, void* stream);
 
+/* ---- batched IDs -------------------------------------------------------
+ * One descriptor per matrix, in DEVICE memory (so a call can be captured in a
+ * HIP graph and replayed).  Inputs: A, m, n, lda, work.  Outputs: perm, R, T,
+ * k, info.  Each item needs its own workspace of
+ * id_batch_item_workspace_size(m, n, opts) bytes, 256-byte aligned; the
+ * caller owns every buffer.  Every item uses the same opts (same rank rule and
+ * tolerance or fixed k).  kcap = min(m, n, k_max if > 0, k_fixed if > 0). */
+typedef struct {
+  const void* A;  /* m x n column-major, storage dtype of the call */
+  int64_t m, n, lda;
+  void* work;     /* this item's workspace */
+  int32_t* perm;  /* [out] n int32 */
+  double* R;      /* [out] k x n float64 in pivot order (R11 upper triangular), ldr >= kcap */
+  int64_t ldr;
+  double* T;      /* [out] k x (n - k) float64, ldt >= kcap; untouched when info != 0 */
+  int64_t ldt;
+  int64_t k;      /* [out] rank */
+  int32_t info;   /* [out] 0, ID_INFO_NONFINITE, ID_INFO_SINGULAR or ID_INFO_RANK_FULL */
+  int32_t pad;
+} id_batch_item;
+
+/* Bytes of workspace one batched item of size m x n needs [host]; 0 for
+ * invalid arguments (the batched path supports n <= 2048). */
+size_t id_batch_item_workspace_size(int64_t m, int64_t n, const id_opts* opts);
+
+/* Many column IDs of uneven sizes (the factorization of Algorithms 1 and 2
+ * plus T = R11^{-1} R12) in one persistent launch: each workgroup takes the
+ * next matrix from a device work queue (in the order "order", e.g. longest
+ * first) and factors it alone, with workgroup-local synchronization only;
+ * a second launch solves every item's T.  No host synchronization, so the call
+ * may be captured in a HIP graph.
+ *
+ *   items         [in/out] device array of "batch" descriptors.
+ *   order         device array of "batch" item indices, or NULL (0..batch-1).
+ *   queue         device int32 scratch for the work counter (reset here).
+ *   max_n         [host] largest n of the batch (sizes the solve grid).
+ *   dtype, opts   [host] as in id_factor (opts->flags must be 0).
+ *   block_threads [host] 256 or 512 threads per workgroup; 0 = 256.
+ *   num_groups    [host] persistent workgroups; 0 = one per compute unit.
+ * Returns ID_ERR_ARG / ID_ERR_DTYPE for invalid host arguments and
+ * ID_ERR_UNSUPPORTED when max_n > 2048; per-item conditions go to items[i].info.
+ * Calls that share "queue" or an item's workspace must not overlap. */
+int id_factor_batched(id_batch_item* items, int32_t batch, const int32_t* order, int32_t* queue,
+                      int64_t max_n, int32_t dtype, const id_opts* opts, int32_t block_threads,
+                      int32_t num_groups, void* stream);
+
 /* Per-kernel timing of the calling thread's last id_factor call made with
  * ID_FLAG_PROFILE (instrumentation, not part of the method).  Times come from
  * HIP events recorded around each launch on the call's stream; "bytes" are the

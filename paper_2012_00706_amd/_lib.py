@@ -44,6 +44,24 @@ class IdProfile(ctypes.Structure):
         return {name: getattr(self, name) for name, _ in self._fields_}
 
 
+class IdBatchItem(ctypes.Structure):
+    _fields_ = [
+        ("A", ctypes.c_void_p),
+        ("m", ctypes.c_int64),
+        ("n", ctypes.c_int64),
+        ("lda", ctypes.c_int64),
+        ("work", ctypes.c_void_p),
+        ("perm", ctypes.c_void_p),
+        ("R", ctypes.c_void_p),
+        ("ldr", ctypes.c_int64),
+        ("T", ctypes.c_void_p),
+        ("ldt", ctypes.c_int64),
+        ("k", ctypes.c_int64),
+        ("info", ctypes.c_int32),
+        ("pad", ctypes.c_int32),
+    ]
+
+
 def _constants():
     """#define ID_* integer constants parsed from the public header."""
     out = {}
@@ -71,6 +89,9 @@ SIGNATURES = {
     "id_backward_workspace_size": (_sz, [_i64, _i64, _i64]),
     "id_backward": (ctypes.c_int, [_vp, _i32, _i64, _i64, _i64, _vp, _i64, _vp, _i64, _vp, _i64,
                                    _vp, _i64, _vp, _i64, _vp, _sz, _P(_i32), _vp]),
+    "id_batch_item_workspace_size": (_sz, [_i64, _i64, _P(IdOpts)]),
+    "id_factor_batched": (ctypes.c_int, [_vp, _i32, _vp, _vp, _i64, _i32, _P(IdOpts), _i32, _i32,
+                                         _vp]),
     "id_last_profile": (ctypes.c_int, [_P(IdProfile)]),
     "id_status_string": (ctypes.c_char_p, [ctypes.c_int]),
 }

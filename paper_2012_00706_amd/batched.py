@@ -1,0 +1,246 @@
+"""Many column IDs of uneven sizes in one persistent launch (id_factor_batched).
+
+A :class:`BatchedID` plan binds a list of device matrices, owns every
+workspace and output buffer, and launches the batched factorization plus the
+batched solve T = R11^{-1} R12 on the current stream without synchronizing, so
+``run()`` can be captured in a CUDA/HIP graph (:meth:`BatchedID.capture`) and
+replayed after new data has been copied into the bound inputs.
+:func:`autotune` picks the workgroup size and panel width for a batch by timing
+them, and caches the choice in a JSON file.
+"""
+from __future__ import annotations
+
+import ctypes
+import json
+import os
+from dataclasses import dataclass
+
+import torch
+
+from . import _lib
+from .api import DTYPE, _stream, colmajor, kcap_of, make_opts
+
+C = _lib.C
+_ALIGN = 256
+
+
+def _round_up(x: int, a: int) -> int:
+    return (x + a - 1) // a * a
+
+
+def _colmajor_view(buf: torch.Tensor, off: int, rows: int, cols: int, ld: int) -> torch.Tensor:
+    """rows x cols column-major view (leading dimension ld) of buf[off:]."""
+    return buf[off:off + ld * cols].view(cols, ld).t()[:rows]
+
+
+@dataclass
+class BatchItemResult:
+    perm: torch.Tensor  # (n,) int32
+    k: int
+    R: torch.Tensor     # (k, n) float64, column-major view
+    T: torch.Tensor     # (k, n - k) float64, column-major view (0 x 0 when not solved)
+    info: int
+
+
+class BatchedID:
+    """Plan for the column IDs of the matrices ``As`` (same dtype and device).
+
+    ``k`` (fixed rank) or ``tol`` (adaptive rank, ``rule``) applies to every
+    item.  Matrices that are not column-major are copied once at bind time;
+    :attr:`inputs` holds the tensors the kernels read (copy new data into them
+    before replaying a captured graph).
+    """
+
+    def __init__(self, As, k=None, tol=None, prec="f64", rule="pivot_rel", k_max=0, nb=0,
+                 block_threads=0, num_groups=0, order="lpt"):
+        if len(As) == 0:
+            raise ValueError("empty batch")
+        dtypes = {A.dtype for A in As}
+        devices = {A.device for A in As}
+        if len(dtypes) != 1 or len(devices) != 1:
+            raise ValueError("all matrices must share dtype and device")
+        if k is not None and int(k) <= 0:
+            raise ValueError("fixed rank must be >= 1")
+        self.dtype = dtypes.pop()
+        self.device = devices.pop()
+        if self.dtype not in DTYPE:
+            raise TypeError("matrices must be float32 or float64")
+        self.opts = make_opts(k, tol, prec, rule, k_max, nb)
+        self.block_threads = int(block_threads)
+        self.num_groups = int(num_groups)
+        lib = _lib.load()
+        self.inputs, ldas = [], []
+        for A in As:
+            Ac, lda = colmajor(A)
+            self.inputs.append(Ac)
+            ldas.append(lda)
+        shapes = [tuple(A.shape) for A in self.inputs]
+        self.shapes = shapes
+        self.batch = len(shapes)
+        self.max_n = max(n for _, n in shapes)
+        ws, kcs = [], []
+        for m, n in shapes:
+            w = int(lib.id_batch_item_workspace_size(m, n, ctypes.byref(self.opts)))
+            if w == 0:
+                raise ValueError(f"unsupported item shape {m} x {n} (the batched path takes n <= 2048)")
+            ws.append(w)
+            kcs.append(kcap_of(m, n, self.opts))
+        self.kcaps = kcs
+        dev = self.device
+        w_off, r_off, p_off = [], [], []
+        tw = tr = tp = 0
+        for (m, n), w, kc in zip(shapes, ws, kcs):
+            w_off.append(tw)
+            tw += _round_up(w, _ALIGN)
+            r_off.append(tr)
+            tr += _round_up(max(kc, 1) * max(n, 1), 32)
+            p_off.append(tp)
+            tp += _round_up(max(n, 1), 64)
+        self.work = torch.empty(tw + _ALIGN, dtype=torch.uint8, device=dev)
+        wbase = _round_up(self.work.data_ptr(), _ALIGN) - self.work.data_ptr()
+        self.R_buf = torch.zeros(tr, dtype=torch.float64, device=dev)
+        self.T_buf = torch.zeros(tr, dtype=torch.float64, device=dev)
+        self.perm_buf = torch.zeros(tp, dtype=torch.int32, device=dev)
+        self._r_off, self._p_off = r_off, p_off
+        items = (_lib.IdBatchItem * self.batch)()
+        for i, ((m, n), kc) in enumerate(zip(shapes, kcs)):
+            it = items[i]
+            it.A = self.inputs[i].data_ptr()
+            it.m, it.n, it.lda = m, n, ldas[i]
+            it.work = self.work.data_ptr() + wbase + w_off[i]
+            it.perm = self.perm_buf.data_ptr() + 4 * p_off[i]
+            it.R = self.R_buf.data_ptr() + 8 * r_off[i]
+            it.ldr = max(kc, 1)
+            it.T = self.T_buf.data_ptr() + 8 * r_off[i]
+            it.ldt = max(kc, 1)
+        raw = bytes(bytearray(items))
+        self.items = torch.frombuffer(bytearray(raw), dtype=torch.uint8).to(dev)
+        if order == "lpt":
+            # longest processing time first: work ~ m n kcap
+            idx = sorted(range(self.batch), key=lambda i: (-shapes[i][0] * shapes[i][1] * kcs[i], i))
+            self.order = torch.tensor(idx, dtype=torch.int32, device=dev)
+        elif order is None:
+            self.order = None
+        else:
+            self.order = torch.as_tensor(order, dtype=torch.int32).to(dev)
+            if sorted(self.order.tolist()) != list(range(self.batch)):
+                raise ValueError("order must be a permutation of the item indices")
+        self.queue = torch.zeros(1, dtype=torch.int32, device=dev)
+
+    def configure(self, block_threads=None, num_groups=None, nb=None):
+        """Change the launch shape or panel width (workspaces do not depend on them)."""
+        if block_threads is not None:
+            self.block_threads = int(block_threads)
+        if num_groups is not None:
+            self.num_groups = int(num_groups)
+        if nb is not None:
+            self.opts.nb = int(nb)
+
+    def run(self):
+        """Enqueue the batched factorization and solve on the current stream."""
+        lib = _lib.load()
+        with torch.cuda.device(self.device):
+            rc = lib.id_factor_batched(
+                self.items.data_ptr(), self.batch,
+                self.order.data_ptr() if self.order is not None else None,
+                self.queue.data_ptr(), self.max_n, DTYPE[self.dtype], ctypes.byref(self.opts),
+                self.block_threads, self.num_groups, _stream(self.device))
+        _lib.check(rc, "id_factor_batched")
+
+    def capture(self) -> torch.cuda.CUDAGraph:
+        """A graph holding one run(); replay it with g.replay()."""
+        side = torch.cuda.Stream(device=self.device)
+        side.wait_stream(torch.cuda.current_stream(self.device))
+        with torch.cuda.stream(side):
+            self.run()
+        torch.cuda.current_stream(self.device).wait_stream(side)
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            self.run()
+        return g
+
+    def results(self):
+        """Per-item results (waits for the device)."""
+        torch.cuda.synchronize(self.device)
+        raw = self.items.cpu().numpy().tobytes()
+        items = (_lib.IdBatchItem * self.batch).from_buffer_copy(raw)
+        out = []
+        for i, (m, n) in enumerate(self.shapes):
+            k, info = int(items[i].k), int(items[i].info)
+            ld = max(self.kcaps[i], 1)
+            perm = self.perm_buf[self._p_off[i]:self._p_off[i] + n]
+            R = _colmajor_view(self.R_buf, self._r_off[i], k, n, ld)
+            solved = info in (0, C["ID_INFO_RANK_FULL"])
+            T = _colmajor_view(self.T_buf, self._r_off[i], k if solved else 0,
+                               n - k if solved else 0, ld)
+            out.append(BatchItemResult(perm, k, R, T, info))
+        return out
+
+
+def factor_batched(As, k=None, tol=None, prec="f64", rule="pivot_rel", k_max=0, nb=0,
+                   block_threads=0, num_groups=0):
+    """Column IDs of every matrix in As in one batched call; list of BatchItemResult."""
+    plan = BatchedID(As, k=k, tol=tol, prec=prec, rule=rule, k_max=k_max, nb=nb,
+                     block_threads=block_threads, num_groups=num_groups)
+    plan.run()
+    return plan.results()
+
+
+def _cache_path():
+    return os.environ.get("MPID_TUNE_CACHE",
+                          os.path.join(os.path.expanduser("~"), ".cache", "mpid", "batched_tune.json"))
+
+
+def _signature(plan: BatchedID) -> str:
+    o = plan.opts
+    name = torch.cuda.get_device_name(plan.device)
+    shapes = ",".join(f"{m}x{n}" for m, n in sorted(plan.shapes))
+    return (f"{name}|{plan.dtype}|prec{o.prec}|rule{o.rank_rule}|k{o.k_fixed}|tol{o.rel_tol}|"
+            f"kmax{o.k_max}|{shapes}")
+
+
+def autotune(plan: BatchedID, candidates=None, reps: int = 3, use_cache: bool = True):
+    """Time the plan under each (block_threads, nb) candidate, configure it with
+    the fastest, and return {"block_threads", "nb", "ms", "table"}.  Results are
+    cached by device, dtype, options and the multiset of shapes."""
+    key = _signature(plan)
+    path = _cache_path()
+    cache = {}
+    if use_cache and os.path.exists(path):
+        try:
+            with open(path) as f:
+                cache = json.load(f)
+        except (OSError, ValueError):
+            cache = {}
+    if use_cache and key in cache:
+        best = cache[key]
+        plan.configure(block_threads=best["block_threads"], nb=best["nb"])
+        return best
+    if candidates is None:
+        candidates = [(bt, nb) for bt in (256, 512) for nb in (16, 32)]
+    table = []
+    for bt, nb in candidates:
+        plan.configure(block_threads=bt, nb=nb)
+        plan.run()  # warm-up
+        times = []
+        for _ in range(reps):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            plan.run()
+            e1.record()
+            e1.synchronize()
+            times.append(e0.elapsed_time(e1))
+        times.sort()
+        table.append({"block_threads": bt, "nb": nb, "ms": times[len(times) // 2]})
+    best = dict(min(table, key=lambda r: r["ms"]))
+    best["table"] = table
+    plan.configure(block_threads=best["block_threads"], nb=best["nb"])
+    if use_cache:
+        cache[key] = best
+        os.makedirs(os.path.dirname(path) or ".", exist_ok=True)
+        tmp = path + f".tmp{os.getpid()}"
+        with open(tmp, "w") as f:
+            json.dump(cache, f, indent=1)
+        os.replace(tmp, path)
+    return best

@@ -48,6 +48,17 @@ int id_backward(const void* A, int32_t dtype, int64_t m, int64_t n, int64_t lda,
                             work, work_bytes, info, (hipStream_t)stream);
 }
 
+size_t id_batch_item_workspace_size(int64_t m, int64_t n, const id_opts* opts) {
+  return mpid::batch_item_workspace(m, n, opts);
+}
+
+int id_factor_batched(id_batch_item* items, int32_t batch, const int32_t* order, int32_t* queue,
+                      int64_t max_n, int32_t dtype, const id_opts* opts, int32_t block_threads,
+                      int32_t num_groups, void* stream) {
+  return mpid::factor_batched_run(items, batch, order, queue, max_n, dtype, opts, block_threads,
+                                  num_groups, (hipStream_t)stream);
+}
+
 int id_last_profile(id_profile* out) {
   if (!out) return ID_ERR_ARG;
   mpid::last_profile(out);

@@ -1,0 +1,735 @@
+// Many column IDs of uneven sizes in one persistent launch.
+//
+// Each workgroup repeatedly takes the next matrix from a device work queue
+// (an atomic counter over a caller-given order, e.g. longest first) and runs
+// the whole rank-k column-pivoted Householder QR of that matrix by itself --
+// the same method as the single-matrix path (Section 1.1, eq. (6)-(7); the
+// MGSQR(A, k) step of Algorithms 1 and 2): row-major working copy, per pivot
+// the pivot-column update, reflector, one sweep of the stale trailing block,
+// new F column and R row, norm downdating; per panel the matrix-core update
+// W -= V F^T with compaction and FP64 norm recomputation.  Only workgroup
+// barriers are used; no workgroup ever waits for another, and every workgroup
+// exits once the queue is drained.  T = R11^{-1} R12 is solved afterwards by a
+// batched launch of the triangular-solve kernel.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+
+#include "device_util.h"
+#include "mpid_internal.h"
+
+namespace mpid {
+
+namespace {
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+template <typename S>
+struct BVec;
+template <>
+struct BVec<float> {
+  typedef float type __attribute__((ext_vector_type(4)));
+  static constexpr int n = 4;
+};
+template <>
+struct BVec<double> {
+  typedef double type __attribute__((ext_vector_type(2)));
+  static constexpr int n = 2;
+};
+
+enum { BOP_F64 = 0, BOP_F16 = 1, BOP_BF16 = 2, BOP_BF16X3 = 3 };
+
+}  // namespace
+
+struct BatchOpts {
+  int64_t k_fixed, k_max;
+  double rel_tol, tol3z;
+  int rule, nb;
+};
+
+struct BatchLayout {
+  int64_t kcap, ldw, ldv, ldf;
+  size_t off_w0, off_w1, off_v, off_f, off_nu, off_nuo, off_colid0, off_colid1, off_pvflag,
+      off_permw, off_posof, off_rorig, bytes;
+};
+
+__host__ __device__ inline int64_t batch_kcap(int64_t m, int64_t n, int64_t k_fixed,
+                                              int64_t k_max) {
+  int64_t kc = m < n ? m : n;
+  if (k_max > 0 && k_max < kc) kc = k_max;
+  if (k_fixed > 0 && k_fixed < kc) kc = k_fixed;
+  return kc;
+}
+
+__host__ __device__ inline BatchLayout batch_layout(int64_t m, int64_t n, int64_t kcap, int wb) {
+  BatchLayout L;
+  const int64_t mm = m > 0 ? m : 1, nn = n > 0 ? n : 1, kk = kcap > 0 ? kcap : 1;
+  L.kcap = kcap;
+  L.ldw = round_up(nn, 64);
+  L.ldv = round_up(mm, 64);
+  L.ldf = L.ldw;
+  size_t off = 0;
+#define MPID_TAKE(field, bytes_)              \
+  L.field = off;                              \
+  off += ((size_t)(bytes_) + 255) / 256 * 256;
+  MPID_TAKE(off_w0, (size_t)mm * L.ldw * wb);
+  MPID_TAKE(off_w1, (size_t)mm * L.ldw * wb);
+  MPID_TAKE(off_v, (size_t)kNbMax * L.ldv * wb);
+  MPID_TAKE(off_f, (size_t)kNbMax * L.ldf * 8);
+  MPID_TAKE(off_nu, (size_t)L.ldf * 8);
+  MPID_TAKE(off_nuo, (size_t)L.ldf * 8);
+  MPID_TAKE(off_colid0, (size_t)L.ldf * 4);
+  MPID_TAKE(off_colid1, (size_t)L.ldf * 4);
+  MPID_TAKE(off_pvflag, (size_t)L.ldf * 4);
+  MPID_TAKE(off_permw, (size_t)nn * 4);
+  MPID_TAKE(off_posof, (size_t)nn * 4);
+  MPID_TAKE(off_rorig, (size_t)kk * nn * 8);
+#undef MPID_TAKE
+  L.bytes = off;
+  return L;
+}
+
+template <int BT>
+struct BatchSmem {
+  union {
+    double red[BT * 4 + 128];  // sweep row-group partials, z-aux partials, wave maxima
+    double tile[64 * 65];      // ingest transpose tile (viewed as S)
+  };
+  double zc[kBatchMaxN];     // z(l) of the current step
+  double colss[BT / 64][64];
+  double g[kNbMax], aux[kNbMax], vj[kNbMax], vscale[kNbMax], zsum[kNbMax];
+  double dscr[BT / 64];
+  AmaxVal ascr[BT / 64];
+  int cidx[64];
+  int piv[kNbMax];
+  int item;
+  double alpha;
+  float fmax;
+};
+
+template <int BT>
+__device__ __forceinline__ double bsum(double v, double* scr) {
+  v = wave_sum(v);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  if (lane == 0) scr[wv] = v;
+  __syncthreads();
+  double t = 0.0;
+#pragma unroll
+  for (int q = 0; q < BT / 64; ++q) t += scr[q];
+  __syncthreads();
+  return t;
+}
+
+template <int BT>
+__device__ __forceinline__ AmaxVal bamax(AmaxVal a, AmaxVal* scr) {
+  a = wave_amax(a);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  if (lane == 0) scr[wv] = a;
+  __syncthreads();
+  AmaxVal r = scr[0];
+#pragma unroll
+  for (int q = 1; q < BT / 64; ++q) r = amax_combine(r, scr[q]);
+  __syncthreads();
+  return r;
+}
+
+// One matrix by one workgroup.  All branches on shared decisions are uniform.
+template <typename S, typename TA, int OP, int BT>
+__device__ void factor_one(id_batch_item& it, const BatchOpts& o, BatchSmem<BT>& sm) {
+  typedef typename BVec<S>::type VT;
+  constexpr int VEC = BVec<S>::n;
+  constexpr int NW = BT / 64;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int64_t m = it.m, n = it.n, lda = it.lda;
+  const int64_t kcap = batch_kcap(m, n, o.k_fixed, o.k_max);
+  const BatchLayout L = batch_layout(m, n, kcap, (int)sizeof(S));
+  char* wb = (char*)it.work;
+  S* W[2] = {(S*)(wb + L.off_w0), (S*)(wb + L.off_w1)};
+  S* V = (S*)(wb + L.off_v);
+  double* F = (double*)(wb + L.off_f);
+  double* nu = (double*)(wb + L.off_nu);
+  double* nuo = (double*)(wb + L.off_nuo);
+  int* colid[2] = {(int*)(wb + L.off_colid0), (int*)(wb + L.off_colid1)};
+  int* pvflag = (int*)(wb + L.off_pvflag);
+  int* permw = (int*)(wb + L.off_permw);
+  int* posof = (int*)(wb + L.off_posof);
+  double* rorig = (double*)(wb + L.off_rorig);
+  const int64_t ldw = L.ldw, ldv = L.ldv, ldf = L.ldf;
+  const TA* A = (const TA*)it.A;
+
+  for (int64_t l = tid; l < n; l += BT) {
+    colid[0][l] = (int)l;
+    pvflag[l] = 0;
+    permw[l] = (int)l;
+    posof[l] = (int)l;
+    it.perm[l] = (int)l;
+  }
+  if (tid == 0) {
+    it.k = 0;
+    it.info = 0;
+  }
+  if (m == 0 || n == 0 || kcap == 0) return;
+
+  // ---- ingest: W0 (row-major) and FP64 column norms, NaN/Inf check
+  double bad = 0.0;
+  {
+    S* tile = (S*)sm.tile;  // 64 x 65
+    for (int64_t c0 = 0; c0 < n; c0 += 64) {
+      double ss = 0.0;
+      for (int64_t r0 = 0; r0 < m; r0 += 64) {
+        for (int e = tid; e < 4096; e += BT) {
+          const int rr = e & 63, cc = e >> 6;
+          const int64_t r = r0 + rr, c = c0 + cc;
+          S v = (S)0;
+          if (r < m && c < n) {
+            const TA x = A[c * lda + r];
+            if (!isfinite((double)x)) bad = 1.0;
+            v = (S)x;
+          }
+          tile[cc * 65 + rr] = v;
+        }
+        __syncthreads();
+        for (int e = tid; e < 4096; e += BT) {
+          const int cc = e & 63, rr = e >> 6;  // cc == lane
+          const int64_t r = r0 + rr, c = c0 + cc;
+          if (r < m && c < n) {
+            const S v = tile[cc * 65 + rr];
+            W[0][r * ldw + c] = v;
+            ss += (double)v * (double)v;
+          }
+        }
+        __syncthreads();
+      }
+      sm.colss[wv][lane] = ss;
+      __syncthreads();
+      if (tid < 64 && c0 + tid < n) {
+        double t = 0.0;
+#pragma unroll
+        for (int q = 0; q < NW; ++q) t += sm.colss[q][tid];
+        nu[c0 + tid] = sqrt(t);
+        nuo[c0 + tid] = sqrt(t);
+      }
+      __syncthreads();
+    }
+  }
+  if (bsum<BT>(bad, sm.dscr) > 0.0) {
+    if (tid == 0) it.info = ID_INFO_NONFINITE;
+    return;
+  }
+
+  int64_t off = 0, ncur = n, kout = 0;
+  int cur = 0, jb = 0;
+  double r00 = 0.0, fro2 = 0.0;
+  for (;;) {
+    const int64_t j = off + jb;
+    S* Wc = W[cur];
+    int* cid = colid[cur];
+    // ---- 1. pivot and rank rule
+    AmaxVal best = amax_none();
+    for (int64_t l = tid; l < ncur; l += BT) {
+      if (!pvflag[l]) {
+        AmaxVal c;
+        c.v = nu[l];
+        c.s2 = c.v * c.v;
+        c.pos = (int)l;
+        c.key = posof[cid[l]];
+        best = amax_combine(best, c);
+      }
+    }
+    best = bamax<BT>(best, sm.ascr);
+    const int p = best.pos;
+    const double vp = best.v;
+    if (j == 0) fro2 = best.s2;
+    bool stop = (j >= kcap) || (jb >= ncur) || (p < 0);
+    if (!stop && o.k_fixed == 0) {
+      if (!(vp > 0.0))
+        stop = true;
+      else if (o.rule == ID_RANK_PIVOT_REL)
+        stop = j > 0 && vp <= o.rel_tol * r00;
+      else
+        stop = sqrt(best.s2) <= o.rel_tol * sqrt(fro2);
+    }
+    if (stop) {
+      kout = j;
+      break;
+    }
+    if (tid == 0) {
+      sm.piv[jb] = p;
+      pvflag[p] = 1;
+      const int q = cid[p];
+      const int pa = posof[q];
+      const int other = permw[j];
+      permw[pa] = other;
+      posof[other] = pa;
+      permw[j] = q;
+      posof[q] = (int)j;
+    }
+    if (tid < jb) sm.g[tid] = sm.vscale[tid] * F[(int64_t)tid * ldf + p];
+    __syncthreads();
+
+    // ---- 2. pivot column w = W(:,p) - V F(p,:)^T on rows i >= j, stored as reflector jb
+    double nn = 0.0;
+    for (int64_t i = j + tid; i < m; i += BT) {
+      double w = (double)Wc[i * ldw + p];
+      for (int cb = 0; cb < jb; cb += 8) {
+        S vr[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) vr[u] = cb + u < jb ? V[(int64_t)(cb + u) * ldv + i] : (S)0;
+#pragma unroll
+        for (int u = 0; u < 8; ++u) w -= (double)vr[u] * (cb + u < jb ? sm.g[cb + u] : 0.0);
+      }
+      V[(int64_t)jb * ldv + i] = (S)w;
+      if (i == j)
+        sm.alpha = w;
+      else
+        nn += w * w;
+    }
+    const double xnorm2 = bsum<BT>(nn, sm.dscr);  // barrier: column jb visible to the block
+    // sum_{i>j} V(i,c) w(i), thread = (column c, row group)
+    {
+      constexpr int RGZ = BT / kNbMax;
+      const int c = tid % kNbMax, rgz = tid / kNbMax;
+      double z = 0.0;
+      if (c < jb) {
+        const S* vc = V + (int64_t)c * ldv;
+        const S* wcol = V + (int64_t)jb * ldv;
+        for (int64_t i = j + 1 + rgz; i < m; i += RGZ) z += (double)vc[i] * (double)wcol[i];
+      }
+      sm.red[rgz * kNbMax + c] = z;
+      __syncthreads();
+      if (tid < jb) {
+        double t = 0.0;
+        for (int q = 0; q < RGZ; ++q) t += sm.red[q * kNbMax + tid];
+        sm.zsum[tid] = t;
+      }
+      __syncthreads();
+    }
+    // ---- 3. reflector (dlarfg conventions)
+    const double alpha = sm.alpha;
+    double beta, tau, scale;
+    if (xnorm2 == 0.0) {
+      beta = alpha;
+      tau = 0.0;
+      scale = 0.0;
+    } else {
+      const double h = hypot(alpha, sqrt(xnorm2));
+      beta = alpha >= 0.0 ? -h : h;
+      tau = (beta - alpha) / beta;
+      scale = 1.0 / (alpha - beta);
+    }
+    if (j == 0) r00 = fabs(beta);
+    if (tid < jb) {
+      const double vjc = sm.vscale[tid] * (double)V[(int64_t)tid * ldv + j];
+      sm.vj[tid] = vjc;
+      sm.aux[tid] = vjc + sm.vscale[tid] * scale * sm.zsum[tid];
+    }
+    // ---- 4. sweep z(l) = sum_{i>j} W(i,l) w(i) (w read back from reflector jb)
+    {
+      int tpr = 64;
+      while (tpr < BT && (int64_t)tpr * VEC < ncur) tpr *= 2;
+      const int RG = BT / tpr;
+      const int rg = tid / tpr, cv = tid % tpr;
+      const S* wcol = V + (int64_t)jb * ldv;
+      for (int64_t cb = 0; cb < ncur; cb += (int64_t)tpr * VEC) {
+        const int64_t l0 = cb + (int64_t)cv * VEC;
+        double acc[VEC];
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) acc[e] = 0.0;
+        if (l0 < ncur) {
+          const S* base = Wc + l0;
+          int64_t i = j + 1 + rg;
+          // U independent row loads in flight per thread (U * BT * VEC * s bytes
+          // per workgroup) to cover the memory latency of one compute unit
+          constexpr int U = BT >= 512 ? 8 : 16;
+          for (; i + (U - 1) * RG < m; i += U * RG) {
+            VT x[U];
+            double w[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) x[u] = *(const VT*)(base + (i + u * RG) * ldw);
+#pragma unroll
+            for (int u = 0; u < U; ++u) w[u] = (double)wcol[i + u * RG];
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+#pragma unroll
+              for (int e = 0; e < VEC; ++e) acc[e] += (double)x[u][e] * w[u];
+          }
+          for (; i < m; i += RG) {
+            const VT x0 = *(const VT*)(base + i * ldw);
+            const double w0 = (double)wcol[i];
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) acc[e] += (double)x0[e] * w0;
+          }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) sm.red[tid * VEC + e] = acc[e];
+        __syncthreads();
+        if (rg == 0 && l0 < ncur) {
+          for (int q = 1; q < RG; ++q)
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) acc[e] += sm.red[(q * tpr + cv) * VEC + e];
+#pragma unroll
+          for (int e = 0; e < VEC; ++e)
+            if (l0 + e < ncur) sm.zc[l0 + e] = acc[e];
+        }
+      }
+      __syncthreads();
+    }
+    // ---- 5. new F column, R row, downdated norms
+    double flag = 0.0;
+    float fm = 0.0f;
+    for (int64_t l = tid; l < ncur; l += BT) {
+      const double wj = (double)Wc[j * ldw + l];
+      const double y = wj + scale * sm.zc[l];
+      double s1 = 0.0, s2 = 0.0;
+      for (int c = 0; c < jb; ++c) {
+        const double fc = F[(int64_t)c * ldf + l];
+        s1 += fc * sm.aux[c];
+        s2 += sm.vj[c] * fc;
+      }
+      const double f = tau * (y - s1);
+      F[(int64_t)jb * ldf + l] = f;
+      if (!pvflag[l]) {
+        const double r = wj - s2 - f;
+        rorig[(int64_t)cid[l] * kcap + j] = r;
+        double nl = nu[l];
+        if (nl != 0.0) {
+          double t = fabs(r) / nl;
+          t = (1.0 + t) * (1.0 - t);
+          if (t < 0.0) t = 0.0;
+          const double ratio = nl / nuo[l];
+          if (t * ratio * ratio <= o.tol3z)
+            flag = 1.0;
+          else
+            nu[l] = nl * sqrt(t);
+        }
+        fm = fmaxf(fm, (float)fabs(f));
+      }
+    }
+    if (tid == 0) {
+      rorig[(int64_t)cid[p] * kcap + j] = beta;
+      sm.vscale[jb] = scale;
+    }
+    {
+      float x = fm;
+#pragma unroll
+      for (int offs = 32; offs > 0; offs >>= 1) x = fmaxf(x, __shfl_xor(x, offs, 64));
+      if (lane == 0) sm.red[wv] = (double)x;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      double x = jb == 0 ? 0.0 : (double)sm.fmax;
+      for (int q = 0; q < NW; ++q) x = fmax(x, sm.red[q]);
+      sm.fmax = (float)x;
+    }
+    const bool end_flag = bsum<BT>(flag, sm.dscr) > 0.0;  // also publishes fmax, F, vscale
+    ++jb;
+    if (j + 1 >= kcap) {
+      kout = j + 1;
+      break;
+    }
+    if (!(end_flag || jb >= o.nb)) continue;
+
+    // ---- 6. end of panel: W_next = W - V F^T on rows >= off + jb, compacted,
+    //         with the FP64 recomputation of every column norm
+    {
+      const int64_t jend = off + jb;
+      S* Wn = W[cur ^ 1];
+      int* cidn = colid[cur ^ 1];
+      const int g4 = lane >> 4, li = lane & 15;
+      int sF = 0, sV = 0;
+      if (OP == BOP_F16) {
+        int e = 0;
+        if (sm.fmax > 0.0f) frexpf(sm.fmax, &e);
+        sF = 15 - e;
+        sV = 14;
+      }
+      const double fscl = ldexp(1.0, sF);
+      const float vscl = ldexpf(1.0f, sV);
+      const double descale = ldexp(1.0, -(sF + sV));
+      for (int64_t l0 = 0; l0 < ncur; l0 += 64) {
+        if (tid < 64) {
+          const int64_t l = l0 + tid;
+          int before = 0;
+          bool pv = false;
+          for (int c = 0; c < jb; ++c) {
+            before += sm.piv[c] < l;
+            pv |= sm.piv[c] == l;
+          }
+          sm.cidx[tid] = (l < ncur && !pv) ? (int)(l - before) : -1;
+        }
+        // A operands (rows of F^T = positions l0 .. l0 + 63) staged in LDS in the
+        // lane order of the matrix-core instruction, so they cost no registers
+        for (int idx = tid; idx < 256; idx += BT) {
+          const int lb = idx >> 6, ln = idx & 63, lg = ln >> 4, ll = ln & 15;
+          if (OP == BOP_F64) {
+            const int64_t pos = l0 + 16 * lb + (4 * (ll % 4) + ll / 4);
+            double* fa = sm.tile + lb * 512 + ln;
+#pragma unroll
+            for (int s8 = 0; s8 < 8; ++s8) {
+              const int c = 4 * s8 + lg;
+              fa[s8 * 64] = (c < jb && pos < ncur) ? F[(int64_t)c * ldf + pos] : 0.0;
+            }
+          } else {
+            const int64_t pos = l0 + 16 * lb + ll;
+            f16x8 xh;
+            bf16x8 xb, xl;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+              const int c = 8 * lg + e;
+              const float x =
+                  (c < jb && pos < ncur) ? (float)(F[(int64_t)c * ldf + pos] * fscl) : 0.0f;
+              xh[e] = (_Float16)x;
+              const __bf16 h = (__bf16)x;
+              xb[e] = h;
+              xl[e] = (__bf16)(x - (float)h);
+            }
+            if (OP == BOP_F16) {
+              ((f16x8*)sm.tile)[idx] = xh;
+            } else {
+              ((bf16x8*)sm.tile)[idx] = xb;
+              ((bf16x8*)sm.tile)[256 + idx] = xl;
+            }
+          }
+        }
+        __syncthreads();
+        double ssl[4][4];
+#pragma unroll
+        for (int lb = 0; lb < 4; ++lb)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) ssl[lb][r] = 0.0;
+        for (int64_t rs = jend + 16 * wv; rs < m; rs += 16 * NW) {
+          const int64_t row = rs + li;
+          const bool rowok = row < m;
+          const S* wrow = Wc + (rowok ? row : jend) * ldw + l0 + 4 * g4;
+          if (OP == BOP_F64) {
+            double b64[8];
+#pragma unroll
+            for (int s8 = 0; s8 < 8; ++s8) {
+              const int c = 4 * s8 + g4;
+              b64[s8] = (c < jb && rowok) ? (double)V[(int64_t)c * ldv + row] * sm.vscale[c] : 0.0;
+            }
+#pragma unroll
+            for (int lb = 0; lb < 4; ++lb) {
+              S wv4[4];
+#pragma unroll
+              for (int r = 0; r < 4; ++r) wv4[r] = wrow[16 * lb + r];
+              const double* fa = sm.tile + lb * 512 + lane;
+              f64x4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+              for (int s8 = 0; s8 < 8; ++s8)
+                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[s8 * 64], b64[s8], acc, 0, 0, 0);
+              if (rowok) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                  const int ci = sm.cidx[16 * lb + 4 * g4 + r];
+                  if (ci >= 0) {
+                    const S v = (S)((double)wv4[r] - acc[r]);
+                    Wn[row * ldw + ci] = v;
+                    ssl[lb][r] += (double)v * (double)v;
+                  }
+                }
+              }
+            }
+          } else {
+            f16x8 bh;
+            bf16x8 bb, bbl;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+              const int c = 8 * g4 + e;
+              const float x =
+                  (c < jb && rowok) ? (float)((double)V[(int64_t)c * ldv + row] * sm.vscale[c]) * vscl
+                                    : 0.0f;
+              if (OP == BOP_F16) {
+                bh[e] = (_Float16)x;
+              } else {
+                const __bf16 h = (__bf16)x;
+                bb[e] = h;
+                if (OP == BOP_BF16X3) bbl[e] = (__bf16)(x - (float)h);
+              }
+            }
+#pragma unroll
+            for (int lb = 0; lb < 4; ++lb) {
+              S wv4[4];
+#pragma unroll
+              for (int r = 0; r < 4; ++r) wv4[r] = wrow[16 * lb + r];
+              f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+              if (OP == BOP_F16) {
+                acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(((const f16x8*)sm.tile)[lb * 64 + lane],
+                                                            bh, acc, 0, 0, 0);
+              } else if (OP == BOP_BF16) {
+                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                    ((const bf16x8*)sm.tile)[lb * 64 + lane], bb, acc, 0, 0, 0);
+              } else {
+                const bf16x8 ahi = ((const bf16x8*)sm.tile)[lb * 64 + lane];
+                const bf16x8 alo = ((const bf16x8*)sm.tile)[256 + lb * 64 + lane];
+                // small terms first, then the leading product
+                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(alo, bb, acc, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi, bbl, acc, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi, bb, acc, 0, 0, 0);
+              }
+              if (rowok) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                  const int ci = sm.cidx[16 * lb + 4 * g4 + r];
+                  if (ci >= 0) {
+                    const S v = (S)((double)wv4[r] - (double)acc[r] * descale);
+                    Wn[row * ldw + ci] = v;
+                    ssl[lb][r] += (double)v * (double)v;
+                  }
+                }
+              }
+            }
+          }
+        }
+        // column sums of squares: over the 16 rows of a lane group, then the waves
+#pragma unroll
+        for (int lb = 0; lb < 4; ++lb)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            double x = ssl[lb][r];
+            x += __shfl_xor(x, 1, 64);
+            x += __shfl_xor(x, 2, 64);
+            x += __shfl_xor(x, 4, 64);
+            x += __shfl_xor(x, 8, 64);
+            if (li == 0) sm.colss[wv][16 * lb + 4 * g4 + r] = x;
+          }
+        __syncthreads();
+        if (tid < 64 && sm.cidx[tid] >= 0) {
+          double t = 0.0;
+#pragma unroll
+          for (int q = 0; q < NW; ++q) t += sm.colss[q][tid];
+          const int np = sm.cidx[tid];
+          nu[np] = sqrt(t);
+          nuo[np] = sqrt(t);
+          pvflag[np] = 0;
+          cidn[np] = cid[l0 + tid];
+        }
+        __syncthreads();
+      }
+    }
+    off += jb;
+    ncur -= jb;
+    cur ^= 1;
+    jb = 0;
+  }
+
+  // ---- outputs: k, perm (swap order), R in pivot order; R11 checked for
+  //      numerical singularity (T is then left unwritten)
+  const int64_t k = kout;
+  for (int64_t l = tid; l < n; l += BT) it.perm[l] = permw[l];
+  for (int64_t e = tid; e < k * n; e += BT) {
+    const int64_t c = e / k, i = e % k;
+    const int id = permw[c];
+    it.R[c * it.ldr + i] = (c >= k || i <= c) ? rorig[(int64_t)id * kcap + i] : 0.0;
+  }
+  __syncthreads();
+  double sing = 0.0;
+  if (k > 0) {
+    const double d0 = fabs(it.R[0]);
+    const double thr = (double)n * ldexp(1.0, -53) * d0;
+    for (int64_t i = tid; i < k; i += BT)
+      if (!(fabs(it.R[i * it.ldr + i]) > thr)) sing = 1.0;
+  }
+  sing = bsum<BT>(sing, sm.dscr);
+  if (tid == 0) {
+    it.k = k;
+    it.info = sing > 0.0 ? ID_INFO_SINGULAR : (k == n ? ID_INFO_RANK_FULL : 0);
+  }
+}
+
+__global__ void k_queue_reset(int32_t* queue) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *queue = 0;
+}
+
+template <typename S, typename TA, int OP, int BT>
+__global__ __launch_bounds__(BT) void k_batched_factor(id_batch_item* items, int32_t batch,
+                                                       const int32_t* order, int32_t* queue,
+                                                       BatchOpts o) {
+  __shared__ BatchSmem<BT> sm;
+  for (;;) {
+    if (threadIdx.x == 0) sm.item = atomicAdd(queue, 1);
+    __syncthreads();
+    const int q = sm.item;
+    __syncthreads();
+    if (q >= batch) return;  // the queue is drained: every workgroup leaves
+    const int it = order ? order[q] : q;
+    factor_one<S, TA, OP, BT>(items[it], o, sm);
+    __syncthreads();
+  }
+}
+
+size_t batch_item_workspace(int64_t m, int64_t n, const id_opts* o) {
+  if (!o || m < 0 || n < 0 || n > kBatchMaxN) return 0;
+  if (o->prec < ID_PREC_F64 || o->prec > ID_PREC_MIXED_BF16X3) return 0;
+  const int wb = o->prec == ID_PREC_F64 ? 8 : 4;
+  return batch_layout(m, n, batch_kcap(m, n, o->k_fixed, o->k_max), wb).bytes;
+}
+
+template <typename S, typename TA, int OP>
+static int launch_batched(id_batch_item* items, int32_t batch, const int32_t* order,
+                          int32_t* queue, const BatchOpts& bo, int bt, int groups, hipStream_t s) {
+  const dim3 grid((unsigned)groups);
+  if (bt == 256)
+    k_batched_factor<S, TA, OP, 256><<<grid, 256, 0, s>>>(items, batch, order, queue, bo);
+  else
+    k_batched_factor<S, TA, OP, 512><<<grid, 512, 0, s>>>(items, batch, order, queue, bo);
+  MPID_LAUNCH_CHECK();
+  return ID_OK;
+}
+
+int factor_batched_run(id_batch_item* items, int32_t batch, const int32_t* order, int32_t* queue,
+                       int64_t max_n, int32_t dtype, const id_opts* o, int32_t block_threads,
+                       int32_t num_groups, hipStream_t s) {
+  if (!o || !items || !queue || batch < 0) return ID_ERR_ARG;
+  if (dtype != ID_F32 && dtype != ID_F64) return ID_ERR_DTYPE;
+  if (o->prec < ID_PREC_F64 || o->prec > ID_PREC_MIXED_BF16X3) return ID_ERR_DTYPE;
+  if (o->flags != 0 || o->k_fixed < 0 || o->k_max < 0 || !(o->rel_tol >= 0.0)) return ID_ERR_ARG;
+  if (o->rank_rule != ID_RANK_PIVOT_REL && o->rank_rule != ID_RANK_FROB_REL) return ID_ERR_ARG;
+  const int nb = o->nb == 0 ? kNbMax : o->nb;
+  if (nb < 1 || nb > kNbMax) return ID_ERR_ARG;
+  if (max_n < 0 || max_n > kBatchMaxN) return ID_ERR_UNSUPPORTED;
+  const int bt = block_threads == 0 ? 256 : block_threads;
+  if (bt != 256 && bt != 512) return ID_ERR_ARG;
+  if (batch == 0) return ID_OK;
+  int groups = num_groups;
+  if (groups <= 0) {
+    int dev = 0, cus = 0;
+    MPID_HIP(hipGetDevice(&dev));
+    MPID_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    groups = cus > 0 ? cus : 256;
+  }
+  if (groups > batch) groups = batch;
+  BatchOpts bo;
+  bo.k_fixed = o->k_fixed;
+  bo.k_max = o->k_max;
+  bo.rel_tol = o->rel_tol;
+  bo.rule = o->rank_rule;
+  bo.nb = nb;
+  const bool f64w = o->prec == ID_PREC_F64;
+  bo.tol3z = std::sqrt(f64w ? std::ldexp(1.0, -53) : std::ldexp(1.0, -24));
+  k_queue_reset<<<1, 64, 0, s>>>(queue);
+  MPID_LAUNCH_CHECK();
+  int rc;
+  if (f64w) {
+    rc = dtype == ID_F64 ? launch_batched<double, double, BOP_F64>(items, batch, order, queue, bo, bt, groups, s)
+                         : launch_batched<double, float, BOP_F64>(items, batch, order, queue, bo, bt, groups, s);
+  } else if (o->prec == ID_PREC_MIXED_F16) {
+    rc = dtype == ID_F64 ? launch_batched<float, double, BOP_F16>(items, batch, order, queue, bo, bt, groups, s)
+                         : launch_batched<float, float, BOP_F16>(items, batch, order, queue, bo, bt, groups, s);
+  } else if (o->prec == ID_PREC_MIXED_BF16) {
+    rc = dtype == ID_F64 ? launch_batched<float, double, BOP_BF16>(items, batch, order, queue, bo, bt, groups, s)
+                         : launch_batched<float, float, BOP_BF16>(items, batch, order, queue, bo, bt, groups, s);
+  } else {
+    rc = dtype == ID_F64 ? launch_batched<float, double, BOP_BF16X3>(items, batch, order, queue, bo, bt, groups, s)
+                         : launch_batched<float, float, BOP_BF16X3>(items, batch, order, queue, bo, bt, groups, s);
+  }
+  if (rc) return rc;
+  return trsm_batched_run(items, batch, max_n, s);
+}
+
+}  // namespace mpid

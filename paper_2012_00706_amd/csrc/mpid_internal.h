@@ -19,6 +19,7 @@ constexpr int kColTileG = 64;   // column tile of the blocked update
 constexpr int kFinCols = 32;    // columns per block of the norm reduction
 constexpr int kFC = 16;         // columns per block of the step finalization
 constexpr int kFL = kThreads / kFC;  // its tile lanes
+constexpr int kBatchMaxN = 2048;  // widest matrix of the batched path
 
 // Device-resident control block of one factorization.  Every field is written
 // by exactly one kind of kernel and read only by later kernels on the stream.
@@ -83,6 +84,13 @@ int gemm64_run(int ta, int tb, int64_t M, int64_t N, int64_t K, double alpha, co
 int reconstruct_run(const void* A, int32_t dtype, int64_t m, int64_t n, int64_t lda,
                     const int32_t* perm, int64_t k, const double* T, int64_t ldt, double* Y,
                     int64_t ldy, int32_t residual, hipStream_t s);
+
+size_t batch_item_workspace(int64_t m, int64_t n, const id_opts* o);
+int factor_batched_run(id_batch_item* items, int32_t batch, const int32_t* order, int32_t* queue,
+                       int64_t max_n, int32_t dtype, const id_opts* o, int32_t block_threads,
+                       int32_t num_groups, hipStream_t s);
+// T of every item (after the batched factorization, same stream).
+int trsm_batched_run(const id_batch_item* items, int32_t batch, int64_t max_n, hipStream_t s);
 
 size_t backward_workspace(int64_t m, int64_t n, int64_t k);
 int backward_run(const void* A, int32_t dtype, int64_t m, int64_t n, int64_t lda,

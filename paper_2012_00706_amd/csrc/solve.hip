@@ -26,22 +26,17 @@ constexpr int kTC = 16;  // right-hand-side columns per block
 // matrix cores (wave w owns rows 16w..16w+15), then op(R)(I, I) As = rhs is
 // solved with each wave owning four columns -- the 64 dependent steps run
 // inside one wavefront, without block barriers.
-__global__ __launch_bounds__(kThreads) void k_trsm_upper(const double* __restrict__ R, int64_t ldr,
-                                                        int64_t k, const double* B, int64_t ldb,
-                                                        int64_t ncols, double* X, int64_t ldx,
-                                                        int trans, const int32_t* info) {
+// Columns c0 .. c0 + kTC - 1 of the solve, by one 256-thread block.
+__device__ __forceinline__ void trsm_block(const double* __restrict__ R, int64_t ldr, int64_t k,
+                                           const double* B, int64_t ldb, int64_t ncols, double* X,
+                                           int64_t ldx, int trans, int64_t c0) {
   __shared__ double Rs[kTB][kTB + 1];
   __shared__ double Xs[kTB][kTC + 1];
   __shared__ double As[kTB][kTC + 1];
   __shared__ double rinv[kTB];
-  __shared__ int s_go;
   const int tid = threadIdx.x;
-  if (tid == 0) s_go = !(info && *info == ID_INFO_SINGULAR);
-  __syncthreads();
-  if (!s_go) return;
   const int lane = tid & 63, wv = tid >> 6, g = lane >> 4, li = lane & 15;
   const int la = tid % kTB, lb = tid / kTB;  // load mapping, rows fastest
-  const int64_t c0 = (int64_t)blockIdx.x * kTC;
   const int64_t nblk = ceil_div(k, kTB);
   auto load_R_tile = [&](int64_t i0, int64_t l0) {
     // Rs[ii][ll] = op(R)(i0 + ii, l0 + ll)
@@ -121,6 +116,28 @@ __global__ __launch_bounds__(kThreads) void k_trsm_upper(const double* __restric
   }
 }
 
+__global__ __launch_bounds__(kThreads) void k_trsm_upper(const double* __restrict__ R, int64_t ldr,
+                                                        int64_t k, const double* B, int64_t ldb,
+                                                        int64_t ncols, double* X, int64_t ldx,
+                                                        int trans, const int32_t* info) {
+  __shared__ int s_go;
+  if (threadIdx.x == 0) s_go = !(info && *info == ID_INFO_SINGULAR);
+  __syncthreads();
+  if (!s_go) return;
+  trsm_block(R, ldr, k, B, ldb, ncols, X, ldx, trans, (int64_t)blockIdx.x * kTC);
+}
+
+// T = R11^{-1} R12 of every item of a batch: blockIdx.x = item, blockIdx.y =
+// column block.  Items whose factorization failed or found R11 singular, and
+// column blocks beyond an item's n - k, leave at once.
+__global__ __launch_bounds__(kThreads) void k_trsm_batched(const id_batch_item* __restrict__ items) {
+  const id_batch_item& it = items[blockIdx.x];
+  const int64_t k = it.k, n = it.n;
+  const int64_t c0 = (int64_t)blockIdx.y * kTC;
+  if (it.info == ID_INFO_SINGULAR || it.info == ID_INFO_NONFINITE || k <= 0 || c0 >= n - k) return;
+  trsm_block(it.R, it.ldr, k, it.R + k * it.ldr, it.ldr, n - k, it.T, it.ldt, 0, c0);
+}
+
 // info = ID_INFO_SINGULAR when some |R_ii| <= n * 2^-53 * |R_00| (or R_00 = 0),
 // ID_INFO_RANK_FULL when k == n, else 0.
 __global__ __launch_bounds__(kThreads) void k_check_diag(const double* __restrict__ R, int64_t ldr,
@@ -146,6 +163,13 @@ int trsm_upper_run(const double* R, int64_t ldr, int64_t k, const double* B, int
   if (k <= 0 || ncols <= 0) return ID_OK;
   k_trsm_upper<<<dim3((unsigned)ceil_div(ncols, kTC)), kThreads, 0, s>>>(R, ldr, k, B, ldb, ncols,
                                                                          X, ldx, trans, nullptr);
+  MPID_LAUNCH_CHECK();
+  return ID_OK;
+}
+
+int trsm_batched_run(const id_batch_item* items, int32_t batch, int64_t max_n, hipStream_t s) {
+  if (batch <= 0 || max_n <= 0) return ID_OK;
+  k_trsm_batched<<<dim3((unsigned)batch, (unsigned)ceil_div(max_n, kTC)), kThreads, 0, s>>>(items);
   MPID_LAUNCH_CHECK();
   return ID_OK;
 }

@@ -1,0 +1,266 @@
+"""The batched path (id_factor_batched through the C ABI): every item against
+the oracle, graph capture and replay against eager runs, launch-shape and
+order independence, per-item error reporting, and the full-size batched
+workload checked through properties that hold at any size."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as orc
+import synth
+from gpu_helpers import host, need_gpu, rel_err, row_sign_align, to_dev
+
+pytestmark = pytest.mark.gpu
+
+# shapes spanning the kernel's tiles: several 64-column tiles with ragged
+# tails, rows below and above the workgroup's row groups, wide, tiny, n = 1
+SHAPES = [(300, 150), (1000, 257), (65, 64), (129, 33), (40, 90), (2100, 100), (1, 1), (9, 1),
+          (1, 7), (513, 200)]
+
+
+def _inputs(shapes, dtype=np.float64, decay=12.0, seed0=300):
+    out = []
+    for i, (m, n) in enumerate(shapes):
+        r = min(m, n)
+        A = synth.spectrum_matrix(m, n, synth.sigma_geom10(r, decay), seed0 + 2 * i, seed0 + 2 * i + 1)
+        out.append(A.astype(dtype))
+    return out
+
+
+def _check_item_f64(A, res, k_req=None, tol=None, rule="pivot_rel"):
+    m, n = A.shape
+    if k_req is not None:
+        ref = orc.cpqr(A, k=min(k_req, m, n))
+    else:
+        ref = orc.cpqr(A, tol=tol, rule=rule)
+    assert res.k == ref.k
+    k = ref.k
+    perm = host(res.perm).astype(np.int64)
+    assert sorted(perm.tolist()) == list(range(n))
+    upto = int(np.argmax(ref.margins < 1e-8)) if np.any(ref.margins < 1e-8) else k
+    assert perm[:upto].tolist() == ref.perm[:upto].tolist()
+    if upto < k or k == 0:
+        return
+    R = host(res.R)
+    np.testing.assert_allclose(row_sign_align(R, ref.R), ref.R, rtol=0,
+                               atol=1e-12 * max(np.abs(ref.R).max(), 1e-300))
+    if res.info == 0 and k < n:
+        Tref = orc.solve_T(ref.R, k)
+        kappa = np.linalg.cond(ref.R[:, :k])
+        assert rel_err(host(res.T), Tref) <= 1e-14 * max(kappa, 1.0) * 100
+
+
+@pytest.mark.parametrize("block_threads", [256, 512])
+def test_batched_fixed_rank_matches_oracle(block_threads):
+    need_gpu()
+    import paper_2012_00706_amd as mp
+    As = _inputs(SHAPES)
+    res = mp.factor_batched([to_dev(A) for A in As], k=40, prec="f64", block_threads=block_threads)
+    for A, r in zip(As, res):
+        _check_item_f64(A, r, k_req=40)
+
+
+@pytest.mark.parametrize("rule", ["pivot_rel", "frob_rel"])
+def test_batched_adaptive_rank_matches_oracle(rule):
+    need_gpu()
+    import paper_2012_00706_amd as mp
+    shapes = [(800, 200), (450, 130), (1200, 96), (333, 300)]
+    As = [synth.spectrum_matrix(m, n, synth.sigma_exp(min(m, n), 10.0), 41 + i, 42 + i)
+          for i, (m, n) in enumerate(shapes)]
+    res = mp.factor_batched([to_dev(A) for A in As], tol=1e-3, rule=rule, prec="f64")
+    for A, r in zip(As, res):
+        _check_item_f64(A, r, tol=1e-3, rule=rule)
+
+
+@pytest.mark.parametrize("nb", [1, 7, 32])
+def test_batched_panel_width(nb):
+    need_gpu()
+    import paper_2012_00706_amd as mp
+    As = _inputs([(500, 120), (700, 64), (260, 200)], decay=15.0, seed0=500)
+    res = mp.factor_batched([to_dev(A) for A in As], k=45, prec="f64", nb=nb)
+    for A, r in zip(As, res):
+        _check_item_f64(A, r, k_req=45)
+
+
+def test_batched_f32_storage_f64_path():
+    need_gpu()
+    import paper_2012_00706_amd as mp
+    As = _inputs([(700, 130), (300, 80)], dtype=np.float32, decay=10.0, seed0=700)
+    res = mp.factor_batched([to_dev(A) for A in As], k=33, prec="f64")
+    for A, r in zip(As, res):
+        _check_item_f64(A.astype(np.float64), r, k_req=33)
+
+
+@pytest.mark.parametrize("prec,u_low", [("mixed_bf16x3", orc.U_BF16), ("mixed_bf16", orc.U_BF16),
+                                        ("mixed_f16", orc.U_HALF)])
+def test_batched_mixed_acceptance(prec, u_low):
+    """Mixed precision is accepted on error: at the rank it chose, each item's
+    spectral error is within 1.1x the oracle's at the same rank plus
+    10 u_low ||A||_2."""
+    need_gpu()
+    import paper_2012_00706_amd as mp
+    shapes = [(3000, 400), (1500, 250), (800, 600), (2000, 97)]
+    As, norms = [], []
+    for i, (m, n) in enumerate(shapes):
+        s = synth.sigma_exp(min(m, n), 40.0)
+        As.append(synth.spectrum_matrix(m, n, s, 51 + 2 * i, 52 + 2 * i).astype(np.float32))
+        norms.append(s[0])
+    res = mp.factor_batched([to_dev(A) for A in As], tol=1e-3, prec=prec)
+    for A, r, nrm in zip(As, res, norms):
+        assert r.k > 0 and r.info in (0, mp.C["ID_INFO_RANK_FULL"])
+        perm = host(r.perm).astype(np.int64)
+        e = orc.id_error(A, perm, r.k, host(r.T))[0]
+        ref = orc.cpqr(A, k=r.k)
+        e_ref = orc.id_error(A, ref.perm, r.k, orc.solve_T(ref.R, r.k))[0]
+        assert e <= 1.1 * e_ref + 10 * u_low * nrm
+
+
+def test_batched_matches_single_path():
+    """FP64: the batched kernel and the multi-kernel path give the same rank,
+    pivots and (to rounding) R on gap-separated inputs."""
+    need_gpu()
+    import paper_2012_00706_amd as mp
+    As = _inputs([(1000, 257), (2100, 100), (300, 150)], seed0=900)
+    res = mp.factor_batched([to_dev(A) for A in As], k=60, prec="f64")
+    for A, r in zip(As, res):
+        fr = mp.factor(to_dev(A), k=60, prec="f64")
+        kk = fr.k
+        assert r.k == kk
+        ref = orc.cpqr(A, k=kk)
+        upto = int(np.argmax(ref.margins < 1e-8)) if np.any(ref.margins < 1e-8) else kk
+        assert host(r.perm)[:upto].tolist() == host(fr.perm)[:upto].tolist()
+        if upto == kk:
+            Rs = host(fr.R)
+            np.testing.assert_allclose(row_sign_align(host(r.R), Rs), Rs, rtol=0,
+                                       atol=1e-12 * np.abs(Rs).max())
+
+
+@pytest.mark.parametrize("bt", [256, 512])
+def test_batched_order_and_group_count_do_not_change_results(bt):
+    """For a given workgroup size the result of an item is bitwise the same
+    whichever workgroup takes it and in whatever order (a different workgroup
+    size changes the reduction order, so only parity with the oracle holds
+    across sizes)."""
+    need_gpu()
+    import paper_2012_00706_amd as mp
+    As = [to_dev(A) for A in _inputs(SHAPES, dtype=np.float32, seed0=1100)]
+    outs = []
+    for order, groups in [("lpt", 0), (None, 3), (list(range(len(As)))[::-1], 1)]:
+        plan = mp.BatchedID(As, tol=1e-3, prec="mixed_bf16x3", order=order, block_threads=bt,
+                            num_groups=groups)
+        plan.run()
+        outs.append([(r.k, host(r.perm).copy(), host(r.R).copy(), host(r.T).copy())
+                     for r in plan.results()])
+    for other in outs[1:]:
+        for a, b in zip(outs[0], other):
+            assert a[0] == b[0]
+            assert np.array_equal(a[1], b[1])
+            assert np.array_equal(a[2], b[2]) and np.array_equal(a[3], b[3])
+
+
+def test_batched_graph_replay_equals_eager():
+    """A captured run replays to the eager result, also after new data is
+    copied into the bound inputs, with unrelated eager work in between."""
+    need_gpu()
+    import paper_2012_00706_amd as mp
+    shapes = [(700, 130), (300, 150), (1000, 64)]
+    A1 = [to_dev(A) for A in _inputs(shapes, dtype=np.float32, seed0=1300)]
+    A2 = [to_dev(A) for A in _inputs(shapes, dtype=np.float32, decay=8.0, seed0=1400)]
+
+    def snapshot(results):
+        return [(r.k, r.info, host(r.perm).copy(), host(r.R).copy(), host(r.T).copy())
+                for r in results]
+
+    eager = {}
+    for tag, As in (("a", A1), ("b", A2)):
+        p = mp.BatchedID(As, tol=1e-4, prec="mixed_bf16x3")
+        p.run()
+        eager[tag] = snapshot(p.results())
+    plan = mp.BatchedID([A.clone() for A in A1], tol=1e-4, prec="mixed_bf16x3")
+    g = plan.capture()
+    junk = torch.randn(512, 512, device="cuda")
+    for rep, tag in enumerate(["a", "a", "b", "a", "b"]):
+        src = A1 if tag == "a" else A2
+        for dst, s in zip(plan.inputs, src):
+            dst.copy_(s)
+        plan.R_buf.fill_(float("nan"))
+        plan.T_buf.fill_(float("nan"))
+        g.replay()
+        junk = junk @ junk.t() / 512.0  # eager work between replays
+        got = snapshot(plan.results())
+        for a, b in zip(got, eager[tag]):
+            assert a[0] == b[0] and a[1] == b[1], rep
+            assert np.array_equal(a[2], b[2]), rep
+            assert np.array_equal(a[3], b[3]) and np.array_equal(a[4], b[4]), rep
+
+
+def test_batched_item_conditions():
+    """NaN in one item, an all-zero item, a full-rank item and a numerically
+    singular fixed-rank item each get their own info; the others are unaffected."""
+    need_gpu()
+    import paper_2012_00706_amd as mp
+    C = mp.C
+    good = synth.spectrum_matrix(200, 60, synth.sigma_geom10(60, 12.0), 1, 2)
+    bad = synth.gaussian(80, 20, seed=3)
+    bad[5, 7] = np.inf
+    zero = np.zeros((50, 20))
+    res = mp.factor_batched([to_dev(x) for x in (good, bad, zero)], tol=1e-3, prec="f64")
+    _check_item_f64(good, res[0], tol=1e-3)
+    assert res[1].info == C["ID_INFO_NONFINITE"] and res[1].k == 0
+    assert res[2].k == 0 and res[2].info == 0
+    full = synth.gaussian(40, 12, seed=2)
+    low = synth.low_rank(60, 20, 4, seed=3)
+    res = mp.factor_batched([to_dev(full), to_dev(low)], k=8, prec="f64")
+    assert res[0].k == 8 and res[0].info == 0
+    assert res[1].k == 8 and res[1].info == C["ID_INFO_SINGULAR"]
+    res = mp.factor_batched([to_dev(full)], tol=1e-14, prec="f64")
+    assert res[0].k == 12 and res[0].info == C["ID_INFO_RANK_FULL"] and res[0].T.shape == (12, 0)
+
+
+def test_batched_rejects_wide_items():
+    need_gpu()
+    import paper_2012_00706_amd as mp
+    with pytest.raises(ValueError):
+        mp.BatchedID([torch.zeros((10, 2049), device="cuda").t().contiguous().t()], k=3)
+
+
+def test_batched_workload_full_size_properties():
+    """Sixteen members of the batched workload (m up to 20000, n up to 800,
+    sigma_j = j^-2, fp32, tol 1e-4, mixed BF16x3) at full size, checked through
+    properties that hold at any size: the rank rule at the chosen k (from the
+    FP64 residual A - A_J T) and pivot dominance of R; the three smallest
+    members against the oracle's error at the same k."""
+    need_gpu()
+    import paper_2012_00706_amd as mp
+    mats = synth.config4(batch=16)
+    As = [to_dev(A) for A in mats]
+    tol = 1e-4
+    plan = mp.BatchedID(As, tol=tol, prec="mixed_bf16x3")
+    plan.run()
+    res = plan.results()
+    for A, r, Ah in zip(As, res, mats):
+        m, n = A.shape
+        k = r.k
+        assert 0 < k <= min(m, n)
+        R = r.R
+        d = R.diagonal()[:k].abs() if k else R.new_zeros(0)
+        r00 = float(d[0])
+        # rank rule: the last kept pivot is above tol |R00|; the residual's
+        # largest column (the next pivot) is at or below it
+        if k < n:
+            assert float(d[-1]) > tol * r00 * (1 - 1e-2)
+            E = mp.reconstruct(A, r.perm, k, r.T, residual=True)
+            assert float(E.norm(dim=0).max()) <= tol * r00 * (1 + 1e-2)
+        # pivot dominance (to the accuracy of the FP32 working copy)
+        Rh = host(R)
+        for j in range(0, k, max(1, k // 16)):
+            tail = np.sqrt((Rh[j:, j + 1:] ** 2).sum(axis=0))
+            assert np.all(abs(Rh[j, j]) >= tail * (1 - 1e-2) - 1e-6)
+    # the three smallest members against the oracle's error at the same k
+    for i in np.argsort([a.shape[0] * a.shape[1] for a in mats])[:3]:
+        A, r = mats[i], res[i]
+        perm = host(r.perm).astype(np.int64)
+        e = orc.id_error(A, perm, r.k, host(r.T))[0]
+        ref = orc.cpqr(A, k=r.k)
+        e_ref = orc.id_error(A, ref.perm, r.k, orc.solve_T(ref.R, r.k))[0]
+        assert e <= 1.1 * e_ref + 10 * orc.U_BF16 * 1.0  # sigma_1 = 1
