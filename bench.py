@@ -183,7 +183,7 @@ def summarize_pmc(fetch_csv, write_csv):
     def sweep_live(d):
         vals = [v for (did, name), v in d.items() if "k_sweep" in name]
         big = max(vals) if vals else 0.0
-        return [v for v in vals if v > 0.05 * big]  # launches that did work
+        return [v for v in vals if v > 0.2 * big]  # launches that did work
 
     def copy_kib(d):
         vals = [v for (did, name), v in d.items()
@@ -203,6 +203,29 @@ def summarize_pmc(fetch_csv, write_csv):
     with open(TRAFFIC_JSON, "w") as fh:
         json.dump(res, fh, indent=1)
     print(json.dumps(res))
+
+
+def summarize_trace(trace_csv):
+    """Per-kernel launch statistics from a rocprofv3 --kernel-trace CSV; for
+    k_sweep also the average over the launches that did work (a launch
+    enqueued after the rank was reached returns at once)."""
+    import csv
+    by = {}
+    with open(trace_csv) as fh:
+        for row in csv.DictReader(fh):
+            name = row["Kernel_Name"].split("(")[0]
+            d = int(row["End_Timestamp"]) - int(row["Start_Timestamp"])
+            by.setdefault(name, []).append(d)
+    lines = [f"{'kernel':<28}{'calls':>8}{'total_ms':>12}{'avg_us':>10}{'min_us':>10}{'max_us':>10}"]
+    for name, ds in sorted(by.items(), key=lambda kv: -sum(kv[1])):
+        lines.append(f"{name[:27]:<28}{len(ds):>8}{sum(ds) / 1e6:>12.3f}{sum(ds) / len(ds) / 1e3:>10.2f}"
+                     f"{min(ds) / 1e3:>10.2f}{max(ds) / 1e3:>10.2f}")
+    sw = by.get("k_sweep", [])
+    if sw:
+        live = [d for d in sw if d > 0.3 * max(sw)]
+        lines.append(f"k_sweep live launches: {len(live)} of {len(sw)}, "
+                     f"average {sum(live) / len(live) / 1e3:.2f} us")
+    print("\n".join(lines))
 
 
 def measured_traffic():
@@ -238,11 +261,16 @@ def main():
                     help="time only the headline precision (no FP64 comparison, no errors)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain 256 MiB device copy (HBM counter calibration)")
+    ap.add_argument("--summarize-trace", metavar="KERNEL_TRACE_CSV",
+                    help="per-kernel statistics of a rocprofv3 --kernel-trace CSV")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="turn two rocprofv3 --pmc counter files into the sweep traffic summary")
     args = ap.parse_args()
     if args.summarize_pmc:
         summarize_pmc(*args.summarize_pmc)
+        return
+    if args.summarize_trace:
+        summarize_trace(args.summarize_trace)
         return
     args.profile_reps = max(args.profile_reps, 1)
 
