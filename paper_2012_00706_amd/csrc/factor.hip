@@ -56,6 +56,7 @@ struct Vec16<double> {
 enum { OP_F64 = 0, OP_F16 = 1, OP_BF16 = 2, OP_BF16X3 = 3 };
 
 constexpr int kPrefetch = 4;  // sweep rows per thread loaded ahead of the pivot search
+constexpr int kSweepU = 4;    // sweep rows per thread in flight in the main loop
 
 // ----------------------------------------------------------------- plan
 
@@ -82,9 +83,13 @@ bool make_factor_plan(int64_t m, int64_t n, int32_t dtype, const id_opts* o, Fac
   p->nb = nb;
   p->wbytes = o->prec == ID_PREC_F64 ? 8 : 4;
   const int64_t mm = m > 0 ? m : 1, nn = n > 0 ? n : 1, kk = kcap > 0 ? kcap : 1;
+  // rows of the working copy an odd multiple of 256 bytes apart, so that
+  // consecutive rows start in different memory channels
+  const int64_t q256 = 256 / p->wbytes;
   p->ldw = round_up(nn, 64);
+  if ((p->ldw / q256) % 2 == 0) p->ldw += q256;
   p->ldv = round_up(mm, 64);
-  p->ldf = p->ldw;
+  p->ldf = round_up(nn, 64);
   p->ntile_s_max = ceil_div(mm, kRtMin);
   p->ntile_g = ceil_div(mm, kRowTileG);
   size_t off = 0;
@@ -493,19 +498,17 @@ __global__ __launch_bounds__(kThreads) void k_sweep(StepArgs<S> a) {
     }
     int64_t i = ib + (int64_t)kPrefetch * RG;
     if (i <= j) i += (j + 1 - i + RG - 1) / RG * RG;
-    for (; i + 3 * RG < r1; i += 4 * RG) {
-      const VT x0 = *(const VT*)(base + i * a.ldw);
-      const VT x1 = *(const VT*)(base + (i + RG) * a.ldw);
-      const VT x2 = *(const VT*)(base + (i + 2 * RG) * a.ldw);
-      const VT x3 = *(const VT*)(base + (i + 3 * RG) * a.ldw);
-      const double w0 = wsh[i - r0], w1 = wsh[i + RG - r0], w2 = wsh[i + 2 * RG - r0],
-                   w3 = wsh[i + 3 * RG - r0];
+    // kSweepU independent row loads in flight per thread: the loop is bound
+    // by memory latency times the number of its iterations
+    for (; i + (kSweepU - 1) * RG < r1; i += kSweepU * RG) {
+      VT x[kSweepU];
 #pragma unroll
-      for (int e = 0; e < VEC; ++e) {
-        acc[e] += (double)x0[e] * w0;
-        acc[e] += (double)x1[e] * w1;
-        acc[e] += (double)x2[e] * w2;
-        acc[e] += (double)x3[e] * w3;
+      for (int u = 0; u < kSweepU; ++u) x[u] = *(const VT*)(base + (i + u * RG) * a.ldw);
+#pragma unroll
+      for (int u = 0; u < kSweepU; ++u) {
+        const double wu = wsh[i + u * RG - r0];
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) acc[e] += (double)x[u][e] * wu;
       }
     }
     for (; i < r1; i += RG) {
@@ -719,9 +722,18 @@ template <typename S, int OP>
 __global__ __launch_bounds__(kThreads) void k_panel_gemm(GemmArgs<S> a) {
   typedef typename std::conditional<OP == OP_F64, double, float>::type AccT;
   __shared__ int spiv[kNbMax];
+  __shared__ double svs[kNbMax];
   __shared__ int cidx[64];
   __shared__ AccT accs[64][64 + 1];
   __shared__ double ssq[4][64];
+  // A operands: FP64 as 4 position blocks x 8 k-steps x 64 lanes; FP16/BF16 as
+  // 8-element vectors (BF16x3: leading parts, then the remainders)
+  constexpr int kOpA = OP == OP_F64 ? 4 * 8 * 64 : 1;
+  constexpr int kOpH = OP == OP_F16 ? 256 : 1;
+  constexpr int kOpB = (OP == OP_BF16 || OP == OP_BF16X3) ? 512 : 1;
+  __shared__ double opa64[kOpA];
+  __shared__ f16x8 opah[kOpH];
+  __shared__ bf16x8 opab[kOpB];
   __shared__ int s_go, s_jb;
   __shared__ uint32_t s_fmax;
   __shared__ int64_t s_off, s_ncur;
@@ -735,6 +747,7 @@ __global__ __launch_bounds__(kThreads) void k_panel_gemm(GemmArgs<S> a) {
     s_ncur = st->ncur;
   }
   if (tid < kNbMax) spiv[tid] = a.pivpos[tid];
+  if (tid >= 64 && tid < 64 + kNbMax) svs[tid - 64] = a.vscale[tid - 64];
   __syncthreads();
   if (!s_go) return;
   if (tid == 0 && blockIdx.x == 0 && blockIdx.y == 0) st->vmax_bits = 0u;  // refilled after
@@ -774,116 +787,135 @@ __global__ __launch_bounds__(kThreads) void k_panel_gemm(GemmArgs<S> a) {
   const float vscl = ldexpf(1.0f, sV);
   const double descale = ldexp(1.0, -(sF + sV));
 
-  // A operands (F^T rows = positions), held for the whole block
-  f16x8 ah[4];
-  bf16x8 ab[4], abl[4];
-  double a64[4][8];
-#pragma unroll
-  for (int lb = 0; lb < 4; ++lb) {
+  // A operands (F^T rows = positions) staged once in LDS, in the lane order of
+  // the matrix-core instruction: 256 threads = 4 position blocks x 64 lanes
+  {
+    const int lb = tid >> 6;
     if (OP == OP_F64) {
       const int64_t pos = l0 + 16 * lb + (4 * (li % 4) + li / 4);
 #pragma unroll
-      for (int s = 0; s < 8; ++s) {
-        const int c = 4 * s + g;
-        a64[lb][s] = (c < jb && pos < ncur) ? a.F[(int64_t)c * a.ldf + pos] : 0.0;
+      for (int s8 = 0; s8 < 8; ++s8) {
+        const int c = 4 * s8 + g;
+        opa64[(lb * 8 + s8) * 64 + lane] =
+            (c < jb && pos < ncur) ? a.F[(int64_t)c * a.ldf + pos] : 0.0;
       }
     } else {
       const int64_t pos = l0 + 16 * lb + li;
+      f16x8 xh;
+      bf16x8 xb, xl;
 #pragma unroll
       for (int e = 0; e < 8; ++e) {
         const int c = 8 * g + e;
         const float x = (c < jb && pos < ncur) ? (float)(a.F[(int64_t)c * a.ldf + pos] * fscl)
                                                  : 0.0f;
-        if (OP == OP_F16) {
-          ah[lb][e] = (_Float16)x;
-        } else {
-          const __bf16 h = (__bf16)x;
-          ab[lb][e] = h;
-          if (OP == OP_BF16X3) abl[lb][e] = (__bf16)(x - (float)h);
-        }
+        xh[e] = (_Float16)x;
+        const __bf16 h = (__bf16)x;
+        xb[e] = h;
+        xl[e] = (__bf16)(x - (float)h);
+      }
+      if (OP == OP_F16) {
+        opah[tid] = xh;
+      } else {
+        opab[tid] = xb;
+        opab[256 + tid] = xl;
       }
     }
   }
+  __syncthreads();
 
+  // The W loads of SL 64-row slices are issued together (64 fp32 or 32 fp64
+  // values per thread in flight), then each slice's product is formed on the
+  // matrix cores, parked in LDS and written out compacted.
+  constexpr int SL = sizeof(S) == 4 ? 4 : 1;
   double ss = 0.0;
-  for (int sb = 0; sb < kRowTileG / 64; ++sb) {
-    const int64_t rs = rbase + 64 * sb;
-    if (rs + 64 <= rbeg || rs >= rend) continue;  // uniform across the block
-    // 1. this thread's 16 elements of the stale W tile, loads issued first
-    S wtile[16];
+  for (int sb0 = 0; sb0 < kRowTileG / 64; sb0 += SL) {
+    S wt[SL][16];
 #pragma unroll
-    for (int q = 0; q < 16; ++q) {
-      const int64_t r = rs + rq + 4 * q;
-      wtile[q] = (myout >= 0 && r >= rbeg && r < rend) ? a.W[r * a.ldw + l0 + cc] : (S)0;
-    }
-    // 2. the product tile on the matrix cores, parked in LDS
-    const int64_t row = rs + 16 * wv + li;
-    const bool rowok = row >= rbeg && row < rend;
-    if (OP == OP_F64) {
-      double b64[8];
-#pragma unroll
-      for (int s = 0; s < 8; ++s) {
-        const int c = 4 * s + g;
-        b64[s] = (c < jb && rowok) ? (double)a.V[(int64_t)c * a.ldv + row] * a.vscale[c] : 0.0;
-      }
-#pragma unroll
-      for (int lb = 0; lb < 4; ++lb) {
-        f64x4 acc = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-        for (int s = 0; s < 8; ++s)
-          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a64[lb][s], b64[s], acc, 0, 0, 0);
-#pragma unroll
-        for (int r = 0; r < 4; ++r) accs[16 * wv + li][16 * lb + 4 * g + r] = (AccT)acc[r];
-      }
-    } else {
-      f16x8 bh;
-      bf16x8 bb, bbl;
-#pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        const int c = 8 * g + e;
-        const float x = (c < jb && rowok)
-                            ? (float)((double)a.V[(int64_t)c * a.ldv + row] * a.vscale[c]) * vscl
-                            : 0.0f;
-        if (OP == OP_F16) {
-          bh[e] = (_Float16)x;
-        } else {
-          const __bf16 h = (__bf16)x;
-          bb[e] = h;
-          if (OP == OP_BF16X3) bbl[e] = (__bf16)(x - (float)h);
-        }
-      }
-#pragma unroll
-      for (int lb = 0; lb < 4; ++lb) {
-        f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
-        if (OP == OP_F16) {
-          acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah[lb], bh, acc, 0, 0, 0);
-        } else if (OP == OP_BF16) {
-          acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ab[lb], bb, acc, 0, 0, 0);
-        } else {
-          // small terms first, then the leading product
-          acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(abl[lb], bb, acc, 0, 0, 0);
-          acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ab[lb], bbl, acc, 0, 0, 0);
-          acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ab[lb], bb, acc, 0, 0, 0);
-        }
-#pragma unroll
-        for (int r = 0; r < 4; ++r) accs[16 * wv + li][16 * lb + 4 * g + r] = (AccT)acc[r];
-      }
-    }
-    __syncthreads();
-    // 3. refreshed column cc of the tile, written to its compacted position
-    if (myout >= 0) {
+    for (int sl = 0; sl < SL; ++sl) {
+      const int64_t rs = rbase + 64 * (sb0 + sl);
+      const S* rowb = a.W + rs * a.ldw + l0;  // uniform base of the slice
 #pragma unroll
       for (int q = 0; q < 16; ++q) {
-        const int rr = rq + 4 * q;
-        const int64_t r = rs + rr;
-        if (r >= rbeg && r < rend) {
-          const S v = (S)((double)wtile[q] - (double)accs[rr][cc] * descale);
-          a.Wn[r * a.ldw + myout] = v;
-          ss += (double)v * (double)v;
-        }
+        const int64_t r = rs + rq + 4 * q;
+        const uint32_t o = (uint32_t)((rq + 4 * q) * a.ldw + cc);
+        wt[sl][q] = (myout >= 0 && r >= rbeg && r < rend) ? rowb[o] : (S)0;
       }
     }
-    __syncthreads();
+#pragma unroll
+    for (int sl = 0; sl < SL; ++sl) {
+      const int64_t rs = rbase + 64 * (sb0 + sl);
+      if (rs + 64 <= rbeg || rs >= rend) continue;  // uniform across the block
+      const int64_t row = rs + 16 * wv + li;
+      const bool rowok = row >= rbeg && row < rend;
+      if (OP == OP_F64) {
+        double b64[8];
+#pragma unroll
+        for (int s8 = 0; s8 < 8; ++s8) {
+          const int c = 4 * s8 + g;
+          b64[s8] = (c < jb && rowok) ? (double)a.V[(int64_t)c * a.ldv + row] * svs[c] : 0.0;
+        }
+#pragma unroll
+        for (int lb = 0; lb < 4; ++lb) {
+          f64x4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+          for (int s8 = 0; s8 < 8; ++s8)
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(opa64[(lb * 8 + s8) * 64 + lane], b64[s8],
+                                                       acc, 0, 0, 0);
+#pragma unroll
+          for (int r = 0; r < 4; ++r) accs[16 * wv + li][16 * lb + 4 * g + r] = (AccT)acc[r];
+        }
+      } else {
+        f16x8 bh;
+        bf16x8 bb, bbl;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          const int c = 8 * g + e;
+          const float x = (c < jb && rowok)
+                              ? (float)((double)a.V[(int64_t)c * a.ldv + row] * svs[c]) * vscl
+                              : 0.0f;
+          if (OP == OP_F16) {
+            bh[e] = (_Float16)x;
+          } else {
+            const __bf16 h = (__bf16)x;
+            bb[e] = h;
+            if (OP == OP_BF16X3) bbl[e] = (__bf16)(x - (float)h);
+          }
+        }
+#pragma unroll
+        for (int lb = 0; lb < 4; ++lb) {
+          f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+          if (OP == OP_F16) {
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(opah[lb * 64 + lane], bh, acc, 0, 0, 0);
+          } else if (OP == OP_BF16) {
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(opab[lb * 64 + lane], bb, acc, 0, 0, 0);
+          } else {
+            const bf16x8 ahi = opab[lb * 64 + lane], alo = opab[256 + lb * 64 + lane];
+            // small terms first, then the leading product
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(alo, bb, acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi, bbl, acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi, bb, acc, 0, 0, 0);
+          }
+#pragma unroll
+          for (int r = 0; r < 4; ++r) accs[16 * wv + li][16 * lb + 4 * g + r] = (AccT)acc[r];
+        }
+      }
+      __syncthreads();
+      // refreshed column cc of the slice, written to its compacted position
+      if (myout >= 0) {
+        S* outb = a.Wn + rs * a.ldw;
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+          const int rr = rq + 4 * q;
+          const int64_t r = rs + rr;
+          if (r >= rbeg && r < rend) {
+            const S v = (S)((double)wt[sl][q] - (double)accs[rr][cc] * descale);
+            outb[(uint32_t)(rr * a.ldw + myout)] = v;
+            ss += (double)v * (double)v;
+          }
+        }
+      }
+      __syncthreads();
+    }
   }
   ssq[rq][cc] = ss;
   __syncthreads();
