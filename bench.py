@@ -241,9 +241,210 @@ def measured_traffic():
     return t.get("traffic_bytes_per_launch")
 
 
+def _timed(fn, steps, warmup):
+    """Average ms of fn() over `steps` calls after `warmup` calls (device events)."""
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        r = fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps, r
+
+
+def _line(args, metric, value, unit, ms, hib, dtype, workload, extra):
+    out = {"metric": metric, "value": value, "unit": unit, "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": hib, "scaling": "weak",
+           "vs_baseline": None, "dtype": dtype, "data": "synthetic", "config": workload}
+    out.update(extra)
+    return out
+
+
+def _sweep_roofline(prof, reps=1):
+    gbs = prof["sweep_bytes"] / (prof["sweep_ms"] * 1e-3) / 1e9 if prof["sweep_ms"] > 0 else 0.0
+    return {"kernel": "k_sweep", "bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS, "traffic": None,
+            "bytes_per_launch": prof["sweep_bytes"] / max(prof["sweep_launches"], 1),
+            "us_per_launch": prof["sweep_ms"] * 1e3 / max(prof["sweep_launches"], 1),
+            "launches_per_id": prof["sweep_launches"] / reps}
+
+
+def run_config1(args):
+    """Parity workload at its own size: 1000 x 500 fp64, FP64 path, k = 50.
+    Latency-bound (4 MB, cache-resident): reported in microseconds."""
+    import numpy as np
+    import torch
+    import synth
+    import oracle as orc
+    A_np = synth.config1()
+    A = torch.from_numpy(np.ascontiguousarray(A_np.T)).cuda().t()
+    pt = PathTimer(A, "f64", k=50)
+    ms, wall, fr, T = pt.timed(args.steps, args.warmup)
+    prof = pt.profiled(1)
+    t0 = time.perf_counter()
+    ref = orc.cpqr(A_np, k=50)
+    orc.solve_T(ref.R, 50)
+    cpu_s = time.perf_counter() - t0
+    m, n = A_np.shape
+    same = bool(np.array_equal(fr.perm[:50].cpu().numpy(), ref.perm[:50]))
+    return _line(args, "rank-50 FP64 ID latency (1000x500)", ms * 1e3, "us", ms, False, "f64",
+                 {"workload": "FP64 ID, 1000x500 fp64, U diag(10^-(i-1)/25) V^T, k = 50",
+                  "m": m, "n": n, "k": 50},
+                 {"pivots_equal_oracle": same, "roofline": dict(_sweep_roofline(prof), note=(
+                     "4 MB working set stays in cache; latency-bound, no roofline claim")),
+                  "cpu_baseline": {"value": cpu_s * 1e6, "unit": "us", "cores": _threads(),
+                                   "kind": "oracle", "sample": "full ID (oracle CPQR + solve)"}})
+
+
+def _threads():
+    threads = len(os.sched_getaffinity(0))
+    try:
+        from threadpoolctl import threadpool_info
+        info = threadpool_info()
+        if info:
+            threads = max(int(d.get("num_threads", 1)) for d in info)
+    except Exception:
+        pass
+    return threads
+
+
+def run_config3(args):
+    """Snapshot stand-in: 1,048,576 x 512 fp32, adaptive rank at tol 1e-3."""
+    import numpy as np
+    import torch
+    import synth
+    log = lambda *a: print(*a, file=sys.stderr, flush=True)  # noqa: E731
+    t0 = time.perf_counter()
+    A_np = synth.config3()
+    log(f"[bench] snapshot matrix {A_np.shape} generated in {time.perf_counter() - t0:.1f} s")
+    A = torch.from_numpy(np.ascontiguousarray(A_np.T)).cuda().t()
+    m, n = A_np.shape
+    res = {}
+    for prec in (args.prec, "f64"):
+        pt = PathTimer(A, prec, tol=1e-3)
+        ms, wall, fr, T = pt.timed(max(args.steps // 5, 2), 1)
+        prof = pt.profiled(1)
+        res[prec] = dict(ms=ms, k=fr.k, prof=prof, tflops=useful_flops(m, n, fr.k) / (ms * 1e-3) / 1e12)
+        log(f"[bench] {prec}: k={fr.k} {ms:.2f} ms/ID")
+        del pt
+        torch.cuda.empty_cache()
+    mx = res[args.prec]
+    out = _line(args, "rank-k ID time & TFLOP/s, mixed vs FP64 (snapshot matrix)", mx["tflops"],
+                "TFLOP/s", mx["ms"], True, {"mixed_bf16": "f32+bf16", "mixed_bf16x3": "f32+bf16x3",
+                                             "mixed_f16": "f32+f16"}[args.prec],
+                {"workload": "snapshot stand-in 64^3 grid x 4 fields x 512 snapshots, fp32, "
+                             "adaptive rank at tol 1e-3 (pivot-relative)", "m": m, "n": n,
+                 "prec": args.prec},
+                {"k": mx["k"], "fp64_gpu": {"ms_per_id": res["f64"]["ms"], "k": res["f64"]["k"]},
+                 "speedup_vs_fp64": res["f64"]["ms"] / mx["ms"],
+                 "roofline": _sweep_roofline(mx["prof"]),
+                 "kernel_ms_per_id": {key: mx["prof"][key] for key in
+                                      ("sweep_ms", "finalize_ms", "gemm_ms", "other_ms", "total_ms")}})
+    if not args.no_cpu_baseline:
+        log("[bench] CPU oracle sample (3 steps) ...")
+        out["cpu_baseline"] = cpu_baseline(A_np, 3, mx["k"])
+    return out
+
+
+def run_config4(args):
+    """Batched workload: `--batch` matrices of uneven sizes in one persistent
+    launch, against a loop of single IDs."""
+    import numpy as np
+    import torch
+    import synth
+    log = lambda *a: print(*a, file=sys.stderr, flush=True)  # noqa: E731
+    t0 = time.perf_counter()
+    mats = synth.config4(batch=args.batch)
+    log(f"[bench] {len(mats)} matrices generated in {time.perf_counter() - t0:.1f} s")
+    As = [torch.from_numpy(np.ascontiguousarray(a.T)).cuda().t() for a in mats]
+    import paper_2012_00706_amd as mp
+    plan = mp.BatchedID(As, tol=1e-4, prec=args.prec)
+    tune = mp.autotune(plan, use_cache=False)
+    ms, _ = _timed(plan.run, max(args.steps // 5, 2), 1)
+    res = plan.results()
+    ks = [r.k for r in res]
+    flops = sum(useful_flops(a.shape[0], a.shape[1], k) for a, k in zip(mats, ks))
+    sweep_bytes = sum(4.0 * sum((a.shape[0] - j) * (a.shape[1] - j - 1) for j in range(k))
+                      for a, k in zip(mats, ks))
+
+    def loop():
+        for A in As:
+            mp.column_id(A, tol=1e-4, prec=args.prec)
+    loop_ms, _ = _timed(loop, 1, 1)
+    log(f"[bench] batched {ms:.1f} ms, loop of single IDs {loop_ms:.1f} ms")
+    out = _line(args, "batched rank-k IDs: aggregate TFLOP/s (one persistent launch)",
+                flops / (ms * 1e-3) / 1e12, "TFLOP/s", ms, True,
+                {"mixed_bf16": "f32+bf16", "mixed_bf16x3": "f32+bf16x3", "mixed_f16": "f32+f16",
+                 "f64": "f64"}.get(args.prec, args.prec),
+                {"workload": f"{len(mats)} matrices, m ~ U{{2000..20000}}, n ~ U{{100..800}}, "
+                             "sigma_j = j^-2, fp32, adaptive rank at tol 1e-4", "batch": len(mats),
+                 "prec": args.prec},
+                {"sum_k": int(sum(ks)), "ids_per_s": len(mats) / (ms * 1e-3),
+                 "loop_of_single_ids_ms": loop_ms, "speedup_vs_loop": loop_ms / ms,
+                 "autotune": {k_: v for k_, v in tune.items() if k_ != "table"},
+                 "roofline": {"kernel": "k_batched_factor (whole launch)", "bound": "hbm",
+                              "achieved": sweep_bytes / (ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
+                              "unit": "GB/s", "frac": sweep_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                              "traffic": None,
+                              "note": "algorithmic sweep bytes of all items / batched time"}})
+    return out
+
+
+def run_config5(args):
+    """Adjoint workload: 8192 x 1024 fp32, k = 128; forward ID and id_backward
+    (both cotangents) timed; FP64 matrix-core products dominate the backward."""
+    import numpy as np
+    import torch
+    import synth
+    import oracle as orc
+    import paper_2012_00706_amd as mp
+    A_np = synth.config5()
+    A = torch.from_numpy(np.ascontiguousarray(A_np.T)).cuda().t()
+    m, n = A_np.shape
+    k = 128
+    res = mp.column_id(A, k=k, prec=args.prec)
+    rng = np.random.default_rng(19)
+    gT = torch.from_numpy(rng.standard_normal((n - k, k)).T.copy()).cuda()
+    gY = torch.from_numpy(np.ascontiguousarray(rng.standard_normal((m, n)).T)).cuda().t()
+    fwd_ms, _ = _timed(lambda: mp.column_id(A, k=k, prec=args.prec), args.steps, args.warmup)
+    bwd_ms, gA = _timed(lambda: mp.backward(A, res.perm, k, res.T, gT=gT, gY=gY), args.steps,
+                        args.warmup)
+    nc = n - k
+    gemm_flops = 12.0 * m * k * nc
+    t0 = time.perf_counter()
+    ref = orc.adjoint(A_np, res.perm.cpu().numpy().astype(np.int64), k, res.T.cpu().numpy(),
+                      gT=gT.cpu().numpy(), gY=gY.cpu().numpy())
+    cpu_s = time.perf_counter() - t0
+    err = float(np.linalg.norm(gA.cpu().numpy() - ref) / np.linalg.norm(ref))
+    return _line(args, "ID adjoint (id_backward) time, J fixed", bwd_ms, "ms", bwd_ms, False, "f64",
+                 {"workload": "8192x1024 fp32, sigma_i = exp(-i/64), k = 128, cotangents of T and Y",
+                  "m": m, "n": n, "k": k},
+                 {"forward_ms": fwd_ms, "rel_err_vs_oracle_adjoint": err,
+                  "roofline": {"kernel": "id_backward (whole call)", "bound": "mfma",
+                               "achieved": gemm_flops / (bwd_ms * 1e-3) / 1e12, "peak": 78.6,
+                               "unit": "TFLOP/s",
+                               "frac": gemm_flops / (bwd_ms * 1e-3) / 1e12 / 78.6, "traffic": None,
+                               "note": "FP64 product flops 12 m k (n-k) over the whole call"},
+                  "cpu_baseline": {"value": cpu_s * 1e3, "unit": "ms", "cores": _threads(),
+                                   "kind": "oracle", "sample": "oracle adjoint, same input"}})
+
+
+WORKLOADS = {"config1": run_config1, "config3": run_config3, "config4": run_config4,
+             "config5": run_config5}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawTextHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--workload", default="config2",
+                    choices=["config1", "config2", "config3", "config4", "config5"],
+                    help="config2 (default) is the headline; the others print their own line")
+    ap.add_argument("--batch", type=int, default=256, help="items of the batched workload")
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--prec", default="mixed_bf16x3",
@@ -286,6 +487,10 @@ def main():
     import synth
 
     mp.load()
+    if args.workload != "config2":
+        out = WORKLOADS[args.workload](args)
+        print(json.dumps(out))
+        return
     m, n, tol = args.m, args.n, args.tol
     log = lambda *a: print(*a, file=sys.stderr, flush=True)  # noqa: E731
     t0 = time.perf_counter()
