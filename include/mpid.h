@@ -39,6 +39,10 @@ extern "C" {
 #define ID_INFO_NONFINITE 1     /* A holds NaN or Inf: nothing was factored (k = 0) */
 #define ID_INFO_SINGULAR 2      /* R11 has |R_ii| <= n * 2^-53 * |R_00|; T not formed */
 #define ID_INFO_RANK_FULL 3     /* k = n: T has no columns, P is a permutation */
+#define ID_INFO_ABORTED 4       /* batched item abandoned (see id_factor_batched) */
+
+/* Most workgroups that may share one batched item. */
+#define ID_BATCH_MAX_GROUPS 16
 
 /* ---- storage dtype of A -------------------------------------------------- */
 #define ID_F32 0
@@ -185,8 +189,10 @@ typedef struct {
   double* T;      /* [out] k x (n - k) float64, ldt >= kcap; untouched when info != 0 */
   int64_t ldt;
   int64_t k;      /* [out] rank */
-  int32_t info;   /* [out] 0, ID_INFO_NONFINITE, ID_INFO_SINGULAR or ID_INFO_RANK_FULL */
-  int32_t pad;
+  int32_t info;   /* [out] 0, ID_INFO_NONFINITE, ID_INFO_SINGULAR, ID_INFO_RANK_FULL or
+                     ID_INFO_ABORTED */
+  int32_t groups; /* [in] workgroups that share this item (1..ID_BATCH_MAX_GROUPS;
+                     0 = 1); used only when a slot list is given */
 } id_batch_item;
 
 /* Bytes of workspace one batched item of size m x n needs [host]; 0 for
@@ -194,25 +200,33 @@ typedef struct {
 size_t id_batch_item_workspace_size(int64_t m, int64_t n, const id_opts* opts);
 
 /* Many column IDs of uneven sizes (the factorization of Algorithms 1 and 2
- * plus T = R11^{-1} R12) in one persistent launch: each workgroup takes the
- * next matrix from a device work queue (in the order "order", e.g. longest
- * first) and factors it alone, with workgroup-local synchronization only;
- * a second launch solves every item's T.  No host synchronization, so the call
- * may be captured in a HIP graph.
+ * plus T = R11^{-1} R12) in one persistent launch, then one launch of the
+ * batched triangular solve.  Workgroups take slots from a device work queue in
+ * the order of "slots"; an item whose index fills items[i].groups consecutive
+ * slots is factored by that many workgroups together (each owns a range of
+ * the working columns; they agree on pivots and reflectors through exchanges
+ * in the item's workspace).  No host synchronization, so the call may be
+ * captured in a HIP graph.
  *
  *   items         [in/out] device array of "batch" descriptors.
- *   order         device array of "batch" item indices, or NULL (0..batch-1).
+ *   slots         device array of "nslots" item indices (each item's entries
+ *                 consecutive, exactly max(groups, 1) of them), or NULL: one
+ *                 workgroup per item, in index order (groups ignored).
  *   queue         device int32 scratch for the work counter (reset here).
  *   max_n         [host] largest n of the batch (sizes the solve grid).
  *   dtype, opts   [host] as in id_factor (opts->flags must be 0).
  *   block_threads [host] 256 or 512 threads per workgroup; 0 = 256.
- *   num_groups    [host] persistent workgroups; 0 = one per compute unit.
+ *   num_groups    [host] persistent workgroups; 0 or more than the compute
+ *                 units = one per compute unit (all must be resident at once).
  * Returns ID_ERR_ARG / ID_ERR_DTYPE for invalid host arguments and
  * ID_ERR_UNSUPPORTED when max_n > 2048; per-item conditions go to items[i].info.
+ * A workgroup that waits more than 20 s for the others sharing its item marks
+ * the item ID_INFO_ABORTED (k = 0) and every workgroup of the item leaves; a
+ * slot list that breaks the rules above ends that way or factors items twice.
  * Calls that share "queue" or an item's workspace must not overlap. */
-int id_factor_batched(id_batch_item* items, int32_t batch, const int32_t* order, int32_t* queue,
-                      int64_t max_n, int32_t dtype, const id_opts* opts, int32_t block_threads,
-                      int32_t num_groups, void* stream);
+int id_factor_batched(id_batch_item* items, int32_t batch, const int32_t* slots, int32_t nslots,
+                      int32_t* queue, int64_t max_n, int32_t dtype, const id_opts* opts,
+                      int32_t block_threads, int32_t num_groups, void* stream);
 
 /* Per-kernel timing of the calling thread's last id_factor call made with
  * ID_FLAG_PROFILE (instrumentation, not part of the method).  Times come from

@@ -58,7 +58,7 @@ class IdBatchItem(ctypes.Structure):
         ("ldt", ctypes.c_int64),
         ("k", ctypes.c_int64),
         ("info", ctypes.c_int32),
-        ("pad", ctypes.c_int32),
+        ("groups", ctypes.c_int32),
     ]
 
 
@@ -90,8 +90,8 @@ SIGNATURES = {
     "id_backward": (ctypes.c_int, [_vp, _i32, _i64, _i64, _i64, _vp, _i64, _vp, _i64, _vp, _i64,
                                    _vp, _i64, _vp, _i64, _vp, _sz, _P(_i32), _vp]),
     "id_batch_item_workspace_size": (_sz, [_i64, _i64, _P(IdOpts)]),
-    "id_factor_batched": (ctypes.c_int, [_vp, _i32, _vp, _vp, _i64, _i32, _P(IdOpts), _i32, _i32,
-                                         _vp]),
+    "id_factor_batched": (ctypes.c_int, [_vp, _i32, _vp, _i32, _vp, _i64, _i32, _P(IdOpts), _i32,
+                                         _i32, _vp]),
     "id_last_profile": (ctypes.c_int, [_P(IdProfile)]),
     "id_status_string": (ctypes.c_char_p, [ctypes.c_int]),
 }

@@ -48,11 +48,14 @@ class BatchedID:
     ``k`` (fixed rank) or ``tol`` (adaptive rank, ``rule``) applies to every
     item.  Matrices that are not column-major are copied once at bind time;
     :attr:`inputs` holds the tensors the kernels read (copy new data into them
-    before replaying a captured graph).
+    before replaying a captured graph).  ``groups``: workgroups per item --
+    "auto" (shares large items so the work per workgroup evens out), an int for
+    every item, or a per-item list.  ``order``: "lpt" (largest first), None
+    (index order) or a permutation.
     """
 
     def __init__(self, As, k=None, tol=None, prec="f64", rule="pivot_rel", k_max=0, nb=0,
-                 block_threads=0, num_groups=0, order="lpt"):
+                 block_threads=0, num_groups=0, order="lpt", groups="auto"):
         if len(As) == 0:
             raise ValueError("empty batch")
         dtypes = {A.dtype for A in As}
@@ -113,19 +116,62 @@ class BatchedID:
             it.ldr = max(kc, 1)
             it.T = self.T_buf.data_ptr() + 8 * r_off[i]
             it.ldt = max(kc, 1)
-        raw = bytes(bytearray(items))
-        self.items = torch.frombuffer(bytearray(raw), dtype=torch.uint8).to(dev)
-        if order == "lpt":
-            # longest processing time first: work ~ m n kcap
-            idx = sorted(range(self.batch), key=lambda i: (-shapes[i][0] * shapes[i][1] * kcs[i], i))
-            self.order = torch.tensor(idx, dtype=torch.int32, device=dev)
-        elif order is None:
-            self.order = None
-        else:
-            self.order = torch.as_tensor(order, dtype=torch.int32).to(dev)
-            if sorted(self.order.tolist()) != list(range(self.batch)):
-                raise ValueError("order must be a permutation of the item indices")
+        self._items_host = items
+        self._order = order
+        self.cus = torch.cuda.get_device_properties(dev).multi_processor_count
         self.queue = torch.zeros(1, dtype=torch.int32, device=dev)
+        self._plan_slots(groups, [None] * self.batch)
+
+    @staticmethod
+    def _cost(m, n, k):
+        """Trailing-block elements read by k pivot steps (~ the work of an item)."""
+        return max(m * n * k - (m + n) * k * k / 2.0 + k ** 3 / 3.0, float(m * n))
+
+    def _plan_slots(self, groups, ks):
+        """Workgroups per item and the slot list (largest first).  Costs use the
+        rank ks[i] when known (e.g. from an earlier run), else kcap."""
+        shapes = self.shapes
+        cost = [self._cost(m, n, kc if k is None else k)
+                for (m, n), kc, k in zip(shapes, self.kcaps, ks)]
+        ngroups = self.cus if self.num_groups <= 0 else min(self.num_groups, self.cus)
+        cap = C["ID_BATCH_MAX_GROUPS"]
+        if groups == "auto":
+            # large items are shared so that no workgroup carries far more than
+            # an even share of the whole batch
+            share = sum(cost) / max(ngroups, 1)
+            self.groups = [max(1, min(cap, -(-n // 64), ngroups, int(c / share + 0.5)))
+                           for c, (_, n) in zip(cost, shapes)]
+        elif isinstance(groups, int):
+            self.groups = [max(1, min(groups, cap, ngroups))] * self.batch
+        else:
+            self.groups = [max(1, min(int(g), cap, ngroups)) for g in groups]
+        self._groups_mode = groups
+        items = self._items_host
+        for i in range(self.batch):
+            items[i].groups = self.groups[i]
+        raw = bytes(bytearray(items))
+        self.items = torch.frombuffer(bytearray(raw), dtype=torch.uint8).to(self.device)
+        order = self._order
+        if order == "lpt":
+            # largest per-workgroup share first; shared items then find their
+            # workgroups free at the start
+            idx = sorted(range(self.batch), key=lambda i: (-cost[i] / self.groups[i], i))
+        elif order is None:
+            idx = list(range(self.batch))
+        else:
+            idx = [int(i) for i in order]
+            if sorted(idx) != list(range(self.batch)):
+                raise ValueError("order must be a permutation of the item indices")
+        slots = [i for i in idx for _ in range(self.groups[i])]
+        self.nslots = len(slots)
+        self.slots = torch.tensor(slots, dtype=torch.int32, device=self.device)
+
+    def rebalance(self, results=None):
+        """Re-plan the workgroups per item from the ranks of a finished run
+        (adaptive ranks are unknown before the first one).  Call before capturing
+        a graph: the plan's device arrays are replaced."""
+        results = self.results() if results is None else results
+        self._plan_slots(self._groups_mode, [r.k for r in results])
 
     def configure(self, block_threads=None, num_groups=None, nb=None):
         """Change the launch shape or panel width (workspaces do not depend on them)."""
@@ -138,11 +184,12 @@ class BatchedID:
 
     def run(self):
         """Enqueue the batched factorization and solve on the current stream."""
+        if 0 < self.num_groups < max(self.groups):
+            raise ValueError("num_groups is below the workgroups an item is shared by")
         lib = _lib.load()
         with torch.cuda.device(self.device):
             rc = lib.id_factor_batched(
-                self.items.data_ptr(), self.batch,
-                self.order.data_ptr() if self.order is not None else None,
+                self.items.data_ptr(), self.batch, self.slots.data_ptr(), self.nslots,
                 self.queue.data_ptr(), self.max_n, DTYPE[self.dtype], ctypes.byref(self.opts),
                 self.block_threads, self.num_groups, _stream(self.device))
         _lib.check(rc, "id_factor_batched")
@@ -201,8 +248,13 @@ def _signature(plan: BatchedID) -> str:
 
 def autotune(plan: BatchedID, candidates=None, reps: int = 3, use_cache: bool = True):
     """Time the plan under each (block_threads, nb) candidate, configure it with
-    the fastest, and return {"block_threads", "nb", "ms", "table"}.  Results are
-    cached by device, dtype, options and the multiset of shapes."""
+    the fastest, and return {"block_threads", "nb", "ms", "table"}.  With
+    groups="auto" the plan is first re-balanced from one run's ranks.  Results
+    are cached by device, dtype, options and the multiset of shapes."""
+    if plan._groups_mode == "auto":
+        # adaptive ranks are known after one run: share the items by real work
+        plan.run()
+        plan.rebalance()
     key = _signature(plan)
     path = _cache_path()
     cache = {}

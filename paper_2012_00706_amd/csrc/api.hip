@@ -52,11 +52,11 @@ size_t id_batch_item_workspace_size(int64_t m, int64_t n, const id_opts* opts) {
   return mpid::batch_item_workspace(m, n, opts);
 }
 
-int id_factor_batched(id_batch_item* items, int32_t batch, const int32_t* order, int32_t* queue,
-                      int64_t max_n, int32_t dtype, const id_opts* opts, int32_t block_threads,
-                      int32_t num_groups, void* stream) {
-  return mpid::factor_batched_run(items, batch, order, queue, max_n, dtype, opts, block_threads,
-                                  num_groups, (hipStream_t)stream);
+int id_factor_batched(id_batch_item* items, int32_t batch, const int32_t* slots, int32_t nslots,
+                      int32_t* queue, int64_t max_n, int32_t dtype, const id_opts* opts,
+                      int32_t block_threads, int32_t num_groups, void* stream) {
+  return mpid::factor_batched_run(items, batch, slots, nslots, queue, max_n, dtype, opts,
+                                  block_threads, num_groups, (hipStream_t)stream);
 }
 
 int id_last_profile(id_profile* out) {
@@ -85,6 +85,8 @@ const char* id_status_string(int code) {
       return "R11 is numerically singular";
     case ID_INFO_RANK_FULL:
       return "full rank: k == n";
+    case ID_INFO_ABORTED:
+      return "batched item abandoned: a workgroup sharing it did not arrive in time";
     default:
       return "unknown code";
   }

@@ -20,6 +20,7 @@ constexpr int kFinCols = 32;    // columns per block of the norm reduction
 constexpr int kFC = 16;         // columns per block of the step finalization
 constexpr int kFL = kThreads / kFC;  // its tile lanes
 constexpr int kBatchMaxN = 2048;  // widest matrix of the batched path
+constexpr int kBatchMaxGroups = ID_BATCH_MAX_GROUPS;  // most workgroups sharing one item
 
 // Device-resident control block of one factorization.  Every field is written
 // by exactly one kind of kernel and read only by later kernels on the stream.
@@ -86,9 +87,9 @@ int reconstruct_run(const void* A, int32_t dtype, int64_t m, int64_t n, int64_t 
                     int64_t ldy, int32_t residual, hipStream_t s);
 
 size_t batch_item_workspace(int64_t m, int64_t n, const id_opts* o);
-int factor_batched_run(id_batch_item* items, int32_t batch, const int32_t* order, int32_t* queue,
-                       int64_t max_n, int32_t dtype, const id_opts* o, int32_t block_threads,
-                       int32_t num_groups, hipStream_t s);
+int factor_batched_run(id_batch_item* items, int32_t batch, const int32_t* slots, int32_t nslots,
+                       int32_t* queue, int64_t max_n, int32_t dtype, const id_opts* o,
+                       int32_t block_threads, int32_t num_groups, hipStream_t s);
 // T of every item (after the batched factorization, same stream).
 int trsm_batched_run(const id_batch_item* items, int32_t batch, int64_t max_n, hipStream_t s);
 

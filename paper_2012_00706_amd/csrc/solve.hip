@@ -128,13 +128,13 @@ __global__ __launch_bounds__(kThreads) void k_trsm_upper(const double* __restric
 }
 
 // T = R11^{-1} R12 of every item of a batch: blockIdx.x = item, blockIdx.y =
-// column block.  Items whose factorization failed or found R11 singular, and
-// column blocks beyond an item's n - k, leave at once.
+// column block.  Items with a nonzero info (failed, singular R11, aborted, or
+// k == n) and column blocks beyond an item's n - k leave at once.
 __global__ __launch_bounds__(kThreads) void k_trsm_batched(const id_batch_item* __restrict__ items) {
   const id_batch_item& it = items[blockIdx.x];
   const int64_t k = it.k, n = it.n;
   const int64_t c0 = (int64_t)blockIdx.y * kTC;
-  if (it.info == ID_INFO_SINGULAR || it.info == ID_INFO_NONFINITE || k <= 0 || c0 >= n - k) return;
+  if (it.info != 0 || k <= 0 || c0 >= n - k) return;
   trsm_block(it.R, it.ldr, k, it.R + k * it.ldr, it.ldr, n - k, it.T, it.ldt, 0, c0);
 }
 

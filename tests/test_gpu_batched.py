@@ -147,7 +147,7 @@ def test_batched_order_and_group_count_do_not_change_results(bt):
     outs = []
     for order, groups in [("lpt", 0), (None, 3), (list(range(len(As)))[::-1], 1)]:
         plan = mp.BatchedID(As, tol=1e-3, prec="mixed_bf16x3", order=order, block_threads=bt,
-                            num_groups=groups)
+                            num_groups=groups, groups=1)
         plan.run()
         outs.append([(r.k, host(r.perm).copy(), host(r.R).copy(), host(r.T).copy())
                      for r in plan.results()])
@@ -156,6 +156,59 @@ def test_batched_order_and_group_count_do_not_change_results(bt):
             assert a[0] == b[0]
             assert np.array_equal(a[1], b[1])
             assert np.array_equal(a[2], b[2]) and np.array_equal(a[3], b[3])
+
+
+@pytest.mark.parametrize("prec", ["f64", "mixed_bf16x3"])
+def test_batched_shared_items_match_oracle(prec):
+    """Items factored by several workgroups together (column ranges, exchanges
+    per pivot step): FP64 parity with the oracle, and for the mixed path the
+    acceptance rule; the result for a given sharing is bitwise reproducible and
+    independent of the slot order."""
+    need_gpu()
+    import paper_2012_00706_amd as mp
+    shapes = [(1500, 300), (900, 257), (2100, 130), (400, 200), (3000, 64)]
+    groups = [4, 3, 2, 3, 1]
+    dtype = np.float64 if prec == "f64" else np.float32
+    As = _inputs(shapes, dtype=dtype, decay=12.0, seed0=1700)
+    dev = [to_dev(A) for A in As]
+    outs = []
+    for order in ("lpt", None):
+        plan = mp.BatchedID(dev, k=90, prec=prec, groups=groups, order=order)
+        plan.run()
+        res = plan.results()
+        outs.append([(r.k, host(r.perm).copy(), host(r.R).copy(), host(r.T).copy()) for r in res])
+        for A, r in zip(As, res):
+            if prec == "f64":
+                _check_item_f64(A, r, k_req=90)
+            else:
+                perm = host(r.perm).astype(np.int64)
+                e = orc.id_error(A, perm, r.k, host(r.T))[0]
+                ref = orc.cpqr(A, k=r.k)
+                e_ref = orc.id_error(A, ref.perm, r.k, orc.solve_T(ref.R, r.k))[0]
+                assert e <= 1.1 * e_ref + 10 * orc.U_BF16 * 1.0
+    for a, b in zip(*outs):
+        assert a[0] == b[0] and np.array_equal(a[1], b[1])
+        assert np.array_equal(a[2], b[2]) and np.array_equal(a[3], b[3])
+
+
+def test_batched_shared_items_adaptive_and_edge_groups():
+    """Adaptive rank with shared items, more workgroups than 64-column ranges
+    (idle ranges), and a NaN in a shared item."""
+    need_gpu()
+    import paper_2012_00706_amd as mp
+    C = mp.C
+    A1 = synth.spectrum_matrix(1200, 260, synth.sigma_exp(260, 10.0), 81, 82)
+    A2 = synth.spectrum_matrix(700, 70, synth.sigma_exp(70, 10.0), 83, 84)
+    bad = synth.gaussian(300, 150, seed=5)
+    bad[17, 99] = np.nan
+    res = mp.factor_batched([to_dev(A1), to_dev(A2), to_dev(bad)], tol=1e-3, prec="f64")
+    plan = mp.BatchedID([to_dev(A1), to_dev(A2), to_dev(bad)], tol=1e-3, prec="f64",
+                        groups=[4, 5, 3])
+    plan.run()
+    res = plan.results()
+    _check_item_f64(A1, res[0], tol=1e-3)
+    _check_item_f64(A2, res[1], tol=1e-3)
+    assert res[2].info == C["ID_INFO_NONFINITE"] and res[2].k == 0
 
 
 def test_batched_graph_replay_equals_eager():
