@@ -215,7 +215,7 @@ size_t id_batch_item_workspace_size(int64_t m, int64_t n, const id_opts* opts);
  *   queue         device int32 scratch for the work counter (reset here).
  *   max_n         [host] largest n of the batch (sizes the solve grid).
  *   dtype, opts   [host] as in id_factor (opts->flags must be 0).
- *   block_threads [host] 256 or 512 threads per workgroup; 0 = 256.
+ *   block_threads [host] 256 or 512 threads per workgroup; 0 = 512.
  *   num_groups    [host] persistent workgroups; 0 or more than the compute
  *                 units = one per compute unit (all must be resident at once).
  * Returns ID_ERR_ARG / ID_ERR_DTYPE for invalid host arguments and

@@ -98,7 +98,7 @@ __host__ __device__ inline BatchLayout batch_layout(int64_t m, int64_t n, int64_
   const int64_t q256 = 256 / wb;
   L.ldw = round_up(nn, 64);
   if ((L.ldw / q256) % 2 == 0) L.ldw += q256;
-  L.ldv = round_up(mm, 64);
+  L.ldv = kNbMax;  // reflectors row-major: V(i, c) at i * kNbMax + c
   L.ldf = round_up(nn, 64);
   size_t off = 0;
 #define MPID_TAKE(field, bytes_)              \
@@ -106,7 +106,7 @@ __host__ __device__ inline BatchLayout batch_layout(int64_t m, int64_t n, int64_
   off += ((size_t)(bytes_) + 255) / 256 * 256;
   MPID_TAKE(off_w0, (size_t)mm * L.ldw * wb);
   MPID_TAKE(off_w1, (size_t)mm * L.ldw * wb);
-  MPID_TAKE(off_v, (size_t)kNbMax * L.ldv * wb);
+  MPID_TAKE(off_v, (size_t)mm * kNbMax * wb);
   MPID_TAKE(off_f, (size_t)kNbMax * L.ldf * 8);
   MPID_TAKE(off_nu, (size_t)L.ldf * 8);
   MPID_TAKE(off_nuo, (size_t)L.ldf * 8);
@@ -304,7 +304,7 @@ __device__ void factor_item(id_batch_item& it, int g, int G, const BatchOpts& o,
   double* rorig = (double*)(wb + L.off_rorig);
   XSlot* xs = (XSlot*)(wb + L.off_xs);
   int* abortp = (int*)(wb + L.off_abort);
-  const int64_t ldw = L.ldw, ldv = L.ldv, ldf = L.ldf;
+  const int64_t ldw = L.ldw, ldf = L.ldf;
   const TA* A = (const TA*)it.A;
   const uint64_t wt = o.wait_ticks;
   int64_t seq = 0;
@@ -423,27 +423,27 @@ __device__ void factor_item(id_batch_item& it, int g, int G, const BatchOpts& o,
           }
           sm.cidx[tid] = (l < cs + cn && !pv) ? (int)(l - before) : -1;
         }
-        // A operands (rows of F^T = positions l0 .. l0 + 63) staged in LDS in the
-        // lane order of the matrix-core instruction, so they cost no registers
+        // B operands (F at the positions l0 .. l0 + 63) staged in LDS in the lane
+        // order of the matrix-core instruction: lane (lg, ll) of position block
+        // lb holds F(l0 + 16 lb + ll, c) for its k indices c = 8 lg + e
         for (int idx = tid; idx < 256; idx += BT) {
           const int lb = idx >> 6, ln = idx & 63, lg = ln >> 4, ll = ln & 15;
+          const int64_t pos = l0 + 16 * lb + ll;
+          const bool pok = pos < cs + cn;
           if (OP == BOP_F64) {
-            const int64_t pos = l0 + 16 * lb + (4 * (ll % 4) + ll / 4);
-            double* fa = sm.tile + lb * 512 + ln;
+            double* fb = sm.tile + lb * 512 + ln;
 #pragma unroll
-            for (int s8 = 0; s8 < 8; ++s8) {
-              const int c = 4 * s8 + lg;
-              fa[s8 * 64] = (c < jb && pos < cs + cn) ? F[(int64_t)c * ldf + pos] : 0.0;
+            for (int e = 0; e < 8; ++e) {
+              const int c = 8 * lg + e;
+              fb[e * 64] = (c < jb && pok) ? F[(int64_t)c * ldf + pos] : 0.0;
             }
           } else {
-            const int64_t pos = l0 + 16 * lb + ll;
             f16x8 xh;
             bf16x8 xb, xl;
 #pragma unroll
             for (int e = 0; e < 8; ++e) {
               const int c = 8 * lg + e;
-              const float x =
-                  (c < jb && pos < cs + cn) ? (float)(F[(int64_t)c * ldf + pos] * fscl) : 0.0f;
+              const float x = (c < jb && pok) ? (float)(F[(int64_t)c * ldf + pos] * fscl) : 0.0f;
               xh[e] = (_Float16)x;
               const __bf16 h = (__bf16)x;
               xb[e] = h;
@@ -458,108 +458,115 @@ __device__ void factor_item(id_batch_item& it, int g, int G, const BatchOpts& o,
           }
         }
         __syncthreads();
-        double ssl[4][4];
-#pragma unroll
-        for (int lb = 0; lb < 4; ++lb)
-#pragma unroll
-          for (int r = 0; r < 4; ++r) ssl[lb][r] = 0.0;
+        // Each wave takes 16 rows at a time: the product tile (16 rows x 64
+        // positions) has the matrix rows along the instruction's M side, so a
+        // lane's results are one position of four rows and the 16 lanes of a
+        // group cover 16 consecutive positions (coalesced loads and stores).
+        double ssl[4] = {0.0, 0.0, 0.0, 0.0};
         for (int64_t rs = jend + 16 * wv; rs < m; rs += 16 * NW) {
-          const int64_t row = rs + li;
-          const bool rowok = row < m;
-          const S* wrow = Wc + (rowok ? row : jend) * ldw + l0 + 4 * g4;
-          if (OP == BOP_F64) {
-            double b64[8];
+          // A operand: V(rs + li, 8 g4 .. 8 g4 + 7), one row-major 8-vector
+          const int64_t arow = rs + li;
+          S va[8];
+          if (arow < m && 8 * g4 < jb) {
+            const S* vp = V + arow * kNbMax + 8 * g4;
 #pragma unroll
-            for (int s8 = 0; s8 < 8; ++s8) {
-              const int c = 4 * s8 + g4;
-              b64[s8] =
-                  (c < jb && rowok) ? (double)V[(int64_t)c * ldv + row] * sm.vscale[c] : 0.0;
+            for (int q = 0; q < 8 / VEC; ++q) {
+              const VT t = *(const VT*)(vp + q * VEC);
+#pragma unroll
+              for (int e = 0; e < VEC; ++e) va[q * VEC + e] = t[e];
+            }
+          } else {
+#pragma unroll
+            for (int e = 0; e < 8; ++e) va[e] = (S)0;
+          }
+          // output rows of this lane: rs + g4 + 4 r (FP64 instruction) or
+          // rs + 4 g4 + r (FP16/BF16 instruction)
+          S wv4[4][4];
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int64_t orow = OP == BOP_F64 ? rs + g4 + 4 * r : rs + 4 * g4 + r;
+#pragma unroll
+            for (int lb = 0; lb < 4; ++lb)
+              wv4[lb][r] = orow < m ? Wc[orow * ldw + l0 + 16 * lb + li] : (S)0;
+          }
+          if (OP == BOP_F64) {
+            double a64[8];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+              const int c = 8 * g4 + e;
+              a64[e] = c < jb ? (double)va[e] * sm.vscale[c] : 0.0;
             }
 #pragma unroll
             for (int lb = 0; lb < 4; ++lb) {
-              S wv4[4];
-#pragma unroll
-              for (int r = 0; r < 4; ++r) wv4[r] = wrow[16 * lb + r];
-              const double* fa = sm.tile + lb * 512 + lane;
+              const double* fb = sm.tile + lb * 512 + lane;
               f64x4 acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-              for (int s8 = 0; s8 < 8; ++s8)
-                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[s8 * 64], b64[s8], acc, 0, 0, 0);
-              if (rowok) {
+              for (int e = 0; e < 8; ++e)
+                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a64[e], fb[e * 64], acc, 0, 0, 0);
+              const int ci = sm.cidx[16 * lb + li];
 #pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                  const int ci = sm.cidx[16 * lb + 4 * g4 + r];
-                  if (ci >= 0) {
-                    const S v = (S)((double)wv4[r] - acc[r]);
-                    Wn[row * ldw + ci] = v;
-                    ssl[lb][r] += (double)v * (double)v;
-                  }
+              for (int r = 0; r < 4; ++r) {
+                const int64_t orow = rs + g4 + 4 * r;
+                if (orow < m && ci >= 0) {
+                  const S v = (S)((double)wv4[lb][r] - acc[r]);
+                  Wn[orow * ldw + ci] = v;
+                  ssl[lb] += (double)v * (double)v;
                 }
               }
             }
           } else {
-            f16x8 bh;
-            bf16x8 bb, bbl;
+            f16x8 ah;
+            bf16x8 ab, abl;
 #pragma unroll
             for (int e = 0; e < 8; ++e) {
               const int c = 8 * g4 + e;
-              const float x = (c < jb && rowok)
-                                  ? (float)((double)V[(int64_t)c * ldv + row] * sm.vscale[c]) * vscl
-                                  : 0.0f;
+              const float x = c < jb ? (float)((double)va[e] * sm.vscale[c]) * vscl : 0.0f;
               if (OP == BOP_F16) {
-                bh[e] = (_Float16)x;
+                ah[e] = (_Float16)x;
               } else {
                 const __bf16 h = (__bf16)x;
-                bb[e] = h;
-                if (OP == BOP_BF16X3) bbl[e] = (__bf16)(x - (float)h);
+                ab[e] = h;
+                if (OP == BOP_BF16X3) abl[e] = (__bf16)(x - (float)h);
               }
             }
 #pragma unroll
             for (int lb = 0; lb < 4; ++lb) {
-              S wv4[4];
-#pragma unroll
-              for (int r = 0; r < 4; ++r) wv4[r] = wrow[16 * lb + r];
               f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
               if (OP == BOP_F16) {
                 acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(
-                    ((const f16x8*)sm.tile)[lb * 64 + lane], bh, acc, 0, 0, 0);
+                    ah, ((const f16x8*)sm.tile)[lb * 64 + lane], acc, 0, 0, 0);
               } else if (OP == BOP_BF16) {
                 acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
-                    ((const bf16x8*)sm.tile)[lb * 64 + lane], bb, acc, 0, 0, 0);
+                    ab, ((const bf16x8*)sm.tile)[lb * 64 + lane], acc, 0, 0, 0);
               } else {
-                const bf16x8 ahi = ((const bf16x8*)sm.tile)[lb * 64 + lane];
-                const bf16x8 alo = ((const bf16x8*)sm.tile)[256 + lb * 64 + lane];
+                const bf16x8 bhi = ((const bf16x8*)sm.tile)[lb * 64 + lane];
+                const bf16x8 blo = ((const bf16x8*)sm.tile)[256 + lb * 64 + lane];
                 // small terms first, then the leading product
-                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(alo, bb, acc, 0, 0, 0);
-                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi, bbl, acc, 0, 0, 0);
-                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi, bb, acc, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(abl, bhi, acc, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ab, blo, acc, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ab, bhi, acc, 0, 0, 0);
               }
-              if (rowok) {
+              const int ci = sm.cidx[16 * lb + li];
 #pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                  const int ci = sm.cidx[16 * lb + 4 * g4 + r];
-                  if (ci >= 0) {
-                    const S v = (S)((double)wv4[r] - (double)acc[r] * descale);
-                    Wn[row * ldw + ci] = v;
-                    ssl[lb][r] += (double)v * (double)v;
-                  }
+              for (int r = 0; r < 4; ++r) {
+                const int64_t orow = rs + 4 * g4 + r;
+                if (orow < m && ci >= 0) {
+                  const S v = (S)((double)wv4[lb][r] - (double)acc[r] * descale);
+                  Wn[orow * ldw + ci] = v;
+                  ssl[lb] += (double)v * (double)v;
                 }
               }
             }
           }
         }
-        // column sums of squares: over the 16 rows of a lane group, then the waves
+        // column sums of squares: over the four lane groups, then the waves
 #pragma unroll
-        for (int lb = 0; lb < 4; ++lb)
-#pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            double x = ssl[lb][r];
-            x += __shfl_xor(x, 1, 64);
-            x += __shfl_xor(x, 2, 64);
-            x += __shfl_xor(x, 4, 64);
-            x += __shfl_xor(x, 8, 64);
-            if (li == 0) sm.colss[wv][16 * lb + 4 * g4 + r] = x;
-          }
+        for (int lb = 0; lb < 4; ++lb) {
+          double x = ssl[lb];
+          x += __shfl_xor(x, 16, 64);
+          x += __shfl_xor(x, 32, 64);
+          if (g4 == 0) sm.colss[wv][16 * lb + li] = x;
+        }
         __syncthreads();
         if (tid < 64 && sm.cidx[tid] >= 0) {
           double t = 0.0;
@@ -637,12 +644,22 @@ __device__ void factor_item(id_batch_item& it, int g, int G, const BatchOpts& o,
     for (int c = 0; c < kNbMax; ++c) zacc[c] = 0.0;
     for (int64_t i = rlo + tid; i < rhi; i += BT) {
       S vr[kNbMax];
+      const S* vrow = V + i * kNbMax;
 #pragma unroll
-      for (int c = 0; c < kNbMax; ++c) vr[c] = c < jb ? V[(int64_t)c * ldv + i] : (S)0;
+      for (int cb = 0; cb < kNbMax; cb += VEC) {
+        if (cb < jb) {  // uniform
+          const VT t = *(const VT*)(vrow + cb);
+#pragma unroll
+          for (int e = 0; e < VEC; ++e) vr[cb + e] = cb + e < jb ? t[e] : (S)0;
+        } else {
+#pragma unroll
+          for (int e = 0; e < VEC; ++e) vr[cb + e] = (S)0;
+        }
+      }
       double w = (double)Wc[i * ldw + p];
 #pragma unroll
       for (int c = 0; c < kNbMax; ++c) w -= (double)vr[c] * sm.g[c];
-      V[(int64_t)jb * ldv + i] = (S)w;
+      V[i * kNbMax + jb] = (S)w;
       if (i == j) {
         sm.alpha = w;
       } else {
@@ -713,7 +730,7 @@ __device__ void factor_item(id_batch_item& it, int g, int G, const BatchOpts& o,
     }
     if (j == 0) r00 = fabs(beta);
     if (tid < jb) {
-      const double vjc = sm.vscale[tid] * (double)V[(int64_t)tid * ldv + j];
+      const double vjc = sm.vscale[tid] * (double)V[j * kNbMax + tid];
       sm.vj[tid] = vjc;
       sm.aux[tid] = vjc + sm.vscale[tid] * scale * sm.zsum[tid];
     }
@@ -723,7 +740,7 @@ __device__ void factor_item(id_batch_item& it, int g, int G, const BatchOpts& o,
       while (tpr < BT && (int64_t)tpr * VEC < cn) tpr *= 2;
       const int RG = BT / tpr;
       const int rg = tid / tpr, cv = tid % tpr;
-      const S* wcol = V + (int64_t)jb * ldv;
+      const S* wcol = V + jb;  // w(i) at wcol[i * kNbMax]
       for (int64_t cb = 0; cb < cn; cb += (int64_t)tpr * VEC) {
         const int64_t l0 = cb + (int64_t)cv * VEC;  // offset in the range
         double acc[VEC];
@@ -741,7 +758,7 @@ __device__ void factor_item(id_batch_item& it, int g, int G, const BatchOpts& o,
 #pragma unroll
             for (int u = 0; u < U; ++u) x[u] = *(const VT*)(base + (i + u * RG) * ldw);
 #pragma unroll
-            for (int u = 0; u < U; ++u) w[u] = (double)wcol[i + u * RG];
+            for (int u = 0; u < U; ++u) w[u] = (double)wcol[(i + u * RG) * kNbMax];
 #pragma unroll
             for (int u = 0; u < U; ++u)
 #pragma unroll
@@ -749,7 +766,7 @@ __device__ void factor_item(id_batch_item& it, int g, int G, const BatchOpts& o,
           }
           for (; i < m; i += RG) {
             const VT x0 = *(const VT*)(base + i * ldw);
-            const double w0 = (double)wcol[i];
+            const double w0 = (double)wcol[i * kNbMax];
 #pragma unroll
             for (int e = 0; e < VEC; ++e) acc[e] += (double)x0[e] * w0;
           }
@@ -956,7 +973,7 @@ int factor_batched_run(id_batch_item* items, int32_t batch, const int32_t* slots
   const int nb = o->nb == 0 ? kNbMax : o->nb;
   if (nb < 1 || nb > kNbMax) return ID_ERR_ARG;
   if (max_n < 0 || max_n > kBatchMaxN) return ID_ERR_UNSUPPORTED;
-  const int bt = block_threads == 0 ? 256 : block_threads;
+  const int bt = block_threads == 0 ? 512 : block_threads;
   if (bt != 256 && bt != 512) return ID_ERR_ARG;
   if (!slots) nslots = batch;
   if (nslots < 0) return ID_ERR_ARG;
