@@ -80,6 +80,8 @@ extern "C" {
 /* ---- flags --------------------------------------------------------------- */
 #define ID_FLAG_NO_PIVOT 1 /* unpivoted Householder QR (perm = identity) */
 #define ID_FLAG_PROFILE 2  /* time every kernel with HIP events (see id_last_profile) */
+#define ID_FLAG_GRAM 4     /* tall-skinny front end: pivots and R from the FP64 Gram
+                              matrix A^T A (one pivoted Cholesky); see id_factor */
 
 typedef struct {
   int32_t prec;      /* ID_PREC_* */

@@ -49,7 +49,7 @@ def _stream(device=None):
 
 
 def make_opts(k=None, tol=None, prec="f64", rule="pivot_rel", k_max=0, nb=0, no_pivot=False,
-              profile=False):
+              profile=False, gram=False):
     if prec not in PREC:
         raise ValueError(f"prec must be one of {sorted(PREC)}")
     if rule not in RULE:
@@ -63,7 +63,8 @@ def make_opts(k=None, tol=None, prec="f64", rule="pivot_rel", k_max=0, nb=0, no_
     o.rel_tol = float(tol) if tol is not None else 0.0
     o.k_max = int(k_max)
     o.nb = int(nb)
-    o.flags = (C["ID_FLAG_NO_PIVOT"] if no_pivot else 0) | (C["ID_FLAG_PROFILE"] if profile else 0)
+    o.flags = ((C["ID_FLAG_NO_PIVOT"] if no_pivot else 0) | (C["ID_FLAG_PROFILE"] if profile else 0)
+               | (C["ID_FLAG_GRAM"] if gram else 0))
     if k is not None and int(k) == 0:
         o.k_max = 0
     return o
@@ -92,15 +93,17 @@ class FactorResult:
 
 def factor(A: torch.Tensor, k=None, tol=None, prec="f64", rule="pivot_rel", k_max=0, nb=0,
            no_pivot=False, work: torch.Tensor | None = None, R_buf: torch.Tensor | None = None,
-           perm_buf: torch.Tensor | None = None, profile: bool = False) -> FactorResult:
-    """Rank-k column-pivoted QR (id_factor).  k=0 gives k = 0."""
+           perm_buf: torch.Tensor | None = None, profile: bool = False,
+           gram: bool = False) -> FactorResult:
+    """Rank-k column-pivoted QR (id_factor).  k=0 gives k = 0.  gram=True takes
+    the tall-skinny front end (pivots and R from the FP64 Gram matrix)."""
     lib = _lib.load()
     A, lda = colmajor(A)
     m, n = A.shape
     if k is not None and int(k) == 0:
         return FactorResult(torch.arange(n, dtype=torch.int32, device=A.device),
                             empty_colmajor(0, n, device=A.device), 0, 0)
-    o = make_opts(k, tol, prec, rule, k_max, nb, no_pivot, profile)
+    o = make_opts(k, tol, prec, rule, k_max, nb, no_pivot, profile, gram)
     ws = workspace_size(m, n, A.dtype, o)
     if ws == 0:
         raise ValueError("invalid factorization arguments")
@@ -214,9 +217,11 @@ class ColumnIDResult:
     R: torch.Tensor     # (k, n) float64
 
 
-def column_id(A: torch.Tensor, k=None, tol=None, prec="f64", rule="pivot_rel", k_max=0, nb=0):
-    """Algorithm 1 (prec="f64") or Algorithm 2's mixed variant end to end."""
-    fr = factor(A, k=k, tol=tol, prec=prec, rule=rule, k_max=k_max, nb=nb)
+def column_id(A: torch.Tensor, k=None, tol=None, prec="f64", rule="pivot_rel", k_max=0, nb=0,
+              gram=False):
+    """Algorithm 1 (prec="f64") or Algorithm 2's mixed variant end to end
+    (gram=True: the Gram-matrix front end for tall inputs)."""
+    fr = factor(A, k=k, tol=tol, prec=prec, rule=rule, k_max=k_max, nb=nb, gram=gram)
     n = A.shape[1]
     T, _ = solve_T(fr.R, fr.k, n)
     return ColumnIDResult(fr.perm[:fr.k].long(), T, fr.perm, fr.k, fr.R)

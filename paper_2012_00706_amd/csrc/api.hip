@@ -7,6 +7,7 @@
 extern "C" {
 
 size_t id_workspace_size(int64_t m, int64_t n, int32_t dtype, const id_opts* opts) {
+  if (opts && (opts->flags & ID_FLAG_GRAM)) return mpid::gram_workspace(m, n, dtype, opts);
   mpid::FactorPlan p;
   if (!mpid::make_factor_plan(m, n, dtype, opts, &p)) return 0;
   return p.bytes;
@@ -20,6 +21,9 @@ int id_factor(const void* A, int32_t dtype, int64_t m, int64_t n, int64_t lda,
   if (opts->prec != ID_PREC_F64 && opts->prec != ID_PREC_MIXED_F16 &&
       opts->prec != ID_PREC_MIXED_BF16 && opts->prec != ID_PREC_MIXED_BF16X3)
     return ID_ERR_DTYPE;
+  if (opts->flags & ID_FLAG_GRAM)
+    return mpid::gram_factor_run(A, dtype, m, n, lda, opts, work, work_bytes, perm, R, ldr, k_out,
+                                 info, (hipStream_t)stream);
   return mpid::factor_run(A, dtype, m, n, lda, opts, work, work_bytes, perm, R, ldr, k_out, info,
                           (hipStream_t)stream);
 }

@@ -1,0 +1,524 @@
+// Tall-skinny front end: the same column-pivoted factorization reached through
+// the FP64 Gram matrix G = A^T A instead of sweeps over A.
+//
+// For A Z = Q R (Section 1.1, eq. (6)-(7)) one has Z^T G Z = R^T R, and the
+// residual norm of column l after j pivot steps is the l-th diagonal entry of
+// the Schur complement of G, d_l = G_ll - sum_{i<j} R_il^2.  Greedy pivoting on
+// d (largest first, ties to the first in swap order) is therefore column
+// pivoting on A, and row j of R is R_jl = (G_pl - sum_{i<j} R_ip R_il) / R_jj
+// with R_jj = sqrt(d_p): a pivoted Cholesky factorization of G.  Only the Gram
+// product (FP64 matrix cores, split over row chunks) touches A; the k pivot
+// steps then work on n x n data.  Rounding: d is formed to about u_64 ||A||^2, so residual
+// norms below ~sqrt(u_64) ||A|| are not resolved and T = R11^{-1} R12 carries
+// about kappa(R11)^2 u_64 relative error (kappa(R11) u_64 for the Householder
+// path); the flag is meant for tall inputs and tolerances >= 1e-6.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+
+#include "device_util.h"
+#include "mpid_internal.h"
+
+namespace mpid {
+
+namespace {
+
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kGT = 64;       // Gram tile (kGT x kGT outputs per block)
+constexpr int kGK = 32;       // rows of A staged per round
+constexpr int kPC = 64;       // columns per block of a pivot step
+constexpr int kGramBlocks = 1536;  // target blocks of the Gram product
+
+struct GramState {
+  int32_t done, info;
+  int32_t pad0, pad1;
+  int64_t k;
+  double r00, fro2;
+};
+
+}  // namespace
+
+struct GramPlan {
+  int64_t m, n, kcap, nt, ntiles, S, chunk, nblk;
+  size_t off_g, off_part, off_rc, off_d, off_pv, off_pos0, off_pos1, off_am0, off_am1, off_state,
+      bytes;
+};
+
+static bool make_gram_plan(int64_t m, int64_t n, int32_t dtype, const id_opts* o, GramPlan* p) {
+  if (!o || !p || m < 0 || n < 0) return false;
+  if (dtype != ID_F32 && dtype != ID_F64) return false;
+  if (o->rank_rule != ID_RANK_PIVOT_REL && o->rank_rule != ID_RANK_FROB_REL) return false;
+  if (o->k_fixed < 0 || o->k_max < 0 || !(o->rel_tol >= 0.0)) return false;
+  if (n > 65536 || m > ((int64_t)1 << 34)) return false;
+  std::memset(p, 0, sizeof(*p));
+  int64_t kcap = m < n ? m : n;
+  if (o->k_max > 0 && o->k_max < kcap) kcap = o->k_max;
+  if (o->k_fixed > 0 && o->k_fixed < kcap) kcap = o->k_fixed;
+  p->m = m;
+  p->n = n;
+  p->kcap = kcap;
+  const int64_t nn = n > 0 ? n : 1, kk = kcap > 0 ? kcap : 1;
+  p->nt = ceil_div(nn, kGT);
+  p->ntiles = p->nt * (p->nt + 1) / 2;
+  // split the rows so that the product has enough blocks
+  int64_t S = ceil_div(kGramBlocks, p->ntiles);
+  const int64_t smax = ceil_div(m > 0 ? m : 1, 4 * kGK);
+  if (S > smax) S = smax;
+  if (S < 1) S = 1;
+  p->chunk = round_up(ceil_div(m > 0 ? m : 1, S), kGK);
+  p->S = ceil_div(m > 0 ? m : 1, p->chunk);
+  p->nblk = ceil_div(nn, kPC);
+  size_t off = 0;
+  auto take = [&](size_t b) {
+    size_t at = off;
+    off += (b + 255) / 256 * 256;
+    return at;
+  };
+  p->off_g = take((size_t)nn * nn * 8);
+  p->off_part = take((size_t)p->S * p->ntiles * kGT * kGT * 8);
+  p->off_rc = take((size_t)nn * kk * 8);
+  p->off_d = take((size_t)nn * 8);
+  p->off_pv = take((size_t)nn * 4);
+  p->off_pos0 = take((size_t)nn * 4);
+  p->off_pos1 = take((size_t)nn * 4);
+  p->off_am0 = take((size_t)p->nblk * sizeof(AmaxPart));
+  p->off_am1 = take((size_t)p->nblk * sizeof(AmaxPart));
+  p->off_state = take(sizeof(GramState));
+  p->bytes = off;
+  return true;
+}
+
+size_t gram_workspace(int64_t m, int64_t n, int32_t dtype, const id_opts* o) {
+  GramPlan p;
+  if (!make_gram_plan(m, n, dtype, o, &p)) return 0;
+  return p.bytes;
+}
+
+// Upper tile (I, J), I <= J, of the Gram matrix over rows [s chunk, (s+1) chunk):
+// P[s][t] = A(rows, I cols)^T A(rows, J cols) on the FP64 matrix cores.  Four
+// waves, each a 32 x 32 quarter as 2 x 2 16x16x4 blocks; rows of A staged in
+// LDS kGK at a time, the next round's loads issued before this round's products.
+template <typename TA>
+__global__ __launch_bounds__(kThreads) void k_gram_partial(const TA* __restrict__ A, int64_t lda,
+                                                          int64_t m, int64_t n, int64_t nt,
+                                                          int64_t chunk, double* __restrict__ P) {
+  __shared__ double As[kGK][kGT + 1];
+  __shared__ double Bs[kGK][kGT + 1];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wv = tid >> 6, g = lane >> 4, li = lane & 15;
+  // tile index -> (I, J) with I <= J, row-major over the upper triangle
+  int64_t t = blockIdx.x, I = 0;
+  while (t >= nt - I) {
+    t -= nt - I;
+    ++I;
+  }
+  const int64_t J = I + t;
+  const int64_t s = blockIdx.y;
+  const int64_t i0 = I * kGT, j0 = J * kGT;
+  const int64_t r0 = s * chunk;
+  const int64_t r1 = r0 + chunk < m ? r0 + chunk : m;
+  const bool diag = I == J;
+  const int wr = (wv & 1) * 32, wc = (wv >> 1) * 32;
+  // load mapping: column c = tid / 4 of the tile, rows 8 (tid % 4) .. + 7
+  const int lc = tid >> 2, lr = (tid & 3) * 8;
+  f64x4 acc[2][2];
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y) acc[x][y] = (f64x4){0.0, 0.0, 0.0, 0.0};
+  double va[8], vb[8];
+  auto load = [&](int64_t k0) {
+    const int64_t ci = i0 + lc, cj = j0 + lc;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const int64_t r = k0 + lr + e;
+      va[e] = (r < r1 && ci < n) ? (double)A[ci * lda + r] : 0.0;
+      vb[e] = (!diag && r < r1 && cj < n) ? (double)A[cj * lda + r] : 0.0;
+    }
+  };
+  load(r0);
+  for (int64_t k0 = r0; k0 < r1; k0 += kGK) {
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      As[lr + e][lc] = va[e];
+      Bs[lr + e][lc] = diag ? va[e] : vb[e];
+    }
+    __syncthreads();
+    if (k0 + kGK < r1) load(k0 + kGK);
+#pragma unroll
+    for (int kk = 0; kk < kGK; kk += 4) {
+      double a[2], b[2];
+#pragma unroll
+      for (int x = 0; x < 2; ++x) a[x] = As[kk + g][wr + 16 * x + li];
+#pragma unroll
+      for (int y = 0; y < 2; ++y) b[y] = Bs[kk + g][wc + 16 * y + li];
+#pragma unroll
+      for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y)
+          acc[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[x], b[y], acc[x][y], 0, 0, 0);
+    }
+  }
+  double* out = P + ((int64_t)s * gridDim.x + blockIdx.x) * (kGT * kGT);
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y)
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        out[(wr + 16 * x + g + 4 * r) * kGT + wc + 16 * y + li] = acc[x][y][r];
+}
+
+// G = sum over the row chunks of the partial tiles (fixed order), both
+// triangles; a non-finite entry marks the input.
+__global__ __launch_bounds__(kThreads) void k_gram_reduce(const double* __restrict__ P, int64_t S,
+                                                         int64_t ntiles, int64_t nt, int64_t n,
+                                                         double* __restrict__ G,
+                                                         GramState* st) {
+  const int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (e >= ntiles * kGT * kGT) return;
+  const int64_t tile = e / (kGT * kGT), w = e % (kGT * kGT);
+  int64_t t = tile, I = 0;
+  while (t >= nt - I) {
+    t -= nt - I;
+    ++I;
+  }
+  const int64_t J = I + t;
+  const int64_t ii = I * kGT + w / kGT, jj = J * kGT + w % kGT;
+  if (ii >= n || jj >= n) return;
+  if (I == J && w / kGT > w % kGT) return;  // diagonal tiles: upper half only (symmetric G)
+  double v = 0.0;
+  for (int64_t s = 0; s < S; ++s) v += P[(s * ntiles + tile) * (kGT * kGT) + w];
+  if (!isfinite(v)) st->info = ID_INFO_NONFINITE;
+  G[jj * n + ii] = v;
+  G[ii * n + jj] = v;
+}
+
+// State, swap-order keys, Schur diagonal, pivot partials of step 0.
+__global__ __launch_bounds__(kThreads) void k_pchol_init(const double* __restrict__ G, int64_t n,
+                                                        double* __restrict__ d, int* __restrict__ pv,
+                                                        int* __restrict__ pos0,
+                                                        AmaxPart* __restrict__ am,
+                                                        GramState* st) {
+  __shared__ AmaxVal ascr[4];
+  const int64_t l = (int64_t)blockIdx.x * kPC + (threadIdx.x % kPC);
+  AmaxVal c = amax_none();
+  if (threadIdx.x < kPC && l < n) {
+    const double v = G[l * n + l];
+    d[l] = v;
+    pv[l] = 0;
+    pos0[l] = (int)l;
+    if (st->info == 0) {
+      c.v = sqrt(v > 0.0 ? v : 0.0);
+      c.s2 = v > 0.0 ? v : 0.0;
+      c.pos = (int)l;
+      c.key = (int)l;
+    }
+  }
+  c = block_amax(c, ascr);
+  if (threadIdx.x == 0) {
+    AmaxPart o;
+    o.v = c.v;
+    o.s2 = c.s2;
+    o.pos = c.pos;
+    o.key = c.key;
+    am[blockIdx.x] = o;
+  }
+}
+
+struct PcholArgs {
+  const double* G;
+  int64_t n, kcap, nblk;
+  double* Rc;  // Rc[l * kcap + i] = R(i, original column l)
+  double* d;
+  int* pv;
+  const int* pos_in;
+  int* pos_out;
+  const AmaxPart* am_in;
+  AmaxPart* am_out;
+  GramState* st;
+  int64_t j;
+  int64_t k_fixed;
+  double rel_tol;
+  int rule;
+};
+
+// Pivot step j.  Every block reduces the previous step's pivot partials (same
+// result everywhere), applies the rank rule, then for its kPC columns forms
+// R(j, l), the new Schur diagonal d_l = G_ll - sum_{i<=j} R_il^2 (recomputed, not
+// downdated), the swap-order keys after this step's swap, and a pivot partial.
+__global__ __launch_bounds__(kThreads) void k_pchol_step(PcholArgs a) {
+  __shared__ double rp[2048];
+  __shared__ AmaxVal ascr[4];
+  __shared__ int s_go;
+  const int tid = threadIdx.x;
+  const int64_t j = a.j;
+  if (tid == 0) s_go = a.st->done == 0 && a.st->info == 0;
+  AmaxVal best = amax_none();
+  for (int64_t q = tid; q < a.nblk; q += kThreads) {
+    const AmaxPart pp = a.am_in[q];
+    AmaxVal c;
+    c.v = pp.v;
+    c.s2 = pp.s2;
+    c.pos = pp.pos;
+    c.key = pp.key;
+    best = amax_combine(best, c);
+  }
+  best = block_amax(best, ascr);  // its barriers also publish s_go
+  if (!s_go) return;
+  const int p = best.pos;
+  const double vp = best.v;
+  const double r00 = j == 0 ? vp : a.st->r00;
+  const double fro2 = j == 0 ? best.s2 : a.st->fro2;
+  bool stop = (j >= a.kcap) || (p < 0);
+  if (!stop && a.k_fixed == 0) {
+    if (!(vp > 0.0))
+      stop = true;
+    else if (a.rule == ID_RANK_PIVOT_REL)
+      stop = j > 0 && vp <= a.rel_tol * r00;
+    else
+      stop = sqrt(best.s2) <= a.rel_tol * sqrt(fro2);
+  }
+  if (stop) {
+    if (blockIdx.x == 0 && tid == 0) {
+      a.st->done = 1;
+      a.st->k = j;
+    }
+    return;
+  }
+  // (reaching kcap is detected by step kcap itself: "done" must not change
+  // while other blocks of this step may still read it)
+  if (blockIdx.x == 0 && tid == 0 && j == 0) {
+    a.st->r00 = r00;
+    a.st->fro2 = fro2;
+  }
+  const double rjj = vp;  // sqrt(d_p)
+  const int jn = (int)j;
+  for (int i = tid; i < jn; i += kThreads) rp[i] = a.Rc[(int64_t)p * a.kcap + i];
+  const int pos_p = a.pos_in[p];
+  __syncthreads();
+  // 4 threads per column: partial sums over i = t, t + 4, ...
+  const int cl = tid >> 2, tq = tid & 3;
+  const int64_t l = (int64_t)blockIdx.x * kPC + cl;
+  AmaxVal cand = amax_none();
+  if (l < a.n) {
+    const int pin = a.pos_in[l];
+    const int key = l == p ? jn : (pin == jn ? pos_p : pin);
+    const bool live = !a.pv[l] && l != p;
+    double dot = 0.0, ss = 0.0;
+    if (live) {
+      const double* rl = a.Rc + l * a.kcap;
+      for (int i = tq; i < jn; i += 4) {
+        const double x = rl[i];
+        dot += rp[i] * x;
+        ss += x * x;
+      }
+    }
+    dot += __shfl_xor(dot, 1, 64);
+    ss += __shfl_xor(ss, 1, 64);
+    dot += __shfl_xor(dot, 2, 64);
+    ss += __shfl_xor(ss, 2, 64);
+    if (tq == 0) {
+      a.pos_out[l] = key;
+      if (l == p) {
+        a.Rc[l * a.kcap + j] = rjj;
+        a.pv[l] = 1;
+        a.d[l] = 0.0;
+      } else if (live) {
+        const double r = (a.G[(int64_t)p * a.n + l] - dot) / rjj;
+        a.Rc[l * a.kcap + j] = r;
+        double dl = a.G[l * a.n + l] - (ss + r * r);
+        if (!(dl > 0.0)) dl = 0.0;
+        a.d[l] = dl;
+        cand.v = sqrt(dl);
+        cand.s2 = dl;
+        cand.pos = (int)l;
+        cand.key = key;
+      }
+    }
+  }
+  cand = block_amax(cand, ascr);
+  if (tid == 0) {
+    AmaxPart o;
+    o.v = cand.v;
+    o.s2 = cand.s2;
+    o.pos = cand.pos;
+    o.key = cand.key;
+    a.am_out[blockIdx.x] = o;
+  }
+}
+
+// perm (swap order: perm[pos[l]] = l) and R in pivot order from Rc.
+__global__ __launch_bounds__(kThreads) void k_pchol_perm(const int* __restrict__ pos, int64_t n,
+                                                        int32_t* __restrict__ perm) {
+  const int64_t l = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (l < n) perm[pos[l]] = (int32_t)l;
+}
+
+__global__ __launch_bounds__(kThreads) void k_pchol_gather(const int32_t* __restrict__ perm,
+                                                          const double* __restrict__ Rc,
+                                                          int64_t kcap, int64_t n, int64_t k,
+                                                          double* __restrict__ R, int64_t ldr) {
+  const int64_t c = blockIdx.x;
+  const int64_t i = (int64_t)blockIdx.y * kThreads + threadIdx.x;
+  if (c >= n || i >= k) return;
+  const int l = perm[c];
+  R[c * ldr + i] = (c >= k || i <= c) ? Rc[(int64_t)l * kcap + i] : 0.0;
+}
+
+__global__ void k_gram_iota(int32_t* perm, int64_t n) {
+  const int64_t l = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (l < n) perm[l] = (int32_t)l;
+}
+
+static int identity_perm(int32_t* perm, int64_t n, hipStream_t s) {
+  if (n <= 0) return ID_OK;
+  k_gram_iota<<<dim3((unsigned)ceil_div(n, kThreads)), kThreads, 0, s>>>(perm, n);
+  MPID_LAUNCH_CHECK();
+  MPID_HIP(hipStreamSynchronize(s));
+  return ID_OK;
+}
+
+__global__ void k_gram_state_init(GramState* st) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    st->done = 0;
+    st->info = 0;
+    st->k = 0;
+    st->r00 = 0.0;
+    st->fro2 = 0.0;
+  }
+}
+
+int gram_factor_run(const void* A, int32_t dtype, int64_t m, int64_t n, int64_t lda,
+                    const id_opts* o, void* work, size_t work_bytes, int32_t* perm, double* R,
+                    int64_t ldr, int64_t* k_out, int32_t* info, hipStream_t s) {
+  GramPlan pl;
+  if (!make_gram_plan(m, n, dtype, o, &pl)) return ID_ERR_ARG;
+  if (o->flags & (ID_FLAG_NO_PIVOT | ID_FLAG_PROFILE)) return ID_ERR_UNSUPPORTED;
+  if (!k_out || !info) return ID_ERR_ARG;
+  if (n > 0 && !perm) return ID_ERR_ARG;
+  if (m > 0 && n > 0 && !A) return ID_ERR_ARG;
+  if (lda < (m > 1 ? m : 1)) return ID_ERR_ARG;
+  if (pl.kcap > 0 && (!R || ldr < pl.kcap)) return ID_ERR_ARG;
+  if (!work || work_bytes < pl.bytes) return ID_ERR_WORKSPACE;
+  if (pl.kcap > 2048) return ID_ERR_UNSUPPORTED;  // column of R staged in LDS
+  *info = 0;
+  *k_out = 0;
+  if (m == 0 || n == 0 || pl.kcap == 0) return identity_perm(perm, n, s);
+  char* wb = (char*)work;
+  double* G = (double*)(wb + pl.off_g);
+  double* P = (double*)(wb + pl.off_part);
+  double* Rc = (double*)(wb + pl.off_rc);
+  double* d = (double*)(wb + pl.off_d);
+  int* pv = (int*)(wb + pl.off_pv);
+  int* pos[2] = {(int*)(wb + pl.off_pos0), (int*)(wb + pl.off_pos1)};
+  AmaxPart* am[2] = {(AmaxPart*)(wb + pl.off_am0), (AmaxPart*)(wb + pl.off_am1)};
+  GramState* st = (GramState*)(wb + pl.off_state);
+
+  k_gram_state_init<<<1, 64, 0, s>>>(st);
+  MPID_LAUNCH_CHECK();
+  const dim3 pgrid((unsigned)pl.ntiles, (unsigned)pl.S);
+  if (dtype == ID_F64)
+    k_gram_partial<double><<<pgrid, kThreads, 0, s>>>((const double*)A, lda, m, n, pl.nt, pl.chunk, P);
+  else
+    k_gram_partial<float><<<pgrid, kThreads, 0, s>>>((const float*)A, lda, m, n, pl.nt, pl.chunk, P);
+  MPID_LAUNCH_CHECK();
+  k_gram_reduce<<<dim3((unsigned)ceil_div(pl.ntiles * kGT * kGT, kThreads)), kThreads, 0, s>>>(
+      P, pl.S, pl.ntiles, pl.nt, n, G, st);
+  MPID_LAUNCH_CHECK();
+  k_pchol_init<<<dim3((unsigned)pl.nblk), kThreads, 0, s>>>(G, n, d, pv, pos[0], am[0], st);
+  MPID_LAUNCH_CHECK();
+
+  // pivot steps, enqueued in groups; the host looks at the device state one
+  // group behind, so the GPU does not wait for it (steps after the stop return)
+  GramState* hs = nullptr;
+  MPID_HIP(hipHostMalloc((void**)&hs, 2 * sizeof(GramState), hipHostMallocDefault));
+  hipEvent_t ev[2];
+  if (hipEventCreateWithFlags(&ev[0], hipEventDisableTiming) != hipSuccess) {
+    (void)hipHostFree(hs);
+    return ID_ERR_HIP;
+  }
+  if (hipEventCreateWithFlags(&ev[1], hipEventDisableTiming) != hipSuccess) {
+    (void)hipEventDestroy(ev[0]);
+    (void)hipHostFree(hs);
+    return ID_ERR_HIP;
+  }
+  int rc = ID_OK;
+  const int64_t group = 32;
+  int64_t j = 0, gidx = 0;
+  bool finished = false;
+  PcholArgs pa;
+  pa.G = G;
+  pa.n = n;
+  pa.kcap = pl.kcap;
+  pa.nblk = pl.nblk;
+  pa.Rc = Rc;
+  pa.d = d;
+  pa.pv = pv;
+  pa.st = st;
+  pa.k_fixed = o->k_fixed;
+  pa.rel_tol = o->rel_tol;
+  pa.rule = o->rank_rule;
+  while (!finished && j < pl.kcap + 1) {
+    const int64_t jend = j + group < pl.kcap + 1 ? j + group : pl.kcap + 1;
+    for (; j < jend; ++j) {
+      pa.j = j;
+      pa.pos_in = pos[j & 1];
+      pa.pos_out = pos[(j + 1) & 1];
+      pa.am_in = am[j & 1];
+      pa.am_out = am[(j + 1) & 1];
+      k_pchol_step<<<dim3((unsigned)pl.nblk), kThreads, 0, s>>>(pa);
+      if (hipGetLastError() != hipSuccess) {
+        rc = ID_ERR_HIP;
+        break;
+      }
+    }
+    if (rc) break;
+    const int slot = (int)(gidx & 1);
+    if (hipMemcpyAsync(&hs[slot], st, sizeof(GramState), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipEventRecord(ev[slot], s) != hipSuccess) {
+      rc = ID_ERR_HIP;
+      break;
+    }
+    // look at the previous group (the one just enqueued keeps the GPU busy)
+    if (gidx >= 1) {
+      const int prev = (int)((gidx - 1) & 1);
+      if (hipEventSynchronize(ev[prev]) != hipSuccess) {
+        rc = ID_ERR_HIP;
+        break;
+      }
+      if (hs[prev].done || hs[prev].info) finished = true;
+    }
+    ++gidx;
+  }
+  if (!rc && hipStreamSynchronize(s) != hipSuccess) rc = ID_ERR_HIP;
+  GramState fin;
+  if (!rc && hipMemcpy(&fin, st, sizeof(GramState), hipMemcpyDeviceToHost) != hipSuccess)
+    rc = ID_ERR_HIP;
+  (void)hipEventDestroy(ev[0]);
+  (void)hipEventDestroy(ev[1]);
+  (void)hipHostFree(hs);
+  if (rc) return rc;
+  if (fin.info) {
+    *info = fin.info;
+    *k_out = 0;
+    return identity_perm(perm, n, s);
+  }
+  const int64_t k = fin.done ? fin.k : pl.kcap;
+  *k_out = k;
+  // the keys after the last executed step are in pos[k & 1]
+  k_pchol_perm<<<dim3((unsigned)ceil_div(n, kThreads)), kThreads, 0, s>>>(pos[k & 1], n, perm);
+  MPID_LAUNCH_CHECK();
+  if (k > 0) {
+    k_pchol_gather<<<dim3((unsigned)n, (unsigned)ceil_div(k, kThreads)), kThreads, 0, s>>>(
+        perm, Rc, pl.kcap, n, k, R, ldr);
+    MPID_LAUNCH_CHECK();
+  }
+  MPID_HIP(hipStreamSynchronize(s));
+  return ID_OK;
+}
+
+}  // namespace mpid

@@ -69,6 +69,12 @@ int factor_run(const void* A, int32_t dtype, int64_t m, int64_t n, int64_t lda,
 
 void last_profile(id_profile* out);
 
+// The factorization through the FP64 Gram matrix (ID_FLAG_GRAM).
+size_t gram_workspace(int64_t m, int64_t n, int32_t dtype, const id_opts* o);
+int gram_factor_run(const void* A, int32_t dtype, int64_t m, int64_t n, int64_t lda,
+                    const id_opts* o, void* work, size_t work_bytes, int32_t* perm, double* R,
+                    int64_t ldr, int64_t* k_out, int32_t* info, hipStream_t s);
+
 int solve_T_run(const double* R, int64_t ldr, int64_t k, int64_t n, double* T, int64_t ldt,
                 int32_t* info, hipStream_t s);
 
