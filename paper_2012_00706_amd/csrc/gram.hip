@@ -28,7 +28,7 @@ typedef double f64x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kGT = 64;       // Gram tile (kGT x kGT outputs per block)
 constexpr int kGK = 32;       // rows of A staged per round
-constexpr int kPC = 64;       // columns per block of a pivot step
+constexpr int kPC = 16;       // columns per block of a pivot step (16 threads each)
 constexpr int kGramBlocks = 1536;  // target blocks of the Gram product
 
 struct GramState {
@@ -128,26 +128,28 @@ __global__ __launch_bounds__(kThreads) void k_gram_partial(const TA* __restrict_
   for (int x = 0; x < 2; ++x)
 #pragma unroll
     for (int y = 0; y < 2; ++y) acc[x][y] = (f64x4){0.0, 0.0, 0.0, 0.0};
-  double va[8], vb[8];
-  auto load = [&](int64_t k0) {
+  // two register stages of raw loads in flight ahead of the products (one
+  // stage of products is short next to a memory round trip)
+  TA ra[2][8], rb[2][8];
+  auto load = [&](int q, int64_t k0) {
     const int64_t ci = i0 + lc, cj = j0 + lc;
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
       const int64_t r = k0 + lr + e;
-      va[e] = (r < r1 && ci < n) ? (double)A[ci * lda + r] : 0.0;
-      vb[e] = (!diag && r < r1 && cj < n) ? (double)A[cj * lda + r] : 0.0;
+      ra[q][e] = (r < r1 && ci < n) ? A[ci * lda + r] : (TA)0;
+      rb[q][e] = (!diag && r < r1 && cj < n) ? A[cj * lda + r] : (TA)0;
     }
   };
-  load(r0);
-  for (int64_t k0 = r0; k0 < r1; k0 += kGK) {
+  auto stage = [&](int q) {
     __syncthreads();
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
-      As[lr + e][lc] = va[e];
-      Bs[lr + e][lc] = diag ? va[e] : vb[e];
+      As[lr + e][lc] = (double)ra[q][e];
+      Bs[lr + e][lc] = diag ? (double)ra[q][e] : (double)rb[q][e];
     }
     __syncthreads();
-    if (k0 + kGK < r1) load(k0 + kGK);
+  };
+  auto products = [&]() {
 #pragma unroll
     for (int kk = 0; kk < kGK; kk += 4) {
       double a[2], b[2];
@@ -161,6 +163,17 @@ __global__ __launch_bounds__(kThreads) void k_gram_partial(const TA* __restrict_
         for (int y = 0; y < 2; ++y)
           acc[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[x], b[y], acc[x][y], 0, 0, 0);
     }
+  };
+  load(0, r0);
+  load(1, r0 + kGK);
+  for (int64_t k0 = r0; k0 < r1; k0 += 2 * kGK) {
+    stage(0);
+    if (k0 + 2 * kGK < r1) load(0, k0 + 2 * kGK);
+    products();
+    if (k0 + kGK >= r1) break;
+    stage(1);
+    if (k0 + 3 * kGK < r1) load(1, k0 + 3 * kGK);
+    products();
   }
   double* out = P + ((int64_t)s * gridDim.x + blockIdx.x) * (kGT * kGT);
 #pragma unroll
@@ -300,8 +313,8 @@ __global__ __launch_bounds__(kThreads) void k_pchol_step(PcholArgs a) {
   for (int i = tid; i < jn; i += kThreads) rp[i] = a.Rc[(int64_t)p * a.kcap + i];
   const int pos_p = a.pos_in[p];
   __syncthreads();
-  // 4 threads per column: partial sums over i = t, t + 4, ...
-  const int cl = tid >> 2, tq = tid & 3;
+  // 16 threads per column: partial sums over i = t, t + 16, ... (coalesced)
+  const int cl = tid >> 4, tq = tid & 15;
   const int64_t l = (int64_t)blockIdx.x * kPC + cl;
   AmaxVal cand = amax_none();
   if (l < a.n) {
@@ -311,16 +324,17 @@ __global__ __launch_bounds__(kThreads) void k_pchol_step(PcholArgs a) {
     double dot = 0.0, ss = 0.0;
     if (live) {
       const double* rl = a.Rc + l * a.kcap;
-      for (int i = tq; i < jn; i += 4) {
+      for (int i = tq; i < jn; i += 16) {
         const double x = rl[i];
         dot += rp[i] * x;
         ss += x * x;
       }
     }
-    dot += __shfl_xor(dot, 1, 64);
-    ss += __shfl_xor(ss, 1, 64);
-    dot += __shfl_xor(dot, 2, 64);
-    ss += __shfl_xor(ss, 2, 64);
+#pragma unroll
+    for (int off = 1; off < 16; off <<= 1) {
+      dot += __shfl_xor(dot, off, 64);
+      ss += __shfl_xor(ss, off, 64);
+    }
     if (tq == 0) {
       a.pos_out[l] = key;
       if (l == p) {
