@@ -333,6 +333,10 @@ def run_config3(args):
         log(f"[bench] {prec}: k={fr.k} {ms:.2f} ms/ID")
         del pt
         torch.cuda.empty_cache()
+    # the tall-skinny front end (pivots and R from the FP64 Gram matrix)
+    import paper_2012_00706_amd as mp
+    gms, gres = _timed(lambda: mp.column_id(A, tol=1e-3, gram=True), 3, 1)
+    log(f"[bench] gram front end: k={gres.k} {gms:.2f} ms/ID")
     mx = res[args.prec]
     out = _line(args, "rank-k ID time & TFLOP/s, mixed vs FP64 (snapshot matrix)", mx["tflops"],
                 "TFLOP/s", mx["ms"], True, {"mixed_bf16": "f32+bf16", "mixed_bf16x3": "f32+bf16x3",
@@ -342,6 +346,8 @@ def run_config3(args):
                  "prec": args.prec},
                 {"k": mx["k"], "fp64_gpu": {"ms_per_id": res["f64"]["ms"], "k": res["f64"]["k"]},
                  "speedup_vs_fp64": res["f64"]["ms"] / mx["ms"],
+                 "gram_front_end": {"ms_per_id": gms, "k": gres.k,
+                                    "speedup_vs_mixed": mx["ms"] / gms},
                  "roofline": _sweep_roofline(mx["prof"]),
                  "kernel_ms_per_id": {key: mx["prof"][key] for key in
                                       ("sweep_ms", "finalize_ms", "gemm_ms", "other_ms", "total_ms")}})
