@@ -28,7 +28,7 @@ if ROOT not in sys.path:
 METRIC = "rank-k ID time & TFLOP/s, mixed vs FP64 on GPU at matched ‖A−CT‖/σ_{k+1}"
 HBM_PEAK_GBS = 8000.0
 U_LOW = {"mixed_bf16": 2.0 ** -8, "mixed_bf16x3": 2.0 ** -8, "mixed_f16": 2.0 ** -11,
-         "f64": 2.0 ** -53}
+         "mixed_f32": 2.0 ** -24, "f64": 2.0 ** -53}
 
 
 def useful_flops(m: int, n: int, k: int, solve: bool = True) -> float:
@@ -340,7 +340,7 @@ def run_config3(args):
     mx = res[args.prec]
     out = _line(args, "rank-k ID time & TFLOP/s, mixed vs FP64 (snapshot matrix)", mx["tflops"],
                 "TFLOP/s", mx["ms"], True, {"mixed_bf16": "f32+bf16", "mixed_bf16x3": "f32+bf16x3",
-                                             "mixed_f16": "f32+f16"}[args.prec],
+                                             "mixed_f16": "f32+f16", "mixed_f32": "f32"}[args.prec],
                 {"workload": "snapshot stand-in 64^3 grid x 4 fields x 512 snapshots, fp32, "
                              "adaptive rank at tol 1e-3 (pivot-relative)", "m": m, "n": n,
                  "prec": args.prec},
@@ -440,21 +440,135 @@ def run_config5(args):
                                    "kind": "oracle", "sample": "oracle adjoint, same input"}})
 
 
+def run_accuracy(args):
+    """The paper's accuracy study (Section 3, Table 3 datasets): 1000-row
+    matrices with sigma_i = i^-1 (Slow), i^-2 (Medium), i^-4 (Fast); relative
+    spectral errors of the ID against the FP64 ID and against the matrix, over
+    the target rank (n = 1000) and over the column count (k = 20), for the
+    precision variants of the paper mapped onto this implementation:
+      double        FP64 path on A (Algorithm 1)
+      mixed_single  A stored in fp32, FP32 matrix-core update, skeleton from A (Algorithm 2)
+      single        same factorization, skeleton from the fp32 matrix (A_L)
+      mixed_single_bf16x3  A stored in fp32, split-BF16 update, skeleton from A
+      mixed_bf16    A stored in bf16, mixed BF16 path, skeleton from A
+      bf16          same, skeleton from the bf16 matrix
+      mixed_half    A stored in fp16 (no scaling), mixed FP16 path, skeleton from A
+      half          same, skeleton from the fp16 matrix
+      mixed_half_scaled  A scaled by a power of two before the fp16 storage
+    A variant "breaks" when its R11 is numerically singular (recorded as null)."""
+    import numpy as np
+    import torch
+    import synth
+    import paper_2012_00706_amd as mp
+    log = lambda *a: print(*a, file=sys.stderr, flush=True)  # noqa: E731
+
+    def dev(a):
+        return torch.from_numpy(np.ascontiguousarray(np.asarray(a).T)).cuda().t()
+
+    gen = torch.Generator(device="cuda").manual_seed(7)
+
+    def norm2(X):
+        # power iteration on X^T X (100 steps, seeded): ample for error ratios
+        v = torch.randn(X.shape[1], 1, dtype=torch.float64, device="cuda", generator=gen)
+        s = 0.0
+        for _ in range(100):
+            w = X.t() @ (X @ v)
+            nw = float(w.norm())
+            if nw == 0.0:
+                return 0.0
+            v = w / nw
+            s = nw
+        return math.sqrt(s)
+
+    def stored(a, dt, scaled=False):
+        x = torch.from_numpy(np.asarray(a, dtype=np.float64))
+        sc = 1.0
+        if scaled:
+            e = math.frexp(float(x.abs().max()))[1]
+            sc = 2.0 ** (14 - e)
+        y = (x * sc).to(dt).to(torch.float64) / sc
+        return y.numpy().astype(np.float32)
+
+    variants = [  # (name, storage dtype, scaled, prec, skeleton from the stored matrix)
+        ("double", None, False, "f64", False),
+        ("mixed_single", torch.float32, False, "mixed_f32", False),
+        ("single", torch.float32, False, "mixed_f32", True),
+        ("mixed_single_bf16x3", torch.float32, False, "mixed_bf16x3", False),
+        ("mixed_bf16", torch.bfloat16, False, "mixed_bf16", False),
+        ("bf16", torch.bfloat16, False, "mixed_bf16", True),
+        ("mixed_half", torch.float16, False, "mixed_f16", False),
+        ("half", torch.float16, False, "mixed_f16", True),
+        ("mixed_half_scaled", torch.float16, True, "mixed_f16", False),
+    ]
+    ks = [1, 2, 4, 6, 8, 10, 12, 15, 18, 20, 21, 22, 25, 30, 35, 40, 50]
+    ns = [50, 100, 200, 300, 400, 500, 600, 700, 800, 900, 1000]
+    t0 = time.perf_counter()
+    table = {}
+    for kind in ("slow", "medium", "fast"):
+        full = synth.paper_dataset(kind)
+        for sweep, pts in (("k", ks), ("n", ns)):
+            for x in pts:
+                k, n = (x, 1000) if sweep == "k" else (20, x)
+                A = full[:, :n]
+                Ad = dev(A)
+                nA = norm2(Ad)
+                ref = None
+                for name, dt, scaled, prec, low_skel in variants:
+                    As = A if dt is None else stored(A, dt, scaled)
+                    Asd = dev(As)
+                    try:
+                        r = mp.column_id(Asd, k=k, prec=prec)
+                        Y = mp.reconstruct(Asd if low_skel else Ad, r.perm, r.k, r.T)
+                    except mp.MpidError:
+                        table.setdefault(kind, {}).setdefault(sweep, {}).setdefault(name, []).append(
+                            None)
+                        continue
+                    if name == "double":
+                        ref = Y
+                    e_truth = norm2(Ad - Y) / nA
+                    e_double = norm2(ref - Y) / norm2(ref)
+                    table.setdefault(kind, {}).setdefault(sweep, {}).setdefault(name, []).append(
+                        [e_double, e_truth])
+        log(f"[bench] accuracy study: {kind} done ({time.perf_counter() - t0:.0f} s)")
+
+    def worst(kind, name, sweep="k", col=0, kmax=50):
+        vals = [v[col] for x, v in zip(ks, table[kind][sweep][name]) if v is not None and x <= kmax]
+        return max(vals) if vals else None
+
+    claims = {
+        "mixed_single_vs_double_max_fast_medium": max(worst("fast", "mixed_single"),
+                                                      worst("medium", "mixed_single")),
+        "mixed_single_vs_double_max_slow": worst("slow", "mixed_single"),
+        "single_vs_double_max_slow": worst("slow", "single"),
+        "mixed_half_breaks_fast_at_k": [x for x, v in zip(ks, table["fast"]["k"]["mixed_half"])
+                                        if v is None],
+        "mixed_half_scaled_breaks_fast_at_k": [x for x, v in zip(
+            ks, table["fast"]["k"]["mixed_half_scaled"]) if v is None],
+    }
+    return _line(args, "relative spectral error of the ID vs the FP64 ID (paper datasets)",
+                 claims["mixed_single_vs_double_max_fast_medium"], "relative error",
+                 (time.perf_counter() - t0) * 1e3, False, "mixed",
+                 {"workload": "paper datasets Slow/Medium/Fast (1000 rows, sigma_i = i^-1, "
+                              "i^-2, i^-4), k sweep at n = 1000 and n sweep at k = 20"},
+                 {"claims": claims, "k_values": ks, "n_values": ns, "errors": table,
+                  "error_columns": ["vs_double_ID", "vs_matrix"]})
+
+
 WORKLOADS = {"config1": run_config1, "config3": run_config3, "config4": run_config4,
-             "config5": run_config5}
+             "config5": run_config5, "accuracy": run_accuracy}
 
 
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawTextHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--workload", default="config2",
-                    choices=["config1", "config2", "config3", "config4", "config5"],
+                    choices=["config1", "config2", "config3", "config4", "config5", "accuracy"],
                     help="config2 (default) is the headline; the others print their own line")
     ap.add_argument("--batch", type=int, default=256, help="items of the batched workload")
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--prec", default="mixed_bf16x3",
-                    choices=["mixed_bf16", "mixed_bf16x3", "mixed_f16"])
+                    choices=["mixed_bf16", "mixed_bf16x3", "mixed_f16", "mixed_f32"])
     ap.add_argument("--compare", default="",
                     help="comma-separated extra precisions to time (reported, not headline)")
     ap.add_argument("--tol", type=float, default=1e-3)
@@ -561,7 +675,7 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": {"mixed_bf16": "f32+bf16", "mixed_bf16x3": "f32+bf16x3",
-                  "mixed_f16": "f32+f16"}[args.prec],
+                  "mixed_f16": "f32+f16", "mixed_f32": "f32"}[args.prec],
         "data": "synthetic",
         "config": {
             "workload": (f"mixed-precision ID, {m}x{n} fp32, A=U diag(exp(-i/40)) V^T (Haar), "

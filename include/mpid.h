@@ -62,11 +62,14 @@ extern "C" {
  *                     hi*hi + hi*lo + lo*hi on BF16 matrix cores with FP32
  *                     accumulation: the update error drops from about 2^-8 to
  *                     about 2^-16 of its size at three times the (idle) matrix
- *                     work of the bandwidth-bound update.                    */
+ *                     work of the bandwidth-bound update.
+ * ID_PREC_MIXED_F32:  as above with FP32 operands on FP32 matrix cores (the
+ *                     single-precision low arithmetic of Algorithm 2).       */
 #define ID_PREC_F64 0
 #define ID_PREC_MIXED_F16 1
 #define ID_PREC_MIXED_BF16 2
 #define ID_PREC_MIXED_BF16X3 3
+#define ID_PREC_MIXED_F32 4
 
 /* ---- adaptive rank rules (used when k_fixed == 0) ------------------------
  * ID_RANK_PIVOT_REL: stop before step j >= 1 once the largest remaining column

@@ -20,6 +20,7 @@ PREC = {
     "mixed_f16": C["ID_PREC_MIXED_F16"],
     "mixed_bf16": C["ID_PREC_MIXED_BF16"],
     "mixed_bf16x3": C["ID_PREC_MIXED_BF16X3"],
+    "mixed_f32": C["ID_PREC_MIXED_F32"],
 }
 RULE = {"pivot_rel": C["ID_RANK_PIVOT_REL"], "frob_rel": C["ID_RANK_FROB_REL"]}
 DTYPE = {torch.float32: C["ID_F32"], torch.float64: C["ID_F64"]}

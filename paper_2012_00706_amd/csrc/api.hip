@@ -19,7 +19,8 @@ int id_factor(const void* A, int32_t dtype, int64_t m, int64_t n, int64_t lda,
   if (dtype != ID_F32 && dtype != ID_F64) return ID_ERR_DTYPE;
   if (!opts) return ID_ERR_ARG;
   if (opts->prec != ID_PREC_F64 && opts->prec != ID_PREC_MIXED_F16 &&
-      opts->prec != ID_PREC_MIXED_BF16 && opts->prec != ID_PREC_MIXED_BF16X3)
+      opts->prec != ID_PREC_MIXED_BF16 && opts->prec != ID_PREC_MIXED_BF16X3 &&
+      opts->prec != ID_PREC_MIXED_F32)
     return ID_ERR_DTYPE;
   if (opts->flags & ID_FLAG_GRAM)
     return mpid::gram_factor_run(A, dtype, m, n, lda, opts, work, work_bytes, perm, R, ldr, k_out,

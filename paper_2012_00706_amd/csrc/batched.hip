@@ -51,7 +51,7 @@ struct BVec<double> {
   static constexpr int n = 2;
 };
 
-enum { BOP_F64 = 0, BOP_F16 = 1, BOP_BF16 = 2, BOP_BF16X3 = 3 };
+enum { BOP_F64 = 0, BOP_F16 = 1, BOP_BF16 = 2, BOP_BF16X3 = 3, BOP_F32 = 4 };
 
 }  // namespace
 
@@ -437,6 +437,13 @@ __device__ void factor_item(id_batch_item& it, int g, int G, const BatchOpts& o,
               const int c = 8 * lg + e;
               fb[e * 64] = (c < jb && pok) ? F[(int64_t)c * ldf + pos] : 0.0;
             }
+          } else if (OP == BOP_F32) {
+            float* fb = (float*)sm.tile + lb * 512 + ln;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+              const int c = 8 * lg + e;
+              fb[e * 64] = (c < jb && pok) ? (float)F[(int64_t)c * ldf + pos] : 0.0f;
+            }
           } else {
             f16x8 xh;
             bf16x8 xb, xl;
@@ -509,6 +516,31 @@ __device__ void factor_item(id_batch_item& it, int g, int G, const BatchOpts& o,
                 const int64_t orow = rs + g4 + 4 * r;
                 if (orow < m && ci >= 0) {
                   const S v = (S)((double)wv4[lb][r] - acc[r]);
+                  Wn[orow * ldw + ci] = v;
+                  ssl[lb] += (double)v * (double)v;
+                }
+              }
+            }
+          } else if (OP == BOP_F32) {
+            float a32[8];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+              const int c = 8 * g4 + e;
+              a32[e] = c < jb ? (float)((double)va[e] * sm.vscale[c]) : 0.0f;
+            }
+#pragma unroll
+            for (int lb = 0; lb < 4; ++lb) {
+              const float* fb = (const float*)sm.tile + lb * 512 + lane;
+              f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+              for (int e = 0; e < 8; ++e)
+                acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a32[e], fb[e * 64], acc, 0, 0, 0);
+              const int ci = sm.cidx[16 * lb + li];
+#pragma unroll
+              for (int r = 0; r < 4; ++r) {
+                const int64_t orow = rs + 4 * g4 + r;
+                if (orow < m && ci >= 0) {
+                  const S v = (S)((double)wv4[lb][r] - (double)acc[r]);
                   Wn[orow * ldw + ci] = v;
                   ssl[lb] += (double)v * (double)v;
                 }
@@ -940,7 +972,7 @@ __global__ __launch_bounds__(BT) void k_batched_factor(id_batch_item* items, int
 
 size_t batch_item_workspace(int64_t m, int64_t n, const id_opts* o) {
   if (!o || m < 0 || n < 0 || n > kBatchMaxN) return 0;
-  if (o->prec < ID_PREC_F64 || o->prec > ID_PREC_MIXED_BF16X3) return 0;
+  if (o->prec < ID_PREC_F64 || o->prec > ID_PREC_MIXED_F32) return 0;
   const int wb = o->prec == ID_PREC_F64 ? 8 : 4;
   return batch_layout(m, n, batch_kcap(m, n, o->k_fixed, o->k_max), wb).bytes;
 }
@@ -967,7 +999,7 @@ int factor_batched_run(id_batch_item* items, int32_t batch, const int32_t* slots
                        int32_t block_threads, int32_t num_groups, hipStream_t s) {
   if (!o || !items || !queue || batch < 0) return ID_ERR_ARG;
   if (dtype != ID_F32 && dtype != ID_F64) return ID_ERR_DTYPE;
-  if (o->prec < ID_PREC_F64 || o->prec > ID_PREC_MIXED_BF16X3) return ID_ERR_DTYPE;
+  if (o->prec < ID_PREC_F64 || o->prec > ID_PREC_MIXED_F32) return ID_ERR_DTYPE;
   if (o->flags != 0 || o->k_fixed < 0 || o->k_max < 0 || !(o->rel_tol >= 0.0)) return ID_ERR_ARG;
   if (o->rank_rule != ID_RANK_PIVOT_REL && o->rank_rule != ID_RANK_FROB_REL) return ID_ERR_ARG;
   const int nb = o->nb == 0 ? kNbMax : o->nb;
@@ -1007,6 +1039,10 @@ int factor_batched_run(id_batch_item* items, int32_t batch, const int32_t* slots
     rc = dtype == ID_F64
              ? launch_batched<float, double, BOP_F16>(items, batch, slots, nslots, queue, bo, bt, groups, s)
              : launch_batched<float, float, BOP_F16>(items, batch, slots, nslots, queue, bo, bt, groups, s);
+  } else if (o->prec == ID_PREC_MIXED_F32) {
+    rc = dtype == ID_F64
+             ? launch_batched<float, double, BOP_F32>(items, batch, slots, nslots, queue, bo, bt, groups, s)
+             : launch_batched<float, float, BOP_F32>(items, batch, slots, nslots, queue, bo, bt, groups, s);
   } else if (o->prec == ID_PREC_MIXED_BF16) {
     rc = dtype == ID_F64
              ? launch_batched<float, double, BOP_BF16>(items, batch, slots, nslots, queue, bo, bt, groups, s)

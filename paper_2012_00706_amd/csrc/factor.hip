@@ -53,7 +53,7 @@ struct Vec16<double> {
   static constexpr int n = 2;
 };
 
-enum { OP_F64 = 0, OP_F16 = 1, OP_BF16 = 2, OP_BF16X3 = 3 };
+enum { OP_F64 = 0, OP_F16 = 1, OP_BF16 = 2, OP_BF16X3 = 3, OP_F32 = 4 };
 
 constexpr int kPrefetch = 4;  // sweep rows per thread loaded ahead of the pivot search
 constexpr int kSweepU = 4;    // sweep rows per thread in flight in the main loop
@@ -64,7 +64,7 @@ bool make_factor_plan(int64_t m, int64_t n, int32_t dtype, const id_opts* o, Fac
   if (!o || !p || m < 0 || n < 0) return false;
   if (dtype != ID_F32 && dtype != ID_F64) return false;
   if (o->prec != ID_PREC_F64 && o->prec != ID_PREC_MIXED_F16 && o->prec != ID_PREC_MIXED_BF16 &&
-      o->prec != ID_PREC_MIXED_BF16X3)
+      o->prec != ID_PREC_MIXED_BF16X3 && o->prec != ID_PREC_MIXED_F32)
     return false;
   if (o->rank_rule != ID_RANK_PIVOT_REL && o->rank_rule != ID_RANK_FROB_REL) return false;
   if (o->k_fixed < 0 || o->k_max < 0 || !(o->rel_tol >= 0.0)) return false;
@@ -731,6 +731,8 @@ __global__ __launch_bounds__(kThreads) void k_panel_gemm(GemmArgs<S> a) {
   constexpr int kOpA = OP == OP_F64 ? 4 * 8 * 64 : 1;
   constexpr int kOpH = OP == OP_F16 ? 256 : 1;
   constexpr int kOpB = (OP == OP_BF16 || OP == OP_BF16X3) ? 512 : 1;
+  constexpr int kOpF = OP == OP_F32 ? 4 * 8 * 64 : 1;
+  __shared__ float opaf[kOpF];
   __shared__ double opa64[kOpA];
   __shared__ f16x8 opah[kOpH];
   __shared__ bf16x8 opab[kOpB];
@@ -799,6 +801,15 @@ __global__ __launch_bounds__(kThreads) void k_panel_gemm(GemmArgs<S> a) {
         opa64[(lb * 8 + s8) * 64 + lane] =
             (c < jb && pos < ncur) ? a.F[(int64_t)c * a.ldf + pos] : 0.0;
       }
+    } else if (OP == OP_F32) {
+      // FP32 16x16x4: step e uses k index c = 8 g + e of lane group g
+      const int64_t pos = l0 + 16 * lb + li;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int c = 8 * g + e;
+        opaf[(lb * 8 + e) * 64 + lane] =
+            (c < jb && pos < ncur) ? (float)a.F[(int64_t)c * a.ldf + pos] : 0.0f;
+      }
     } else {
       const int64_t pos = l0 + 16 * lb + li;
       f16x8 xh;
@@ -861,6 +872,24 @@ __global__ __launch_bounds__(kThreads) void k_panel_gemm(GemmArgs<S> a) {
           for (int s8 = 0; s8 < 8; ++s8)
             acc = __builtin_amdgcn_mfma_f64_16x16x4f64(opa64[(lb * 8 + s8) * 64 + lane], b64[s8],
                                                        acc, 0, 0, 0);
+#pragma unroll
+          for (int r = 0; r < 4; ++r) accs[16 * wv + li][16 * lb + 4 * g + r] = (AccT)acc[r];
+        }
+      } else if (OP == OP_F32) {
+        float bf[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          const int c = 8 * g + e;
+          bf[e] = (c < jb && rowok) ? (float)((double)a.V[(int64_t)c * a.ldv + row] * svs[c])
+                                    : 0.0f;
+        }
+#pragma unroll
+        for (int lb = 0; lb < 4; ++lb) {
+          f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+          for (int e = 0; e < 8; ++e)
+            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(opaf[(lb * 8 + e) * 64 + lane], bf[e], acc,
+                                                       0, 0, 0);
 #pragma unroll
           for (int r = 0; r < 4; ++r) accs[16 * wv + li][16 * lb + 4 * g + r] = (AccT)acc[r];
         }
@@ -1358,6 +1387,13 @@ int factor_run(const void* A, int32_t dtype, int64_t m, int64_t n, int64_t lda,
       return factor_impl<double, float, OP_F16>((const double*)A, lda, pl, o, wb, perm, R, ldr,
                                                 k_out, info, s);
     return factor_impl<float, float, OP_F16>((const float*)A, lda, pl, o, wb, perm, R, ldr, k_out,
+                                             info, s);
+  }
+  if (pl.prec == ID_PREC_MIXED_F32) {
+    if (dtype == ID_F64)
+      return factor_impl<double, float, OP_F32>((const double*)A, lda, pl, o, wb, perm, R, ldr,
+                                                k_out, info, s);
+    return factor_impl<float, float, OP_F32>((const float*)A, lda, pl, o, wb, perm, R, ldr, k_out,
                                              info, s);
   }
   if (pl.prec == ID_PREC_MIXED_BF16X3) {

@@ -92,7 +92,7 @@ def test_batched_f32_storage_f64_path():
 
 
 @pytest.mark.parametrize("prec,u_low", [("mixed_bf16x3", orc.U_BF16), ("mixed_bf16", orc.U_BF16),
-                                        ("mixed_f16", orc.U_HALF)])
+                                        ("mixed_f16", orc.U_HALF), ("mixed_f32", orc.U_SINGLE)])
 def test_batched_mixed_acceptance(prec, u_low):
     """Mixed precision is accepted on error: at the rank it chose, each item's
     spectral error is within 1.1x the oracle's at the same rank plus

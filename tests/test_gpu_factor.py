@@ -91,7 +91,8 @@ def test_exact_low_rank_recovered():
     assert ef <= 1e-12 * np.linalg.norm(A)
 
 
-@pytest.mark.parametrize("prec,u_low", [("mixed_bf16", orc.U_BF16), ("mixed_f16", orc.U_HALF)])
+@pytest.mark.parametrize("prec,u_low", [("mixed_bf16", orc.U_BF16), ("mixed_f16", orc.U_HALF),
+                                        ("mixed_bf16x3", orc.U_BF16), ("mixed_f32", orc.U_SINGLE)])
 def test_mixed_acceptance_bound(prec, u_low):
     need_gpu()
     A = synth.spectrum_matrix(3000, 400, synth.sigma_exp(400, 40.0), 51, 52).astype(np.float32)
@@ -198,3 +199,18 @@ def test_fixed_rank_below_n_multi_panel(m, n, k):
         np.testing.assert_allclose(row_sign_align(R, ref.R), ref.R, rtol=0,
                                    atol=1e-11 * np.abs(ref.R).max())
         assert rel_err(T, orc.solve_T(ref.R, k)) <= 1e-10
+
+
+def test_mixed_f32_matches_fp64_pivots():
+    """The FP32 matrix-core update keeps the FP32 working copy accurate to
+    about u_32: on a gap-separated input the pivots equal the oracle's and T
+    agrees to the FP32 level."""
+    need_gpu()
+    A = synth.spectrum_matrix(2000, 300, synth.sigma_geom10(300, 30.0), 91, 92).astype(np.float32)
+    perm, kk, R, T = gpu_id(A, k=60, prec="mixed_f32")
+    ref = orc.cpqr(A, k=60)
+    upto = int(np.argmax(ref.margins < 1e-4)) if np.any(ref.margins < 1e-4) else 60
+    assert perm[:upto].tolist() == ref.perm[:upto].tolist()
+    if upto == 60:
+        kappa = np.linalg.cond(ref.R[:, :60])
+        assert rel_err(T, orc.solve_T(ref.R, 60)) <= 1e-5 * kappa
