@@ -138,15 +138,26 @@ def cpu_baseline(A_np, steps: int, k_full: int):
 COPY_BYTES = 256 << 20
 TRAFFIC_JSON = os.path.join(ROOT, "profiles", "sweep_traffic.json")
 SWEEP_SOURCES = [os.path.join(ROOT, "paper_2012_00706_amd", "csrc", f)
-                 for f in ("factor.hip", "device_util.h", "mpid_internal.h")]
+                 for f in ("factor.hip", "device_util.h")]
 
 
 def sweep_source_hash() -> str:
+    """Hash of the reflector sweep's own source: the k_sweep kernel, its
+    argument struct and constants in factor.hip, and the device helpers."""
     import hashlib
+    import re
     h = hashlib.sha256()
-    for f in SWEEP_SOURCES:
-        with open(f, "rb") as fh:
-            h.update(fh.read())
+    text = open(SWEEP_SOURCES[0]).read()
+    parts = []
+    for pat in (r"constexpr int kPrefetch[^\n]*\n", r"constexpr int kSweepU[^\n]*\n",
+                r"template <typename S>\nstruct StepArgs \{.*?\n\};\n",
+                r"template <typename S, int G>\n__global__ __launch_bounds__\(kThreads\) void "
+                r"k_sweep\(.*?\n\}\n"):
+        mt = re.search(pat, text, flags=re.S)
+        parts.append(mt.group(0) if mt else "")
+    h.update("".join(parts).encode())
+    with open(SWEEP_SOURCES[1], "rb") as fh:
+        h.update(fh.read())
     return h.hexdigest()[:16]
 
 
