@@ -26,10 +26,10 @@ namespace {
 
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 
-constexpr int kGT = 64;       // Gram tile (kGT x kGT outputs per block)
-constexpr int kGK = 32;       // rows of A staged per round
+constexpr int kGK64 = 32;     // rows of A staged per round, 64 x 64 tiles
+constexpr int kGK128 = 16;    // rows of A staged per round, 128 x 128 tiles
 constexpr int kPC = 16;       // columns per block of a pivot step (16 threads each)
-constexpr int kGramBlocks = 1536;  // target blocks of the Gram product
+constexpr int kGramBlocks = 1024;  // target blocks of the Gram product
 
 struct GramState {
   int32_t done, info;
@@ -41,7 +41,7 @@ struct GramState {
 }  // namespace
 
 struct GramPlan {
-  int64_t m, n, kcap, nt, ntiles, S, chunk, nblk;
+  int64_t m, n, kcap, gt, nt, ntiles, S, chunk, nblk;
   size_t off_g, off_part, off_rc, off_d, off_pv, off_pos0, off_pos1, off_am0, off_am1, off_state,
       bytes;
 };
@@ -60,14 +60,18 @@ static bool make_gram_plan(int64_t m, int64_t n, int32_t dtype, const id_opts* o
   p->n = n;
   p->kcap = kcap;
   const int64_t nn = n > 0 ? n : 1, kk = kcap > 0 ? kcap : 1;
-  p->nt = ceil_div(nn, kGT);
+  // 128 x 128 tiles for wide matrices (each LDS operand feeds four products),
+  // 64 x 64 below 1024 columns (more tiles, so more blocks per row chunk)
+  p->gt = nn >= 1024 ? 128 : 64;
+  const int64_t gk = p->gt == 128 ? kGK128 : kGK64;
+  p->nt = ceil_div(nn, p->gt);
   p->ntiles = p->nt * (p->nt + 1) / 2;
   // split the rows so that the product has enough blocks
-  int64_t S = ceil_div(kGramBlocks, p->ntiles);
-  const int64_t smax = ceil_div(m > 0 ? m : 1, 4 * kGK);
+  int64_t S = ceil_div(p->gt == 128 ? kGramBlocks : 3 * kGramBlocks / 2, p->ntiles);
+  const int64_t smax = ceil_div(m > 0 ? m : 1, 4 * gk);
   if (S > smax) S = smax;
   if (S < 1) S = 1;
-  p->chunk = round_up(ceil_div(m > 0 ? m : 1, S), kGK);
+  p->chunk = round_up(ceil_div(m > 0 ? m : 1, S), gk);
   p->S = ceil_div(m > 0 ? m : 1, p->chunk);
   p->nblk = ceil_div(nn, kPC);
   size_t off = 0;
@@ -77,7 +81,7 @@ static bool make_gram_plan(int64_t m, int64_t n, int32_t dtype, const id_opts* o
     return at;
   };
   p->off_g = take((size_t)nn * nn * 8);
-  p->off_part = take((size_t)p->S * p->ntiles * kGT * kGT * 8);
+  p->off_part = take((size_t)p->S * p->ntiles * p->gt * p->gt * 8);
   p->off_rc = take((size_t)nn * kk * 8);
   p->off_d = take((size_t)nn * 8);
   p->off_pv = take((size_t)nn * 4);
@@ -96,16 +100,17 @@ size_t gram_workspace(int64_t m, int64_t n, int32_t dtype, const id_opts* o) {
   return p.bytes;
 }
 
+// 64 x 64 variant (narrow matrices: more tiles, so more blocks per row chunk).
 // Upper tile (I, J), I <= J, of the Gram matrix over rows [s chunk, (s+1) chunk):
 // P[s][t] = A(rows, I cols)^T A(rows, J cols) on the FP64 matrix cores.  Four
 // waves, each a 32 x 32 quarter as 2 x 2 16x16x4 blocks; rows of A staged in
-// LDS kGK at a time, the next round's loads issued before this round's products.
+// LDS kGK64 at a time, the next round's loads issued before this round's products.
 template <typename TA>
-__global__ __launch_bounds__(kThreads) void k_gram_partial(const TA* __restrict__ A, int64_t lda,
+__global__ __launch_bounds__(kThreads) void k_gram_partial64(const TA* __restrict__ A, int64_t lda,
                                                           int64_t m, int64_t n, int64_t nt,
                                                           int64_t chunk, double* __restrict__ P) {
-  __shared__ double As[kGK][kGT + 1];
-  __shared__ double Bs[kGK][kGT + 1];
+  __shared__ double As[kGK64][64 + 1];
+  __shared__ double Bs[kGK64][64 + 1];
   const int tid = threadIdx.x;
   const int lane = tid & 63, wv = tid >> 6, g = lane >> 4, li = lane & 15;
   // tile index -> (I, J) with I <= J, row-major over the upper triangle
@@ -116,7 +121,7 @@ __global__ __launch_bounds__(kThreads) void k_gram_partial(const TA* __restrict_
   }
   const int64_t J = I + t;
   const int64_t s = blockIdx.y;
-  const int64_t i0 = I * kGT, j0 = J * kGT;
+  const int64_t i0 = I * 64, j0 = J * 64;
   const int64_t r0 = s * chunk;
   const int64_t r1 = r0 + chunk < m ? r0 + chunk : m;
   const bool diag = I == J;
@@ -151,7 +156,7 @@ __global__ __launch_bounds__(kThreads) void k_gram_partial(const TA* __restrict_
   };
   auto products = [&]() {
 #pragma unroll
-    for (int kk = 0; kk < kGK; kk += 4) {
+    for (int kk = 0; kk < kGK64; kk += 4) {
       double a[2], b[2];
 #pragma unroll
       for (int x = 0; x < 2; ++x) a[x] = As[kk + g][wr + 16 * x + li];
@@ -165,46 +170,124 @@ __global__ __launch_bounds__(kThreads) void k_gram_partial(const TA* __restrict_
     }
   };
   load(0, r0);
-  load(1, r0 + kGK);
-  for (int64_t k0 = r0; k0 < r1; k0 += 2 * kGK) {
+  load(1, r0 + kGK64);
+  for (int64_t k0 = r0; k0 < r1; k0 += 2 * kGK64) {
     stage(0);
-    if (k0 + 2 * kGK < r1) load(0, k0 + 2 * kGK);
+    if (k0 + 2 * kGK64 < r1) load(0, k0 + 2 * kGK64);
     products();
-    if (k0 + kGK >= r1) break;
+    if (k0 + kGK64 >= r1) break;
     stage(1);
-    if (k0 + 3 * kGK < r1) load(1, k0 + 3 * kGK);
+    if (k0 + 3 * kGK64 < r1) load(1, k0 + 3 * kGK64);
     products();
   }
-  double* out = P + ((int64_t)s * gridDim.x + blockIdx.x) * (kGT * kGT);
+  double* out = P + ((int64_t)s * gridDim.x + blockIdx.x) * (64 * 64);
 #pragma unroll
   for (int x = 0; x < 2; ++x)
 #pragma unroll
     for (int y = 0; y < 2; ++y)
 #pragma unroll
       for (int r = 0; r < 4; ++r)
-        out[(wr + 16 * x + g + 4 * r) * kGT + wc + 16 * y + li] = acc[x][y][r];
+        out[(wr + 16 * x + g + 4 * r) * 64 + wc + 16 * y + li] = acc[x][y][r];
+}
+
+// Upper tile (I, J), I <= J, of the Gram matrix over rows [s chunk, (s+1) chunk):
+// P[s][t] = A(rows, I cols)^T A(rows, J cols) on the FP64 matrix cores.  Four
+// waves, each a 64 x 64 quarter as 4 x 4 16x16x4 blocks (each LDS operand
+// feeds four products); rows of A staged in LDS kGK128 at a time, the next
+// round's loads in flight during this round's products.
+template <typename TA>
+__global__ __launch_bounds__(kThreads) void k_gram_partial128(const TA* __restrict__ A, int64_t lda,
+                                                          int64_t m, int64_t n, int64_t nt,
+                                                          int64_t chunk, double* __restrict__ P) {
+  __shared__ double As[kGK128][128 + 1];
+  __shared__ double Bs[kGK128][128 + 1];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wv = tid >> 6, g = lane >> 4, li = lane & 15;
+  // tile index -> (I, J) with I <= J, row-major over the upper triangle
+  int64_t t = blockIdx.x, I = 0;
+  while (t >= nt - I) {
+    t -= nt - I;
+    ++I;
+  }
+  const int64_t J = I + t;
+  const int64_t s = blockIdx.y;
+  const int64_t i0 = I * 128, j0 = J * 128;
+  const int64_t r0 = s * chunk;
+  const int64_t r1 = r0 + chunk < m ? r0 + chunk : m;
+  const bool diag = I == J;
+  const int wr = (wv & 1) * 64, wc = (wv >> 1) * 64;
+  // load mapping: column c = tid / 2 of the tile, rows 8 (tid % 2) .. + 7
+  const int lc = tid >> 1, lr = (tid & 1) * 8;
+  f64x4 acc[4][4];
+#pragma unroll
+  for (int x = 0; x < 4; ++x)
+#pragma unroll
+    for (int y = 0; y < 4; ++y) acc[x][y] = (f64x4){0.0, 0.0, 0.0, 0.0};
+  TA ra[8], rb[8];
+  auto load = [&](int64_t k0) {
+    const int64_t ci = i0 + lc, cj = j0 + lc;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const int64_t r = k0 + lr + e;
+      ra[e] = (r < r1 && ci < n) ? A[ci * lda + r] : (TA)0;
+      rb[e] = (!diag && r < r1 && cj < n) ? A[cj * lda + r] : (TA)0;
+    }
+  };
+  load(r0);
+  for (int64_t k0 = r0; k0 < r1; k0 += kGK128) {
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      As[lr + e][lc] = (double)ra[e];
+      Bs[lr + e][lc] = diag ? (double)ra[e] : (double)rb[e];
+    }
+    __syncthreads();
+    if (k0 + kGK128 < r1) load(k0 + kGK128);  // next round's loads in flight during the products
+#pragma unroll
+    for (int kk = 0; kk < kGK128; kk += 4) {
+      double a[4], b[4];
+#pragma unroll
+      for (int x = 0; x < 4; ++x) a[x] = As[kk + g][wr + 16 * x + li];
+#pragma unroll
+      for (int y = 0; y < 4; ++y) b[y] = Bs[kk + g][wc + 16 * y + li];
+#pragma unroll
+      for (int x = 0; x < 4; ++x)
+#pragma unroll
+        for (int y = 0; y < 4; ++y)
+          acc[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[x], b[y], acc[x][y], 0, 0, 0);
+    }
+  }
+  double* out = P + ((int64_t)s * gridDim.x + blockIdx.x) * (128 * 128);
+#pragma unroll
+  for (int x = 0; x < 4; ++x)
+#pragma unroll
+    for (int y = 0; y < 4; ++y)
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        out[(wr + 16 * x + g + 4 * r) * 128 + wc + 16 * y + li] = acc[x][y][r];
 }
 
 // G = sum over the row chunks of the partial tiles (fixed order), both
 // triangles; a non-finite entry marks the input.
 __global__ __launch_bounds__(kThreads) void k_gram_reduce(const double* __restrict__ P, int64_t S,
-                                                         int64_t ntiles, int64_t nt, int64_t n,
-                                                         double* __restrict__ G,
+                                                         int64_t ntiles, int64_t nt, int64_t gt,
+                                                         int64_t n, double* __restrict__ G,
                                                          GramState* st) {
   const int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-  if (e >= ntiles * kGT * kGT) return;
-  const int64_t tile = e / (kGT * kGT), w = e % (kGT * kGT);
+  const int64_t tt = gt * gt;
+  if (e >= ntiles * tt) return;
+  const int64_t tile = e / tt, w = e % tt;
   int64_t t = tile, I = 0;
   while (t >= nt - I) {
     t -= nt - I;
     ++I;
   }
   const int64_t J = I + t;
-  const int64_t ii = I * kGT + w / kGT, jj = J * kGT + w % kGT;
+  const int64_t ii = I * gt + w / gt, jj = J * gt + w % gt;
   if (ii >= n || jj >= n) return;
-  if (I == J && w / kGT > w % kGT) return;  // diagonal tiles: upper half only (symmetric G)
+  if (I == J && w / gt > w % gt) return;  // diagonal tiles: upper half only (symmetric G)
   double v = 0.0;
-  for (int64_t s = 0; s < S; ++s) v += P[(s * ntiles + tile) * (kGT * kGT) + w];
+  for (int64_t s = 0; s < S; ++s) v += P[(s * ntiles + tile) * tt + w];
   if (!isfinite(v)) st->info = ID_INFO_NONFINITE;
   G[jj * n + ii] = v;
   G[ii * n + jj] = v;
@@ -435,13 +518,24 @@ int gram_factor_run(const void* A, int32_t dtype, int64_t m, int64_t n, int64_t 
   k_gram_state_init<<<1, 64, 0, s>>>(st);
   MPID_LAUNCH_CHECK();
   const dim3 pgrid((unsigned)pl.ntiles, (unsigned)pl.S);
-  if (dtype == ID_F64)
-    k_gram_partial<double><<<pgrid, kThreads, 0, s>>>((const double*)A, lda, m, n, pl.nt, pl.chunk, P);
-  else
-    k_gram_partial<float><<<pgrid, kThreads, 0, s>>>((const float*)A, lda, m, n, pl.nt, pl.chunk, P);
+  if (pl.gt == 128) {
+    if (dtype == ID_F64)
+      k_gram_partial128<double><<<pgrid, kThreads, 0, s>>>((const double*)A, lda, m, n, pl.nt,
+                                                           pl.chunk, P);
+    else
+      k_gram_partial128<float><<<pgrid, kThreads, 0, s>>>((const float*)A, lda, m, n, pl.nt,
+                                                          pl.chunk, P);
+  } else {
+    if (dtype == ID_F64)
+      k_gram_partial64<double><<<pgrid, kThreads, 0, s>>>((const double*)A, lda, m, n, pl.nt,
+                                                          pl.chunk, P);
+    else
+      k_gram_partial64<float><<<pgrid, kThreads, 0, s>>>((const float*)A, lda, m, n, pl.nt,
+                                                         pl.chunk, P);
+  }
   MPID_LAUNCH_CHECK();
-  k_gram_reduce<<<dim3((unsigned)ceil_div(pl.ntiles * kGT * kGT, kThreads)), kThreads, 0, s>>>(
-      P, pl.S, pl.ntiles, pl.nt, n, G, st);
+  k_gram_reduce<<<dim3((unsigned)ceil_div(pl.ntiles * pl.gt * pl.gt, kThreads)), kThreads, 0, s>>>(
+      P, pl.S, pl.ntiles, pl.nt, pl.gt, n, G, st);
   MPID_LAUNCH_CHECK();
   k_pchol_init<<<dim3((unsigned)pl.nblk), kThreads, 0, s>>>(G, n, d, pv, pos[0], am[0], st);
   MPID_LAUNCH_CHECK();
