@@ -11,8 +11,10 @@
 // recomputation.
 //
 // With G workgroups each owns a contiguous range of the working columns (its
-// sweep, F/R/downdate and panel update) and a slice of the rows for the pivot
-// column; they agree on every decision through two exchanges per pivot step:
+// sweep, F/R/downdate and panel update; the ranges are re-split evenly after
+// every panel, whose update compacts all of them into one layout) and a slice
+// of the rows for the pivot column; they agree on every decision through two
+// exchanges per pivot step (and one more per panel, after the update):
 //   A: pivot candidates, "end the panel" flags and the panel's max |F|;
 //   B: partial sums of the pivot column (||w||^2, V^T w) and its leading entry.
 // Every workgroup publishes its part with a device-scope release and reads the
@@ -309,10 +311,16 @@ __device__ void factor_item(id_batch_item& it, int g, int G, const BatchOpts& o,
   const uint64_t wt = o.wait_ticks;
   int64_t seq = 0;
 
-  // this workgroup's column range (multiples of 64 positions)
-  const int64_t span = round_up(ceil_div(n > 0 ? n : 1, G), 64);
-  const int64_t cs = (int64_t)g * span;
-  int64_t cn = n - cs < 0 ? 0 : (n - cs < span ? n - cs : span);
+  // This workgroup's column range: the live positions 0 .. ncur-1 split evenly
+  // (multiples of 4 positions); re-split after every panel, when the update
+  // compacts all ranges into one contiguous layout.
+  int64_t ncur = n, cs = 0, cn = 0;
+  auto split = [&]() {
+    const int64_t span = round_up(ceil_div(ncur > 0 ? ncur : 1, G), 4);
+    cs = (int64_t)g * span < ncur ? (int64_t)g * span : ncur;
+    cn = ncur - cs < span ? ncur - cs : span;
+  };
+  split();
 
   if (tid == 0) sm.xfail = 0;
   for (int64_t l = cs + tid; l < cs + cn; l += BT) {
@@ -410,15 +418,15 @@ __device__ void factor_item(id_batch_item& it, int g, int G, const BatchOpts& o,
       const double fscl = ldexp(1.0, sF);
       const float vscl = ldexpf(1.0f, sV);
       const double descale = ldexp(1.0, -(sF + sV));
-      int removed = 0;
-      for (int c = 0; c < jb; ++c) removed += sm.piv[c] >= cs && sm.piv[c] < cs + cn;
+      // new positions: all of the panel's pivots leave, whatever range they
+      // were in, so the next panel's layout is contiguous
       for (int64_t l0 = cs; l0 < cs + cn; l0 += 64) {
         if (tid < 64) {
           const int64_t l = l0 + tid;
           int before = 0;
           bool pv = false;
           for (int c = 0; c < jb; ++c) {
-            before += sm.piv[c] >= cs && sm.piv[c] < l;
+            before += sm.piv[c] < l;
             pv |= sm.piv[c] == l;
           }
           sm.cidx[tid] = (l < cs + cn && !pv) ? (int)(l - before) : -1;
@@ -493,8 +501,10 @@ __device__ void factor_item(id_batch_item& it, int g, int G, const BatchOpts& o,
           for (int r = 0; r < 4; ++r) {
             const int64_t orow = OP == BOP_F64 ? rs + g4 + 4 * r : rs + 4 * g4 + r;
 #pragma unroll
-            for (int lb = 0; lb < 4; ++lb)
-              wv4[lb][r] = orow < m ? Wc[orow * ldw + l0 + 16 * lb + li] : (S)0;
+            for (int lb = 0; lb < 4; ++lb) {
+              const int64_t pos = l0 + 16 * lb + li;
+              wv4[lb][r] = (orow < m && pos < cs + cn) ? Wc[orow * ldw + pos] : (S)0;
+            }
           }
           if (OP == BOP_F64) {
             double a64[8];
@@ -613,9 +623,15 @@ __device__ void factor_item(id_batch_item& it, int g, int G, const BatchOpts& o,
         __syncthreads();
       }
       off += jb;
-      cn -= removed;
+      ncur -= jb;
+      split();
       cur ^= 1;
       jb = 0;
+      // the new ranges hold columns other workgroups just wrote: wait for them
+      if (G > 1 && !exchange<BT>(xs, abortp, g, G, ++seq, wt, sm)) {
+        aborted = true;
+        break;
+      }
       mine = range_best<BT>(nu, pvflag, colid[cur], posof, cs, cn, sm);
       myflag = 0;
       myfmax = 0.0f;
