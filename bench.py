@@ -431,6 +431,11 @@ def run_config5(args):
     fwd_ms, _ = _timed(lambda: mp.column_id(A, k=k, prec=args.prec), args.steps, args.warmup)
     bwd_ms, gA = _timed(lambda: mp.backward(A, res.perm, k, res.T, gT=gT, gY=gY), args.steps,
                         args.warmup)
+    # the FP64 forward's R11 is the skeleton's R factor: the backward can reuse it
+    res64 = mp.column_id(A, k=k, prec="f64")
+    R11 = res64.R[:, :k]
+    bwdR_ms, _ = _timed(lambda: mp.backward(A, res64.perm, k, res64.T, gT=gT, gY=gY, R11=R11),
+                        args.steps, args.warmup)
     nc = n - k
     gemm_flops = 12.0 * m * k * nc
     t0 = time.perf_counter()
@@ -442,6 +447,7 @@ def run_config5(args):
                  {"workload": "8192x1024 fp32, sigma_i = exp(-i/64), k = 128, cotangents of T and Y",
                   "m": m, "n": n, "k": k},
                  {"forward_ms": fwd_ms, "rel_err_vs_oracle_adjoint": err,
+                  "backward_with_forward_R_ms": bwdR_ms,
                   "roofline": {"kernel": "id_backward (whole call)", "bound": "mfma",
                                "achieved": gemm_flops / (bwd_ms * 1e-3) / 1e12, "peak": 78.6,
                                "unit": "TFLOP/s",

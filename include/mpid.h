@@ -162,10 +162,14 @@ size_t id_backward_workspace_size(int64_t m, int64_t n, int64_t k);
  *     Tbar = gT + B^T gY(:, Jc),   X = (B^T B)^{-1} Tbar,
  *     gA(:, Jc) = B X,
  *     gA(:, J)  = (C - B T) X^T - B X T^T + gY(:, J) + gY(:, Jc) T^T.
- * (B^T B)^{-1} is applied through the R factor of an FP64 Householder QR of B.
+ * (B^T B)^{-1} is applied through an R factor of B: the caller's Rb when given
+ * (any upper-triangular R with R^T R = B^T B, e.g. R11 = the first k columns of
+ * the R that an FP64 id_factor wrote when it chose J), else that of an
+ * unpivoted FP64 Householder QR of B computed here.
  *
  *   A       [in]  m x n, lda, storage dtype "dtype"; perm [in] n int32; k [host].
  *   T       [in]  k x (n-k) float64, ldt.
+ *   Rb      [in]  k x k float64 upper triangular, ldrb >= k, or NULL.
  *   gT      [in]  k x (n-k) float64, ldgt, or NULL.
  *   gY      [in]  m x n float64, ldgy, or NULL.
  *   gA      [out] m x n float64, ldga.
@@ -173,9 +177,10 @@ size_t id_backward_workspace_size(int64_t m, int64_t n, int64_t k);
  *   info    [host,out] 0 or ID_INFO_SINGULAR (B numerically rank deficient).
  * Synchronizes "stream" before returning. */
 int id_backward(const void* A, int32_t dtype, int64_t m, int64_t n, int64_t lda,
-                const int32_t* perm, int64_t k, const double* T, int64_t ldt, const double* gT,
-                int64_t ldgt, const double* gY, int64_t ldgy, double* gA, int64_t ldga,
-                void* work, size_t work_bytes, int32_t* info, void* stream);
+                const int32_t* perm, int64_t k, const double* T, int64_t ldt, const double* Rb,
+                int64_t ldrb, const double* gT, int64_t ldgt, const double* gY, int64_t ldgy,
+                double* gA, int64_t ldga, void* work, size_t work_bytes, int32_t* info,
+                void* stream);
 
 /* ---- batched IDs -------------------------------------------------------
  * One descriptor per matrix, in DEVICE memory (so a call can be captured in a

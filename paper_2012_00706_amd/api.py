@@ -167,8 +167,11 @@ def reconstruct(A: torch.Tensor, perm: torch.Tensor, k: int, T: torch.Tensor,
     return Y
 
 
-def backward(A: torch.Tensor, perm: torch.Tensor, k: int, T: torch.Tensor, gT=None, gY=None):
-    """Adjoint with the skeleton fixed (id_backward): returns gA (float64, m x n)."""
+def backward(A: torch.Tensor, perm: torch.Tensor, k: int, T: torch.Tensor, gT=None, gY=None,
+             R11: torch.Tensor | None = None):
+    """Adjoint with the skeleton fixed (id_backward): returns gA (float64, m x n).
+    R11: optional k x k R factor of A(:, perm[:k]) (e.g. the first k columns
+    of an FP64 factor()'s R) -- saves the QR of the skeleton."""
     lib = _lib.load()
     A, lda = colmajor(A)
     m, n = A.shape
@@ -183,6 +186,11 @@ def backward(A: torch.Tensor, perm: torch.Tensor, k: int, T: torch.Tensor, gT=No
     gYc = None
     if gY is not None:
         gYc, _ = colmajor(gY.to(torch.float64))
+    Rc = None
+    if R11 is not None and k > 0:
+        if tuple(R11.shape) != (k, k) or R11.dtype != torch.float64:
+            raise ValueError("R11 must be a k x k float64 matrix")
+        Rc = R11 if R11.stride(0) == 1 else R11.t().contiguous().t()
     ws = int(lib.id_backward_workspace_size(m, n, k))
     work = torch.empty(max(ws, 1), dtype=torch.uint8, device=dev)
     info = ctypes.c_int32(0)
@@ -190,6 +198,8 @@ def backward(A: torch.Tensor, perm: torch.Tensor, k: int, T: torch.Tensor, gT=No
         rc = lib.id_backward(
             A.data_ptr(), DTYPE[A.dtype], m, n, lda, perm.data_ptr(), k,
             Tc.data_ptr() if Tc.numel() else None, ldt,
+            Rc.data_ptr() if Rc is not None else None,
+            max(Rc.stride(1), k) if Rc is not None and k > 1 else max(k, 1),
             gTc.data_ptr() if gTc is not None and gTc.numel() else None,
             max(gTc.stride(1) if (gTc is not None and (n - k) > 1) else k, 1),
             gYc.data_ptr() if gYc is not None else None,
@@ -239,13 +249,15 @@ class ColumnID(torch.autograd.Function):
     def forward(ctx, A, k=None, tol=None, prec="f64", rule="pivot_rel"):
         res = column_id(A.detach(), k=k, tol=tol, prec=prec, rule=rule)
         Y = reconstruct(A.detach(), res.perm, res.k, res.T)
-        ctx.save_for_backward(A.detach(), res.perm, res.T)
+        # an FP64 forward's R11 is the skeleton's R factor: the backward reuses it
+        R11 = res.R[:, :res.k] if prec == "f64" else res.R.new_empty(0)
+        ctx.save_for_backward(A.detach(), res.perm, res.T, R11)
         ctx.k = res.k
         ColumnID.last = res
         return res.T, Y
 
     @staticmethod
     def backward(ctx, gT, gY):
-        A, perm, T = ctx.saved_tensors
-        gA = backward(A, perm, ctx.k, T, gT=gT, gY=gY)
+        A, perm, T, R11 = ctx.saved_tensors
+        gA = backward(A, perm, ctx.k, T, gT=gT, gY=gY, R11=R11 if R11.numel() else None)
         return gA.to(A.dtype), None, None, None, None

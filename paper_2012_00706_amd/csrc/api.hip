@@ -46,11 +46,12 @@ size_t id_backward_workspace_size(int64_t m, int64_t n, int64_t k) {
 }
 
 int id_backward(const void* A, int32_t dtype, int64_t m, int64_t n, int64_t lda,
-                const int32_t* perm, int64_t k, const double* T, int64_t ldt, const double* gT,
-                int64_t ldgt, const double* gY, int64_t ldgy, double* gA, int64_t ldga,
-                void* work, size_t work_bytes, int32_t* info, void* stream) {
-  return mpid::backward_run(A, dtype, m, n, lda, perm, k, T, ldt, gT, ldgt, gY, ldgy, gA, ldga,
-                            work, work_bytes, info, (hipStream_t)stream);
+                const int32_t* perm, int64_t k, const double* T, int64_t ldt, const double* Rb,
+                int64_t ldrb, const double* gT, int64_t ldgt, const double* gY, int64_t ldgy,
+                double* gA, int64_t ldga, void* work, size_t work_bytes, int32_t* info,
+                void* stream) {
+  return mpid::backward_run(A, dtype, m, n, lda, perm, k, T, ldt, Rb, ldrb, gT, ldgt, gY, ldgy,
+                            gA, ldga, work, work_bytes, info, (hipStream_t)stream);
 }
 
 size_t id_batch_item_workspace_size(int64_t m, int64_t n, const id_opts* opts) {

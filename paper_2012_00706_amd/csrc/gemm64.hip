@@ -266,9 +266,10 @@ size_t backward_workspace(int64_t m, int64_t n, int64_t k) {
 
 template <typename TA>
 static int backward_impl(const TA* A, int64_t m, int64_t n, int64_t lda, const int32_t* perm,
-                         int64_t k, const double* T, int64_t ldt, const double* gT, int64_t ldgt,
-                         const double* gY, int64_t ldgy, double* gA, int64_t ldga, char* wb,
-                         const BwdPlan& p, int32_t* info, hipStream_t s) {
+                         int64_t k, const double* T, int64_t ldt, const double* Rb, int64_t ldrb,
+                         const double* gT, int64_t ldgt, const double* gY, int64_t ldgy,
+                         double* gA, int64_t ldga, char* wb, const BwdPlan& p, int32_t* info,
+                         hipStream_t s) {
   const int64_t nc = n - k;
   double* Bm = (double*)(wb + p.off_b);
   double* Cm = (double*)(wb + p.off_c);
@@ -293,22 +294,29 @@ static int backward_impl(const TA* A, int64_t m, int64_t n, int64_t lda, const i
     if ((rc = gather<double>(nullptr, 1, m, nullptr, k, gYJ, m, nullptr, 1, s))) return rc;
   }
   if (nc > 0) {
-    // R factor of B (unpivoted FP64 Householder QR)
-    id_opts o;
-    std::memset(&o, 0, sizeof(o));
-    o.prec = ID_PREC_F64;
-    o.k_fixed = k;
-    o.flags = ID_FLAG_NO_PIVOT;
-    int64_t kq = 0;
-    int32_t iq = 0;
-    rc = factor_run(Bm, ID_F64, m, k, m, &o, wb + p.off_fws, p.fws_bytes, permq, Rq, k, &kq, &iq,
-                    s);
-    if (rc) return rc;
-    if (iq != 0 || kq != k) {
-      *info = ID_INFO_SINGULAR;
-      return ID_OK;
+    // R factor of B: the caller's (any R with R^T R = B^T B, e.g. R11 of the
+    // FP64 factorization that chose J), else an unpivoted FP64 Householder QR
+    const double* Rf = Rb;
+    int64_t ldrf = ldrb;
+    if (!Rf) {
+      id_opts o;
+      std::memset(&o, 0, sizeof(o));
+      o.prec = ID_PREC_F64;
+      o.k_fixed = k;
+      o.flags = ID_FLAG_NO_PIVOT;
+      int64_t kq = 0;
+      int32_t iq = 0;
+      rc = factor_run(Bm, ID_F64, m, k, m, &o, wb + p.off_fws, p.fws_bytes, permq, Rq, k, &kq,
+                      &iq, s);
+      if (rc) return rc;
+      if (iq != 0 || kq != k) {
+        *info = ID_INFO_SINGULAR;
+        return ID_OK;
+      }
+      Rf = Rq;
+      ldrf = k;
     }
-    if ((rc = solve_T_run(Rq, k, k, k, nullptr, 1, dinfo, s))) return rc;
+    if ((rc = solve_T_run(Rf, ldrf, k, k, nullptr, 1, dinfo, s))) return rc;
     int32_t hinfo = 0;
     MPID_HIP(hipMemcpyAsync(&hinfo, dinfo, 4, hipMemcpyDeviceToHost, s));
     MPID_HIP(hipStreamSynchronize(s));
@@ -324,8 +332,8 @@ static int backward_impl(const TA* A, int64_t m, int64_t n, int64_t lda, const i
     }
     if (gY && (rc = gemm64_run(1, 0, k, nc, m, 1.0, Bm, m, gYc, m, 1.0, Tb, k, s))) return rc;
     // X = (B^T B)^{-1} Tbar = R^{-1} R^{-T} Tbar
-    if ((rc = trsm_upper_run(Rq, k, k, Tb, k, nc, Tb, k, 1, s))) return rc;
-    if ((rc = trsm_upper_run(Rq, k, k, Tb, k, nc, Tb, k, 0, s))) return rc;
+    if ((rc = trsm_upper_run(Rf, ldrf, k, Tb, k, nc, Tb, k, 1, s))) return rc;
+    if ((rc = trsm_upper_run(Rf, ldrf, k, Tb, k, nc, Tb, k, 0, s))) return rc;
     // Wt = B X  (= dL/dC)
     if ((rc = gemm64_run(0, 0, m, nc, k, 1.0, Bm, m, Tb, k, 0.0, Wt, m, s))) return rc;
     // Rres = C - B T (in place in Cm)
@@ -348,9 +356,10 @@ static int backward_impl(const TA* A, int64_t m, int64_t n, int64_t lda, const i
 }
 
 int backward_run(const void* A, int32_t dtype, int64_t m, int64_t n, int64_t lda,
-                 const int32_t* perm, int64_t k, const double* T, int64_t ldt, const double* gT,
-                 int64_t ldgt, const double* gY, int64_t ldgy, double* gA, int64_t ldga,
-                 void* work, size_t work_bytes, int32_t* info, hipStream_t s) {
+                 const int32_t* perm, int64_t k, const double* T, int64_t ldt, const double* Rb,
+                 int64_t ldrb, const double* gT, int64_t ldgt, const double* gY, int64_t ldgy,
+                 double* gA, int64_t ldga, void* work, size_t work_bytes, int32_t* info,
+                 hipStream_t s) {
   if (dtype != ID_F32 && dtype != ID_F64) return ID_ERR_DTYPE;
   if (!info || m < 0 || n < 0 || k < 0 || k > n) return ID_ERR_ARG;
   *info = 0;
@@ -359,14 +368,15 @@ int backward_run(const void* A, int32_t dtype, int64_t m, int64_t n, int64_t lda
   if (k > 0 && n - k > 0 && (!T || ldt < k)) return ID_ERR_ARG;
   if (gT && ldgt < (k > 0 ? k : 1)) return ID_ERR_ARG;
   if (gY && ldgy < m) return ID_ERR_ARG;
+  if (Rb && ldrb < (k > 0 ? k : 1)) return ID_ERR_ARG;
   BwdPlan p;
   if (!make_bwd_plan(m, n, k, &p)) return ID_ERR_ARG;
   if (!work || work_bytes < p.bytes) return ID_ERR_WORKSPACE;
   if (dtype == ID_F64)
-    return backward_impl<double>((const double*)A, m, n, lda, perm, k, T, ldt, gT, ldgt, gY, ldgy,
-                                 gA, ldga, (char*)work, p, info, s);
-  return backward_impl<float>((const float*)A, m, n, lda, perm, k, T, ldt, gT, ldgt, gY, ldgy, gA,
-                              ldga, (char*)work, p, info, s);
+    return backward_impl<double>((const double*)A, m, n, lda, perm, k, T, ldt, Rb, ldrb, gT, ldgt,
+                                 gY, ldgy, gA, ldga, (char*)work, p, info, s);
+  return backward_impl<float>((const float*)A, m, n, lda, perm, k, T, ldt, Rb, ldrb, gT, ldgt, gY,
+                              ldgy, gA, ldga, (char*)work, p, info, s);
 }
 
 }  // namespace mpid

@@ -101,9 +101,10 @@ int trsm_batched_run(const id_batch_item* items, int32_t batch, int64_t max_n, h
 
 size_t backward_workspace(int64_t m, int64_t n, int64_t k);
 int backward_run(const void* A, int32_t dtype, int64_t m, int64_t n, int64_t lda,
-                 const int32_t* perm, int64_t k, const double* T, int64_t ldt, const double* gT,
-                 int64_t ldgt, const double* gY, int64_t ldgy, double* gA, int64_t ldga,
-                 void* work, size_t work_bytes, int32_t* info, hipStream_t s);
+                 const int32_t* perm, int64_t k, const double* T, int64_t ldt, const double* Rb,
+                 int64_t ldrb, const double* gT, int64_t ldgt, const double* gY, int64_t ldgy,
+                 double* gA, int64_t ldga, void* work, size_t work_bytes, int32_t* info,
+                 hipStream_t s);
 
 __host__ __device__ inline int64_t round_up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
 __host__ __device__ inline int64_t ceil_div(int64_t x, int64_t a) { return (x + a - 1) / a; }

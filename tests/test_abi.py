@@ -90,8 +90,12 @@ def test_argument_errors_return_before_any_device_call(lib):
     # reconstruct: k > n
     rc = lib.id_reconstruct(fake, C["ID_F32"], 4, 3, 4, fake, 5, fake, 5, fake, 4, 0, None)
     assert rc == C["ID_ERR_ARG"]
-    rc = lib.id_backward(fake, C["ID_F32"], 4, 3, 4, fake, 5, fake, 5, None, 1, None, 4, fake, 4,
-                         fake, 1 << 20, ctypes.byref(info), None)
+    rc = lib.id_backward(fake, C["ID_F32"], 4, 3, 4, fake, 5, fake, 5, None, 1, None, 1, None, 4,
+                         fake, 4, fake, 1 << 20, ctypes.byref(info), None)
+    assert rc == C["ID_ERR_ARG"]
+    # backward: a supplied R11 with ldrb < k
+    rc = lib.id_backward(fake, C["ID_F32"], 8, 6, 8, fake, 3, fake, 3, fake, 2, None, 1, None, 8,
+                         fake, 8, fake, 1 << 20, ctypes.byref(info), None)
     assert rc == C["ID_ERR_ARG"]
     assert lib.id_backward_workspace_size(4, 3, 5) == 0
 

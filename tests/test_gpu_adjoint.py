@@ -102,3 +102,21 @@ def test_config5_adjoint_central_differences():
         worst_T = max(worst_T, abs(fd_T - an_T) / max(abs(an_T), 1e-3))
     assert worst_L <= 1e-6, worst_L
     assert worst_T <= 1e-6, worst_T
+
+
+def test_backward_with_forward_R_factor():
+    """Passing R11 of the FP64 forward factorization (the skeleton's R factor)
+    gives the same adjoint as recomputing it, to rounding."""
+    need_gpu()
+    import paper_2012_00706_amd as mp
+    rng = np.random.default_rng(5)
+    A = synth.spectrum_matrix(900, 150, synth.sigma_exp(150, 12.0), 21, 22)
+    At = to_dev(A)
+    res = mp.column_id(At, k=40, prec="f64")
+    gT = to_dev(rng.standard_normal((40, 110)))
+    gY = to_dev(rng.standard_normal((900, 150)))
+    g0 = host(mp.backward(At, res.perm, 40, res.T, gT=gT, gY=gY))
+    g1 = host(mp.backward(At, res.perm, 40, res.T, gT=gT, gY=gY, R11=res.R[:, :40]))
+    assert rel_err(g1, g0) <= 1e-12
+    ref = orc.adjoint(A, host(res.perm).astype(np.int64), 40, host(res.T), gT=host(gT), gY=host(gY))
+    assert rel_err(g1, ref) <= 1e-10
