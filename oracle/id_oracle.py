@@ -25,6 +25,9 @@ What is computed (paper references are to sections / equations / algorithms):
                     fixed.  Not in the paper: derived from T = A_J^+ A_Jc.
 * ``brute_force_best_subset`` -- exhaustive best k-column subset on tiny
                     inputs (the existence statement of Lemma 1).
+* ``sketch_id``  -- randomized ID through a sketch Y = Omega A (named as
+                    future work in Section 5, without an algorithm): the
+                    skeleton and T come from the column-pivoted QR of Y.
 
 Every function here is pinned by tests under ``tests/`` against something
 other than itself: closed forms, LAPACK's pivoted QR, least squares,
@@ -57,6 +60,8 @@ __all__ = [
     "loss_gradient",
     "brute_force_best_subset",
     "column_id",
+    "SketchIDResult",
+    "sketch_id",
 ]
 
 # Unit round-off u = 2^-t of the formats of Table 1 (IEEE half, single,
@@ -331,3 +336,37 @@ def brute_force_best_subset(A, k: int):
             best, best_s = e, S
     return best, best_s
 
+
+
+@dataclass
+class SketchIDResult:
+    perm: np.ndarray     # (n,) int64 pivot order of Y's factorization
+    k: int               # rank reached on Y
+    T: np.ndarray        # (k, n-k) interpolation coefficients, A ~ A(:, perm[:k]) T
+    Y: np.ndarray        # (l, n) the sketch Omega A
+    R: np.ndarray        # (k, n) R factor of Y in pivot order
+    margins: np.ndarray  # pivot margins of Y's factorization (see CPQRResult)
+
+
+def sketch_id(A, Omega, k: int | None = None, tol: float | None = None,
+              rule: str = "pivot_rel") -> SketchIDResult:
+    """Column ID of A from a sketch of its columns.
+
+    Section 5 names sketching as a way to cut the cost of the ID but gives no
+    algorithm; this is the usual randomized column ID.  A random test matrix
+    Omega (l x m, l << m, drawn by the caller) compresses every column of A to
+    l entries, Y = Omega A.  Since Omega is close to an isometry on the range
+    of A, the column-pivoted QR of Y (same rank rules as ``cpqr``, tolerances
+    applied to Y's residual norms) chooses the skeleton J, and the
+    coefficients solve Y(:, J) T = Y(:, Jc) through Y's R factor (eq. (8) on
+    Y): T = R_Y11^{-1} R_Y12.  When A has exact rank r <= l and Omega is
+    injective on its range, A(:, Jc) = A(:, J) T exactly for k = r.
+    """
+    A64 = np.asarray(A, dtype=np.float64)
+    Om = np.asarray(Omega, dtype=np.float64)
+    if A64.ndim != 2 or Om.ndim != 2 or Om.shape[1] != A64.shape[0]:
+        raise ValueError("sketch_id: Omega must be l x m for an m x n matrix A")
+    Y = Om @ A64
+    res = cpqr(Y, k=k, tol=tol, rule=rule)
+    T = solve_T(res.R, res.k)
+    return SketchIDResult(perm=res.perm, k=res.k, T=T, Y=Y, R=res.R, margins=res.margins)

@@ -41,6 +41,7 @@ __all__ = [
     "snapshot_matrix",
     "gaussian",
     "low_rank",
+    "sketch_matrix",
     "CONFIG_SEEDS",
 ]
 
@@ -267,3 +268,10 @@ def low_rank(m: int, n: int, r: int, seed: int, dtype=np.float64) -> np.ndarray:
     b = rng.standard_normal((m, r))
     c = rng.standard_normal((r, n))
     return np.asfortranarray((b @ c).astype(dtype))
+
+
+def sketch_matrix(l: int, m: int, seed: int) -> np.ndarray:
+    """Gaussian test matrix Omega (l x m, standard normal entries) for a sketch
+    Y = Omega A, row-major: Omega[r, i] is element r * m + i."""
+    rng = np.random.default_rng(seed)
+    return np.ascontiguousarray(rng.standard_normal((l, m)))

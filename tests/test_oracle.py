@@ -383,3 +383,74 @@ def test_pins_catch_planted_transposed_solve():
     Tb = np.linalg.solve(bad[:, :10], R[:, 10:])
     ls = _T_frozen(a, res.perm, 10)
     assert np.max(np.abs(Tb - ls)) > 1e-3
+
+
+# ---------------------------------------------------------------- sketching front end
+
+def test_sketch_identity_reduces_to_deterministic_id():
+    """Omega = I: the sketch is A itself, so the randomized ID is the ID."""
+    A = synth.spectrum_matrix(60, 25, synth.sigma_geom10(25, 6.0), 3, 4)
+    sk = orc.sketch_id(A, np.eye(60), tol=1e-4)
+    ref = orc.cpqr(A, tol=1e-4)
+    assert sk.k == ref.k and sk.perm.tolist() == ref.perm.tolist()
+    np.testing.assert_array_equal(sk.T, orc.solve_T(ref.R, ref.k))
+
+
+def test_sketch_exact_rank_recovered():
+    """Exact rank r, l > r Gaussian rows: Y has the row space of A, so the
+    ID read off Y reproduces A exactly at k = r."""
+    A = synth.low_rank(300, 70, 9, seed=12)
+    Om = synth.sketch_matrix(20, 300, seed=13)
+    sk = orc.sketch_id(A, Om, k=9)
+    J = sk.perm[:9]
+    E = A[:, sk.perm[9:]] - A[:, J] @ sk.T
+    assert np.linalg.norm(E) <= 1e-12 * np.linalg.norm(A)
+    # the adaptive rule stops at the exact rank too
+    assert orc.sketch_id(A, Om, tol=1e-10).k == 9
+
+
+def test_sketch_left_orthogonal_invariance():
+    """Replacing Omega by Q Omega (Q orthogonal l x l) leaves every residual
+    column norm and R up to row signs unchanged: same pivots, same T."""
+    A = synth.spectrum_matrix(200, 40, synth.sigma_exp(40, 5.0), 5, 6)
+    Om = synth.sketch_matrix(24, 200, seed=7)
+    Q = synth.haar(24, 24, seed=8)
+    a = orc.sketch_id(A, Om, tol=1e-3)
+    b = orc.sketch_id(A, Q @ Om, tol=1e-3)
+    upto = int(np.argmax(a.margins < 1e-8)) if np.any(a.margins < 1e-8) else a.k
+    assert a.k == b.k and a.perm[:upto].tolist() == b.perm[:upto].tolist()
+    if upto == a.k:
+        np.testing.assert_allclose(b.T, a.T, rtol=0, atol=1e-10 * max(1.0, np.abs(a.T).max()))
+    # and a scaled sketch gives the same coefficients
+    c = orc.sketch_id(A, 3.0 * Om, tol=1e-3)
+    assert c.perm.tolist() == a.perm.tolist()
+    np.testing.assert_allclose(c.T, a.T, rtol=0, atol=1e-12 * max(1.0, np.abs(a.T).max()))
+
+
+def test_sketch_Y_is_the_left_product():
+    """Y(r, l) is the dot product of row r of Omega with column l of A (brute
+    force, entry by entry)."""
+    A = synth.gaussian(17, 5, seed=21)
+    Om = synth.sketch_matrix(3, 17, seed=22)
+    sk = orc.sketch_id(A, Om, k=2)
+    for r in range(3):
+        for l in range(5):
+            assert abs(sk.Y[r, l] - math.fsum(Om[r, i] * A[i, l] for i in range(17))) <= 1e-13
+    with pytest.raises(ValueError):
+        orc.sketch_id(A, Om.T, k=2)
+
+
+def test_sketch_error_near_best_subset():
+    """On a tiny matrix the randomized ID with oversampling stays within a
+    modest factor of the best k-column subset (brute force) and of sigma_{k+1}."""
+    A = synth.spectrum_matrix(40, 10, synth.sigma_geom10(10, 3.0), 31, 32)
+    k = 3
+    best, _ = orc.brute_force_best_subset(A, k)
+    sig = np.linalg.svd(A, compute_uv=False)
+    worst = 0.0
+    for seed in range(5):
+        sk = orc.sketch_id(A, synth.sketch_matrix(k + 8, 40, seed=100 + seed), k=k)
+        e = orc.id_error(A, sk.perm, k, sk.T)[0]
+        assert e >= best * (1 - 1e-12)
+        worst = max(worst, e / sig[k])
+    assert worst <= 10.0 * math.sqrt(1 + k * (10 - k))
