@@ -182,6 +182,33 @@ int id_backward(const void* A, int32_t dtype, int64_t m, int64_t n, int64_t lda,
                 double* gA, int64_t ldga, void* work, size_t work_bytes, int32_t* info,
                 void* stream);
 
+/* ---- sketching front end ----------------------------------------------
+ * Randomized column ID (Section 5 names sketching as future work; the paper
+ * gives no algorithm).  A random test matrix Omega (l x m, l << m, drawn by
+ * the caller, e.g. standard Gaussian entries) compresses the columns of A:
+ * Y = Omega A (l x n).  id_factor on Y (FP64, any rank rule) then chooses the
+ * skeleton J = perm[0:k] and id_solve_T on Y's R gives T = R_Y11^{-1} R_Y12,
+ * so that A ~ A(:, J) T.  For A of exact rank r <= l the result is exact at
+ * k = r (Omega injective on the range of A). */
+
+/* Bytes of device workspace id_sketch needs [host]; 0 for invalid sizes. */
+size_t id_sketch_workspace_size(int64_t l, int64_t m, int64_t n);
+
+/* Y = Omega A in float64 on the FP64 matrix cores (contraction split over
+ * row chunks, chunks summed in a fixed order: the result does not depend on
+ * scheduling).
+ *   A       [in]  m x n column-major, lda >= max(1, m), dtype ID_F32/ID_F64.
+ *   Omega   [in]  l x m float64, ROW-major, ldo >= max(1, m):
+ *                 Omega(r, i) = Omega[r * ldo + i].
+ *   Y       [out] l x n float64 column-major, ldy >= max(1, l).
+ *   work    [in]  workspace of >= id_sketch_workspace_size(l, m, n) bytes,
+ *                 8-byte aligned.
+ * A non-finite entry of A or Omega propagates into Y (id_factor on Y then
+ * reports ID_INFO_NONFINITE).  m = 0 gives Y = 0.  Asynchronous on "stream". */
+int id_sketch(const void* A, int32_t dtype, int64_t m, int64_t n, int64_t lda,
+              const double* Omega, int64_t l, int64_t ldo, double* Y, int64_t ldy, void* work,
+              size_t work_bytes, void* stream);
+
 /* ---- batched IDs -------------------------------------------------------
  * One descriptor per matrix, in DEVICE memory (so a call can be captured in a
  * HIP graph and replayed).  Inputs: A, m, n, lda, work.  Outputs: perm, R, T,

@@ -19,7 +19,10 @@ from .api import (  # noqa: F401
     kcap_of,
     last_profile,
     make_opts,
+    SketchIDResult,
     reconstruct,
+    sketch,
+    sketch_id,
     solve_T,
     workspace_size,
 )

@@ -89,6 +89,9 @@ SIGNATURES = {
     "id_backward_workspace_size": (_sz, [_i64, _i64, _i64]),
     "id_backward": (ctypes.c_int, [_vp, _i32, _i64, _i64, _i64, _vp, _i64, _vp, _i64, _vp, _i64,
                                    _vp, _i64, _vp, _i64, _vp, _i64, _vp, _sz, _P(_i32), _vp]),
+    "id_sketch_workspace_size": (_sz, [_i64, _i64, _i64]),
+    "id_sketch": (ctypes.c_int, [_vp, _i32, _i64, _i64, _i64, _vp, _i64, _i64, _vp, _i64, _vp,
+                                 _sz, _vp]),
     "id_batch_item_workspace_size": (_sz, [_i64, _i64, _P(IdOpts)]),
     "id_factor_batched": (ctypes.c_int, [_vp, _i32, _vp, _i32, _vp, _i64, _i32, _P(IdOpts), _i32,
                                          _i32, _vp]),

@@ -261,3 +261,43 @@ class ColumnID(torch.autograd.Function):
         A, perm, T, R11 = ctx.saved_tensors
         gA = backward(A, perm, ctx.k, T, gT=gT, gY=gY, R11=R11 if R11.numel() else None)
         return gA.to(A.dtype), None, None, None, None
+
+
+def sketch(A: torch.Tensor, Omega: torch.Tensor) -> torch.Tensor:
+    """Y = Omega A (id_sketch): Omega l x m float64, A m x n; Y l x n float64,
+    column-major."""
+    lib = _lib.load()
+    A, lda = colmajor(A)
+    m, n = A.shape
+    if Omega.dim() != 2 or Omega.shape[1] != m or Omega.dtype != torch.float64:
+        raise ValueError("Omega must be an l x m float64 matrix")
+    if Omega.device != A.device:
+        raise ValueError("Omega and A must be on the same device")
+    l = Omega.shape[0]
+    # row-major Omega: unit stride along the rows of A
+    Om = Omega if (m <= 1 or Omega.stride(1) == 1) else Omega.contiguous()
+    ldo = max(Om.stride(0) if l > 1 else m, m, 1)
+    Y = empty_colmajor(l, n, device=A.device)
+    ws = int(lib.id_sketch_workspace_size(l, m, n))
+    work = torch.empty(max(ws, 8), dtype=torch.uint8, device=A.device)
+    with torch.cuda.device(A.device):
+        rc = lib.id_sketch(A.data_ptr(), DTYPE[A.dtype], m, n, lda, Om.data_ptr(), l, ldo,
+                           Y.data_ptr(), Y.stride(1) if n > 1 else max(l, 1), work.data_ptr(),
+                           work.numel(), _stream(A.device))
+    _lib.check(rc, "id_sketch")
+    return Y
+
+
+@dataclass
+class SketchIDResult(ColumnIDResult):
+    Y: torch.Tensor = None  # (l, n) float64 sketch Omega A
+
+
+def sketch_id(A: torch.Tensor, Omega: torch.Tensor, k=None, tol=None, rule="pivot_rel",
+              k_max=0) -> SketchIDResult:
+    """Randomized column ID: Y = Omega A (id_sketch), then the FP64
+    column-pivoted factorization of Y (id_factor) and T from Y's R
+    (id_solve_T); A ~ A[:, J] T.  Rank rules act on Y's residual norms."""
+    Y = sketch(A, Omega)
+    res = column_id(Y, k=k, tol=tol, prec="f64", rule=rule, k_max=k_max)
+    return SketchIDResult(res.J, res.T, res.perm, res.k, res.R, Y)

@@ -54,6 +54,17 @@ int id_backward(const void* A, int32_t dtype, int64_t m, int64_t n, int64_t lda,
                             gA, ldga, work, work_bytes, info, (hipStream_t)stream);
 }
 
+size_t id_sketch_workspace_size(int64_t l, int64_t m, int64_t n) {
+  return mpid::sketch_workspace(l, m, n);
+}
+
+int id_sketch(const void* A, int32_t dtype, int64_t m, int64_t n, int64_t lda,
+              const double* Omega, int64_t l, int64_t ldo, double* Y, int64_t ldy, void* work,
+              size_t work_bytes, void* stream) {
+  return mpid::sketch_run(A, dtype, m, n, lda, Omega, l, ldo, Y, ldy, work, work_bytes,
+                          (hipStream_t)stream);
+}
+
 size_t id_batch_item_workspace_size(int64_t m, int64_t n, const id_opts* opts) {
   return mpid::batch_item_workspace(m, n, opts);
 }

@@ -106,6 +106,11 @@ int backward_run(const void* A, int32_t dtype, int64_t m, int64_t n, int64_t lda
                  double* gA, int64_t ldga, void* work, size_t work_bytes, int32_t* info,
                  hipStream_t s);
 
+size_t sketch_workspace(int64_t l, int64_t m, int64_t n);
+int sketch_run(const void* A, int32_t dtype, int64_t m, int64_t n, int64_t lda, const double* Om,
+               int64_t l, int64_t ldo, double* Y, int64_t ldy, void* work, size_t work_bytes,
+               hipStream_t s);
+
 __host__ __device__ inline int64_t round_up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
 __host__ __device__ inline int64_t ceil_div(int64_t x, int64_t a) { return (x + a - 1) / a; }
 

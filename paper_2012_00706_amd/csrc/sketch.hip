@@ -1,0 +1,202 @@
+// Sketching front end: Y = Omega A on the FP64 matrix cores.
+//
+// Section 5 names sketching as a way to make the ID cheaper; the randomized
+// column ID compresses every column of A (m x n) to l << m entries with a
+// random test matrix Omega (l x m, drawn by the caller), Y = Omega A, and runs
+// the column-pivoted factorization on Y instead of A (the skeleton and T of
+// Y are those of the randomized ID of A).  This file forms Y; the
+// factorization of Y is the ordinary id_factor on an l x n FP64 matrix.
+//
+// Y is a product with a long contraction (m) and a small output (l x n), so
+// the contraction is split over row chunks: every block forms one 64 x 64
+// output tile over one chunk of rows into a partial buffer, and a second
+// kernel sums the chunks in a fixed order (deterministic results).  Omega is
+// row-major (each of its rows runs along the rows of A), so both operands are
+// read along the contraction with the same coalesced pattern.  Blocks are
+// remapped so that the tiles of one row chunk run on the same XCD: they share
+// that chunk's rows of A and of Omega through the XCD's L2.
+#include <hip/hip_runtime.h>
+
+#include <cstring>
+
+#include "mpid_internal.h"
+
+namespace mpid {
+
+namespace {
+
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kSK = 32;              // rows of the contraction staged per round
+constexpr int kSketchBlocks = 1536;  // target blocks of the partial products
+
+struct SketchPlan {
+  int64_t ntl, ntn, ntiles, S, chunk;
+  size_t bytes;
+};
+
+bool make_sketch_plan(int64_t l, int64_t m, int64_t n, SketchPlan* p) {
+  if (l < 0 || m < 0 || n < 0 || l > ((int64_t)1 << 20) || n > ((int64_t)1 << 30)) return false;
+  std::memset(p, 0, sizeof(*p));
+  const int64_t mm = m > 0 ? m : 1;
+  p->ntl = ceil_div(l > 0 ? l : 1, 64);
+  p->ntn = ceil_div(n > 0 ? n : 1, 64);
+  p->ntiles = p->ntl * p->ntn;
+  int64_t S = ceil_div(kSketchBlocks, p->ntiles);
+  const int64_t smax = ceil_div(mm, 4 * kSK);
+  if (S > smax) S = smax;
+  if (S < 1) S = 1;
+  p->chunk = round_up(ceil_div(mm, S), kSK);
+  p->S = ceil_div(mm, p->chunk);
+  p->bytes = (size_t)p->S * p->ntiles * 64 * 64 * 8;
+  return true;
+}
+
+// Partial tile (I, J) over rows [s chunk, (s+1) chunk):
+// P[s][I ntn + J](x, y) = sum_i Omega(64 I + x, i) A(i, 64 J + y).
+// Four waves, each a 32 x 32 quarter as 2 x 2 FP64 16x16x4 blocks; kSK rows
+// staged in LDS per round, two register stages of loads in flight ahead of
+// the products.
+template <typename TA>
+__global__ __launch_bounds__(kThreads) void k_sketch_partial(const double* __restrict__ Om,
+                                                           int64_t ldo, const TA* __restrict__ A,
+                                                           int64_t lda, int64_t l, int64_t m,
+                                                           int64_t n, int64_t ntn, int64_t ntiles,
+                                                           int64_t S, int64_t chunk,
+                                                           double* __restrict__ P) {
+  __shared__ double Os[kSK][64 + 1];  // Os[kk][x] = Omega(i0 + x, r0 + kk)
+  __shared__ double As[kSK][64 + 1];  // As[kk][y] = A(r0 + kk, j0 + y)
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wv = tid >> 6, g = lane >> 4, li = lane & 15;
+  // XCD-aware order: hardware block b runs on XCD b % 8; logical blocks
+  // x per .. (x + 1) per - 1 go to XCD x, chunk-major
+  const int64_t total = S * ntiles;
+  const int64_t per = gridDim.x / 8;
+  const int64_t v = (int64_t)(blockIdx.x % 8) * per + blockIdx.x / 8;
+  if (v >= total) return;
+  const int64_t s = v / ntiles, tile = v % ntiles;
+  const int64_t I = tile / ntn, J = tile % ntn;
+  const int64_t i0 = I * 64, j0 = J * 64;
+  const int64_t r0 = s * chunk;
+  const int64_t r1 = r0 + chunk < m ? r0 + chunk : m;
+  const int wr = (wv & 1) * 32, wc = (wv >> 1) * 32;
+  // load mapping: tile column c = tid / 4, contraction rows 8 (tid % 4) .. + 7
+  const int lc = tid >> 2, lr = (tid & 3) * 8;
+  const bool okO = i0 + lc < l, okA = j0 + lc < n;
+  const double* orow = Om + (okO ? (i0 + lc) * ldo : 0);
+  const TA* acol = A + (okA ? (j0 + lc) * lda : 0);
+  f64x4 acc[2][2];
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y) acc[x][y] = (f64x4){0.0, 0.0, 0.0, 0.0};
+  double ro[2][8];
+  TA ra[2][8];
+  auto load = [&](int q, int64_t k0) {
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const int64_t r = k0 + lr + e;
+      ro[q][e] = (okO && r < r1) ? orow[r] : 0.0;
+      ra[q][e] = (okA && r < r1) ? acol[r] : (TA)0;
+    }
+  };
+  auto stage = [&](int q) {
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      Os[lr + e][lc] = ro[q][e];
+      As[lr + e][lc] = (double)ra[q][e];
+    }
+    __syncthreads();
+  };
+  auto products = [&]() {
+#pragma unroll
+    for (int kk = 0; kk < kSK; kk += 4) {
+      double a[2], b[2];
+#pragma unroll
+      for (int x = 0; x < 2; ++x) a[x] = Os[kk + g][wr + 16 * x + li];
+#pragma unroll
+      for (int y = 0; y < 2; ++y) b[y] = As[kk + g][wc + 16 * y + li];
+#pragma unroll
+      for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y)
+          acc[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[x], b[y], acc[x][y], 0, 0, 0);
+    }
+  };
+  load(0, r0);
+  load(1, r0 + kSK);
+  for (int64_t k0 = r0; k0 < r1; k0 += 2 * kSK) {
+    stage(0);
+    if (k0 + 2 * kSK < r1) load(0, k0 + 2 * kSK);
+    products();
+    if (k0 + kSK >= r1) break;
+    stage(1);
+    if (k0 + 3 * kSK < r1) load(1, k0 + 3 * kSK);
+    products();
+  }
+  // acc[x][y][r] = tile(wr + 16 x + g + 4 r, wc + 16 y + li); row-major tile
+  double* out = P + (s * ntiles + tile) * (64 * 64);
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y)
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        out[(wr + 16 * x + g + 4 * r) * 64 + wc + 16 * y + li] = acc[x][y][r];
+}
+
+// Y(x, y) = sum over the row chunks of the partial tiles, in chunk order.
+__global__ __launch_bounds__(kThreads) void k_sketch_reduce(const double* __restrict__ P,
+                                                          int64_t S, int64_t ntiles, int64_t ntn,
+                                                          int64_t l, int64_t n,
+                                                          double* __restrict__ Y, int64_t ldy) {
+  const int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (e >= ntiles * 4096) return;
+  const int64_t tile = e / 4096, w = e % 4096;
+  const int64_t x = (tile / ntn) * 64 + w / 64, y = (tile % ntn) * 64 + w % 64;
+  if (x >= l || y >= n) return;
+  double v = 0.0;
+  for (int64_t s = 0; s < S; ++s) v += P[(s * ntiles + tile) * 4096 + w];
+  Y[y * ldy + x] = v;
+}
+
+template <typename TA>
+int sketch_impl(const TA* A, int64_t m, int64_t n, int64_t lda, const double* Om, int64_t l,
+                int64_t ldo, double* Y, int64_t ldy, const SketchPlan& p, double* P,
+                hipStream_t s) {
+  const int64_t total = p.S * p.ntiles;
+  k_sketch_partial<TA><<<dim3((unsigned)round_up(total, 8)), kThreads, 0, s>>>(
+      Om, ldo, A, lda, l, m, n, p.ntn, p.ntiles, p.S, p.chunk, P);
+  MPID_LAUNCH_CHECK();
+  k_sketch_reduce<<<dim3((unsigned)ceil_div(p.ntiles * 4096, kThreads)), kThreads, 0, s>>>(
+      P, p.S, p.ntiles, p.ntn, l, n, Y, ldy);
+  MPID_LAUNCH_CHECK();
+  return ID_OK;
+}
+
+}  // namespace
+
+size_t sketch_workspace(int64_t l, int64_t m, int64_t n) {
+  SketchPlan p;
+  if (!make_sketch_plan(l, m, n, &p)) return 0;
+  return p.bytes;
+}
+
+int sketch_run(const void* A, int32_t dtype, int64_t m, int64_t n, int64_t lda, const double* Om,
+               int64_t l, int64_t ldo, double* Y, int64_t ldy, void* work, size_t work_bytes,
+               hipStream_t s) {
+  if (dtype != ID_F32 && dtype != ID_F64) return ID_ERR_DTYPE;
+  SketchPlan p;
+  if (!make_sketch_plan(l, m, n, &p)) return ID_ERR_ARG;
+  if (l == 0 || n == 0) return ID_OK;
+  if (!Y || ldy < l) return ID_ERR_ARG;
+  if (m > 0 && (!A || !Om || lda < m || ldo < m)) return ID_ERR_ARG;
+  if (!work || work_bytes < p.bytes) return ID_ERR_WORKSPACE;
+  double* P = (double*)work;
+  if (dtype == ID_F64)
+    return sketch_impl<double>((const double*)A, m, n, lda, Om, l, ldo, Y, ldy, p, P, s);
+  return sketch_impl<float>((const float*)A, m, n, lda, Om, l, ldo, Y, ldy, p, P, s);
+}
+
+}  // namespace mpid

@@ -98,6 +98,17 @@ def test_argument_errors_return_before_any_device_call(lib):
                          fake, 8, fake, 1 << 20, ctypes.byref(info), None)
     assert rc == C["ID_ERR_ARG"]
     assert lib.id_backward_workspace_size(4, 3, 5) == 0
+    # sketch: ldo < m, ldy < l, small workspace, bad dtype
+    ws = lib.id_sketch_workspace_size(8, 100, 10)
+    assert ws > 0 and lib.id_sketch_workspace_size(-1, 100, 10) == 0
+    rc = lib.id_sketch(fake, C["ID_F32"], 100, 10, 100, fake, 8, 99, fake, 8, fake, ws, None)
+    assert rc == C["ID_ERR_ARG"]
+    rc = lib.id_sketch(fake, C["ID_F32"], 100, 10, 100, fake, 8, 100, fake, 7, fake, ws, None)
+    assert rc == C["ID_ERR_ARG"]
+    rc = lib.id_sketch(fake, C["ID_F32"], 100, 10, 100, fake, 8, 100, fake, 8, fake, ws - 8, None)
+    assert rc == C["ID_ERR_WORKSPACE"]
+    rc = lib.id_sketch(fake, 7, 100, 10, 100, fake, 8, 100, fake, 8, fake, ws, None)
+    assert rc == C["ID_ERR_DTYPE"]
 
 
 def test_options_validation():
