@@ -285,6 +285,84 @@ def _sweep_roofline(prof, reps=1):
             "launches_per_id": prof["sweep_launches"] / reps}
 
 
+FP64_PEAK_TFLOPS = 78.6
+
+
+def _sketch_front_end(A, l, tol, steps, sigma=None):
+    """Randomized ID through a Gaussian sketch of l rows (id_sketch, then the
+    FP64 factorization of the l x n sketch and T): whole-call time, the sketch
+    kernel's own time and FP64 matrix-core rate, rank and error."""
+    import numpy as np
+    import torch
+    import paper_2012_00706_amd as mp
+    import synth
+    m, n = A.shape
+    Om = torch.from_numpy(synth.sketch_matrix(l, m, seed=2024)).cuda()
+    sk_ms, _ = _timed(lambda: mp.sketch(A, Om), steps, 2)
+    id_ms, res = _timed(lambda: mp.sketch_id(A, Om, tol=tol), steps, 2)
+    del Om
+    E = mp.reconstruct(A, res.perm, res.k, res.T, residual=True)
+    err = spectral_norm_dev(E)
+    del E
+    torch.cuda.empty_cache()
+    flops = 2.0 * l * m * n
+    out = {"l": l, "ms_per_id": id_ms, "k": res.k, "err2": err,
+           "sketch_kernel_ms": sk_ms,
+           "sketch_roofline": {"kernel": "k_sketch_partial + k_sketch_reduce (Y = Omega A)",
+                               "bound": "mfma", "achieved": flops / (sk_ms * 1e-3) / 1e12,
+                               "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                               "frac": flops / (sk_ms * 1e-3) / 1e12 / FP64_PEAK_TFLOPS}}
+    if sigma is not None and res.k < len(sigma):
+        out["err_ratio_sigma_k1"] = err / float(sigma[res.k])
+    return out
+
+
+def run_sketch(args):
+    """Sketching front end alone on the snapshot stand-in (1,048,576 x 512
+    fp32, l = --sketch-rows Gaussian rows, tol 1e-3)."""
+    import numpy as np
+    import torch
+    import synth
+    log = lambda *a: print(*a, file=sys.stderr, flush=True)  # noqa: E731
+    A_np = synth.config3()
+    A = torch.from_numpy(np.ascontiguousarray(A_np.T)).cuda().t()
+    m, n = A_np.shape
+    del A_np
+    sk = _sketch_front_end(A, args.sketch_rows, 1e-3, args.steps)
+    log(f"[bench] sketch front end (l={args.sketch_rows}): k={sk['k']} {sk['ms_per_id']:.2f} ms/ID "
+        f"(sketch {sk['sketch_kernel_ms']:.2f} ms, {sk['sketch_roofline']['achieved']:.1f} TFLOP/s)")
+    roof = dict(sk.pop("sketch_roofline"))
+    roof["traffic"] = None
+    return _line(args, "randomized ID time through a sketch (snapshot matrix)", sk["ms_per_id"],
+                 "ms", sk["ms_per_id"], False, "f64",
+                 {"workload": f"snapshot stand-in 1,048,576 x 512 fp32, Gaussian sketch of "
+                              f"{args.sketch_rows} rows, adaptive rank at tol 1e-3", "m": m, "n": n,
+                  "l": args.sketch_rows},
+                 dict(sk, roofline=roof))
+
+
+def run_gram(args):
+    """Tall-skinny (Gram) front end alone on the snapshot stand-in
+    (1,048,576 x 512 fp32, tol 1e-3)."""
+    import numpy as np
+    import torch
+    import paper_2012_00706_amd as mp
+    import synth
+    log = lambda *a: print(*a, file=sys.stderr, flush=True)  # noqa: E731
+    A_np = synth.config3()
+    A = torch.from_numpy(np.ascontiguousarray(A_np.T)).cuda().t()
+    m, n = A_np.shape
+    del A_np
+    ms, res = _timed(lambda: mp.column_id(A, tol=1e-3, gram=True), args.steps, 2)
+    log(f"[bench] gram front end: k={res.k} {ms:.2f} ms/ID")
+    return _line(args, "column ID time through the Gram front end (snapshot matrix)", ms, "ms", ms,
+                 False, "f64", {"workload": "snapshot stand-in 1,048,576 x 512 fp32, FP64 Gram "
+                                            "matrix + pivoted Cholesky, adaptive rank at tol 1e-3",
+                                "m": m, "n": n},
+                 {"k": res.k, "gram_flops_per_id": float(m) * n * n,
+                  "note": "FP64 MFMA product over the upper triangle of 64 x 64 tiles"})
+
+
 def run_config1(args):
     """Parity workload at its own size: 1000 x 500 fp64, FP64 path, k = 50.
     Latency-bound (4 MB, cache-resident): reported in microseconds."""
@@ -348,6 +426,9 @@ def run_config3(args):
     import paper_2012_00706_amd as mp
     gms, gres = _timed(lambda: mp.column_id(A, tol=1e-3, gram=True), 3, 1)
     log(f"[bench] gram front end: k={gres.k} {gms:.2f} ms/ID")
+    sk = _sketch_front_end(A, 320, 1e-3, 3)
+    log(f"[bench] sketch front end (l=320): k={sk['k']} {sk['ms_per_id']:.2f} ms/ID "
+        f"(sketch {sk['sketch_kernel_ms']:.2f} ms, {sk['sketch_roofline']['achieved']:.1f} TFLOP/s)")
     mx = res[args.prec]
     out = _line(args, "rank-k ID time & TFLOP/s, mixed vs FP64 (snapshot matrix)", mx["tflops"],
                 "TFLOP/s", mx["ms"], True, {"mixed_bf16": "f32+bf16", "mixed_bf16x3": "f32+bf16x3",
@@ -359,6 +440,7 @@ def run_config3(args):
                  "speedup_vs_fp64": res["f64"]["ms"] / mx["ms"],
                  "gram_front_end": {"ms_per_id": gms, "k": gres.k,
                                     "speedup_vs_mixed": mx["ms"] / gms},
+                 "sketch_front_end": sk,
                  "roofline": _sweep_roofline(mx["prof"]),
                  "kernel_ms_per_id": {key: mx["prof"][key] for key in
                                       ("sweep_ms", "finalize_ms", "gemm_ms", "other_ms", "total_ms")}})
@@ -572,16 +654,19 @@ def run_accuracy(args):
 
 
 WORKLOADS = {"config1": run_config1, "config3": run_config3, "config4": run_config4,
-             "config5": run_config5, "accuracy": run_accuracy}
+             "config5": run_config5, "accuracy": run_accuracy, "sketch": run_sketch,
+             "gram": run_gram}
 
 
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawTextHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--workload", default="config2",
-                    choices=["config1", "config2", "config3", "config4", "config5", "accuracy"],
+                    choices=["config1", "config2", "config3", "config4", "config5", "accuracy",
+                             "sketch", "gram"],
                     help="config2 (default) is the headline; the others print their own line")
     ap.add_argument("--batch", type=int, default=256, help="items of the batched workload")
+    ap.add_argument("--sketch-rows", type=int, default=320, help="rows of the sketch (--workload sketch)")
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--prec", default="mixed_bf16x3",
@@ -674,6 +759,10 @@ def main():
     err_f64_same_k = spectral_norm_dev(E)
     del E, pt
     bound = 1.1 * err_f64_same_k + 10.0 * U_LOW[args.prec] * float(sigma[0])
+    sk = _sketch_front_end(A, 400, tol, args.steps, sigma)
+    log(f"[bench] sketch front end (l=400): k={sk['k']} {sk['ms_per_id']:.2f} ms/ID "
+        f"ratio={sk.get('err_ratio_sigma_k1', float('nan')):.3f} "
+        f"(sketch {sk['sketch_kernel_ms']:.3f} ms, {sk['sketch_roofline']['achieved']:.1f} TFLOP/s)")
 
     prof = mx["prof"]
     sweep_gbs = prof["sweep_bytes"] / (prof["sweep_ms"] * 1e-3) / 1e9 if prof["sweep_ms"] > 0 else 0.0
@@ -707,6 +796,7 @@ def main():
         "fp64_gpu": {"ms_per_id": f64["ms"], "k": f64["k"], "tflops": f64["tflops"],
                      "err2": f64["err2"], "err_ratio_sigma_k1": f64["ratio"]},
         "speedup_vs_fp64": f64["ms"] / mx["ms"],
+        "sketch_front_end": sk,
         "other_precisions": {p: {"ms_per_id": res[p]["ms"], "k": res[p]["k"],
                                  "err2": res[p]["err2"],
                                  "err_ratio_sigma_k1": res[p]["ratio"]} for p in extra},

@@ -15,6 +15,8 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <cstdint>
+#include <cstdlib>
 #include <cstring>
 
 #include "device_util.h"
@@ -26,10 +28,11 @@ namespace {
 
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 
-constexpr int kGK64 = 32;     // rows of A staged per round, 64 x 64 tiles
-constexpr int kGK128 = 16;    // rows of A staged per round, 128 x 128 tiles
+constexpr int kGK64 = 16;     // rows of A staged per round
 constexpr int kPC = 16;       // columns per block of a pivot step (16 threads each)
-constexpr int kGramBlocks = 1024;  // target blocks of the Gram product
+constexpr int kGramBlocks = 4096;  // target blocks of the Gram product (16 resident per CU)
+constexpr int kGR = kGK64 * 64 / kThreads;  // rows per thread per round, 64 x 64 tiles
+constexpr int kGTH = kGK64 / kGR;           // threads per tile column
 
 struct GramState {
   int32_t done, info;
@@ -60,15 +63,13 @@ static bool make_gram_plan(int64_t m, int64_t n, int32_t dtype, const id_opts* o
   p->n = n;
   p->kcap = kcap;
   const int64_t nn = n > 0 ? n : 1, kk = kcap > 0 ? kcap : 1;
-  // 128 x 128 tiles for wide matrices (each LDS operand feeds four products),
-  // 64 x 64 below 1024 columns (more tiles, so more blocks per row chunk)
-  p->gt = nn >= 1024 ? 128 : 64;
-  const int64_t gk = p->gt == 128 ? kGK128 : kGK64;
+  p->gt = 64;
+  const int64_t gk = kGK64;
   p->nt = ceil_div(nn, p->gt);
   p->ntiles = p->nt * (p->nt + 1) / 2;
   // split the rows so that the product has enough blocks
-  int64_t S = ceil_div(p->gt == 128 ? kGramBlocks : 3 * kGramBlocks / 2, p->ntiles);
-  const int64_t smax = ceil_div(m > 0 ? m : 1, 4 * gk);
+  int64_t S = ceil_div(kGramBlocks, p->ntiles);
+  const int64_t smax = ceil_div(m > 0 ? m : 1, 8 * gk);
   if (S > smax) S = smax;
   if (S < 1) S = 1;
   p->chunk = round_up(ceil_div(m > 0 ? m : 1, S), gk);
@@ -100,55 +101,97 @@ size_t gram_workspace(int64_t m, int64_t n, int32_t dtype, const id_opts* o) {
   return p.bytes;
 }
 
-// 64 x 64 variant (narrow matrices: more tiles, so more blocks per row chunk).
+template <typename T>
+struct Vec16B;  // 16-byte vector of T
+template <>
+struct Vec16B<float> {
+  typedef float4 type;
+  static constexpr int n = 4;
+};
+template <>
+struct Vec16B<double> {
+  typedef double2 type;
+  static constexpr int n = 2;
+};
+
 // Upper tile (I, J), I <= J, of the Gram matrix over rows [s chunk, (s+1) chunk):
-// P[s][t] = A(rows, I cols)^T A(rows, J cols) on the FP64 matrix cores.  Four
-// waves, each a 32 x 32 quarter as 2 x 2 16x16x4 blocks; rows of A staged in
-// LDS kGK64 at a time, the next round's loads issued before this round's products.
-template <typename TA>
-__global__ __launch_bounds__(kThreads) void k_gram_partial64(const TA* __restrict__ A, int64_t lda,
-                                                          int64_t m, int64_t n, int64_t nt,
-                                                          int64_t chunk, double* __restrict__ P) {
+// P[s][t] = A(rows, I cols)^T A(rows, J cols) on the FP64 matrix cores, 64 x 64
+// tiles.  Four waves, each a 32 x 32 quarter as 2 x 2 16x16x4 blocks; kGK64
+// rows of A staged in LDS per round, the next two rounds' loads in flight in
+// registers.  VEC: every column of A starts on a 16-byte boundary, so full
+// rounds use 16-byte loads (the scalar, bounds-checked form serves the last
+// round of a chunk and unaligned inputs).  The 1-D grid is remapped so that
+// the tiles of one row chunk run on the same XCD (they share its rows of A
+// through that XCD's L2); four waves per SIMD keep 16 blocks resident per CU.
+template <typename TA, bool VEC>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4, 4))) void
+k_gram_partial64(const TA* __restrict__ A, int64_t lda, int64_t m, int64_t n, int64_t nt,
+                 int64_t ntiles, int64_t S, int64_t chunk, double* __restrict__ P) {
   __shared__ double As[kGK64][64 + 1];
   __shared__ double Bs[kGK64][64 + 1];
   const int tid = threadIdx.x;
   const int lane = tid & 63, wv = tid >> 6, g = lane >> 4, li = lane & 15;
+  const int64_t per = gridDim.x / 8;
+  const int64_t v = (int64_t)(blockIdx.x % 8) * per + blockIdx.x / 8;
+  if (v >= S * ntiles) return;
+  const int64_t s = v / ntiles;
   // tile index -> (I, J) with I <= J, row-major over the upper triangle
-  int64_t t = blockIdx.x, I = 0;
+  int64_t t = v % ntiles, I = 0;
   while (t >= nt - I) {
     t -= nt - I;
     ++I;
   }
   const int64_t J = I + t;
-  const int64_t s = blockIdx.y;
+  const int64_t tile = v % ntiles;
   const int64_t i0 = I * 64, j0 = J * 64;
   const int64_t r0 = s * chunk;
   const int64_t r1 = r0 + chunk < m ? r0 + chunk : m;
   const bool diag = I == J;
   const int wr = (wv & 1) * 32, wc = (wv >> 1) * 32;
-  // load mapping: column c = tid / 4 of the tile, rows 8 (tid % 4) .. + 7
-  const int lc = tid >> 2, lr = (tid & 3) * 8;
+  // load mapping: tile column c = tid / kGTH, rows kGR (tid % kGTH) .. + kGR - 1
+  const int lc = tid / kGTH, lr = (tid % kGTH) * kGR;
+  const bool okI = i0 + lc < n, okJ = !diag && j0 + lc < n;
+  const TA* ci = A + (okI ? (i0 + lc) * lda : 0) + lr;
+  const TA* cj = A + (okJ ? (j0 + lc) * lda : 0) + lr;
   f64x4 acc[2][2];
 #pragma unroll
   for (int x = 0; x < 2; ++x)
 #pragma unroll
     for (int y = 0; y < 2; ++y) acc[x][y] = (f64x4){0.0, 0.0, 0.0, 0.0};
-  // two register stages of raw loads in flight ahead of the products (one
-  // stage of products is short next to a memory round trip)
-  TA ra[2][8], rb[2][8];
+  TA ra[2][kGR], rb[2][kGR];
   auto load = [&](int q, int64_t k0) {
-    const int64_t ci = i0 + lc, cj = j0 + lc;
+    if (VEC && k0 + kGK64 <= r1) {
+      typedef typename Vec16B<TA>::type VT;
+      constexpr int NV = Vec16B<TA>::n;
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      const int64_t r = k0 + lr + e;
-      ra[q][e] = (r < r1 && ci < n) ? A[ci * lda + r] : (TA)0;
-      rb[q][e] = (!diag && r < r1 && cj < n) ? A[cj * lda + r] : (TA)0;
+      for (int e = 0; e < kGR; e += NV) {
+        VT x, y;
+#pragma unroll
+        for (int c = 0; c < NV; ++c) {
+          x[c] = (TA)0;
+          y[c] = (TA)0;
+        }
+        if (okI) x = *(const VT*)(ci + k0 + e);
+        if (okJ) y = *(const VT*)(cj + k0 + e);
+#pragma unroll
+        for (int c = 0; c < NV; ++c) {
+          ra[q][e + c] = x[c];
+          rb[q][e + c] = y[c];
+        }
+      }
+      return;
+    }
+#pragma unroll
+    for (int e = 0; e < kGR; ++e) {
+      const bool in = k0 + lr + e < r1;
+      ra[q][e] = (okI && in) ? ci[k0 + e] : (TA)0;
+      rb[q][e] = (okJ && in) ? cj[k0 + e] : (TA)0;
     }
   };
   auto stage = [&](int q) {
     __syncthreads();
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
+    for (int e = 0; e < kGR; ++e) {
       As[lr + e][lc] = (double)ra[q][e];
       Bs[lr + e][lc] = diag ? (double)ra[q][e] : (double)rb[q][e];
     }
@@ -180,7 +223,7 @@ __global__ __launch_bounds__(kThreads) void k_gram_partial64(const TA* __restric
     if (k0 + 3 * kGK64 < r1) load(1, k0 + 3 * kGK64);
     products();
   }
-  double* out = P + ((int64_t)s * gridDim.x + blockIdx.x) * (64 * 64);
+  double* out = P + (s * ntiles + tile) * (64 * 64);
 #pragma unroll
   for (int x = 0; x < 2; ++x)
 #pragma unroll
@@ -188,83 +231,6 @@ __global__ __launch_bounds__(kThreads) void k_gram_partial64(const TA* __restric
 #pragma unroll
       for (int r = 0; r < 4; ++r)
         out[(wr + 16 * x + g + 4 * r) * 64 + wc + 16 * y + li] = acc[x][y][r];
-}
-
-// Upper tile (I, J), I <= J, of the Gram matrix over rows [s chunk, (s+1) chunk):
-// P[s][t] = A(rows, I cols)^T A(rows, J cols) on the FP64 matrix cores.  Four
-// waves, each a 64 x 64 quarter as 4 x 4 16x16x4 blocks (each LDS operand
-// feeds four products); rows of A staged in LDS kGK128 at a time, the next
-// round's loads in flight during this round's products.
-template <typename TA>
-__global__ __launch_bounds__(kThreads) void k_gram_partial128(const TA* __restrict__ A, int64_t lda,
-                                                          int64_t m, int64_t n, int64_t nt,
-                                                          int64_t chunk, double* __restrict__ P) {
-  __shared__ double As[kGK128][128 + 1];
-  __shared__ double Bs[kGK128][128 + 1];
-  const int tid = threadIdx.x;
-  const int lane = tid & 63, wv = tid >> 6, g = lane >> 4, li = lane & 15;
-  // tile index -> (I, J) with I <= J, row-major over the upper triangle
-  int64_t t = blockIdx.x, I = 0;
-  while (t >= nt - I) {
-    t -= nt - I;
-    ++I;
-  }
-  const int64_t J = I + t;
-  const int64_t s = blockIdx.y;
-  const int64_t i0 = I * 128, j0 = J * 128;
-  const int64_t r0 = s * chunk;
-  const int64_t r1 = r0 + chunk < m ? r0 + chunk : m;
-  const bool diag = I == J;
-  const int wr = (wv & 1) * 64, wc = (wv >> 1) * 64;
-  // load mapping: column c = tid / 2 of the tile, rows 8 (tid % 2) .. + 7
-  const int lc = tid >> 1, lr = (tid & 1) * 8;
-  f64x4 acc[4][4];
-#pragma unroll
-  for (int x = 0; x < 4; ++x)
-#pragma unroll
-    for (int y = 0; y < 4; ++y) acc[x][y] = (f64x4){0.0, 0.0, 0.0, 0.0};
-  TA ra[8], rb[8];
-  auto load = [&](int64_t k0) {
-    const int64_t ci = i0 + lc, cj = j0 + lc;
-#pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      const int64_t r = k0 + lr + e;
-      ra[e] = (r < r1 && ci < n) ? A[ci * lda + r] : (TA)0;
-      rb[e] = (!diag && r < r1 && cj < n) ? A[cj * lda + r] : (TA)0;
-    }
-  };
-  load(r0);
-  for (int64_t k0 = r0; k0 < r1; k0 += kGK128) {
-    __syncthreads();
-#pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      As[lr + e][lc] = (double)ra[e];
-      Bs[lr + e][lc] = diag ? (double)ra[e] : (double)rb[e];
-    }
-    __syncthreads();
-    if (k0 + kGK128 < r1) load(k0 + kGK128);  // next round's loads in flight during the products
-#pragma unroll
-    for (int kk = 0; kk < kGK128; kk += 4) {
-      double a[4], b[4];
-#pragma unroll
-      for (int x = 0; x < 4; ++x) a[x] = As[kk + g][wr + 16 * x + li];
-#pragma unroll
-      for (int y = 0; y < 4; ++y) b[y] = Bs[kk + g][wc + 16 * y + li];
-#pragma unroll
-      for (int x = 0; x < 4; ++x)
-#pragma unroll
-        for (int y = 0; y < 4; ++y)
-          acc[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[x], b[y], acc[x][y], 0, 0, 0);
-    }
-  }
-  double* out = P + ((int64_t)s * gridDim.x + blockIdx.x) * (128 * 128);
-#pragma unroll
-  for (int x = 0; x < 4; ++x)
-#pragma unroll
-    for (int y = 0; y < 4; ++y)
-#pragma unroll
-      for (int r = 0; r < 4; ++r)
-        out[(wr + 16 * x + g + 4 * r) * 128 + wc + 16 * y + li] = acc[x][y][r];
 }
 
 // G = sum over the row chunks of the partial tiles (fixed order), both
@@ -517,21 +483,26 @@ int gram_factor_run(const void* A, int32_t dtype, int64_t m, int64_t n, int64_t 
 
   k_gram_state_init<<<1, 64, 0, s>>>(st);
   MPID_LAUNCH_CHECK();
-  const dim3 pgrid((unsigned)pl.ntiles, (unsigned)pl.S);
-  if (pl.gt == 128) {
-    if (dtype == ID_F64)
-      k_gram_partial128<double><<<pgrid, kThreads, 0, s>>>((const double*)A, lda, m, n, pl.nt,
-                                                           pl.chunk, P);
-    else
-      k_gram_partial128<float><<<pgrid, kThreads, 0, s>>>((const float*)A, lda, m, n, pl.nt,
-                                                          pl.chunk, P);
-  } else {
-    if (dtype == ID_F64)
-      k_gram_partial64<double><<<pgrid, kThreads, 0, s>>>((const double*)A, lda, m, n, pl.nt,
-                                                          pl.chunk, P);
-    else
-      k_gram_partial64<float><<<pgrid, kThreads, 0, s>>>((const float*)A, lda, m, n, pl.nt,
-                                                         pl.chunk, P);
+  {
+    const dim3 g1((unsigned)round_up(pl.S * pl.ntiles, 8));
+    // 16-byte loads need 16-byte aligned columns of A
+    const int64_t esz = dtype == ID_F64 ? 8 : 4;
+    const bool vec = ((uintptr_t)A % 16 == 0) && ((lda * esz) % 16 == 0);
+    if (dtype == ID_F64) {
+      if (vec)
+        k_gram_partial64<double, true><<<g1, kThreads, 0, s>>>(
+            (const double*)A, lda, m, n, pl.nt, pl.ntiles, pl.S, pl.chunk, P);
+      else
+        k_gram_partial64<double, false><<<g1, kThreads, 0, s>>>(
+            (const double*)A, lda, m, n, pl.nt, pl.ntiles, pl.S, pl.chunk, P);
+    } else {
+      if (vec)
+        k_gram_partial64<float, true><<<g1, kThreads, 0, s>>>(
+            (const float*)A, lda, m, n, pl.nt, pl.ntiles, pl.S, pl.chunk, P);
+      else
+        k_gram_partial64<float, false><<<g1, kThreads, 0, s>>>(
+            (const float*)A, lda, m, n, pl.nt, pl.ntiles, pl.S, pl.chunk, P);
+    }
   }
   MPID_LAUNCH_CHECK();
   k_gram_reduce<<<dim3((unsigned)ceil_div(pl.ntiles * pl.gt * pl.gt, kThreads)), kThreads, 0, s>>>(

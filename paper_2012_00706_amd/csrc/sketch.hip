@@ -17,6 +17,8 @@
 // that chunk's rows of A and of Omega through the XCD's L2.
 #include <hip/hip_runtime.h>
 
+#include <cstdint>
+#include <cstdlib>
 #include <cstring>
 
 #include "mpid_internal.h"
@@ -27,8 +29,14 @@ namespace {
 
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 
-constexpr int kSK = 32;              // rows of the contraction staged per round
-constexpr int kSketchBlocks = 1536;  // target blocks of the partial products
+constexpr int kSK = 16;  // rows of the contraction staged per round
+constexpr int kOR = kSK * 64 / kThreads;  // contraction rows per thread per operand and round
+constexpr int kTH = kSK / kOR;            // threads per tile row / column
+
+int env_int(const char* name, int dflt) {
+  const char* v = std::getenv(name);
+  return (v && *v) ? std::atoi(v) : dflt;
+}
 
 struct SketchPlan {
   int64_t ntl, ntn, ntiles, S, chunk;
@@ -42,8 +50,9 @@ bool make_sketch_plan(int64_t l, int64_t m, int64_t n, SketchPlan* p) {
   p->ntl = ceil_div(l > 0 ? l : 1, 64);
   p->ntn = ceil_div(n > 0 ? n : 1, 64);
   p->ntiles = p->ntl * p->ntn;
-  int64_t S = ceil_div(kSketchBlocks, p->ntiles);
-  const int64_t smax = ceil_div(mm, 4 * kSK);
+  // many short chunks: ~16 resident blocks per CU and a short tail
+  int64_t S = ceil_div(env_int("MPID_SKETCH_BLOCKS", 4096), p->ntiles);
+  const int64_t smax = ceil_div(mm, 8 * kSK);
   if (S > smax) S = smax;
   if (S < 1) S = 1;
   p->chunk = round_up(ceil_div(mm, S), kSK);
@@ -52,18 +61,32 @@ bool make_sketch_plan(int64_t l, int64_t m, int64_t n, SketchPlan* p) {
   return true;
 }
 
+template <typename T>
+struct Vec2x;  // 16-byte vector of T
+template <>
+struct Vec2x<float> {
+  typedef float4 type;
+  static constexpr int n = 4;
+};
+template <>
+struct Vec2x<double> {
+  typedef double2 type;
+  static constexpr int n = 2;
+};
+
 // Partial tile (I, J) over rows [s chunk, (s+1) chunk):
 // P[s][I ntn + J](x, y) = sum_i Omega(64 I + x, i) A(i, 64 J + y).
 // Four waves, each a 32 x 32 quarter as 2 x 2 FP64 16x16x4 blocks; kSK rows
-// staged in LDS per round, two register stages of loads in flight ahead of
-// the products.
-template <typename TA>
-__global__ __launch_bounds__(kThreads) void k_sketch_partial(const double* __restrict__ Om,
-                                                           int64_t ldo, const TA* __restrict__ A,
-                                                           int64_t lda, int64_t l, int64_t m,
-                                                           int64_t n, int64_t ntn, int64_t ntiles,
-                                                           int64_t S, int64_t chunk,
-                                                           double* __restrict__ P) {
+// of both operands staged in LDS per round, the next two rounds' loads in
+// flight in registers.  VEC: every row of Omega and column of A starts on a
+// 16-byte boundary, so full rounds use 16-byte loads (the scalar, bounds-
+// checked form serves the last round of a chunk and unaligned operands).
+// Four waves per SIMD: the register budget keeps 16 blocks resident per CU.
+template <typename TA, bool VEC>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4, 4))) void
+k_sketch_partial(const double* __restrict__ Om, int64_t ldo, const TA* __restrict__ A, int64_t lda,
+                 int64_t l, int64_t m, int64_t n, int64_t ntn, int64_t ntiles, int64_t S,
+                 int64_t chunk, double* __restrict__ P) {
   __shared__ double Os[kSK][64 + 1];  // Os[kk][x] = Omega(i0 + x, r0 + kk)
   __shared__ double As[kSK][64 + 1];  // As[kk][y] = A(r0 + kk, j0 + y)
   const int tid = threadIdx.x;
@@ -80,30 +103,54 @@ __global__ __launch_bounds__(kThreads) void k_sketch_partial(const double* __res
   const int64_t r0 = s * chunk;
   const int64_t r1 = r0 + chunk < m ? r0 + chunk : m;
   const int wr = (wv & 1) * 32, wc = (wv >> 1) * 32;
-  // load mapping: tile column c = tid / 4, contraction rows 8 (tid % 4) .. + 7
-  const int lc = tid >> 2, lr = (tid & 3) * 8;
+  // load mapping: tile row / column c = tid / kTH, contraction rows
+  // kOR (tid % kTH) .. + kOR - 1 of both operands
+  const int lc = tid / kTH, lr = (tid % kTH) * kOR;
   const bool okO = i0 + lc < l, okA = j0 + lc < n;
-  const double* orow = Om + (okO ? (i0 + lc) * ldo : 0);
-  const TA* acol = A + (okA ? (j0 + lc) * lda : 0);
+  const double* orow = Om + (okO ? (i0 + lc) * ldo : 0) + lr;
+  const TA* acol = A + (okA ? (j0 + lc) * lda : 0) + lr;
   f64x4 acc[2][2];
 #pragma unroll
   for (int x = 0; x < 2; ++x)
 #pragma unroll
     for (int y = 0; y < 2; ++y) acc[x][y] = (f64x4){0.0, 0.0, 0.0, 0.0};
-  double ro[2][8];
-  TA ra[2][8];
+  double ro[2][kOR];
+  TA ra[2][kOR];
   auto load = [&](int q, int64_t k0) {
+    if (VEC && k0 + kSK <= r1) {
+      typedef typename Vec2x<TA>::type VT;
+      constexpr int NA = Vec2x<TA>::n;
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      const int64_t r = k0 + lr + e;
-      ro[q][e] = (okO && r < r1) ? orow[r] : 0.0;
-      ra[q][e] = (okA && r < r1) ? acol[r] : (TA)0;
+      for (int e = 0; e < kOR; e += 2) {
+        const double2 t = okO ? *(const double2*)(orow + k0 + e) : make_double2(0.0, 0.0);
+        ro[q][e] = t.x;
+        ro[q][e + 1] = t.y;
+      }
+#pragma unroll
+      for (int e = 0; e < kOR; e += NA) {
+        VT t;
+        if (okA) {
+          t = *(const VT*)(acol + k0 + e);
+        } else {
+#pragma unroll
+          for (int c = 0; c < NA; ++c) t[c] = (TA)0;
+        }
+#pragma unroll
+        for (int c = 0; c < NA; ++c) ra[q][e + c] = t[c];
+      }
+      return;
+    }
+#pragma unroll
+    for (int e = 0; e < kOR; ++e) {
+      const bool in = k0 + lr + e < r1;
+      ro[q][e] = (okO && in) ? orow[k0 + e] : 0.0;
+      ra[q][e] = (okA && in) ? acol[k0 + e] : (TA)0;
     }
   };
   auto stage = [&](int q) {
     __syncthreads();
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
+    for (int e = 0; e < kOR; ++e) {
       Os[lr + e][lc] = ro[q][e];
       As[lr + e][lc] = (double)ra[q][e];
     }
@@ -165,9 +212,16 @@ template <typename TA>
 int sketch_impl(const TA* A, int64_t m, int64_t n, int64_t lda, const double* Om, int64_t l,
                 int64_t ldo, double* Y, int64_t ldy, const SketchPlan& p, double* P,
                 hipStream_t s) {
-  const int64_t total = p.S * p.ntiles;
-  k_sketch_partial<TA><<<dim3((unsigned)round_up(total, 8)), kThreads, 0, s>>>(
-      Om, ldo, A, lda, l, m, n, p.ntn, p.ntiles, p.S, p.chunk, P);
+  const dim3 grid((unsigned)round_up(p.S * p.ntiles, 8));
+  // 16-byte loads need 16-byte aligned rows of Omega and columns of A
+  const bool vec = ((uintptr_t)Om % 16 == 0) && (ldo % 2 == 0) && ((uintptr_t)A % 16 == 0) &&
+                   ((lda * (int64_t)sizeof(TA)) % 16 == 0);
+  if (vec)
+    k_sketch_partial<TA, true><<<grid, kThreads, 0, s>>>(Om, ldo, A, lda, l, m, n, p.ntn,
+                                                         p.ntiles, p.S, p.chunk, P);
+  else
+    k_sketch_partial<TA, false><<<grid, kThreads, 0, s>>>(Om, ldo, A, lda, l, m, n, p.ntn,
+                                                          p.ntiles, p.S, p.chunk, P);
   MPID_LAUNCH_CHECK();
   k_sketch_reduce<<<dim3((unsigned)ceil_div(p.ntiles * 4096, kThreads)), kThreads, 0, s>>>(
       P, p.S, p.ntiles, p.ntn, l, n, Y, ldy);
