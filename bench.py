@@ -530,11 +530,15 @@ def run_config5(args):
                   "m": m, "n": n, "k": k},
                  {"forward_ms": fwd_ms, "rel_err_vs_oracle_adjoint": err,
                   "backward_with_forward_R_ms": bwdR_ms,
-                  "roofline": {"kernel": "id_backward (whole call)", "bound": "mfma",
-                               "achieved": gemm_flops / (bwd_ms * 1e-3) / 1e12, "peak": 78.6,
+                  "roofline": {"kernel": "id_backward reusing R11 (whole call: gathers, "
+                                         "two triangular solves, five FP64 MFMA products)",
+                               "bound": "mfma",
+                               "achieved": gemm_flops / (bwdR_ms * 1e-3) / 1e12, "peak": 78.6,
                                "unit": "TFLOP/s",
-                               "frac": gemm_flops / (bwd_ms * 1e-3) / 1e12 / 78.6, "traffic": None,
-                               "note": "FP64 product flops 12 m k (n-k) over the whole call"},
+                               "frac": gemm_flops / (bwdR_ms * 1e-3) / 1e12 / 78.6, "traffic": None,
+                               "note": "FP64 product flops 12 m k (n-k) over the whole call; "
+                                       "without R11 the call adds an unpivoted FP64 QR of the "
+                                       "skeleton (value)"},
                   "cpu_baseline": {"value": cpu_s * 1e3, "unit": "ms", "cores": _threads(),
                                    "kind": "oracle", "sample": "oracle adjoint, same input"}})
 

@@ -32,7 +32,8 @@ struct G64Args {
 };
 
 // C = alpha op(A) op(B) + beta Cin, 64 x 64 tile per block, K chunks of 16
-// staged through LDS, four waves of 2 x 2 FP64 16x16x4 MFMA blocks.
+// staged through LDS (the next chunk loaded into registers during the
+// products), four waves of 2 x 2 FP64 16x16x4 MFMA blocks.
 template <typename TA, typename TC>
 __global__ __launch_bounds__(kThreads) void k_gemm64(G64Args<TA, TC> a) {
   __shared__ double As[16][64 + 1];  // As[kk][i] = op(A)(m0 + i, k0 + kk)
@@ -47,7 +48,10 @@ __global__ __launch_bounds__(kThreads) void k_gemm64(G64Args<TA, TC> a) {
 #pragma unroll
     for (int y = 0; y < 2; ++y) acc[x][y] = (f64x4){0.0, 0.0, 0.0, 0.0};
 
-  for (int64_t k0 = 0; k0 < a.K; k0 += 16) {
+  // the next K chunk's operands are loaded into registers while the current
+  // one is multiplied out of LDS
+  double ra[4], rb[4];
+  auto load = [&](int64_t k0) {
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       if (a.ta == 0) {
@@ -58,23 +62,39 @@ __global__ __launch_bounds__(kThreads) void k_gemm64(G64Args<TA, TC> a) {
           const int64_t col = a.amap ? (int64_t)a.amap[gk] : gk;
           v = (double)a.A[col * a.lda + gi];
         }
-        As[kk][i] = v;
+        ra[q] = v;
       } else {
         const int kk = tid % 16, i = tid / 16 + 16 * q;
         const int64_t gi = m0 + i, gk = k0 + kk;
-        As[kk][i] = (gi < a.M && gk < a.K) ? (double)a.A[gi * a.lda + gk] : 0.0;
+        ra[q] = (gi < a.M && gk < a.K) ? (double)a.A[gi * a.lda + gk] : 0.0;
       }
       if (a.tb == 0) {
         const int kk = tid % 16, j = tid / 16 + 16 * q;
         const int64_t gj = n0 + j, gk = k0 + kk;
-        Bs[kk][j] = (gj < a.N && gk < a.K) ? a.B[gj * a.ldb + gk] : 0.0;
+        rb[q] = (gj < a.N && gk < a.K) ? a.B[gj * a.ldb + gk] : 0.0;
       } else {
         const int j = tid % 64, kk = tid / 64 + 4 * q;
         const int64_t gj = n0 + j, gk = k0 + kk;
-        Bs[kk][j] = (gj < a.N && gk < a.K) ? a.B[gk * a.ldb + gj] : 0.0;
+        rb[q] = (gj < a.N && gk < a.K) ? a.B[gk * a.ldb + gj] : 0.0;
       }
     }
+  };
+  load(0);
+  for (int64_t k0 = 0; k0 < a.K; k0 += 16) {
+    __syncthreads();  // the previous chunk's products are done with LDS
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      if (a.ta == 0)
+        As[tid / 64 + 4 * q][tid % 64] = ra[q];
+      else
+        As[tid % 16][tid / 16 + 16 * q] = ra[q];
+      if (a.tb == 0)
+        Bs[tid % 16][tid / 16 + 16 * q] = rb[q];
+      else
+        Bs[tid / 64 + 4 * q][tid % 64] = rb[q];
+    }
     __syncthreads();
+    if (k0 + 16 < a.K) load(k0 + 16);
 #pragma unroll
     for (int ks = 0; ks < 4; ++ks) {
       double af[2], bf[2];
@@ -88,7 +108,6 @@ __global__ __launch_bounds__(kThreads) void k_gemm64(G64Args<TA, TC> a) {
         for (int y = 0; y < 2; ++y)
           acc[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[x], bf[y], acc[x][y], 0, 0, 0);
     }
-    __syncthreads();
   }
   // acc[x][y][r] = C(m0 + wr + 16x + g + 4r, n0 + wc + 16y + li)
 #pragma unroll
@@ -223,8 +242,9 @@ int reconstruct_run(const void* A, int32_t dtype, int64_t m, int64_t n, int64_t 
 // ---------------------------------------------------------------- adjoint
 
 struct BwdPlan {
-  size_t off_b, off_c, off_gyj, off_gyc, off_tbar, off_wt, off_rq, off_permq, off_info, off_fws;
-  size_t fws_bytes, bytes;
+  size_t off_b, off_c, off_gyj, off_gyc, off_tbar, off_wt, off_rq, off_permq, off_info, off_fws,
+      off_btg, off_sk;
+  size_t fws_bytes, sk_bytes, bytes;
 };
 
 static bool make_bwd_plan(int64_t m, int64_t n, int64_t k, BwdPlan* p) {
@@ -255,6 +275,11 @@ static bool make_bwd_plan(int64_t m, int64_t n, int64_t k, BwdPlan* p) {
   if (!make_factor_plan(mm, kk, ID_F64, &o, &fp)) return false;
   p->fws_bytes = fp.bytes;
   p->off_fws = take(fp.bytes);
+  // B^T gY(:, Jc): k x (n-k) with a contraction over all m rows, split over
+  // row chunks (few output tiles, long contraction)
+  p->off_btg = take((size_t)kk * cc * 8);
+  p->sk_bytes = sketch_workspace(kk, mm, cc);
+  p->off_sk = take(p->sk_bytes);
   p->bytes = off;
   return true;
 }
@@ -330,7 +355,15 @@ static int backward_impl(const TA* A, int64_t m, int64_t n, int64_t lda, const i
     } else {
       if ((rc = gather<double>(nullptr, 1, k, nullptr, nc, Tb, k, nullptr, 1, s))) return rc;
     }
-    if (gY && (rc = gemm64_run(1, 0, k, nc, m, 1.0, Bm, m, gYc, m, 1.0, Tb, k, s))) return rc;
+    if (gY) {
+      // B^T as a row-major k x m matrix is B's column-major storage
+      double* btg = (double*)(wb + p.off_btg);
+      if ((rc = sketch_run(gYc, ID_F64, m, nc, m, Bm, k, m, btg, k, wb + p.off_sk, p.sk_bytes, s)))
+        return rc;
+      k_axpy_cols<<<dim3((unsigned)ceil_div(k, kThreads), (unsigned)nc), kThreads, 0, s>>>(
+          Tb, k, btg, k, k, 1.0);
+      MPID_LAUNCH_CHECK();
+    }
     // X = (B^T B)^{-1} Tbar = R^{-1} R^{-T} Tbar
     if ((rc = trsm_upper_run(Rf, ldrf, k, Tb, k, nc, Tb, k, 1, s))) return rc;
     if ((rc = trsm_upper_run(Rf, ldrf, k, Tb, k, nc, Tb, k, 0, s))) return rc;
