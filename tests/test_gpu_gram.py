@@ -45,6 +45,16 @@ def test_gram_fixed_rank_matches_oracle(m, n, k):
     _check(A, ref, *_gram_id(A, k=k))
 
 
+@pytest.mark.parametrize("m,n,k,dtype", [(3001, 150, 40, np.float32), (2999, 130, 30, np.float64)])
+def test_gram_unaligned_columns(m, n, k, dtype):
+    """Odd row counts: columns of A are not 16-byte aligned, so the Gram
+    product takes its bounds-checked scalar loads."""
+    need_gpu()
+    A = synth.spectrum_matrix(m, n, synth.sigma_geom10(min(m, n), 20.0), m + 5, n + 5).astype(dtype)
+    ref = orc.cpqr(A.astype(np.float64), k=k)
+    _check(A.astype(np.float64), ref, *_gram_id(A, k=k))
+
+
 @pytest.mark.parametrize("rule", ["pivot_rel", "frob_rel"])
 def test_gram_adaptive_rank_matches_oracle(rule):
     need_gpu()
