@@ -42,6 +42,7 @@ __all__ = [
     "gaussian",
     "low_rank",
     "sketch_matrix",
+    "tie_matrix",
     "CONFIG_SEEDS",
 ]
 
@@ -275,3 +276,21 @@ def sketch_matrix(l: int, m: int, seed: int) -> np.ndarray:
     Y = Omega A, row-major: Omega[r, i] is element r * m + i."""
     rng = np.random.default_rng(seed)
     return np.ascontiguousarray(rng.standard_normal((l, m)))
+
+
+def tie_matrix(n: int, seed: int, levels: int = 6, rows_per_col: int = 4, top: int = 40,
+               dtype=np.float64) -> np.ndarray:
+    """Columns with disjoint row supports below the first ``top`` rows, each
+    holding ``rows_per_col`` equal small-integer entries drawn from ``levels``
+    values: the columns are exactly orthogonal, every squared norm is an exact
+    integer, and many norms tie exactly (before and after any number of
+    Householder steps, which leave disjoint columns untouched)."""
+    rng = np.random.default_rng(seed)
+    m = top + rows_per_col * n
+    a = np.zeros((m, n))
+    lev = rng.integers(1, levels + 1, n)
+    sign = rng.choice([-1.0, 1.0], (rows_per_col, n))
+    for col in range(n):
+        r0 = top + rows_per_col * col
+        a[r0:r0 + rows_per_col, col] = lev[col] * sign[:, col]
+    return np.asfortranarray(a.astype(dtype))

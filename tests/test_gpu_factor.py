@@ -214,3 +214,24 @@ def test_mixed_f32_matches_fp64_pivots():
     if upto == 60:
         kappa = np.linalg.cond(ref.R[:, :60])
         assert rel_err(T, orc.solve_T(ref.R, 60)) <= 1e-5 * kappa
+
+
+@pytest.mark.parametrize("path", ["f64", "mixed_bf16x3", "gram", "batched"])
+def test_exact_ties_follow_swap_order(path):
+    """Exact norm ties at every step, across panel boundaries (n = 90, k = 70,
+    panels of 32): the pivot order equals the oracle's (first maximum in the
+    current swap order), for the FP64 and mixed paths, the Gram front end and
+    the batched kernel."""
+    need_gpu()
+    import paper_2012_00706_amd as mp
+    A = synth.tie_matrix(90, seed=5)
+    ref = orc.cpqr(A, k=70)
+    Ad = to_dev(A.astype(np.float32) if path == "mixed_bf16x3" else A)
+    if path == "batched":
+        r = mp.factor_batched([Ad], k=70, prec="f64")[0]
+        perm, k = host(r.perm), r.k
+    else:
+        res = mp.column_id(Ad, k=70, prec="f64" if path == "gram" else path, gram=path == "gram")
+        perm, k = host(res.perm), res.k
+    assert k == 70
+    assert perm[:70].tolist() == ref.perm[:70].tolist()

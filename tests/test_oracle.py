@@ -238,6 +238,20 @@ def test_tie_break_first_in_order():
     assert res.perm[0] == p_l[0]
 
 
+def test_tie_break_follows_swap_order_like_dgeqp3():
+    """Exact ties at every step (orthogonal disjoint-support columns with
+    repeated integer norms): the whole pivot order equals LAPACK's dgeqp3,
+    including ties between columns whose order earlier swaps changed."""
+    a = synth.tie_matrix(70, seed=3)
+    res = orc.cpqr(a, k=40)
+    _, p_l = scipy.linalg.qr(a, pivoting=True, mode="r")
+    assert res.perm[:40].tolist() == p_l[:40].tolist()
+    # the swap order differs from "smallest original index first" somewhere
+    lev = np.abs(a).max(axis=0)
+    naive = sorted(range(70), key=lambda c: (-lev[c], c))
+    assert res.perm[:40].tolist() != naive[:40]
+
+
 # ---------------------------------------------------------------- metamorphic
 
 def test_metamorphic_invariances(c1_small):
