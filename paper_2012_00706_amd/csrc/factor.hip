@@ -56,6 +56,8 @@ struct Vec16<double> {
 enum { OP_F64 = 0, OP_F16 = 1, OP_BF16 = 2, OP_BF16X3 = 3, OP_F32 = 4 };
 
 constexpr int kPrefetch = 4;  // sweep rows per thread loaded ahead of the pivot search
+constexpr int kFinZ = 12;     // column partials per lane and round trip in the finalization
+constexpr int kFinA = 24;     // reflector-product partials per thread and round trip
 constexpr int kSweepU = 4;    // sweep rows per thread in flight in the main loop
 
 // ----------------------------------------------------------------- plan
@@ -329,15 +331,13 @@ __global__ __launch_bounds__(kThreads) void k_sweep(StepArgs<S> a) {
   const int64_t r1 = r0 + a.Rt < a.m ? r0 + a.Rt : a.m;
 
   // ---- round trip 1: nothing here depends on the pivot (or on the exact
-  // panel offset: the rows loaded from the bound jlb on are a superset)
-  if (tid == 0) {
-    s_go = (st->done == 0 && st->end_flag == 0);
-    s_info = st->info;
-    s_r00 = st->r00;
-    s_fro2 = st->fro2;
-    s_off = st->off;
-    s_ncur = st->ncur;
-  }
+  // panel offset: the rows loaded from the bound jlb on are a superset).
+  // Loads of this round trip are unconditional, from clamped in-bounds
+  // addresses (values out of range are never used, or masked after the
+  // pivot search): conditional loads make the compiler wait for earlier
+  // ones in between, which would split the round trip.
+  // the first pivot partial of every thread (there is at least one)
+  const AmaxPart pp0 = a.amax[tid < a.namax ? tid : 0];
   // sweep geometry and the first rows of the sweep
   const int TPR = a.CW / VEC;
   const int RG = kThreads / TPR;
@@ -346,30 +346,52 @@ __global__ __launch_bounds__(kThreads) void k_sweep(StepArgs<S> a) {
   const int64_t ib = (r0 > jlb + 1 ? r0 : jlb + 1) + rg;
   const S* base = a.W + l0;
   VT pf[kPrefetch];
+  {
+    const S* pbase = a.W + (l0 < a.ncur ? l0 : 0);
 #pragma unroll
-  for (int u = 0; u < kPrefetch; ++u) {
-    const int64_t i = ib + (int64_t)u * RG;
-    if (l0 < a.ncur && i < r1) pf[u] = *(const VT*)(base + i * a.ldw);
+    for (int u = 0; u < kPrefetch; ++u) {
+      const int64_t i = ib + (int64_t)u * RG;
+      pf[u] = *(const VT*)(pbase + (i < r1 ? i : r0) * a.ldw);
+    }
   }
   // reflector entries of this thread's row: c = gi, gi + G, ...
   const int rsub = tid / G, gi = tid % G;
   const int64_t iw = r0 + rsub;
+  // (masked after the pivot search: a select next to its load is turned
+  // back into a conditional load)
   S vr[SLOTS];
+  {
+    const int64_t iwc = iw < a.m ? iw : a.m - 1;
 #pragma unroll
-  for (int q = 0; q < SLOTS; ++q) {
-    const int c = gi + G * q;
-    vr[q] = (iw >= jlb && iw < r1 && c < jj) ? a.V[(int64_t)c * a.ldv + iw] : (S)0;
+    for (int q = 0; q < SLOTS; ++q) vr[q] = a.V[(int64_t)(gi + G * q) * a.ldv + iwc];
+  }
+  // the step state, after the vector loads are on their way
+  if (tid == 0) {
+    s_go = (st->done == 0 && st->end_flag == 0);
+    s_info = st->info;
+    s_r00 = st->r00;
+    s_fro2 = st->fro2;
+    s_off = st->off;
+    s_ncur = st->ncur;
   }
   // pivot partials
   AmaxVal best = amax_none();
-  for (int q = tid; q < a.namax; q += kThreads) {
-    const AmaxPart pp = a.amax[q];
-    AmaxVal c;
-    c.v = pp.v;
-    c.s2 = pp.s2;
-    c.pos = pp.pos;
-    c.key = pp.key;
-    best = amax_combine(best, c);
+  if (tid < a.namax) {
+    best.v = pp0.v;
+    best.s2 = pp0.s2;
+    best.pos = pp0.pos;
+    best.key = pp0.key;
+  }
+  if (a.namax > kThreads) {  // uniform; more than one partial per thread
+    for (int q = tid + kThreads; q < a.namax; q += kThreads) {
+      const AmaxPart pp = a.amax[q];
+      AmaxVal c;
+      c.v = pp.v;
+      c.s2 = pp.s2;
+      c.pos = pp.pos;
+      c.key = pp.key;
+      best = amax_combine(best, c);
+    }
   }
   best = block_amax(best, ascr);  // its barriers also publish the flags
   if (!s_go) return;
@@ -431,12 +453,12 @@ __global__ __launch_bounds__(kThreads) void k_sweep(StepArgs<S> a) {
     return;
   }
 
-  // rows loaded from the lower bound jlb on but below the step hold stale
-  // workspace data (possibly not even finite): drop them, never scale by 0
-  if (!rowok) {
+  // keep the reflector entries of the step's rows only: other rows of the
+  // tile and columns c >= jj hold stale workspace data (possibly not even
+  // finite): drop them, never scale by 0
 #pragma unroll
-    for (int q = 0; q < SLOTS; ++q) vr[q] = (S)0;
-  }
+  for (int q = 0; q < SLOTS; ++q)
+    if (!(rowok && gi + G * q < jj)) vr[q] = (S)0;
 
   // ---- round trip 2: F(c, p) and the pivot column itself
   if (tid < kNbMax) gsh[tid] = tid < jj ? a.vscale[tid] * a.F[(int64_t)tid * a.ldf + p] : 0.0;
@@ -560,43 +582,90 @@ __global__ __launch_bounds__(kThreads) void k_finalize(StepArgs<S> a) {
   const int64_t l = (int64_t)blockIdx.x * kFC + cl;
   const bool lb = l < a.ncur;  // within the host's column bound
 
-  // round trip 1: loads that depend neither on each other nor on the exact
-  // step (partials below the step's row were zeroed by the sweep)
+  // Round trip 1: loads that depend neither on each other nor on the exact
+  // step (partials below the step's row were zeroed by the sweep).  They are
+  // unconditional, from clamped in-bounds addresses, and masked after the
+  // barrier: a conditional load (or a select next to its load, which the
+  // compiler turns into one) makes it wait for every earlier load first.
+  const int64_t lc = lb ? l : 0;
+  double nl = a.nu[lc], nlo = a.nuo[lc];
+  int pv = a.pvflag[lc], id = a.colid[lc];
+  double fv[kNbMax / kFL];
+#pragma unroll
+  for (int q = 0; q < kNbMax / kFL; ++q) fv[q] = a.F[(int64_t)(tl + kFL * q) * a.ldf + lc];
+  double vsc = a.vscale[tid % kNbMax];
+  // partial sums over the row tiles [t0, tend), one batch of loads per round
+  // trip (one batch covers up to kFinZ kFL = kFinA 8 = 192 tiles); indices
+  // past tend are clamped to tend - 1 (written this step, finite) and
+  // weighted 0
+  const int ca = tid % kNbMax, sla = tid / kNbMax;
+  const int64_t caa = ca < jj ? ca : 0;
+  double sz = 0.0, sa = 0.0, sn = 0.0;
+  {
+    const int64_t nbz = ceil_div(a.ntile, (int64_t)kFinZ * kFL);
+    const int64_t nba = ceil_div(a.ntile, (int64_t)kFinA * 8);
+    const int64_t nbn = ceil_div(a.ntile, (int64_t)kThreads);
+    const int64_t nbat = nbz > nba ? (nbz > nbn ? nbz : nbn) : (nba > nbn ? nba : nbn);
+    for (int64_t b = 0; b < nbat; ++b) {
+      double xz[kFinZ], xa[kFinA], wz[kFinZ], wa[kFinA];
+#pragma unroll
+      for (int u = 0; u < kFinZ; ++u) {
+        const int64_t t = a.t0 + tl + kFL * (b * kFinZ + u);
+        wz[u] = t < tend ? 1.0 : 0.0;
+        xz[u] = a.zpart[(t < tend ? t : tend - 1) * a.ldf + lc];
+      }
+#pragma unroll
+      for (int u = 0; u < kFinA; ++u) {
+        const int64_t t = a.t0 + sla + 8 * (b * kFinA + u);
+        wa[u] = t < tend ? 1.0 : 0.0;
+        xa[u] = a.auxpart[(t < tend ? t : tend - 1) * kNbMax + caa];
+      }
+      const int64_t tn = a.t0 + tid + (int64_t)kThreads * b;
+      const double wn = tn < tend ? 1.0 : 0.0;
+      const double xn = a.nrm2part[tn < tend ? tn : tend - 1];
+      // keep the scheduler from interleaving the sums with the loads (it
+      // would wait for all loads issued so far, several times per batch)
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int u = 0; u < kFinZ; ++u) sz += xz[u] * wz[u];
+#pragma unroll
+      for (int u = 0; u < kFinA; ++u) sa += xa[u] * wa[u];
+      sn += xn * wn;
+    }
+  }
   if (tid == 0) {
     s_go = (st->jb == jj + 1);
     s_alpha = st->alpha;
     s_off = st->off;
     s_ncur = st->ncur;
   }
-  double nl = 0.0, nlo = 1.0;
-  int pv = 1, id = 0;
-  if (tl == 0 && lb) {
-    nl = a.nu[l];
-    nlo = a.nuo[l];
-    pv = a.pvflag[l];
-    id = a.colid[l];
-  }
 #pragma unroll
-  for (int q = 0; q < kNbMax / kFL; ++q) {
-    const int cf = tl + kFL * q;
-    Fsh[cf][cl] = (cf < jj && lb) ? a.F[(int64_t)cf * a.ldf + l] : 0.0;
-  }
-  const double vsc = tid < jj ? a.vscale[tid] : 0.0;
-  const double pn = strided_sum(a.nrm2part, 1, a.t0 + tid, tend, kThreads);
-  {
-    const int c = tid % kNbMax, sl = tid / kNbMax;
-    ared[sl][c] = c < jj ? strided_sum(a.auxpart + c, kNbMax, a.t0 + sl, tend, 8) : 0.0;
-  }
-  red[tl][cl] = lb ? strided_sum(a.zpart + l, a.ldf, a.t0 + tl, tend, kFL) : 0.0;
+  for (int q = 0; q < kNbMax / kFL; ++q) Fsh[tl + kFL * q][cl] = fv[q];  // rows >= jj unused
+  ared[sla][ca] = sa;  // columns >= jj unused
+  red[tl][cl] = sz;    // positions >= ncur unused
 
-  const double xnorm2 = block_sum(pn, dscr);  // also publishes the LDS writes above
+  const double xnorm2 = block_sum(sn, dscr);  // also publishes the LDS writes above
   if (!s_go) return;
+  if (!(tl == 0 && lb)) {
+    nl = 0.0;
+    nlo = 1.0;
+    pv = 1;
+    id = 0;
+  }
+  if (tid >= jj) vsc = 0.0;
   // round trip 2: the step's row
   const int64_t j = s_off + jj;
   const bool lv = l < s_ncur;
-  const double wj = (tl == 0 && lv) ? (double)a.W[j * a.ldw + l] : 0.0;
-  const double vjr = tid < jj ? (double)a.V[(int64_t)tid * a.ldv + j] : 0.0;
-  const int key = (tl == 0 && lv) ? a.posof[id] : 0;
+  double wj = (double)a.W[j * a.ldw + lc];
+  double vjr = (double)a.V[(int64_t)(tid % kNbMax) * a.ldv + j];
+  // colid entries past the live columns are stale or were never written:
+  // clamp the id into range (the key is used for live columns only)
+  int key = a.posof[(uint32_t)id < (uint32_t)a.n ? id : 0];
+  if (!(tl == 0 && lv)) {
+    wj = 0.0;
+    key = 0;
+  }
+  if (tid >= jj) vjr = 0.0;
   const double alpha = s_alpha;
   double beta, tau, scale;
   if (xnorm2 == 0.0) {

@@ -235,3 +235,38 @@ def test_exact_ties_follow_swap_order(path):
         perm, k = host(res.perm), res.k
     assert k == 70
     assert perm[:70].tolist() == ref.perm[:70].tolist()
+
+
+@pytest.mark.parametrize("prec", ["f64", "mixed_bf16x3"])
+def test_stale_workspace_does_not_leak(prec):
+    """Regression: the step finalization loads per-position data for every
+    position up to the host's (lagged) column bound, past the live columns,
+    where the workspace holds stale or never-written entries.  Results with a
+    workspace filled with 0xFF bytes (NaN doubles, -1 integers) or random
+    bytes equal, bitwise, those with a zeroed one (several panels, adaptive
+    rank)."""
+    need_gpu()
+    import paper_2012_00706_amd as mp
+    A = synth.spectrum_matrix(3000, 300, synth.sigma_exp(300, 12.0), 97, 98)
+    if prec != "f64":
+        A = A.astype(np.float32)
+    Ad = to_dev(A)
+    o = mp.make_opts(tol=1e-4, prec=prec)
+    ws = mp.workspace_size(3000, 300, Ad.dtype, o)
+    outs = []
+    gen = torch.Generator(device="cuda").manual_seed(3)
+    for fill in ("zero", "ones", "random"):
+        if fill == "zero":
+            work = torch.zeros(ws, dtype=torch.uint8, device="cuda")
+        elif fill == "ones":
+            work = torch.full((ws,), 255, dtype=torch.uint8, device="cuda")
+        else:
+            work = torch.randint(0, 256, (ws,), dtype=torch.uint8, device="cuda", generator=gen)
+        fr = mp.factor(Ad, tol=1e-4, prec=prec, work=work)
+        torch.cuda.synchronize()
+        outs.append((fr.k, host(fr.perm).copy(), host(fr.R).copy()))
+    assert outs[0][0] > 64  # more than two panels
+    for k, perm, R in outs[1:]:
+        assert k == outs[0][0]
+        assert np.array_equal(perm, outs[0][1])
+        assert np.array_equal(R, outs[0][2])
