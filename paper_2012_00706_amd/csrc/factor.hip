@@ -460,9 +460,12 @@ __global__ __launch_bounds__(kThreads) void k_sweep(StepArgs<S> a) {
   for (int q = 0; q < SLOTS; ++q)
     if (!(rowok && gi + G * q < jj)) vr[q] = (S)0;
 
-  // ---- round trip 2: F(c, p) and the pivot column itself
-  if (tid < kNbMax) gsh[tid] = tid < jj ? a.vscale[tid] * a.F[(int64_t)tid * a.ldf + p] : 0.0;
-  const double wp = rowok ? (double)a.W[iw * a.ldw + p] : 0.0;  // same address on the G lanes
+  // ---- round trip 2: F(c, p) and the pivot column itself, both loads issued
+  // before either is used (unconditional, clamped; w below is masked by rowok)
+  const double wp = (double)a.W[(iw < a.m ? iw : a.m - 1) * a.ldw + p];  // same on the G lanes
+  const double fp = a.F[(int64_t)(tid % kNbMax) * a.ldf + p];
+  const double vsp = a.vscale[tid % kNbMax];
+  if (tid < kNbMax) gsh[tid] = tid < jj ? vsp * fp : 0.0;
   __syncthreads();
   double part = 0.0;
 #pragma unroll
