@@ -26,6 +26,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <cstddef>
 #include <cstring>
 
 #include "device_util.h"
@@ -54,6 +55,30 @@ struct BVec<double> {
 };
 
 enum { BOP_F64 = 0, BOP_F16 = 1, BOP_BF16 = 2, BOP_BF16X3 = 3, BOP_F32 = 4 };
+
+// pointer into the global address space
+template <typename T>
+using GlobalPtr = T __attribute__((address_space(1)))*;
+
+// id_batch_item as device code reads it: the same layout with the pointers
+// typed as global memory, so that everything derived from them uses global
+// instead of flat (generic) memory instructions (flat accesses also count as
+// LDS accesses and force extra waits)
+struct BatchItemDev {
+  GlobalPtr<const void> A;
+  int64_t m, n, lda;
+  GlobalPtr<void> work;
+  GlobalPtr<int32_t> perm;
+  GlobalPtr<double> R;
+  int64_t ldr;
+  GlobalPtr<double> T;
+  int64_t ldt;
+  int64_t k;
+  int32_t info;
+  int32_t groups;
+};
+static_assert(sizeof(BatchItemDev) == sizeof(id_batch_item), "layout");
+static_assert(offsetof(BatchItemDev, groups) == offsetof(id_batch_item, groups), "layout");
 
 }  // namespace
 
@@ -293,13 +318,16 @@ __device__ void factor_item(id_batch_item& it, int g, int G, const BatchOpts& o,
   const int64_t m = it.m, n = it.n, lda = it.lda;
   const int64_t kcap = batch_kcap(m, n, o.k_fixed, o.k_max);
   const BatchLayout L = batch_layout(m, n, kcap, (int)sizeof(S));
-  char* wb = (char*)it.work;
-  S* W[2] = {(S*)(wb + L.off_w0), (S*)(wb + L.off_w1)};
+  const BatchItemDev& di = reinterpret_cast<const BatchItemDev&>(it);
+  char* wb = (char*)di.work;
+  S* const W0 = (S*)(wb + L.off_w0);
+  S* const W1 = (S*)(wb + L.off_w1);
   S* V = (S*)(wb + L.off_v);
   double* F = (double*)(wb + L.off_f);
   double* nu = (double*)(wb + L.off_nu);
   double* nuo = (double*)(wb + L.off_nuo);
-  int* colid[2] = {(int*)(wb + L.off_colid0), (int*)(wb + L.off_colid1)};
+  int* const colid0 = (int*)(wb + L.off_colid0);
+  int* const colid1 = (int*)(wb + L.off_colid1);
   int* pvflag = (int*)(wb + L.off_pvflag);
   int* permw = (int*)(wb + L.off_permw);
   int* posof = (int*)(wb + L.off_posof);
@@ -307,7 +335,9 @@ __device__ void factor_item(id_batch_item& it, int g, int G, const BatchOpts& o,
   XSlot* xs = (XSlot*)(wb + L.off_xs);
   int* abortp = (int*)(wb + L.off_abort);
   const int64_t ldw = L.ldw, ldf = L.ldf;
-  const TA* A = (const TA*)it.A;
+  const TA* A = (const TA*)di.A;
+  int32_t* perm_out = (int32_t*)di.perm;
+  double* R_out = (double*)di.R;
   const uint64_t wt = o.wait_ticks;
   int64_t seq = 0;
 
@@ -324,11 +354,11 @@ __device__ void factor_item(id_batch_item& it, int g, int G, const BatchOpts& o,
 
   if (tid == 0) sm.xfail = 0;
   for (int64_t l = cs + tid; l < cs + cn; l += BT) {
-    colid[0][l] = (int)l;
+    colid0[l] = (int)l;
     pvflag[l] = 0;
     permw[l] = (int)l;
     posof[l] = (int)l;
-    it.perm[l] = (int)l;
+    perm_out[l] = (int)l;
   }
   if (g == 0 && tid == 0) {
     it.k = 0;
@@ -362,7 +392,7 @@ __device__ void factor_item(id_batch_item& it, int g, int G, const BatchOpts& o,
           const int64_t r = r0 + rr, c = c0 + cc;
           if (r < m && c < cend) {
             const S v = tile[cc * 65 + rr];
-            W[0][r * ldw + c] = v;
+            W0[r * ldw + c] = v;
             ss += (double)v * (double)v;
           }
         }
@@ -385,7 +415,7 @@ __device__ void factor_item(id_batch_item& it, int g, int G, const BatchOpts& o,
   int64_t off = 0, kout = 0;
   int cur = 0, jb = 0;
   double r00 = 0.0, fro2 = 0.0;
-  AmaxVal mine = range_best<BT>(nu, pvflag, colid[0], posof, cs, cn, sm);
+  AmaxVal mine = range_best<BT>(nu, pvflag, colid0, posof, cs, cn, sm);
   int myflag = 0;
   float myfmax = 0.0f;
   bool aborted = false;
@@ -403,10 +433,10 @@ __device__ void factor_item(id_batch_item& it, int g, int G, const BatchOpts& o,
       // ---- end of panel: W_next = W - V F^T on rows >= off + jb for the own
       //      columns, compacted, with the FP64 recomputation of their norms
       const int64_t jend = off + jb;
-      S* Wc = W[cur];
-      int* cid = colid[cur];
-      S* Wn = W[cur ^ 1];
-      int* cidn = colid[cur ^ 1];
+      S* Wc = cur ? W1 : W0;
+      int* cid = cur ? colid1 : colid0;
+      S* Wn = cur ? W0 : W1;
+      int* cidn = cur ? colid0 : colid1;
       const int g4 = lane >> 4, li = lane & 15;
       int sF = 0, sV = 0;
       if (OP == BOP_F16) {
@@ -632,7 +662,7 @@ __device__ void factor_item(id_batch_item& it, int g, int G, const BatchOpts& o,
         aborted = true;
         break;
       }
-      mine = range_best<BT>(nu, pvflag, colid[cur], posof, cs, cn, sm);
+      mine = range_best<BT>(nu, pvflag, cur ? colid1 : colid0, posof, cs, cn, sm);
       myflag = 0;
       myfmax = 0.0f;
       if (!exchange_a<BT>(xs, abortp, g, G, ++seq, wt, mine, 0, 0, 0.0f, sm)) {
@@ -642,8 +672,8 @@ __device__ void factor_item(id_batch_item& it, int g, int G, const BatchOpts& o,
     }
 
     const int64_t j = off + jb;
-    S* Wc = W[cur];
-    int* cid = colid[cur];
+    S* Wc = cur ? W1 : W0;
+    int* cid = cur ? colid1 : colid0;
     // ---- 1. pivot and rank rule (identical decisions in every workgroup)
     const AmaxVal best = sm.best;
     const int p = best.pos;
@@ -842,10 +872,19 @@ __device__ void factor_item(id_batch_item& it, int g, int G, const BatchOpts& o,
       const double wj = (double)Wc[j * ldw + l];
       const double y = wj + scale * sm.zc[l - cs];
       double s1 = 0.0, s2 = 0.0;
-      for (int c = 0; c < jb; ++c) {
-        const double fc = F[(int64_t)c * ldf + l];
-        s1 += fc * sm.aux[c];
-        s2 += sm.vj[c] * fc;
+      // F(c, l) for c < jb, loaded 16 rows at a time as one group (rows
+      // >= jb hold stale data: excluded by the select on the products)
+      for (int c0 = 0; c0 < jb; c0 += 16) {
+        double fc[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) fc[u] = F[(int64_t)((c0 + u) & (kNbMax - 1)) * ldf + l];
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+          const int c = c0 + u;
+          s1 += c < jb ? fc[u] * sm.aux[c & (kNbMax - 1)] : 0.0;
+          s2 += c < jb ? sm.vj[c & (kNbMax - 1)] * fc[u] : 0.0;
+        }
       }
       const double f = tau * (y - s1);
       F[(int64_t)jb * ldf + l] = f;
@@ -912,19 +951,19 @@ __device__ void factor_item(id_batch_item& it, int g, int G, const BatchOpts& o,
   // ---- outputs (workgroup 0): k, perm (swap order), R in pivot order; R11
   //      checked for numerical singularity (T is then left unwritten)
   const int64_t k = kout;
-  for (int64_t l = tid; l < n; l += BT) it.perm[l] = permw[l];
+  for (int64_t l = tid; l < n; l += BT) perm_out[l] = permw[l];
   for (int64_t e = tid; e < k * n; e += BT) {
     const int64_t c = e / k, i = e % k;
     const int id = permw[c];
-    it.R[c * it.ldr + i] = (c >= k || i <= c) ? rorig[(int64_t)id * kcap + i] : 0.0;
+    R_out[c * it.ldr + i] = (c >= k || i <= c) ? rorig[(int64_t)id * kcap + i] : 0.0;
   }
   __syncthreads();
   double sing = 0.0;
   if (k > 0) {
-    const double d0 = fabs(it.R[0]);
+    const double d0 = fabs(R_out[0]);
     const double thr = (double)n * ldexp(1.0, -53) * d0;
     for (int64_t i = tid; i < k; i += BT)
-      if (!(fabs(it.R[i * it.ldr + i]) > thr)) sing = 1.0;
+      if (!(fabs(R_out[i * it.ldr + i]) > thr)) sing = 1.0;
   }
   sing = bsum<BT>(sing, sm.dscr);
   if (tid == 0) {
