@@ -30,6 +30,7 @@ typedef double f64x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kGK64 = 16;     // rows of A staged per round
 constexpr int kPC = 16;       // columns per block of a pivot step (16 threads each)
+constexpr int kPcR = 16;      // entries of a column of R per thread held in registers
 constexpr int kGramBlocks = 4096;  // target blocks of the Gram product (16 resident per CU)
 constexpr int kGR = kGK64 * 64 / kThreads;  // rows per thread per round, 64 x 64 tiles
 constexpr int kGTH = kGK64 / kGR;           // threads per tile column
@@ -318,16 +319,45 @@ __global__ __launch_bounds__(kThreads) void k_pchol_step(PcholArgs a) {
   __shared__ int s_go;
   const int tid = threadIdx.x;
   const int64_t j = a.j;
+  const int jn = (int)j;
+  // 16 threads per column: partial sums over i = t, t + 16, ... (coalesced)
+  const int cl = tid >> 4, tq = tid & 15;
+  const int64_t l = (int64_t)blockIdx.x * kPC + cl;
+  const int64_t lc = l < a.n ? l : 0;
+  // Round trip 1, everything that does not depend on the pivot, issued as one
+  // group: unconditional loads from clamped in-bounds addresses (a
+  // conditional load makes the compiler wait for every earlier load first);
+  // values out of range are masked after the barrier.  The first kPcR
+  // entries per thread of column l of R are kept in registers.
+  const AmaxPart pp0 = a.am_in[tid < a.nblk ? tid : 0];
+  const int pin = a.pos_in[lc];
+  const int pvl = a.pv[lc];
+  const double gll = a.G[lc * a.n + lc];
+  const double* rl = a.Rc + lc * a.kcap;
+  double xr[kPcR];
+#pragma unroll
+  for (int u = 0; u < kPcR; ++u) {
+    const int i = tq + 16 * u;
+    xr[u] = rl[i < jn ? i : 0];  // entries i >= j are not used
+  }
   if (tid == 0) s_go = a.st->done == 0 && a.st->info == 0;
   AmaxVal best = amax_none();
-  for (int64_t q = tid; q < a.nblk; q += kThreads) {
-    const AmaxPart pp = a.am_in[q];
-    AmaxVal c;
-    c.v = pp.v;
-    c.s2 = pp.s2;
-    c.pos = pp.pos;
-    c.key = pp.key;
-    best = amax_combine(best, c);
+  if (tid < a.nblk) {
+    best.v = pp0.v;
+    best.s2 = pp0.s2;
+    best.pos = pp0.pos;
+    best.key = pp0.key;
+  }
+  if (a.nblk > kThreads) {  // uniform; more than one partial per thread
+    for (int64_t q = tid + kThreads; q < a.nblk; q += kThreads) {
+      const AmaxPart pp = a.am_in[q];
+      AmaxVal c;
+      c.v = pp.v;
+      c.s2 = pp.s2;
+      c.pos = pp.pos;
+      c.key = pp.key;
+      best = amax_combine(best, c);
+    }
   }
   best = block_amax(best, ascr);  // its barriers also publish s_go
   if (!s_go) return;
@@ -358,22 +388,26 @@ __global__ __launch_bounds__(kThreads) void k_pchol_step(PcholArgs a) {
     a.st->fro2 = fro2;
   }
   const double rjj = vp;  // sqrt(d_p)
-  const int jn = (int)j;
-  for (int i = tid; i < jn; i += kThreads) rp[i] = a.Rc[(int64_t)p * a.kcap + i];
+  // round trip 2: the pivot's column of R (to LDS), G(p, l), its key
+  const double gpl = a.G[(int64_t)p * a.n + lc];
   const int pos_p = a.pos_in[p];
+  for (int i = tid; i < jn; i += kThreads) rp[i] = a.Rc[(int64_t)p * a.kcap + i];
   __syncthreads();
-  // 16 threads per column: partial sums over i = t, t + 16, ... (coalesced)
-  const int cl = tid >> 4, tq = tid & 15;
-  const int64_t l = (int64_t)blockIdx.x * kPC + cl;
   AmaxVal cand = amax_none();
   if (l < a.n) {
-    const int pin = a.pos_in[l];
     const int key = l == p ? jn : (pin == jn ? pos_p : pin);
-    const bool live = !a.pv[l] && l != p;
+    const bool live = !pvl && l != p;
     double dot = 0.0, ss = 0.0;
     if (live) {
-      const double* rl = a.Rc + l * a.kcap;
-      for (int i = tq; i < jn; i += 16) {
+#pragma unroll
+      for (int u = 0; u < kPcR; ++u) {
+        const int i = tq + 16 * u;
+        if (i < jn) {
+          dot += rp[i] * xr[u];
+          ss += xr[u] * xr[u];
+        }
+      }
+      for (int i = tq + 16 * kPcR; i < jn; i += 16) {
         const double x = rl[i];
         dot += rp[i] * x;
         ss += x * x;
@@ -391,9 +425,9 @@ __global__ __launch_bounds__(kThreads) void k_pchol_step(PcholArgs a) {
         a.pv[l] = 1;
         a.d[l] = 0.0;
       } else if (live) {
-        const double r = (a.G[(int64_t)p * a.n + l] - dot) / rjj;
+        const double r = (gpl - dot) / rjj;
         a.Rc[l * a.kcap + j] = r;
-        double dl = a.G[l * a.n + l] - (ss + r * r);
+        double dl = gll - (ss + r * r);
         if (!(dl > 0.0)) dl = 0.0;
         a.d[l] = dl;
         cand.v = sqrt(dl);
