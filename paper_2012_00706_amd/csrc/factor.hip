@@ -865,32 +865,44 @@ __global__ __launch_bounds__(kThreads) void k_panel_gemm(GemmArgs<S> a) {
   // the matrix-core instruction: 256 threads = 4 position blocks x 64 lanes
   {
     const int lb = tid >> 6;
+    // (all eight loads issued before any is used: unconditional, from a
+    // clamped position; stale rows c >= jb and positions past ncur are
+    // dropped by selects on the computed values)
     if (OP == OP_F64) {
       const int64_t pos = l0 + 16 * lb + (4 * (li % 4) + li / 4);
+      const int64_t posc = pos < ncur ? pos : 0;
+      double fv[8];
+#pragma unroll
+      for (int s8 = 0; s8 < 8; ++s8) fv[s8] = a.F[(int64_t)(4 * s8 + g) * a.ldf + posc];
 #pragma unroll
       for (int s8 = 0; s8 < 8; ++s8) {
         const int c = 4 * s8 + g;
-        opa64[(lb * 8 + s8) * 64 + lane] =
-            (c < jb && pos < ncur) ? a.F[(int64_t)c * a.ldf + pos] : 0.0;
+        opa64[(lb * 8 + s8) * 64 + lane] = (c < jb && pos < ncur) ? fv[s8] * 1.0 : 0.0;
       }
     } else if (OP == OP_F32) {
       // FP32 16x16x4: step e uses k index c = 8 g + e of lane group g
       const int64_t pos = l0 + 16 * lb + li;
+      const int64_t posc = pos < ncur ? pos : 0;
+      double fv[8];
+#pragma unroll
+      for (int e = 0; e < 8; ++e) fv[e] = a.F[(int64_t)(8 * g + e) * a.ldf + posc];
 #pragma unroll
       for (int e = 0; e < 8; ++e) {
         const int c = 8 * g + e;
-        opaf[(lb * 8 + e) * 64 + lane] =
-            (c < jb && pos < ncur) ? (float)a.F[(int64_t)c * a.ldf + pos] : 0.0f;
+        opaf[(lb * 8 + e) * 64 + lane] = (c < jb && pos < ncur) ? (float)fv[e] : 0.0f;
       }
     } else {
       const int64_t pos = l0 + 16 * lb + li;
+      const int64_t posc = pos < ncur ? pos : 0;
+      double fv[8];
+#pragma unroll
+      for (int e = 0; e < 8; ++e) fv[e] = a.F[(int64_t)(8 * g + e) * a.ldf + posc];
       f16x8 xh;
       bf16x8 xb, xl;
 #pragma unroll
       for (int e = 0; e < 8; ++e) {
         const int c = 8 * g + e;
-        const float x = (c < jb && pos < ncur) ? (float)(a.F[(int64_t)c * a.ldf + pos] * fscl)
-                                                 : 0.0f;
+        const float x = (c < jb && pos < ncur) ? (float)(fv[e] * fscl) : 0.0f;
         xh[e] = (_Float16)x;
         const __bf16 h = (__bf16)x;
         xb[e] = h;
@@ -924,6 +936,20 @@ __global__ __launch_bounds__(kThreads) void k_panel_gemm(GemmArgs<S> a) {
         wt[sl][q] = (myout >= 0 && r >= rbeg && r < rend) ? rowb[o] : (S)0;
       }
     }
+    // the reflector entries of the slices' rows, with the W loads (each an
+    // unconditional load from a clamped row; selects on the computed values
+    // drop rows outside [rbeg, rend) and stale columns c >= jb)
+    S vv[SL][8];
+#pragma unroll
+    for (int sl = 0; sl < SL; ++sl) {
+      const int64_t row = rbase + 64 * (sb0 + sl) + 16 * wv + li;
+      const int64_t rowc = row < rend ? row : rend - 1;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int c = OP == OP_F64 ? 4 * e + g : 8 * g + e;
+        vv[sl][e] = a.V[(int64_t)c * a.ldv + rowc];
+      }
+    }
 #pragma unroll
     for (int sl = 0; sl < SL; ++sl) {
       const int64_t rs = rbase + 64 * (sb0 + sl);
@@ -935,7 +961,7 @@ __global__ __launch_bounds__(kThreads) void k_panel_gemm(GemmArgs<S> a) {
 #pragma unroll
         for (int s8 = 0; s8 < 8; ++s8) {
           const int c = 4 * s8 + g;
-          b64[s8] = (c < jb && rowok) ? (double)a.V[(int64_t)c * a.ldv + row] * svs[c] : 0.0;
+          b64[s8] = (c < jb && rowok) ? (double)vv[sl][s8] * svs[c] : 0.0;
         }
 #pragma unroll
         for (int lb = 0; lb < 4; ++lb) {
@@ -952,8 +978,7 @@ __global__ __launch_bounds__(kThreads) void k_panel_gemm(GemmArgs<S> a) {
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
           const int c = 8 * g + e;
-          bf[e] = (c < jb && rowok) ? (float)((double)a.V[(int64_t)c * a.ldv + row] * svs[c])
-                                    : 0.0f;
+          bf[e] = (c < jb && rowok) ? (float)((double)vv[sl][e] * svs[c]) : 0.0f;
         }
 #pragma unroll
         for (int lb = 0; lb < 4; ++lb) {
@@ -971,9 +996,8 @@ __global__ __launch_bounds__(kThreads) void k_panel_gemm(GemmArgs<S> a) {
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
           const int c = 8 * g + e;
-          const float x = (c < jb && rowok)
-                              ? (float)((double)a.V[(int64_t)c * a.ldv + row] * svs[c]) * vscl
-                              : 0.0f;
+          const float x =
+              (c < jb && rowok) ? (float)((double)vv[sl][e] * svs[c]) * vscl : 0.0f;
           if (OP == OP_F16) {
             bh[e] = (_Float16)x;
           } else {
