@@ -38,46 +38,69 @@ __device__ __forceinline__ void trsm_block(const double* __restrict__ R, int64_t
   const int lane = tid & 63, wv = tid >> 6, g = lane >> 4, li = lane & 15;
   const int la = tid % kTB, lb = tid / kTB;  // load mapping, rows fastest
   const int64_t nblk = ceil_div(k, kTB);
+  // Loads are unconditional and issued as one group (a conditional load
+  // makes the compiler wait for every earlier load first); entries outside
+  // the matrix read R(0, 0) (finite: a nonzero diagonal entry) and are
+  // weighted 0.
   auto load_R_tile = [&](int64_t i0, int64_t l0) {
     // Rs[ii][ll] = op(R)(i0 + ii, l0 + ll)
-#pragma unroll 4
+    double v[16], w[16];
+#pragma unroll
     for (int q = 0; q < 16; ++q) {
       const int b = lb + 4 * q;
-      double v = 0.0;
-      if (!trans) {
-        const int64_t i = i0 + la, l = l0 + b;
-        if (i < k && l < k) v = R[l * ldr + i];
-        Rs[la][b] = v;
-      } else {
-        const int64_t l = l0 + la, i = i0 + b;
-        if (i < k && l < k) v = R[i * ldr + l];
-        Rs[b][la] = v;
-      }
+      const int64_t i = i0 + (trans ? b : la), l = l0 + (trans ? la : b);
+      const bool in = i < k && l < k;
+      w[q] = in ? 1.0 : 0.0;
+      v[q] = R[in ? (trans ? i * ldr + l : l * ldr + i) : 0];
+    }
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int b = lb + 4 * q;
+      if (!trans)
+        Rs[la][b] = v[q] * w[q];
+      else
+        Rs[b][la] = v[q] * w[q];
     }
   };
   for (int64_t bi = 0; bi < nblk; ++bi) {
     const int64_t I = trans ? bi : nblk - 1 - bi;
     const int64_t i0 = I * kTB;
     const int ib = (int)((k - i0) < kTB ? (k - i0) : kTB);
+    {
+      // right-hand side (entries outside read B(0, 0), weighted 0) and the
+      // reciprocal diagonal, as one group of loads
+      double bv[kTC / 4], bw[kTC / 4];
 #pragma unroll
-    for (int q = 0; q < kTC / 4; ++q) {
-      const int b = lb + 4 * q;
-      const int64_t c = c0 + b;
-      As[la][b] = (la < ib && c < ncols) ? B[c * ldb + i0 + la] : 0.0;
+      for (int q = 0; q < kTC / 4; ++q) {
+        const int64_t c = c0 + lb + 4 * q;
+        const bool in = la < ib && c < ncols;
+        bw[q] = in ? 1.0 : 0.0;
+        bv[q] = B[in ? c * ldb + i0 + la : 0];
+      }
+      const int td = tid < ib ? tid : 0;
+      const double dg = R[(i0 + td) * ldr + i0 + td];
+#pragma unroll
+      for (int q = 0; q < kTC / 4; ++q) As[la][lb + 4 * q] = bv[q] * bw[q];
+      if (tid < kTB) rinv[tid] = tid < ib ? 1.0 / dg : 0.0;
     }
-    if (tid < kTB) rinv[tid] = tid < ib ? 1.0 / R[(i0 + tid) * ldr + i0 + tid] : 0.0;
     f64x4 acc = {0.0, 0.0, 0.0, 0.0};
     for (int64_t bl = 0; bl < bi; ++bl) {
       const int64_t L = trans ? bl : nblk - 1 - bl;
       const int64_t l0 = L * kTB;
       __syncthreads();
-      load_R_tile(i0, l0);
+      // solved rows of block L (rows past k read row k - 1 and columns past
+      // ncols read column ncols - 1: both solved by this block, finite;
+      // weighted 0), issued with the R tile
+      double xv[kTC / 4], xw[kTC / 4];
 #pragma unroll
       for (int q = 0; q < kTC / 4; ++q) {
-        const int b = lb + 4 * q;
-        const int64_t c = c0 + b, xr = l0 + la;
-        Xs[la][b] = (xr < k && c < ncols) ? X[c * ldx + xr] : 0.0;
+        const int64_t c = c0 + lb + 4 * q, xr = l0 + la;
+        xw[q] = (xr < k && c < ncols) ? 1.0 : 0.0;
+        xv[q] = X[(c < ncols ? c : ncols - 1) * ldx + (xr < k ? xr : k - 1)];
       }
+      load_R_tile(i0, l0);
+#pragma unroll
+      for (int q = 0; q < kTC / 4; ++q) Xs[la][lb + 4 * q] = xv[q] * xw[q];
       __syncthreads();
 #pragma unroll
       for (int ks = 0; ks < kTB / 4; ++ks)
