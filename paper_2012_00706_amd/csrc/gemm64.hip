@@ -50,32 +50,56 @@ __global__ __launch_bounds__(kThreads) void k_gemm64(G64Args<TA, TC> a) {
 
   // the next K chunk's operands are loaded into registers while the current
   // one is multiplied out of LDS
-  double ra[4], rb[4];
+  // Loads are unconditional, from indices clamped into the operands, and
+  // issued as one group (a conditional load makes the compiler wait for every
+  // earlier load first); entries outside the operands are weighted 0.  A
+  // clamped entry is a real entry of the same operand row or column, so a
+  // non-finite value there already reaches every output it could reach here.
+  double ra[4], rb[4], wa[4], wb[4];
   auto load = [&](int64_t k0) {
+    // op(A) columns through the column map: the four map entries first
+    int64_t col[4];
+    if (a.ta == 0 && a.amap) {  // uniform
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int64_t gk = k0 + tid / 64 + 4 * q;
+        col[q] = (int64_t)a.amap[gk < a.K ? gk : a.K - 1];
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int64_t gk = k0 + tid / 64 + 4 * q;
+        col[q] = gk < a.K ? gk : a.K - 1;
+      }
+    }
+    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       if (a.ta == 0) {
         const int i = tid % 64, kk = tid / 64 + 4 * q;
         const int64_t gi = m0 + i, gk = k0 + kk;
-        double v = 0.0;
-        if (gi < a.M && gk < a.K) {
-          const int64_t col = a.amap ? (int64_t)a.amap[gk] : gk;
-          v = (double)a.A[col * a.lda + gi];
-        }
-        ra[q] = v;
+        const int64_t gic = gi < a.M ? gi : a.M - 1;
+        wa[q] = (gi < a.M && gk < a.K) ? 1.0 : 0.0;
+        ra[q] = (double)a.A[col[q] * a.lda + gic];
       } else {
         const int kk = tid % 16, i = tid / 16 + 16 * q;
         const int64_t gi = m0 + i, gk = k0 + kk;
-        ra[q] = (gi < a.M && gk < a.K) ? (double)a.A[gi * a.lda + gk] : 0.0;
+        const int64_t gic = gi < a.M ? gi : a.M - 1, gkc = gk < a.K ? gk : a.K - 1;
+        wa[q] = (gi < a.M && gk < a.K) ? 1.0 : 0.0;
+        ra[q] = (double)a.A[gic * a.lda + gkc];
       }
       if (a.tb == 0) {
         const int kk = tid % 16, j = tid / 16 + 16 * q;
         const int64_t gj = n0 + j, gk = k0 + kk;
-        rb[q] = (gj < a.N && gk < a.K) ? a.B[gj * a.ldb + gk] : 0.0;
+        const int64_t gjc = gj < a.N ? gj : a.N - 1, gkc = gk < a.K ? gk : a.K - 1;
+        wb[q] = (gj < a.N && gk < a.K) ? 1.0 : 0.0;
+        rb[q] = a.B[gjc * a.ldb + gkc];
       } else {
         const int j = tid % 64, kk = tid / 64 + 4 * q;
         const int64_t gj = n0 + j, gk = k0 + kk;
-        rb[q] = (gj < a.N && gk < a.K) ? a.B[gk * a.ldb + gj] : 0.0;
+        const int64_t gjc = gj < a.N ? gj : a.N - 1, gkc = gk < a.K ? gk : a.K - 1;
+        wb[q] = (gj < a.N && gk < a.K) ? 1.0 : 0.0;
+        rb[q] = a.B[gkc * a.ldb + gjc];
       }
     }
   };
@@ -85,13 +109,13 @@ __global__ __launch_bounds__(kThreads) void k_gemm64(G64Args<TA, TC> a) {
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       if (a.ta == 0)
-        As[tid / 64 + 4 * q][tid % 64] = ra[q];
+        As[tid / 64 + 4 * q][tid % 64] = ra[q] * wa[q];
       else
-        As[tid % 16][tid / 16 + 16 * q] = ra[q];
+        As[tid % 16][tid / 16 + 16 * q] = ra[q] * wa[q];
       if (a.tb == 0)
-        Bs[tid % 16][tid / 16 + 16 * q] = rb[q];
+        Bs[tid % 16][tid / 16 + 16 * q] = rb[q] * wb[q];
       else
-        Bs[tid / 64 + 4 * q][tid % 64] = rb[q];
+        Bs[tid / 64 + 4 * q][tid % 64] = rb[q] * wb[q];
     }
     __syncthreads();
     if (k0 + 16 < a.K) load(k0 + 16);
@@ -109,22 +133,42 @@ __global__ __launch_bounds__(kThreads) void k_gemm64(G64Args<TA, TC> a) {
           acc[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[x], bf[y], acc[x][y], 0, 0, 0);
     }
   }
-  // acc[x][y][r] = C(m0 + wr + 16x + g + 4r, n0 + wc + 16y + li)
+  // acc[x][y][r] = C(m0 + wr + 16x + g + 4r, n0 + wc + 16y + li); the
+  // column maps, then every Cin entry (clamped indices, used only in range),
+  // are loaded as groups before the stores
+  int64_t cj[2], ij[2];
+#pragma unroll
+  for (int y = 0; y < 2; ++y) {
+    const int64_t j = n0 + wc + 16 * y + li;
+    const int64_t jc = j < a.N ? j : a.N - 1;
+    cj[y] = a.cmap ? (int64_t)a.cmap[jc] : jc;
+    ij[y] = a.cinmap ? (int64_t)a.cinmap[jc] : jc;
+  }
+  double cin[2][2][4];
+  if (a.beta != 0.0) {
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+      for (int y = 0; y < 2; ++y)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int64_t i = m0 + wr + 16 * x + g + 4 * r;
+          cin[x][y][r] = (double)a.Cin[ij[y] * a.ldcin + (i < a.M ? i : a.M - 1)];
+        }
+  }
 #pragma unroll
   for (int x = 0; x < 2; ++x)
 #pragma unroll
     for (int y = 0; y < 2; ++y) {
       const int64_t j = n0 + wc + 16 * y + li;
       if (j >= a.N) continue;
-      const int64_t cj = a.cmap ? (int64_t)a.cmap[j] : j;
-      const int64_t ij = a.cinmap ? (int64_t)a.cinmap[j] : j;
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int64_t i = m0 + wr + 16 * x + g + 4 * r;
         if (i >= a.M) continue;
         double v = a.alpha * acc[x][y][r];
-        if (a.beta != 0.0) v += a.beta * (double)a.Cin[ij * a.ldcin + i];
-        a.C[cj * a.ldc + i] = v;
+        if (a.beta != 0.0) v += a.beta * cin[x][y][r];
+        a.C[cj[y] * a.ldc + i] = v;
       }
     }
 }
