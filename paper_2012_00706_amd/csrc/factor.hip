@@ -175,17 +175,22 @@ __global__ __launch_bounds__(kThreads) void k_ingest(const TA* __restrict__ A, i
   double ss = 0.0;
   bool bad = false;
   for (int64_t rs = rb; rs < re; rs += 64) {
-#pragma unroll 4
+    // the 16 loads of a thread issued as one group: unconditional, from
+    // clamped in-range addresses (tile entries outside the matrix are never
+    // stored or summed)
+    TA xv[16];
+#pragma unroll
     for (int q = 0; q < 16; ++q) {
       const int cc = q * 4 + tid / 64, rr = tid % 64;
       const int64_t r = rs + rr, c = c0 + cc;
-      S v = (S)0;
-      if (r < re && c < n) {
-        const TA x = A[c * lda + r];
-        if (!isfinite((double)x)) bad = true;
-        v = (S)x;
-      }
-      tile[cc][rr] = v;
+      xv[q] = A[(c < n ? c : n - 1) * lda + (r < re ? r : re - 1)];
+    }
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int cc = q * 4 + tid / 64, rr = tid % 64;
+      const int64_t r = rs + rr, c = c0 + cc;
+      if (r < re && c < n && !isfinite((double)xv[q])) bad = true;
+      tile[cc][rr] = (S)xv[q];
     }
     __syncthreads();
 #pragma unroll 4
