@@ -470,6 +470,20 @@ __global__ __launch_bounds__(kThreads) void k_sweep(StepArgs<S> a) {
   const double wp = (double)a.W[(iw < a.m ? iw : a.m - 1) * a.ldw + p];  // same on the G lanes
   const double fp = a.F[(int64_t)(tid % kNbMax) * a.ldf + p];
   const double vsp = a.vscale[tid % kNbMax];
+  // the first kSweepU rows of the main loop, in flight with round trip 2
+  // (issued after its loads, so waiting for those leaves these outstanding;
+  // rows past the tile are loaded from r1 - 1 and not used)
+  int64_t i1 = ib + (int64_t)kPrefetch * RG;
+  if (i1 <= j) i1 += (j + 1 - i1 + RG - 1) / RG * RG;
+  VT x0[kSweepU];
+  {
+    const S* pb = a.W + (colok ? l0 : 0);
+#pragma unroll
+    for (int u = 0; u < kSweepU; ++u) {
+      const int64_t r = i1 + (int64_t)u * RG;
+      x0[u] = *(const VT*)(pb + (r < r1 ? r : r1 - 1) * a.ldw);
+    }
+  }
   if (tid < kNbMax) gsh[tid] = tid < jj ? vsp * fp : 0.0;
   __syncthreads();
   double part = 0.0;
@@ -526,8 +540,17 @@ __global__ __launch_bounds__(kThreads) void k_sweep(StepArgs<S> a) {
         for (int e = 0; e < VEC; ++e) acc[e] += (double)pf[u][e] * w0;
       }
     }
-    int64_t i = ib + (int64_t)kPrefetch * RG;
-    if (i <= j) i += (j + 1 - i + RG - 1) / RG * RG;
+    // the rows loaded with round trip 2
+#pragma unroll
+    for (int u = 0; u < kSweepU; ++u) {
+      const int64_t r = i1 + (int64_t)u * RG;
+      if (r < r1) {
+        const double w0 = wsh[r - r0];
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) acc[e] += (double)x0[u][e] * w0;
+      }
+    }
+    int64_t i = i1 + (int64_t)kSweepU * RG;
     // kSweepU independent row loads in flight per thread: the loop is bound
     // by memory latency times the number of its iterations
     for (; i + (kSweepU - 1) * RG < r1; i += kSweepU * RG) {
