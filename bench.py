@@ -150,6 +150,7 @@ def sweep_source_hash() -> str:
     text = open(SWEEP_SOURCES[0]).read()
     parts = []
     for pat in (r"constexpr int kPrefetch[^\n]*\n", r"constexpr int kSweepU[^\n]*\n",
+                r"template <typename S, int G>\nconstexpr int overlap_rows\(\) \{.*?\n\}\n",
                 r"template <typename S>\nstruct StepArgs \{.*?\n\};\n",
                 r"template <typename S, int G>\n__global__ __launch_bounds__\(kThreads\) void "
                 r"k_sweep\(.*?\n\}\n"):

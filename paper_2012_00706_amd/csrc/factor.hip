@@ -59,6 +59,12 @@ constexpr int kPrefetch = 4;  // sweep rows per thread loaded ahead of the pivot
 constexpr int kFinZ = 12;     // column partials per lane and round trip in the finalization
 constexpr int kFinA = 24;     // reflector-product partials per thread and round trip
 constexpr int kSweepU = 4;    // sweep rows per thread in flight in the main loop
+// main-loop rows per thread loaded with the second round trip: 8 where the
+// registers allow it without lowering occupancy (fp32, row tiles <= 128)
+template <typename S, int G>
+constexpr int overlap_rows() {
+  return (sizeof(S) == 4 && G >= 2) ? 8 : 4;
+}
 
 // ----------------------------------------------------------------- plan
 
@@ -470,16 +476,17 @@ __global__ __launch_bounds__(kThreads) void k_sweep(StepArgs<S> a) {
   const double wp = (double)a.W[(iw < a.m ? iw : a.m - 1) * a.ldw + p];  // same on the G lanes
   const double fp = a.F[(int64_t)(tid % kNbMax) * a.ldf + p];
   const double vsp = a.vscale[tid % kNbMax];
-  // the first kSweepU rows of the main loop, in flight with round trip 2
+  // the first kOverlap rows of the main loop, in flight with round trip 2
   // (issued after its loads, so waiting for those leaves these outstanding;
   // rows past the tile are loaded from r1 - 1 and not used)
   int64_t i1 = ib + (int64_t)kPrefetch * RG;
   if (i1 <= j) i1 += (j + 1 - i1 + RG - 1) / RG * RG;
-  VT x0[kSweepU];
+  constexpr int kOverlap = overlap_rows<S, G>();
+  VT x0[kOverlap];
   {
     const S* pb = a.W + (colok ? l0 : 0);
 #pragma unroll
-    for (int u = 0; u < kSweepU; ++u) {
+    for (int u = 0; u < kOverlap; ++u) {
       const int64_t r = i1 + (int64_t)u * RG;
       x0[u] = *(const VT*)(pb + (r < r1 ? r : r1 - 1) * a.ldw);
     }
@@ -542,7 +549,7 @@ __global__ __launch_bounds__(kThreads) void k_sweep(StepArgs<S> a) {
     }
     // the rows loaded with round trip 2
 #pragma unroll
-    for (int u = 0; u < kSweepU; ++u) {
+    for (int u = 0; u < kOverlap; ++u) {
       const int64_t r = i1 + (int64_t)u * RG;
       if (r < r1) {
         const double w0 = wsh[r - r0];
@@ -550,7 +557,7 @@ __global__ __launch_bounds__(kThreads) void k_sweep(StepArgs<S> a) {
         for (int e = 0; e < VEC; ++e) acc[e] += (double)x0[u][e] * w0;
       }
     }
-    int64_t i = i1 + (int64_t)kSweepU * RG;
+    int64_t i = i1 + (int64_t)kOverlap * RG;
     // kSweepU independent row loads in flight per thread: the loop is bound
     // by memory latency times the number of its iterations
     for (; i + (kSweepU - 1) * RG < r1; i += kSweepU * RG) {
