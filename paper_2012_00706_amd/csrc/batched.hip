@@ -869,15 +869,23 @@ __device__ void factor_item(id_batch_item& it, int g, int G, const BatchOpts& o,
     float fm = 0.0f;
     AmaxVal cand = amax_none();
     for (int64_t l = cs + tid; l < cs + cn; l += BT) {
+      // the column's own data first (one group with the F loads below), its
+      // swap-order key (which depends on the id) right after the F loads
       const double wj = (double)Wc[j * ldw + l];
+      const int pvl = pvflag[l];
+      const int id = cid[l];
+      double nl = nu[l];
+      const double nlo = nuo[l];
       const double y = wj + scale * sm.zc[l - cs];
       double s1 = 0.0, s2 = 0.0;
+      int key = 0;
       // F(c, l) for c < jb, loaded 16 rows at a time as one group (rows
       // >= jb hold stale data: excluded by the select on the products)
       for (int c0 = 0; c0 < jb; c0 += 16) {
         double fc[16];
 #pragma unroll
         for (int u = 0; u < 16; ++u) fc[u] = F[(int64_t)((c0 + u) & (kNbMax - 1)) * ldf + l];
+        if (c0 == 0) key = posof[id];
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int u = 0; u < 16; ++u) {
@@ -886,18 +894,17 @@ __device__ void factor_item(id_batch_item& it, int g, int G, const BatchOpts& o,
           s2 += c < jb ? sm.vj[c & (kNbMax - 1)] * fc[u] : 0.0;
         }
       }
+      if (jb == 0) key = posof[id];
       const double f = tau * (y - s1);
       F[(int64_t)jb * ldf + l] = f;
-      if (!pvflag[l]) {
+      if (!pvl) {
         const double r = wj - s2 - f;
-        const int id = cid[l];
         rorig[(int64_t)id * kcap + j] = r;
-        double nl = nu[l];
         if (nl != 0.0) {
           double t = fabs(r) / nl;
           t = (1.0 + t) * (1.0 - t);
           if (t < 0.0) t = 0.0;
-          const double ratio = nl / nuo[l];
+          const double ratio = nl / nlo;
           if (t * ratio * ratio <= o.tol3z) {
             flag = 1.0;
           } else {
@@ -910,7 +917,7 @@ __device__ void factor_item(id_batch_item& it, int g, int G, const BatchOpts& o,
         c.v = nl;
         c.s2 = nl * nl;
         c.pos = (int)l;
-        c.key = posof[id];
+        c.key = key;
         cand = amax_combine(cand, c);
       }
     }
