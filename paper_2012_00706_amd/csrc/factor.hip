@@ -56,7 +56,7 @@ struct Vec16<double> {
 enum { OP_F64 = 0, OP_F16 = 1, OP_BF16 = 2, OP_BF16X3 = 3, OP_F32 = 4 };
 
 constexpr int kPrefetch = 4;  // sweep rows per thread loaded ahead of the pivot search
-constexpr int kFinZ = 12;     // column partials per lane and round trip in the finalization
+constexpr int kFinZ = (192 + kFL - 1) / kFL;  // column partials per lane and round trip in the finalization
 constexpr int kFinA = 24;     // reflector-product partials per thread and round trip
 constexpr int kSweepU = 4;    // sweep rows per thread in flight in the main loop
 // main-loop rows per thread loaded with the second round trip: 8 where the
