@@ -58,6 +58,7 @@ enum { OP_F64 = 0, OP_F16 = 1, OP_BF16 = 2, OP_BF16X3 = 3, OP_F32 = 4 };
 constexpr int kPrefetch = 4;  // sweep rows per thread loaded ahead of the pivot search
 constexpr int kFinZ = (192 + kFL - 1) / kFL;  // column partials per lane and round trip in the finalization
 constexpr int kFinA = 24;     // reflector-product partials per thread and round trip
+constexpr int kFold = 32;     // row tiles summed per folded partial (tall inputs)
 constexpr int kSweepU = 4;    // sweep rows per thread in flight in the main loop
 // main-loop rows per thread loaded with the second round trip: 8 where the
 // registers allow it without lowering occupancy (fp32, row tiles <= 128)
@@ -113,6 +114,10 @@ bool make_factor_plan(int64_t m, int64_t n, int32_t dtype, const id_opts* o, Fac
   p->off_zpart = take((size_t)p->ntile_s_max * p->ldf * 8);
   p->off_auxpart = take((size_t)p->ntile_s_max * kNbMax * 8);
   p->off_nrm2part = take((size_t)p->ntile_s_max * 8);
+  const int64_t nfold = ceil_div(p->ntile_s_max, kFold);
+  p->off_zfold = take((size_t)nfold * p->ldf * 8);
+  p->off_afold = take((size_t)nfold * kNbMax * 8);
+  p->off_nfold = take((size_t)nfold * 8);
   p->off_colpart = take((size_t)p->ntile_g * p->ldf * 8);
   p->off_nu = take((size_t)p->ldf * 8);
   p->off_nuo = take((size_t)p->ldf * 8);
@@ -592,6 +597,46 @@ __global__ __launch_bounds__(kThreads) void k_sweep(StepArgs<S> a) {
 #pragma unroll
     for (int e = 0; e < VEC; ++e) a.zpart[tile * a.ldf + l0 + e] = acc[e];
   }
+}
+
+// Tall inputs (more row tiles than one round trip of the finalization
+// covers): sums the per-tile partials of the step in groups of kFold tiles,
+// in tile order, so that the finalization reads ceil(ntile / kFold) of them.
+// Thread = (column or reflector-product slot, group); its kFold loads are
+// issued as one group (unconditional, clamped; tiles past the end weighted 0).
+// Grid: ceil((ncur + kNbMax + 1) nfold / kThreads).
+template <typename S>
+__global__ __launch_bounds__(kThreads) void k_fold(StepArgs<S> a, double* __restrict__ zf,
+                                                   double* __restrict__ af,
+                                                   double* __restrict__ nf, int64_t nfold) {
+  const int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  const int64_t ncol = a.ncur, slots = ncol + kNbMax + 1;
+  if (e >= slots * nfold) return;
+  const int64_t gidx = e / slots, sl = e % slots;
+  const int64_t tend = a.t0 + a.ntile;
+  const int64_t tb = a.t0 + gidx * kFold;
+  double x[kFold], w[kFold];
+#pragma unroll
+  for (int u = 0; u < kFold; ++u) {
+    const int64_t t = tb + u;
+    const int64_t tc = t < tend ? t : tend - 1;
+    w[u] = t < tend ? 1.0 : 0.0;
+    if (sl < ncol)
+      x[u] = a.zpart[tc * a.ldf + sl];
+    else if (sl < ncol + kNbMax)
+      x[u] = a.auxpart[tc * kNbMax + (sl - ncol)];
+    else
+      x[u] = a.nrm2part[tc];
+  }
+  double t = 0.0;
+#pragma unroll
+  for (int u = 0; u < kFold; ++u) t += x[u] * w[u];
+  if (sl < ncol)
+    zf[gidx * a.ldf + sl] = t;
+  else if (sl < ncol + kNbMax)
+    af[gidx * kNbMax + (sl - ncol)] = t;
+  else
+    nf[gidx] = t;
 }
 
 // One pivot step, part 2.  Grid: ceil(ncur / kFC) blocks of kFC columns x kFL
@@ -1225,6 +1270,9 @@ static int factor_impl(const TA* A, int64_t lda, const FactorPlan& pl, const id_
   double* zpart = (double*)(wb + pl.off_zpart);
   double* auxpart = (double*)(wb + pl.off_auxpart);
   double* nrm2part = (double*)(wb + pl.off_nrm2part);
+  double* zfold = (double*)(wb + pl.off_zfold);
+  double* afold = (double*)(wb + pl.off_afold);
+  double* nfoldb = (double*)(wb + pl.off_nfold);
   double* colpart = (double*)(wb + pl.off_colpart);
   double* nu = (double*)(wb + pl.off_nu);
   double* nuo = (double*)(wb + pl.off_nuo);
@@ -1414,7 +1462,23 @@ static int factor_impl(const TA* A, int64_t lda, const FactorPlan& pl, const id_
         prof.launch(PK_SWEEP, tag, k_sweep<S, 4>, sgrid, s, a);
       MPID_LAUNCH_CHECK();
       namax = (int)ceil_div(ncur_ub, kFC);
-      prof.launch(PK_FINALIZE, tag, k_finalize<S>, dim3((unsigned)namax), s, a);
+      if (a.ntile > kFinZ * kFL) {
+        // tall input: fold the partials so that one round trip reads them
+        const int64_t nfold = ceil_div(a.ntile, kFold);
+        const int64_t nthr = (ncur_ub + kNbMax + 1) * nfold;
+        prof.launch(PK_FINALIZE, tag, k_fold<S>, dim3((unsigned)ceil_div(nthr, kThreads)), s, a,
+                    zfold, afold, nfoldb, nfold);
+        MPID_LAUNCH_CHECK();
+        StepArgs<S> af = a;
+        af.zpart = zfold;
+        af.auxpart = afold;
+        af.nrm2part = nfoldb;
+        af.t0 = 0;
+        af.ntile = (int)nfold;
+        prof.launch(PK_FINALIZE, tag, k_finalize<S>, dim3((unsigned)namax), s, af);
+      } else {
+        prof.launch(PK_FINALIZE, tag, k_finalize<S>, dim3((unsigned)namax), s, a);
+      }
       MPID_LAUNCH_CHECK();
     }
     GemmArgs<S> g;

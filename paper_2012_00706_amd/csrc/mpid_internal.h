@@ -55,7 +55,8 @@ struct FactorPlan {
   int32_t dtype, prec, nb, wbytes;  // wbytes: 4 (fp32 working copy) or 8
   int64_t ldw, ldv, ldf;
   int64_t ntile_s_max, ntile_g;
-  size_t off_w0, off_w1, off_v, off_f, off_zpart, off_auxpart, off_nrm2part, off_colpart,
+  size_t off_w0, off_w1, off_v, off_f, off_zpart, off_auxpart, off_nrm2part, off_zfold,
+      off_afold, off_nfold, off_colpart,
       off_nu, off_nuo, off_amax, off_colid0, off_colid1, off_pvflag, off_pivpos, off_pivid,
       off_permw, off_posof, off_tau, off_vscale, off_rorig, off_state;
   size_t bytes;

@@ -270,3 +270,20 @@ def test_stale_workspace_does_not_leak(prec):
         assert k == outs[0][0]
         assert np.array_equal(perm, outs[0][1])
         assert np.array_equal(R, outs[0][2])
+
+
+@pytest.mark.parametrize("prec", ["f64", "mixed_bf16x3"])
+def test_tall_input_folded_partials(prec):
+    """30000 x 100 (469 row tiles of 64 rows: the step finalization reads
+    partials folded over groups of row tiles): FP64 pivots and T equal the
+    oracle's; the mixed path's pivots too on this gap-separated input."""
+    need_gpu()
+    A = synth.spectrum_matrix(30000, 100, synth.sigma_geom10(100, 15.0), 101, 102)
+    if prec == "f64":
+        _check_f64_parity(A, 40)
+    else:
+        A32 = A.astype(np.float32)
+        perm, k, R, T = gpu_id(A32, k=40, prec=prec)
+        ref = orc.cpqr(A32.astype(np.float64), k=40)
+        assert k == 40 and perm[:40].tolist() == ref.perm[:40].tolist()
+        assert rel_err(T, orc.solve_T(ref.R, 40)) <= 1e-4
