@@ -859,6 +859,8 @@ struct GemmArgs {
   int* colid_n;
   double* colpart;
   int64_t off, tg0;
+  int64_t gx, gy;  // column blocks and row tiles of the grid
+  int remap;       // group the column blocks of a row tile on one XCD
 };
 
 // End of a panel: Wn(i, newpos(l)) = W(i, l) - sum_c V(i, c) F(c, l) for rows
@@ -893,6 +895,19 @@ __global__ __launch_bounds__(kThreads) void k_panel_gemm(GemmArgs<S> a) {
   __shared__ int64_t s_off, s_ncur;
   FactorState* st = a.st;
   const int tid = threadIdx.x;
+  // For narrow panels (few column blocks, where re-reading a row tile's
+  // reflector rows on every XCD adds 2 / gx to the traffic) an XCD-aware
+  // order (hardware block b runs on XCD b % 8): the column blocks of one row
+  // tile run on the same XCD and share those rows in its L2.
+  // Without the remap the grid is (gx, gy) as launched.
+  int64_t bx = blockIdx.x, by = blockIdx.y;
+  if (a.remap) {
+    const uint32_t per = gridDim.x / 8u;
+    const uint32_t v = (blockIdx.x % 8u) * per + blockIdx.x / 8u;
+    if (v >= (uint32_t)(a.gx * a.gy)) return;
+    bx = v % (uint32_t)a.gx;
+    by = v / (uint32_t)a.gx;
+  }
   if (tid == 0) {
     s_go = (st->done == 0);
     s_jb = st->jb;
@@ -904,12 +919,12 @@ __global__ __launch_bounds__(kThreads) void k_panel_gemm(GemmArgs<S> a) {
   if (tid >= 64 && tid < 64 + kNbMax) svs[tid - 64] = a.vscale[tid - 64];
   __syncthreads();
   if (!s_go) return;
-  if (tid == 0 && blockIdx.x == 0 && blockIdx.y == 0) st->vmax_bits = 0u;  // refilled after
+  if (tid == 0 && bx == 0 && by == 0) st->vmax_bits = 0u;  // refilled after
   const int jb = s_jb;
   const int64_t ncur = s_ncur;  // a.ncur is the host's bound that sized the grid
   const int64_t jend = s_off + jb;
-  const int64_t l0 = (int64_t)blockIdx.x * 64;
-  const int64_t tg = a.tg0 + blockIdx.y;
+  const int64_t l0 = bx * 64;
+  const int64_t tg = a.tg0 + by;
   const int64_t rbase = tg * kRowTileG;
   const int64_t rbeg = rbase > jend ? rbase : jend;
   const int64_t rend = rbase + kRowTileG < a.m ? rbase + kRowTileG : a.m;
@@ -1126,7 +1141,7 @@ __global__ __launch_bounds__(kThreads) void k_panel_gemm(GemmArgs<S> a) {
   __syncthreads();
   if (tid < 64 && cidx[tid] >= 0) {
     a.colpart[tg * a.ldf + cidx[tid]] = ssq[0][tid] + ssq[1][tid] + ssq[2][tid] + ssq[3][tid];
-    if (blockIdx.y == 0) a.colid_n[cidx[tid]] = a.colid[l0 + tid];
+    if (by == 0) a.colid_n[cidx[tid]] = a.colid[l0 + tid];
   }
 }
 
@@ -1499,8 +1514,13 @@ static int factor_impl(const TA* A, int64_t lda, const FactorPlan& pl, const id_
     g.colpart = colpart;
     g.off = off_lb;
     g.tg0 = off_lb / kRowTileG;
+    g.gx = ceil_div(ncur_ub, 64);
+    g.gy = ntg - g.tg0;
+    g.remap = g.gx <= 8 ? 1 : 0;
     prof.launch(PK_GEMM, (int64_t)panel * 1024, k_panel_gemm<S, OP>,
-                dim3((unsigned)ceil_div(ncur_ub, 64), (unsigned)(ntg - g.tg0)), s, g);
+                g.remap ? dim3((unsigned)round_up(g.gx * g.gy, 8))
+                        : dim3((unsigned)g.gx, (unsigned)g.gy),
+                s, g);
     MPID_LAUNCH_CHECK();
     namax = (int)ceil_div(ncur_ub, kFinCols);
     prof.begin(PK_OTHER, (int64_t)panel * 1024, s);
