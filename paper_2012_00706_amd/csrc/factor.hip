@@ -24,6 +24,7 @@
 #include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
@@ -159,6 +160,7 @@ __global__ __launch_bounds__(kThreads) void k_init(FactorState* st, int* colid0,
     st->info = 0;
     st->fmax_bits = 0u;
     st->vmax_bits = 0u;
+    st->nabove = 0u;
     st->k = 0;
     st->r00 = 0.0;
     st->alpha = 0.0;
@@ -227,12 +229,16 @@ __global__ __launch_bounds__(kThreads) void k_ingest(const TA* __restrict__ A, i
 
 // Column norms from per-row-tile partial sums of squares (FP64): nu = nu_orig
 // = sqrt(sum); clears the per-panel pivot flags; per-block pivot partials.
+// With rel_tol >= 0, also counts the columns whose norm exceeds
+// rel_tol |R_00| (the pivot-relative threshold, in the step's own arithmetic).
+// Norms only shrink under the later reflectors, so the next stop comes within
+// that many steps plus one.
 // Block: 32 columns x 8 tile lanes.
 __global__ __launch_bounds__(kThreads) void k_colreduce(
     const double* __restrict__ colpart, int64_t ldf, int64_t tg0, int64_t tg1, int64_t ncols_base,
     int subtract_jb, double* __restrict__ nu, double* __restrict__ nuo, AmaxPart* __restrict__ amax,
     const int* __restrict__ colid, const int* __restrict__ posof, int* __restrict__ pvflag,
-    FactorState* st) {
+    FactorState* st, double rel_tol) {
   __shared__ double red[8][kFinCols + 1];
   __shared__ AmaxVal ascr[4];
   __shared__ int s_go;
@@ -245,6 +251,7 @@ __global__ __launch_bounds__(kThreads) void k_colreduce(
   red[tl][cl] = l < ncols ? strided_sum(colpart + l, ldf, tg0 + tl, tg1, 8) : 0.0;
   __syncthreads();
   AmaxVal cand = amax_none();
+  int above = 0;
   if (tl == 0 && l < ncols) {
     double tot = 0.0;
 #pragma unroll
@@ -257,9 +264,12 @@ __global__ __launch_bounds__(kThreads) void k_colreduce(
     cand.s2 = tot;
     cand.pos = (int)l;
     cand.key = posof[colid[l]];
+    above = v > rel_tol * st->r00 ? 1 : 0;
   }
   cand = block_amax(cand, ascr);
+  const int nabove = __syncthreads_count(above);
   if (tid == 0) {
+    if (rel_tol >= 0.0 && nabove > 0) atomicAdd(&st->nabove, (uint32_t)nabove);
     AmaxPart o;
     o.v = cand.v;
     o.s2 = cand.s2;
@@ -919,7 +929,10 @@ __global__ __launch_bounds__(kThreads) void k_panel_gemm(GemmArgs<S> a) {
   if (tid >= 64 && tid < 64 + kNbMax) svs[tid - 64] = a.vscale[tid - 64];
   __syncthreads();
   if (!s_go) return;
-  if (tid == 0 && bx == 0 && by == 0) st->vmax_bits = 0u;  // refilled after
+  if (tid == 0 && bx == 0 && by == 0) {  // refilled after
+    st->vmax_bits = 0u;
+    st->nabove = 0u;
+  }
   const int jb = s_jb;
   const int64_t ncur = s_ncur;  // a.ncur is the host's bound that sized the grid
   const int64_t jend = s_off + jb;
@@ -1329,7 +1342,7 @@ static int factor_impl(const TA* A, int64_t lda, const FactorPlan& pl, const id_
   MPID_LAUNCH_CHECK();
   int namax = (int)ceil_div(n, kFinCols);
   k_colreduce<<<dim3((unsigned)namax), kThreads, 0, s>>>(colpart, ldf, 0, ntg, n, 0, nu, nuo,
-                                                          amax, colid[0], posof, pvflag, st);
+                                                          amax, colid[0], posof, pvflag, st, -1.0);
   MPID_LAUNCH_CHECK();
   prof.end(s);
 
@@ -1412,6 +1425,12 @@ static int factor_impl(const TA* A, int64_t lda, const FactorPlan& pl, const id_
       }
     }
   };
+  // Pivot-relative rule: the end state counts the columns above the stop
+  // threshold; a panel enqueued right after its predecessor settled launches
+  // at most that many steps plus one (the rest would only find the done flag).
+  const bool count_rule = o->k_fixed == 0 && o->rank_rule == ID_RANK_PIVOT_REL;
+  const double count_tol = count_rule ? o->rel_tol : -1.0;
+  int64_t step_lim = pl.nb;  // from the last settled end state
   int settled = 0;           // panels whose end state has been processed
   bool drain = false;        // near the end: settle every panel before the next
   const FactorState* fin_drain = nullptr;
@@ -1427,6 +1446,7 @@ static int factor_impl(const TA* A, int64_t lda, const FactorPlan& pl, const id_
       }
       if (h.last_jb <= 0) return ID_ERR_HIP;  // a live panel always makes progress
       known_off += h.last_jb;
+      step_lim = count_rule ? (int64_t)h.nabove + 1 : pl.nb;
       // the rank rule is near: largest norm within a few panels' decay of the
       // threshold, or kcap within two panels
       float vmaxf;
@@ -1454,7 +1474,9 @@ static int factor_impl(const TA* A, int64_t lda, const FactorPlan& pl, const id_
     a.W = W[cur];
     a.colid = colid[cur];
     a.ncur = ncur_ub;
-    for (int jj = 0; jj < pl.nb; ++jj) {
+    // the limit holds only when the previous panel's end state is known
+    const int64_t nsteps = settled == panel ? std::min<int64_t>(pl.nb, step_lim) : pl.nb;
+    for (int jj = 0; jj < nsteps; ++jj) {
       const int64_t jlb = off_lb + jj;
       if (jlb >= kcap || jj >= ncur_ub) break;
       const SweepShape sh = choose_sweep_shape(m - jlb, ncur_ub, pl.wbytes);
@@ -1526,7 +1548,7 @@ static int factor_impl(const TA* A, int64_t lda, const FactorPlan& pl, const id_
     prof.begin(PK_OTHER, (int64_t)panel * 1024, s);
     k_colreduce<<<dim3((unsigned)namax), kThreads, 0, s>>>(colpart, ldf, g.tg0, ntg, ncur_ub, 1,
                                                             nu, nuo, amax, colid[cur ^ 1], posof,
-                                                            pvflag, st);
+                                                            pvflag, st, count_tol);
     MPID_LAUNCH_CHECK();
     k_advance<<<1, 64, 0, s>>>(st);
     MPID_LAUNCH_CHECK();

@@ -32,7 +32,7 @@ struct FactorState {
   int32_t info;      // ID_INFO_NONFINITE when the input holds NaN/Inf
   uint32_t fmax_bits;  // max |F| of the current panel, as float bits
   uint32_t vmax_bits;  // largest column norm after the last recomputation (float bits)
-  int32_t pad0;
+  uint32_t nabove;   // live columns whose norm exceeds rel_tol |R_00| after the last recomputation
   int64_t k;         // rank (valid when done)
   double r00;        // |R_00|
   double alpha;      // leading entry of the current pivot column
