@@ -161,6 +161,7 @@ __global__ __launch_bounds__(kThreads) void k_init(FactorState* st, int* colid0,
     st->fmax_bits = 0u;
     st->vmax_bits = 0u;
     st->nabove = 0u;
+    st->nred = 0u;
     st->k = 0;
     st->r00 = 0.0;
     st->alpha = 0.0;
@@ -227,25 +228,13 @@ __global__ __launch_bounds__(kThreads) void k_ingest(const TA* __restrict__ A, i
   if (bad) st->info = ID_INFO_NONFINITE;
 }
 
-// Column norms from per-row-tile partial sums of squares (FP64): nu = nu_orig
-// = sqrt(sum); clears the per-panel pivot flags; per-block pivot partials.
-// With rel_tol >= 0, also counts the columns whose norm exceeds
-// rel_tol |R_00| (the pivot-relative threshold, in the step's own arithmetic).
-// Norms only shrink under the later reflectors, so the next stop comes within
-// that many steps plus one.
-// Block: 32 columns x 8 tile lanes.
-__global__ __launch_bounds__(kThreads) void k_colreduce(
+// One block of the column-norm reduction (see k_colreduce).
+__device__ __forceinline__ void colreduce_block(
     const double* __restrict__ colpart, int64_t ldf, int64_t tg0, int64_t tg1, int64_t ncols_base,
     int subtract_jb, double* __restrict__ nu, double* __restrict__ nuo, AmaxPart* __restrict__ amax,
     const int* __restrict__ colid, const int* __restrict__ posof, int* __restrict__ pvflag,
-    FactorState* st, double rel_tol) {
-  __shared__ double red[8][kFinCols + 1];
-  __shared__ AmaxVal ascr[4];
-  __shared__ int s_go;
+    FactorState* st, double rel_tol, double (*red)[kFinCols + 1], AmaxVal* ascr) {
   const int tid = threadIdx.x, cl = tid % kFinCols, tl = tid / kFinCols;
-  if (tid == 0) s_go = (st->done == 0);
-  __syncthreads();
-  if (!s_go) return;
   const int64_t ncols = subtract_jb ? st->ncur - st->jb : ncols_base;
   const int64_t l = (int64_t)blockIdx.x * kFinCols + cl;
   red[tl][cl] = l < ncols ? strided_sum(colpart + l, ldf, tg0 + tl, tg1, 8) : 0.0;
@@ -278,6 +267,55 @@ __global__ __launch_bounds__(kThreads) void k_colreduce(
     amax[blockIdx.x] = o;
     // the host's view of how close the rank rule is (norms are >= 0)
     if (cand.v > 0.0) atomicMax(&st->vmax_bits, __float_as_uint((float)cand.v));
+  }
+}
+
+// Column norms from per-row-tile partial sums of squares (FP64): nu = nu_orig
+// = sqrt(sum); clears the per-panel pivot flags; per-block pivot partials.
+// With rel_tol >= 0, also counts the columns whose norm exceeds
+// rel_tol |R_00| (the pivot-relative threshold, in the step's own arithmetic).
+// Norms only shrink under the later reflectors, so the next stop comes within
+// that many steps plus one.
+// At a panel's end (hs != nullptr) the last block to finish also advances the
+// state to the next panel and publishes it to the host slot hs with tag seq.
+// Block: 32 columns x 8 tile lanes.
+__global__ __launch_bounds__(kThreads) void k_colreduce(
+    const double* __restrict__ colpart, int64_t ldf, int64_t tg0, int64_t tg1, int64_t ncols_base,
+    int subtract_jb, double* __restrict__ nu, double* __restrict__ nuo, AmaxPart* __restrict__ amax,
+    const int* __restrict__ colid, const int* __restrict__ posof, int* __restrict__ pvflag,
+    FactorState* st, double rel_tol, FactorHostSlot* hs, int64_t seq) {
+  __shared__ double red[8][kFinCols + 1];
+  __shared__ AmaxVal ascr[4];
+  __shared__ int s_go, s_last;
+  const int tid = threadIdx.x;
+  if (tid == 0) s_go = (st->done == 0);
+  __syncthreads();
+  if (s_go)
+    colreduce_block(colpart, ldf, tg0, tg1, ncols_base, subtract_jb, nu, nuo, amax, colid, posof,
+                    pvflag, st, rel_tol, red, ascr);
+  if (hs == nullptr) return;
+  if (tid == 0) {
+    __threadfence();  // this block's counts before its arrival
+    s_last = atomicAdd(&st->nred, 1u) == gridDim.x - 1;
+  }
+  __syncthreads();
+  if (s_last && tid == 0) {
+    __threadfence();  // every block's counts (vmax_bits, nabove) before reading them
+    st->nred = 0u;
+    if (st->done) {
+      // panels enqueued after the stop must not match any step's jb
+      st->jb = 0;
+    } else {
+      st->last_jb = st->jb;
+      st->off += st->jb;
+      st->ncur -= st->jb;
+      st->jb = 0;
+      st->end_flag = 0;
+      st->fmax_bits = 0u;
+    }
+    hs->s = *st;
+    __threadfence_system();  // the state before its tag
+    __hip_atomic_store(&hs->seq, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
   }
 }
 
@@ -1158,22 +1196,6 @@ __global__ __launch_bounds__(kThreads) void k_panel_gemm(GemmArgs<S> a) {
   }
 }
 
-__global__ void k_advance(FactorState* st) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) {
-    if (st->done) {
-      // panels enqueued after the stop must not match any step's jb
-      st->jb = 0;
-      return;
-    }
-    st->last_jb = st->jb;
-    st->off += st->jb;
-    st->ncur -= st->jb;
-    st->jb = 0;
-    st->end_flag = 0;
-    st->fmax_bits = 0u;
-  }
-}
-
 // perm (swap order) and R gathered into pivot order: R(i, c) = Rorig(i, perm[c])
 // for i < k, zero below the diagonal of the first k columns.
 __global__ __launch_bounds__(kThreads) void k_finish(const int* __restrict__ permw,
@@ -1287,6 +1309,16 @@ struct Profiler {
 };
 }  // namespace
 
+// Waits (after the panel's event completed) until the host slot holds the
+// state tagged seq: the device's system-scope release makes it visible by
+// then; a bounded wait turns anything else into an error.
+static int await_slot(const FactorHostSlot* hs, int64_t seq) {
+  for (long spin = 0; spin < (1L << 26); ++spin) {
+    if (__atomic_load_n(&hs->seq, __ATOMIC_ACQUIRE) == seq) return ID_OK;
+  }
+  return ID_ERR_HIP;
+}
+
 template <typename TA, typename S, int OP>
 static int factor_impl(const TA* A, int64_t lda, const FactorPlan& pl, const id_opts* o,
                        char* wb, int32_t* perm, double* R, int64_t ldr, int64_t* k_out,
@@ -1342,7 +1374,7 @@ static int factor_impl(const TA* A, int64_t lda, const FactorPlan& pl, const id_
   MPID_LAUNCH_CHECK();
   int namax = (int)ceil_div(n, kFinCols);
   k_colreduce<<<dim3((unsigned)namax), kThreads, 0, s>>>(colpart, ldf, 0, ntg, n, 0, nu, nuo,
-                                                          amax, colid[0], posof, pvflag, st, -1.0);
+                                                          amax, colid[0], posof, pvflag, st, -1.0, nullptr, 0);
   MPID_LAUNCH_CHECK();
   prof.end(s);
 
@@ -1385,9 +1417,16 @@ static int factor_impl(const TA* A, int64_t lda, const FactorPlan& pl, const id_
   // kernels take the exact offset and column count from the device state.
   // Every live panel compacts into the other buffer, so panel P works on
   // buffer P & 1.
-  static thread_local FactorState* hslot = nullptr;
+  // The panel-end reduction writes the state after panel P into slot P & 1,
+  // tagged with this call's number and P.
+  static thread_local FactorHostSlot* hslot = nullptr;
   static thread_local hipEvent_t pev[2] = {nullptr, nullptr};
-  if (!hslot) MPID_HIP(hipHostMalloc((void**)&hslot, 2 * sizeof(FactorState), hipHostMallocDefault));
+  static thread_local int64_t ncalls = 0;
+  if (!hslot) {
+    MPID_HIP(hipHostMalloc((void**)&hslot, 2 * sizeof(FactorHostSlot), hipHostMallocCoherent));
+    hslot[0].seq = hslot[1].seq = 0;
+  }
+  const int64_t seq0 = (++ncalls) << 24;
   for (int q = 0; q < 2; ++q)
     if (!pev[q]) MPID_HIP(hipEventCreateWithFlags(&pev[q], hipEventDisableTiming));
   int64_t off_lb = 0;     // lower bound of the offset of the panel being enqueued
@@ -1437,7 +1476,9 @@ static int factor_impl(const TA* A, int64_t lda, const FactorPlan& pl, const id_
   auto settle_upto = [&](int target, const FactorState** done_state) -> int {
     while (settled <= target) {
       MPID_HIP(hipEventSynchronize(pev[settled & 1]));
-      const FactorState& h = hslot[settled & 1];
+      const int rs = await_slot(&hslot[settled & 1], seq0 + settled + 1);
+      if (rs) return rs;
+      const FactorState& h = hslot[settled & 1].s;
       settle(settled, known_off, h);
       ++settled;
       if (h.done) {
@@ -1548,12 +1589,10 @@ static int factor_impl(const TA* A, int64_t lda, const FactorPlan& pl, const id_
     prof.begin(PK_OTHER, (int64_t)panel * 1024, s);
     k_colreduce<<<dim3((unsigned)namax), kThreads, 0, s>>>(colpart, ldf, g.tg0, ntg, ncur_ub, 1,
                                                             nu, nuo, amax, colid[cur ^ 1], posof,
-                                                            pvflag, st, count_tol);
-    MPID_LAUNCH_CHECK();
-    k_advance<<<1, 64, 0, s>>>(st);
+                                                            pvflag, st, count_tol, &hslot[cur],
+                                                            seq0 + panel + 1);
     MPID_LAUNCH_CHECK();
     prof.end(s);
-    MPID_HIP(hipMemcpyAsync(&hslot[cur], st, sizeof(FactorState), hipMemcpyDeviceToHost, s));
     MPID_HIP(hipEventRecord(pev[cur], s));
     // Settle panels up to the previous one (the panel just enqueued keeps the
     // GPU busy meanwhile).  Near the end (drain) the next iteration settles

@@ -39,6 +39,15 @@ struct FactorState {
   double fro2;       // ||A||_F^2
   int64_t off;       // first step of the current panel
   int64_t ncur;      // columns of the current (compacted) working copy
+  uint32_t nred;     // blocks of the panel-end column reduction that finished
+  int32_t pad1;
+};
+
+// The host's copy of the state after a panel (pinned host memory, written by
+// the device); seq tells which panel of which call it holds.
+struct FactorHostSlot {
+  FactorState s;
+  int64_t seq;
 };
 
 // Per-block partial of the pivot search.
