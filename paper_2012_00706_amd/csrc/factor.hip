@@ -953,8 +953,10 @@ __global__ __launch_bounds__(kThreads) void k_panel_gemm(GemmArgs<S> a) {
     const uint32_t per = gridDim.x / 8u;
     const uint32_t v = (blockIdx.x % 8u) * per + blockIdx.x / 8u;
     if (v >= (uint32_t)(a.gx * a.gy)) return;
-    bx = v % (uint32_t)a.gx;
-    by = v / (uint32_t)a.gx;
+    // uniform: kept in scalar registers (the division is expanded into
+    // vector instructions)
+    bx = __builtin_amdgcn_readfirstlane((int)(v % (uint32_t)a.gx));
+    by = __builtin_amdgcn_readfirstlane((int)(v / (uint32_t)a.gx));
   }
   if (tid == 0) {
     s_go = (st->done == 0);
