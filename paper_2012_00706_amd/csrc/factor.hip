@@ -908,7 +908,6 @@ struct GemmArgs {
   double* colpart;
   int64_t off, tg0;
   int64_t gx, gy;  // column blocks and row tiles of the grid
-  int remap;       // group the column blocks of a row tile on one XCD
 };
 
 // End of a panel: Wn(i, newpos(l)) = W(i, l) - sum_c V(i, c) F(c, l) for rows
@@ -943,21 +942,17 @@ __global__ __launch_bounds__(kThreads) void k_panel_gemm(GemmArgs<S> a) {
   __shared__ int64_t s_off, s_ncur;
   FactorState* st = a.st;
   const int tid = threadIdx.x;
-  // For narrow panels (few column blocks, where re-reading a row tile's
-  // reflector rows on every XCD adds 2 / gx to the traffic) an XCD-aware
-  // order (hardware block b runs on XCD b % 8): the column blocks of one row
-  // tile run on the same XCD and share those rows in its L2.
-  // Without the remap the grid is (gx, gy) as launched.
-  int64_t bx = blockIdx.x, by = blockIdx.y;
-  if (a.remap) {
-    const uint32_t per = gridDim.x / 8u;
-    const uint32_t v = (blockIdx.x % 8u) * per + blockIdx.x / 8u;
-    if (v >= (uint32_t)(a.gx * a.gy)) return;
-    // uniform: kept in scalar registers (the division is expanded into
-    // vector instructions)
-    bx = __builtin_amdgcn_readfirstlane((int)(v % (uint32_t)a.gx));
-    by = __builtin_amdgcn_readfirstlane((int)(v / (uint32_t)a.gx));
-  }
+  // XCD-aware block order (hardware block b runs on XCD b % 8): each XCD
+  // takes a contiguous range of row tiles with all their column blocks, so a
+  // row tile's reflector rows are read from HBM once, not once per XCD.  The
+  // indices are uniform and kept in scalar registers (the division is
+  // expanded into vector instructions, which would move everything derived
+  // from them into vector registers).
+  const uint32_t per = gridDim.x / 8u;
+  const uint32_t vb = (blockIdx.x % 8u) * per + blockIdx.x / 8u;
+  if (vb >= (uint32_t)(a.gx * a.gy)) return;
+  const int64_t bx = __builtin_amdgcn_readfirstlane((int)(vb % (uint32_t)a.gx));
+  const int64_t by = __builtin_amdgcn_readfirstlane((int)(vb / (uint32_t)a.gx));
   if (tid == 0) {
     s_go = (st->done == 0);
     s_jb = st->jb;
@@ -1581,11 +1576,8 @@ static int factor_impl(const TA* A, int64_t lda, const FactorPlan& pl, const id_
     g.tg0 = off_lb / kRowTileG;
     g.gx = ceil_div(ncur_ub, 64);
     g.gy = ntg - g.tg0;
-    g.remap = g.gx <= 8 ? 1 : 0;
     prof.launch(PK_GEMM, (int64_t)panel * 1024, k_panel_gemm<S, OP>,
-                g.remap ? dim3((unsigned)round_up(g.gx * g.gy, 8))
-                        : dim3((unsigned)g.gx, (unsigned)g.gy),
-                s, g);
+                dim3((unsigned)round_up(g.gx * g.gy, 8)), s, g);
     MPID_LAUNCH_CHECK();
     namax = (int)ceil_div(ncur_ub, kFinCols);
     prof.begin(PK_OTHER, (int64_t)panel * 1024, s);
