@@ -223,11 +223,17 @@ def summarize_trace(trace_csv):
     enqueued after the rank was reached returns at once)."""
     import csv
     by = {}
+    calls = []  # per factorization call (each starts with k_init): name -> durations
     with open(trace_csv) as fh:
-        for row in csv.DictReader(fh):
-            name = row["Kernel_Name"].split("(")[0]
-            d = int(row["End_Timestamp"]) - int(row["Start_Timestamp"])
-            by.setdefault(name, []).append(d)
+        rows = sorted(csv.DictReader(fh), key=lambda r: int(r["Start_Timestamp"]))
+    for row in rows:
+        name = row["Kernel_Name"].split("(")[0]
+        d = int(row["End_Timestamp"]) - int(row["Start_Timestamp"])
+        by.setdefault(name, []).append(d)
+        if name == "k_init":
+            calls.append({})
+        if calls:
+            calls[-1].setdefault(name, []).append(d)
     lines = [f"{'kernel':<28}{'calls':>8}{'total_ms':>12}{'avg_us':>10}{'min_us':>10}{'max_us':>10}"]
     for name, ds in sorted(by.items(), key=lambda kv: -sum(kv[1])):
         lines.append(f"{name[:27]:<28}{len(ds):>8}{sum(ds) / 1e6:>12.3f}{sum(ds) / len(ds) / 1e3:>10.2f}"
@@ -237,6 +243,21 @@ def summarize_trace(trace_csv):
         live = [d for d in sw if d > 0.3 * max(sw)]
         lines.append(f"k_sweep live launches: {len(live)} of {len(sw)}, "
                      f"average {sum(live) / len(live) / 1e3:.2f} us")
+    if len(calls) > 1:
+        # per call (launches that return at once, under a third of the call's
+        # longest, are counted apart)
+        lines.append("")
+        lines.append(f"{'call':>4}{'sweep_live':>11}{'avg_us':>9}{'idle':>6}{'finalize_us':>13}"
+                     f"{'fold_us':>9}{'gemm_live':>10}{'avg_us':>9}{'colred_us':>11}")
+        avg = lambda v: sum(v) / len(v) / 1e3 if v else 0.0  # noqa: E731
+        for i, c in enumerate(calls):
+            sw = c.get("k_sweep", [])
+            gm = c.get("k_panel_gemm", [])
+            lsw = [d for d in sw if sw and d > max(sw) / 3]
+            lgm = [d for d in gm if gm and d > max(gm) / 3]
+            lines.append(f"{i:>4}{len(lsw):>11}{avg(lsw):>9.1f}{len(sw) - len(lsw):>6}"
+                         f"{avg(c.get('k_finalize', [])):>13.2f}{avg(c.get('k_fold', [])):>9.2f}"
+                         f"{len(lgm):>10}{avg(lgm):>9.1f}{avg(c.get('k_colreduce', [])):>11.1f}")
     print("\n".join(lines))
 
 
