@@ -1497,8 +1497,67 @@ static int factor_impl(const TA* A, int64_t lda, const FactorPlan& pl, const id_
     }
     return ID_OK;
   };
+  // One pivot step (sweep, fold for tall inputs, finalization) of panel
+  // `panel`, grids sized from the offset lower bound off_b.  Returns 1 when
+  // the bounds leave nothing to launch.
+  auto launch_step = [&](int panel, int jj, int64_t off_b) -> int {
+    const int64_t ncur_b = n - off_b;
+    const int64_t jlb = off_b + jj;
+    if (jlb >= kcap || jj >= ncur_b) return 1;
+    const SweepShape sh = choose_sweep_shape(m - jlb, ncur_b, pl.wbytes);
+    a.ncur = ncur_b;
+    a.j = jlb;
+    a.jj = jj;
+    a.Rt = sh.Rt;
+    a.CW = sh.CW;
+    a.t0 = jlb / sh.Rt;
+    a.ntile = (int)(ceil_div(m, sh.Rt) - a.t0);
+    a.nchunk = (int)ceil_div(ncur_b, sh.CW);
+    a.namax = namax;
+    const int64_t total = (int64_t)a.ntile * a.nchunk;
+    const dim3 sgrid((unsigned)round_up(total, 8));
+    const int64_t tag = (int64_t)panel * 1024 + jj;
+    if (sh.Rt >= 256)
+      prof.launch(PK_SWEEP, tag, k_sweep<S, 1>, sgrid, s, a);
+    else if (sh.Rt >= 128)
+      prof.launch(PK_SWEEP, tag, k_sweep<S, 2>, sgrid, s, a);
+    else
+      prof.launch(PK_SWEEP, tag, k_sweep<S, 4>, sgrid, s, a);
+    MPID_LAUNCH_CHECK();
+    // the finalization's grid sets how many pivot partials the next sweep reads
+    namax = (int)ceil_div(ncur_b, kFC);
+    if (a.ntile > kFinZ * kFL) {
+      // tall input: fold the partials so that one round trip reads them
+      const int64_t nfold = ceil_div(a.ntile, kFold);
+      const int64_t nthr = (ncur_b + kNbMax + 1) * nfold;
+      prof.launch(PK_FINALIZE, tag, k_fold<S>, dim3((unsigned)ceil_div(nthr, kThreads)), s, a,
+                  zfold, afold, nfoldb, nfold);
+      MPID_LAUNCH_CHECK();
+      StepArgs<S> af = a;
+      af.zpart = zfold;
+      af.auxpart = afold;
+      af.nrm2part = nfoldb;
+      af.t0 = 0;
+      af.ntile = (int)nfold;
+      prof.launch(PK_FINALIZE, tag, k_finalize<S>, dim3((unsigned)namax), s, af);
+    } else {
+      prof.launch(PK_FINALIZE, tag, k_finalize<S>, dim3((unsigned)namax), s, a);
+    }
+    MPID_LAUNCH_CHECK();
+    return ID_OK;
+  };
   for (int panel = 0;; ++panel) {
+    const int cur = panel & 1;
+    a.W = W[cur];
+    a.colid = colid[cur];
+    int jj0 = 0;  // first step not yet enqueued
     if (drain && settled < panel) {
+      // the panel's first step goes ahead of the wait for the previous panel
+      // (sized from the lagged bound), so the GPU is not idle meanwhile; if
+      // the stop came first it only finds the done flag
+      const int rl = launch_step(panel, 0, off_lb);
+      if (rl < 0) return rl;
+      jj0 = rl == ID_OK ? 1 : 0;
       const int rc = settle_upto(panel - 1, &fin_drain);
       if (rc) return rc;
       if (fin_drain) {
@@ -1507,54 +1566,13 @@ static int factor_impl(const TA* A, int64_t lda, const FactorPlan& pl, const id_
       }
       off_lb = known_off;
     }
-    const int cur = panel & 1;
     const int64_t ncur_ub = n - off_lb;
-    a.W = W[cur];
-    a.colid = colid[cur];
-    a.ncur = ncur_ub;
     // the limit holds only when the previous panel's end state is known
     const int64_t nsteps = settled == panel ? std::min<int64_t>(pl.nb, step_lim) : pl.nb;
-    for (int jj = 0; jj < nsteps; ++jj) {
-      const int64_t jlb = off_lb + jj;
-      if (jlb >= kcap || jj >= ncur_ub) break;
-      const SweepShape sh = choose_sweep_shape(m - jlb, ncur_ub, pl.wbytes);
-      a.j = jlb;
-      a.jj = jj;
-      a.Rt = sh.Rt;
-      a.CW = sh.CW;
-      a.t0 = jlb / sh.Rt;
-      a.ntile = (int)(ceil_div(m, sh.Rt) - a.t0);
-      a.nchunk = (int)ceil_div(ncur_ub, sh.CW);
-      a.namax = namax;
-      const int64_t total = (int64_t)a.ntile * a.nchunk;
-      const dim3 sgrid((unsigned)round_up(total, 8));
-      const int64_t tag = (int64_t)panel * 1024 + jj;
-      if (sh.Rt >= 256)
-        prof.launch(PK_SWEEP, tag, k_sweep<S, 1>, sgrid, s, a);
-      else if (sh.Rt >= 128)
-        prof.launch(PK_SWEEP, tag, k_sweep<S, 2>, sgrid, s, a);
-      else
-        prof.launch(PK_SWEEP, tag, k_sweep<S, 4>, sgrid, s, a);
-      MPID_LAUNCH_CHECK();
-      namax = (int)ceil_div(ncur_ub, kFC);
-      if (a.ntile > kFinZ * kFL) {
-        // tall input: fold the partials so that one round trip reads them
-        const int64_t nfold = ceil_div(a.ntile, kFold);
-        const int64_t nthr = (ncur_ub + kNbMax + 1) * nfold;
-        prof.launch(PK_FINALIZE, tag, k_fold<S>, dim3((unsigned)ceil_div(nthr, kThreads)), s, a,
-                    zfold, afold, nfoldb, nfold);
-        MPID_LAUNCH_CHECK();
-        StepArgs<S> af = a;
-        af.zpart = zfold;
-        af.auxpart = afold;
-        af.nrm2part = nfoldb;
-        af.t0 = 0;
-        af.ntile = (int)nfold;
-        prof.launch(PK_FINALIZE, tag, k_finalize<S>, dim3((unsigned)namax), s, af);
-      } else {
-        prof.launch(PK_FINALIZE, tag, k_finalize<S>, dim3((unsigned)namax), s, a);
-      }
-      MPID_LAUNCH_CHECK();
+    for (int jj = jj0; jj < nsteps; ++jj) {
+      const int rl = launch_step(panel, jj, off_lb);
+      if (rl < 0) return rl;
+      if (rl != ID_OK) break;
     }
     GemmArgs<S> g;
     g.W = W[cur];
