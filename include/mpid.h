@@ -40,6 +40,7 @@ extern "C" {
 #define ID_INFO_SINGULAR 2      /* R11 has |R_ii| <= n * 2^-53 * |R_00|; T not formed */
 #define ID_INFO_RANK_FULL 3     /* k = n: T has no columns, P is a permutation */
 #define ID_INFO_ABORTED 4       /* batched item abandoned (see id_factor_batched) */
+#define ID_INFO_GRAM_LIMIT 5    /* ID_FLAG_GRAM stopped at its resolution floor (see id_factor) */
 
 /* Most workgroups that may share one batched item. */
 #define ID_BATCH_MAX_GROUPS 16
@@ -114,7 +115,18 @@ size_t id_workspace_size(int64_t m, int64_t n, int32_t dtype, const id_opts* opt
  *                factor in pivot order are written (zeros below the diagonal);
  *                rows k..kcap-1 are left untouched.
  *   k_out  [host,out] the rank k.
- *   info   [host,out] 0, or ID_INFO_NONFINITE.
+ *   info   [host,out] 0, ID_INFO_NONFINITE, or (ID_FLAG_GRAM only)
+ *          ID_INFO_GRAM_LIMIT.
+ *
+ * ID_FLAG_GRAM (tall inputs): pivots and R come from a pivoted Cholesky
+ * factorization of the FP64 Gram matrix A^T A (equal to the Householder
+ * pivots and R up to row signs in exact arithmetic).  Its residual norms are
+ * resolved only down to about sqrt(8 n 2^-53) |R_00|: an adaptive rel_tol
+ * below 1e-6 returns ID_ERR_UNSUPPORTED, and the factorization stops before
+ * any step whose pivot's residual norm is at or below that floor, fixed rank
+ * included, with info = ID_INFO_GRAM_LIMIT and k the steps completed (R and T
+ * of those steps are valid).  The flag supports k <= 2048 and no
+ * ID_FLAG_NO_PIVOT / ID_FLAG_PROFILE.
  *
  * Pivoting follows the largest remaining column norm with ties going to the
  * first column in the current (LAPACK swap) order.  The call enqueues work on
@@ -257,6 +269,8 @@ size_t id_batch_item_workspace_size(int64_t m, int64_t n, const id_opts* opts);
  *                 units = one per compute unit (all must be resident at once).
  * Returns ID_ERR_ARG / ID_ERR_DTYPE for invalid host arguments and
  * ID_ERR_UNSUPPORTED when max_n > 2048; per-item conditions go to items[i].info.
+ * An item whose groups exceed the launch's workgroups (num_groups after the
+ * caps above) is marked ID_INFO_ABORTED (k = 0) at once, without waiting.
  * A workgroup that waits more than 20 s for the others sharing its item marks
  * the item ID_INFO_ABORTED (k = 0) and every workgroup of the item leaves; a
  * slot list that breaks the rules above ends that way or factors items twice.

@@ -226,6 +226,7 @@ class ColumnIDResult:
     perm: torch.Tensor  # (n,) int32
     k: int
     R: torch.Tensor     # (k, n) float64
+    info: int = 0       # id_factor's info (e.g. ID_INFO_GRAM_LIMIT)
 
 
 def column_id(A: torch.Tensor, k=None, tol=None, prec="f64", rule="pivot_rel", k_max=0, nb=0,
@@ -235,7 +236,7 @@ def column_id(A: torch.Tensor, k=None, tol=None, prec="f64", rule="pivot_rel", k
     fr = factor(A, k=k, tol=tol, prec=prec, rule=rule, k_max=k_max, nb=nb, gram=gram)
     n = A.shape[1]
     T, _ = solve_T(fr.R, fr.k, n)
-    return ColumnIDResult(fr.perm[:fr.k].long(), T, fr.perm, fr.k, fr.R)
+    return ColumnIDResult(fr.perm[:fr.k].long(), T, fr.perm, fr.k, fr.R, fr.info)
 
 
 class ColumnID(torch.autograd.Function):
@@ -300,4 +301,4 @@ def sketch_id(A: torch.Tensor, Omega: torch.Tensor, k=None, tol=None, rule="pivo
     (id_solve_T); A ~ A[:, J] T.  Rank rules act on Y's residual norms."""
     Y = sketch(A, Omega)
     res = column_id(Y, k=k, tol=tol, prec="f64", rule=rule, k_max=k_max)
-    return SketchIDResult(res.J, res.T, res.perm, res.k, res.R, Y)
+    return SketchIDResult(res.J, res.T, res.perm, res.k, res.R, res.info, Y=Y)

@@ -104,6 +104,8 @@ const char* id_status_string(int code) {
       return "full rank: k == n";
     case ID_INFO_ABORTED:
       return "batched item abandoned: a workgroup sharing it did not arrive in time";
+    case ID_INFO_GRAM_LIMIT:
+      return "Gram front end stopped at its resolution floor (k is the steps completed)";
     default:
       return "unknown code";
   }

@@ -1016,7 +1016,17 @@ __global__ __launch_bounds__(BT) void k_batched_factor(id_batch_item* items, int
           G = G < 1 ? 1 : (G > kBatchMaxGroups ? kBatchMaxGroups : G);
           // position within the run of equal entries ending at q
           while (g < G && q - g - 1 >= 0 && slots && slots[q - g - 1] == item) ++g;
-          if (g >= G) item = -2;
+          if (g >= G) {
+            item = -2;
+          } else if (G > (int)gridDim.x) {
+            // its G workgroups can never all be running: the first marks the
+            // item abandoned at once instead of waiting for the others
+            if (g == 0) {
+              items[item].k = 0;
+              items[item].info = ID_INFO_ABORTED;
+            }
+            item = -2;
+          }
         }
       }
       sm.item = item;

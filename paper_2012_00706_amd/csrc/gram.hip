@@ -11,7 +11,12 @@
 // steps then work on n x n data.  Rounding: d is formed to about u_64 ||A||^2, so residual
 // norms below ~sqrt(u_64) ||A|| are not resolved and T = R11^{-1} R12 carries
 // about kappa(R11)^2 u_64 relative error (kappa(R11) u_64 for the Householder
-// path); the flag is meant for tall inputs and tolerances >= 1e-6.
+// path).  Two guards keep the route inside its resolution: adaptive
+// tolerances below kGramMinTol are refused (ID_ERR_UNSUPPORTED), and the
+// factorization stops, with ID_INFO_GRAM_LIMIT, before any step whose pivot
+// has d_p <= kGramFloor n u_64 |R_00|^2 (|R_00|^2 = max_l G_ll): below that the
+// Schur diagonal is rounding noise, so neither the pivot nor row j of R would
+// mean anything.  This holds for a fixed rank too.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -34,10 +39,13 @@ constexpr int kPcR = 16;      // entries of a column of R per thread held in reg
 constexpr int kGramBlocks = 4096;  // target blocks of the Gram product (16 resident per CU)
 constexpr int kGR = kGK64 * 64 / kThreads;  // rows per thread per round, 64 x 64 tiles
 constexpr int kGTH = kGK64 / kGR;           // threads per tile column
+constexpr double kGramMinTol = 1e-6;        // smallest adaptive tolerance accepted
+constexpr double kGramFloor = 8.0;          // resolution floor of d, in units of n u_64 |R_00|^2
 
 struct GramState {
   int32_t done, info;
-  int32_t pad0, pad1;
+  int32_t limit;  // stopped at the resolution floor (ID_INFO_GRAM_LIMIT)
+  int32_t pad1;
   int64_t k;
   double r00, fro2;
 };
@@ -306,6 +314,7 @@ struct PcholArgs {
   int64_t j;
   int64_t k_fixed;
   double rel_tol;
+  double floor_rel;  // kGramFloor n u_64: the resolution floor of d_p / |R_00|^2
   int rule;
 };
 
@@ -374,10 +383,13 @@ __global__ __launch_bounds__(kThreads) void k_pchol_step(PcholArgs a) {
     else
       stop = sqrt(best.s2) <= a.rel_tol * sqrt(fro2);
   }
-  if (stop) {
+  // the resolution guard (every block takes the same decision: same best)
+  const bool at_floor = !stop && j > 0 && vp * vp <= a.floor_rel * r00 * r00;
+  if (stop || at_floor) {
     if (blockIdx.x == 0 && tid == 0) {
       a.st->done = 1;
       a.st->k = j;
+      if (at_floor) a.st->limit = 1;
     }
     return;
   }
@@ -483,6 +495,7 @@ __global__ void k_gram_state_init(GramState* st) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
     st->done = 0;
     st->info = 0;
+    st->limit = 0;
     st->k = 0;
     st->r00 = 0.0;
     st->fro2 = 0.0;
@@ -502,6 +515,8 @@ int gram_factor_run(const void* A, int32_t dtype, int64_t m, int64_t n, int64_t 
   if (pl.kcap > 0 && (!R || ldr < pl.kcap)) return ID_ERR_ARG;
   if (!work || work_bytes < pl.bytes) return ID_ERR_WORKSPACE;
   if (pl.kcap > 2048) return ID_ERR_UNSUPPORTED;  // column of R staged in LDS
+  // adaptive tolerances below the route's resolution cannot be honoured
+  if (o->k_fixed == 0 && o->rel_tol < kGramMinTol) return ID_ERR_UNSUPPORTED;
   *info = 0;
   *k_out = 0;
   if (m == 0 || n == 0 || pl.kcap == 0) return identity_perm(perm, n, s);
@@ -574,6 +589,7 @@ int gram_factor_run(const void* A, int32_t dtype, int64_t m, int64_t n, int64_t 
   pa.st = st;
   pa.k_fixed = o->k_fixed;
   pa.rel_tol = o->rel_tol;
+  pa.floor_rel = kGramFloor * (double)n * std::ldexp(1.0, -53);
   pa.rule = o->rank_rule;
   while (!finished && j < pl.kcap + 1) {
     const int64_t jend = j + group < pl.kcap + 1 ? j + group : pl.kcap + 1;
@@ -622,6 +638,7 @@ int gram_factor_run(const void* A, int32_t dtype, int64_t m, int64_t n, int64_t 
   }
   const int64_t k = fin.done ? fin.k : pl.kcap;
   *k_out = k;
+  if (fin.limit) *info = ID_INFO_GRAM_LIMIT;
   // the keys after the last executed step are in pos[k & 1]
   k_pchol_perm<<<dim3((unsigned)ceil_div(n, kThreads)), kThreads, 0, s>>>(pos[k & 1], n, perm);
   MPID_LAUNCH_CHECK();

@@ -6,6 +6,18 @@ import torch
 
 import oracle as orc
 
+# Unit round-off of the split-BF16 update (ID_PREC_MIXED_BF16X3): each operand
+# is x = hi + lo with hi, lo BF16 (8 significand bits each), and the product is
+# hi*hi + hi*lo + lo*hi with FP32 accumulation.  The dropped lo*lo term and the
+# remainder of the split are each below 2^-16 of the product, so the update is
+# accurate to about 2^-16 of its size (the FP32 accumulation adds 2^-24).
+U_BF16X3 = 2.0 ** -16
+
+# Unit round-off per precision policy, for the acceptance rule
+# err_mixed <= 1.1 err_oracle + 10 u_low ||A||_2.
+U_LOW = {"mixed_bf16": orc.U_BF16, "mixed_bf16x3": U_BF16X3, "mixed_f16": orc.U_HALF,
+         "mixed_f32": orc.U_SINGLE, "f64": orc.U_DOUBLE}
+
 
 def need_gpu():
     if not torch.cuda.is_available():
@@ -53,3 +65,34 @@ def acceptance_bound(err_oracle, u_low, norm2_a):
 
 def spectral_error(A_np, perm, k, T):
     return orc.id_error(A_np, perm, k, T)[0]
+
+
+def assert_f64_parity(perm, k, R, T, ref, n, info=0):
+    """Strict parity of an FP64 result with the oracle's CPQR ``ref`` (same k).
+
+    The input must be gap-separated (every oracle pivot margin > 1e-8: the
+    check fails otherwise, so no comparison is skipped).  Then the pivots are
+    equal, R matches row by row up to row signs to 1e-12 max|R| element-wise,
+    and T = R11^{-1} R12 matches element-wise to
+    1e-12 max|T| max(1, kappa(R11) / 1e3) (the solve amplifies the rounding of
+    R by up to kappa(R11)).  Returns the number of T entries compared."""
+    assert k == ref.k
+    if k:
+        assert ref.margins.min() > 1e-8, "input not gap-separated"
+    perm = np.asarray(perm).astype(np.int64)
+    assert perm[:k].tolist() == ref.perm[:k].tolist()
+    if k == 0:
+        return 0
+    np.testing.assert_allclose(row_sign_align(R[:k], ref.R), ref.R, rtol=0,
+                               atol=1e-12 * np.abs(ref.R).max())
+    if k == n:
+        assert T.size == 0
+        return 0
+    assert info == 0
+    Tref = orc.solve_T(ref.R, k)
+    kappa = np.linalg.cond(ref.R[:, :k])
+    tol = 1e-12 * np.abs(Tref).max() * max(1.0, kappa / 1e3)
+    assert T.shape == Tref.shape
+    dmax = np.abs(T - Tref).max()
+    assert dmax <= tol, f"max |dT| {dmax:.3e} > {tol:.3e} (kappa {kappa:.2e})"
+    return T.size

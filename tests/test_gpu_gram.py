@@ -116,3 +116,42 @@ def test_gram_edge_cases():
     assert res.k == 12 and res.T.shape == (12, 0)
     with pytest.raises(mp.MpidError):
         mp.factor(to_dev(full), k=3, gram=True, no_pivot=True)
+
+
+def test_gram_guard_stops_at_resolution_floor():
+    """sigma_i = 10^(-(i-1)/8), k = 60 (sigma_60 / sigma_1 = 4e-8): the Gram
+    route resolves residual norms only down to about sqrt(8 n u_64) |R_00|
+    (4.2e-7 at n = 200), so it stops there with ID_INFO_GRAM_LIMIT instead of
+    returning pivots chosen by rounding noise.  The steps it made follow the
+    oracle's pivots wherever the Gram rounding (relative perturbation of the
+    residual norms about 64 u_64 |R_00|^2 / r_j^2) cannot reorder them."""
+    need_gpu()
+    import paper_2012_00706_amd as mp
+    n = 200
+    A = synth.spectrum_matrix(3000, n, synth.sigma_geom10(n, 8.0), 3003, 203)
+    res = mp.column_id(to_dev(A), k=60, gram=True)
+    assert res.info == mp.C["ID_INFO_GRAM_LIMIT"]
+    k = res.k
+    assert 0 < k < 60
+    ref = orc.cpqr(A, k=60)
+    r00 = ref.pivot_norms[0]
+    floor = np.sqrt(8 * n * 2.0 ** -53) * r00
+    # the stop sits at the floor (within the Gram route's own rounding)
+    assert ref.pivot_norms[k] <= 1.5 * floor and ref.pivot_norms[k - 1] >= floor / 1.5
+    delta = 64 * 2.0 ** -53 * r00 ** 2 / ref.pivot_norms ** 2
+    bad = ref.margins[:k] <= delta[:k]
+    upto = int(np.argmax(bad)) if np.any(bad) else k
+    assert upto >= k // 2
+    perm = host(res.perm).astype(np.int64)
+    assert perm[:upto].tolist() == ref.perm[:upto].tolist()
+
+
+def test_gram_refuses_tolerance_below_resolution():
+    need_gpu()
+    import paper_2012_00706_amd as mp
+    A = synth.spectrum_matrix(2000, 100, synth.sigma_geom10(100, 8.0), 5, 6)
+    with pytest.raises(mp.MpidError) as e:
+        mp.column_id(to_dev(A), tol=1e-7, gram=True)
+    assert e.value.code == mp.C["ID_ERR_UNSUPPORTED"]
+    res = mp.column_id(to_dev(A), tol=1e-6, gram=True)  # at the limit: accepted
+    assert res.k > 0
