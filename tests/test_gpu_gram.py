@@ -112,8 +112,12 @@ def test_gram_edge_cases():
     perm, k, R, T = _gram_id(one, k=1)
     assert k == 1 and abs(abs(R[0, 0]) - np.linalg.norm(one)) <= 1e-13 * np.linalg.norm(one)
     full = synth.gaussian(300, 12, seed=6)
-    res = mp.column_id(to_dev(full), tol=1e-12, gram=True)
+    # full rank through the fixed rank (an adaptive 1e-12 is below the
+    # route's resolution and refused)
+    res = mp.column_id(to_dev(full), k=12, gram=True)
     assert res.k == 12 and res.T.shape == (12, 0)
+    with pytest.raises(mp.MpidError):
+        mp.column_id(to_dev(full), tol=1e-12, gram=True)
     with pytest.raises(mp.MpidError):
         mp.factor(to_dev(full), k=3, gram=True, no_pivot=True)
 
