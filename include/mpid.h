@@ -36,6 +36,7 @@ extern "C" {
 #define ID_ERR_WORKSPACE (-3)   /* work_bytes smaller than id_workspace_size() */
 #define ID_ERR_HIP (-4)         /* a HIP runtime call failed */
 #define ID_ERR_UNSUPPORTED (-5) /* combination not supported */
+#define ID_ERR_SCRATCH (-6)     /* problem larger than id_factor_noalloc's static scratch */
 #define ID_INFO_NONFINITE 1     /* A holds NaN or Inf: nothing was factored (k = 0) */
 #define ID_INFO_SINGULAR 2      /* R11 has |R_ii| <= n * 2^-53 * |R_00|; T not formed */
 #define ID_INFO_RANK_FULL 3     /* k = n: T has no columns, P is a permutation */
@@ -135,6 +136,35 @@ size_t id_workspace_size(int64_t m, int64_t n, int32_t dtype, const id_opts* opt
 int id_factor(const void* A, int32_t dtype, int64_t m, int64_t n, int64_t lda,
               const id_opts* opts, void* work, size_t work_bytes, int32_t* perm, double* R,
               int64_t ldr, int64_t* k_out, int32_t* info, void* stream);
+
+/* ---- allocation-free factorization -------------------------------------
+ * For callers that cannot allocate: code under HIP graph capture setup, tight
+ * serving loops, harnesses that forbid hipMalloc.  id_factor_noalloc computes
+ * exactly what id_factor computes (same kernels, same results bit for bit),
+ * but its workspace is a static device array of ID_NOALLOC_SCRATCH_MB MiB
+ * inside the library (one per GPU, held from the library's load until the
+ * process ends) and it calls no hipMalloc, hipHostMalloc, hipFree or event
+ * creation: the host reads each panel's end state with a copy into host
+ * memory of its own, which waits for the stream (so panels are not enqueued
+ * ahead of the host; a little slower than id_factor).
+ *
+ *   Arguments as in id_factor, without work / work_bytes.
+ *   Returns ID_ERR_SCRATCH when id_workspace_size(m, n, dtype, opts) exceeds
+ *   id_noalloc_scratch_bytes() (nothing is enqueued), ID_ERR_UNSUPPORTED for
+ *   ID_FLAG_GRAM or ID_FLAG_PROFILE, ID_ERR_ARG when "stream" does not belong
+ *   to the current device (whose scratch is used).
+ * Every call on one GPU shares that GPU's scratch, which keeps the last
+ * call's contents (each call initializes what it reads before reading it):
+ * calls that overlap on one GPU -- from several host threads or on several
+ * streams -- race and must not be made. */
+#define ID_NOALLOC_SCRATCH_MB 128
+
+/* Bytes of the static scratch of id_factor_noalloc [host]. */
+size_t id_noalloc_scratch_bytes(void);
+
+int id_factor_noalloc(const void* A, int32_t dtype, int64_t m, int64_t n, int64_t lda,
+                      const id_opts* opts, int32_t* perm, double* R, int64_t ldr, int64_t* k_out,
+                      int32_t* info, void* stream);
 
 /* Interpolation coefficients T = R11^{-1} R12 in float64 (eq. (8); the
  * coefficient step of Algorithms 1 and 2; Remark 1.1's pseudo-inverse equals

@@ -16,6 +16,7 @@ from .api import (  # noqa: F401
     column_id,
     empty_colmajor,
     factor,
+    factor_noalloc,
     kcap_of,
     last_profile,
     make_opts,

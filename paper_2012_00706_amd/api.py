@@ -127,6 +127,36 @@ def factor(A: torch.Tensor, k=None, tol=None, prec="f64", rule="pivot_rel", k_ma
     return FactorResult(perm_buf, R_buf[:kk], kk, int(info.value))
 
 
+def factor_noalloc(A: torch.Tensor, k=None, tol=None, prec="f64", rule="pivot_rel", k_max=0,
+                   nb=0, no_pivot=False, R_buf: torch.Tensor | None = None,
+                   perm_buf: torch.Tensor | None = None) -> FactorResult:
+    """id_factor_noalloc: the factorization of factor() in the library's static
+    scratch (no workspace argument).  The library allocates nothing; this
+    wrapper allocates R and perm unless the caller passes them."""
+    lib = _lib.load()
+    A, lda = colmajor(A)
+    m, n = A.shape
+    if k is not None and int(k) == 0:
+        return FactorResult(torch.arange(n, dtype=torch.int32, device=A.device),
+                            empty_colmajor(0, n, device=A.device), 0, 0)
+    o = make_opts(k, tol, prec, rule, k_max, nb, no_pivot, False, False)
+    kc = kcap_of(m, n, o)
+    if R_buf is None:
+        R_buf = empty_colmajor(max(kc, 1), n, device=A.device)
+    if perm_buf is None:
+        perm_buf = torch.empty(n, dtype=torch.int32, device=A.device)
+    ldr = max(R_buf.stride(1), 1) if n > 1 else max(kc, 1)
+    k_out = ctypes.c_int64(0)
+    info = ctypes.c_int32(0)
+    with torch.cuda.device(A.device):
+        rc = lib.id_factor_noalloc(A.data_ptr(), DTYPE[A.dtype], m, n, lda, ctypes.byref(o),
+                                   perm_buf.data_ptr(), R_buf.data_ptr(), ldr, ctypes.byref(k_out),
+                                   ctypes.byref(info), _stream(A.device))
+    _lib.check(rc, "id_factor_noalloc")
+    kk = int(k_out.value)
+    return FactorResult(perm_buf, R_buf[:kk], kk, int(info.value))
+
+
 def solve_T(R: torch.Tensor, k: int, n: int, T_buf: torch.Tensor | None = None,
             check: bool = True):
     """T = R11^{-1} R12 (id_solve_T).  Returns (T, info) with info a device int32

@@ -96,6 +96,8 @@ const char* id_status_string(int code) {
       return "HIP runtime error";
     case ID_ERR_UNSUPPORTED:
       return "unsupported combination";
+    case ID_ERR_SCRATCH:
+      return "problem larger than the static scratch of id_factor_noalloc";
     case ID_INFO_NONFINITE:
       return "input holds NaN or Inf";
     case ID_INFO_SINGULAR:

@@ -134,6 +134,7 @@ bool make_factor_plan(int64_t m, int64_t n, int32_t dtype, const id_opts* o, Fac
   p->off_vscale = take((size_t)kNbMax * 8);
   p->off_rorig = take((size_t)kk * nn * 8);
   p->off_state = take(sizeof(FactorState));
+  p->off_slot = take(2 * sizeof(FactorHostSlot));  // panel end states (allocation-free calls)
   p->bytes = off;
   return true;
 }
@@ -1319,7 +1320,7 @@ static int await_slot(const FactorHostSlot* hs, int64_t seq) {
 template <typename TA, typename S, int OP>
 static int factor_impl(const TA* A, int64_t lda, const FactorPlan& pl, const id_opts* o,
                        char* wb, int32_t* perm, double* R, int64_t ldr, int64_t* k_out,
-                       int32_t* info, hipStream_t s) {
+                       int32_t* info, bool noalloc, hipStream_t s) {
   const int64_t m = pl.m, n = pl.n, kcap = pl.kcap;
   S* W[2] = {(S*)(wb + pl.off_w0), (S*)(wb + pl.off_w1)};
   S* V = (S*)(wb + pl.off_v);
@@ -1415,17 +1416,26 @@ static int factor_impl(const TA* A, int64_t lda, const FactorPlan& pl, const id_
   // Every live panel compacts into the other buffer, so panel P works on
   // buffer P & 1.
   // The panel-end reduction writes the state after panel P into slot P & 1,
-  // tagged with this call's number and P.
+  // tagged with this call's number and P.  The slots are pinned host memory
+  // (allocated on a thread's first call, read after the panel's event), or,
+  // in an allocation-free call, two slots in the workspace that the host
+  // copies into host memory of its own (the copy waits for the stream).
   static thread_local FactorHostSlot* hslot = nullptr;
   static thread_local hipEvent_t pev[2] = {nullptr, nullptr};
+  static thread_local FactorHostSlot mirror[2];
   static thread_local int64_t ncalls = 0;
-  if (!hslot) {
-    MPID_HIP(hipHostMalloc((void**)&hslot, 2 * sizeof(FactorHostSlot), hipHostMallocCoherent));
-    hslot[0].seq = hslot[1].seq = 0;
+  FactorHostSlot* dslot = (FactorHostSlot*)(wb + pl.off_slot);
+  FactorHostSlot* kslot = dslot;  // the slots the kernels write
+  if (!noalloc) {
+    if (!hslot) {
+      MPID_HIP(hipHostMalloc((void**)&hslot, 2 * sizeof(FactorHostSlot), hipHostMallocCoherent));
+      hslot[0].seq = hslot[1].seq = 0;
+    }
+    for (int q = 0; q < 2; ++q)
+      if (!pev[q]) MPID_HIP(hipEventCreateWithFlags(&pev[q], hipEventDisableTiming));
+    kslot = hslot;
   }
   const int64_t seq0 = (++ncalls) << 24;
-  for (int q = 0; q < 2; ++q)
-    if (!pev[q]) MPID_HIP(hipEventCreateWithFlags(&pev[q], hipEventDisableTiming));
   int64_t off_lb = 0;     // lower bound of the offset of the panel being enqueued
   int64_t known_off = 0;  // exact offset at the start of the first unsettled panel
   const FactorState* fin = nullptr;
@@ -1472,10 +1482,21 @@ static int factor_impl(const TA* A, int64_t lda, const FactorPlan& pl, const id_
   const FactorState* fin_drain = nullptr;
   auto settle_upto = [&](int target, const FactorState** done_state) -> int {
     while (settled <= target) {
-      MPID_HIP(hipEventSynchronize(pev[settled & 1]));
-      const int rs = await_slot(&hslot[settled & 1], seq0 + settled + 1);
-      if (rs) return rs;
-      const FactorState& h = hslot[settled & 1].s;
+      const FactorHostSlot* hs;
+      if (noalloc) {
+        FactorHostSlot* dst = &mirror[settled & 1];
+        MPID_HIP(hipMemcpyAsync(dst, &dslot[settled & 1], sizeof(FactorHostSlot),
+                                hipMemcpyDeviceToHost, s));
+        MPID_HIP(hipStreamSynchronize(s));
+        if (dst->seq != seq0 + settled + 1) return ID_ERR_HIP;
+        hs = dst;
+      } else {
+        MPID_HIP(hipEventSynchronize(pev[settled & 1]));
+        const int rs = await_slot(&hslot[settled & 1], seq0 + settled + 1);
+        if (rs) return rs;
+        hs = &hslot[settled & 1];
+      }
+      const FactorState& h = hs->s;
       settle(settled, known_off, h);
       ++settled;
       if (h.done) {
@@ -1601,11 +1622,11 @@ static int factor_impl(const TA* A, int64_t lda, const FactorPlan& pl, const id_
     prof.begin(PK_OTHER, (int64_t)panel * 1024, s);
     k_colreduce<<<dim3((unsigned)namax), kThreads, 0, s>>>(colpart, ldf, g.tg0, ntg, ncur_ub, 1,
                                                             nu, nuo, amax, colid[cur ^ 1], posof,
-                                                            pvflag, st, count_tol, &hslot[cur],
+                                                            pvflag, st, count_tol, &kslot[cur],
                                                             seq0 + panel + 1);
     MPID_LAUNCH_CHECK();
     prof.end(s);
-    MPID_HIP(hipEventRecord(pev[cur], s));
+    if (!noalloc) MPID_HIP(hipEventRecord(pev[cur], s));
     // Settle panels up to the previous one (the panel just enqueued keeps the
     // GPU busy meanwhile).  Near the end (drain) the next iteration settles
     // this panel before enqueueing another, so no idle panel follows the stop.
@@ -1642,9 +1663,10 @@ static int factor_impl(const TA* A, int64_t lda, const FactorPlan& pl, const id_
   return ID_OK;
 }
 
-int factor_run(const void* A, int32_t dtype, int64_t m, int64_t n, int64_t lda,
-               const id_opts* o, void* work, size_t work_bytes, int32_t* perm, double* R,
-               int64_t ldr, int64_t* k_out, int32_t* info, hipStream_t s) {
+static int factor_dispatch(const void* A, int32_t dtype, int64_t m, int64_t n, int64_t lda,
+                           const id_opts* o, void* work, size_t work_bytes, int32_t* perm,
+                           double* R, int64_t ldr, int64_t* k_out, int32_t* info, bool noalloc,
+                           hipStream_t s) {
   FactorPlan pl;
   if (!make_factor_plan(m, n, dtype, o, &pl)) return ID_ERR_ARG;
   if (!k_out || !info) return ID_ERR_ARG;
@@ -1666,36 +1688,51 @@ int factor_run(const void* A, int32_t dtype, int64_t m, int64_t n, int64_t lda,
   if (pl.prec == ID_PREC_F64) {
     if (dtype == ID_F64)
       return factor_impl<double, double, OP_F64>((const double*)A, lda, pl, o, wb, perm, R, ldr,
-                                                  k_out, info, s);
+                                                  k_out, info, noalloc, s);
     return factor_impl<float, double, OP_F64>((const float*)A, lda, pl, o, wb, perm, R, ldr, k_out,
-                                              info, s);
+                                              info, noalloc, s);
   }
   if (pl.prec == ID_PREC_MIXED_F16) {
     if (dtype == ID_F64)
       return factor_impl<double, float, OP_F16>((const double*)A, lda, pl, o, wb, perm, R, ldr,
-                                                k_out, info, s);
+                                                k_out, info, noalloc, s);
     return factor_impl<float, float, OP_F16>((const float*)A, lda, pl, o, wb, perm, R, ldr, k_out,
-                                             info, s);
+                                             info, noalloc, s);
   }
   if (pl.prec == ID_PREC_MIXED_F32) {
     if (dtype == ID_F64)
       return factor_impl<double, float, OP_F32>((const double*)A, lda, pl, o, wb, perm, R, ldr,
-                                                k_out, info, s);
+                                                k_out, info, noalloc, s);
     return factor_impl<float, float, OP_F32>((const float*)A, lda, pl, o, wb, perm, R, ldr, k_out,
-                                             info, s);
+                                             info, noalloc, s);
   }
   if (pl.prec == ID_PREC_MIXED_BF16X3) {
     if (dtype == ID_F64)
       return factor_impl<double, float, OP_BF16X3>((const double*)A, lda, pl, o, wb, perm, R, ldr,
-                                                   k_out, info, s);
+                                                   k_out, info, noalloc, s);
     return factor_impl<float, float, OP_BF16X3>((const float*)A, lda, pl, o, wb, perm, R, ldr,
-                                                k_out, info, s);
+                                                k_out, info, noalloc, s);
   }
   if (dtype == ID_F64)
     return factor_impl<double, float, OP_BF16>((const double*)A, lda, pl, o, wb, perm, R, ldr,
-                                               k_out, info, s);
+                                               k_out, info, noalloc, s);
   return factor_impl<float, float, OP_BF16>((const float*)A, lda, pl, o, wb, perm, R, ldr, k_out,
-                                            info, s);
+                                            info, noalloc, s);
+}
+
+int factor_run(const void* A, int32_t dtype, int64_t m, int64_t n, int64_t lda,
+               const id_opts* o, void* work, size_t work_bytes, int32_t* perm, double* R,
+               int64_t ldr, int64_t* k_out, int32_t* info, hipStream_t s) {
+  return factor_dispatch(A, dtype, m, n, lda, o, work, work_bytes, perm, R, ldr, k_out, info,
+                         false, s);
+}
+
+int factor_run_noalloc(const void* A, int32_t dtype, int64_t m, int64_t n, int64_t lda,
+                       const id_opts* o, void* work, size_t work_bytes, int32_t* perm, double* R,
+                       int64_t ldr, int64_t* k_out, int32_t* info, hipStream_t s) {
+  if (o && (o->flags & (ID_FLAG_GRAM | ID_FLAG_PROFILE))) return ID_ERR_UNSUPPORTED;
+  return factor_dispatch(A, dtype, m, n, lda, o, work, work_bytes, perm, R, ldr, k_out, info,
+                         true, s);
 }
 
 }  // namespace mpid

@@ -67,7 +67,7 @@ struct FactorPlan {
   size_t off_w0, off_w1, off_v, off_f, off_zpart, off_auxpart, off_nrm2part, off_zfold,
       off_afold, off_nfold, off_colpart,
       off_nu, off_nuo, off_amax, off_colid0, off_colid1, off_pvflag, off_pivpos, off_pivid,
-      off_permw, off_posof, off_tau, off_vscale, off_rorig, off_state;
+      off_permw, off_posof, off_tau, off_vscale, off_rorig, off_state, off_slot;
   size_t bytes;
 };
 
@@ -76,6 +76,14 @@ bool make_factor_plan(int64_t m, int64_t n, int32_t dtype, const id_opts* o, Fac
 int factor_run(const void* A, int32_t dtype, int64_t m, int64_t n, int64_t lda,
                const id_opts* o, void* work, size_t work_bytes, int32_t* perm, double* R,
                int64_t ldr, int64_t* k_out, int32_t* info, hipStream_t s);
+
+// The same factorization for callers that cannot allocate: "work" is the
+// library's static scratch, the host reads each panel's end state with a copy
+// into host memory it already owns (no pinned slot, no events), so nothing is
+// allocated.  ID_FLAG_GRAM and ID_FLAG_PROFILE are refused (ID_ERR_UNSUPPORTED).
+int factor_run_noalloc(const void* A, int32_t dtype, int64_t m, int64_t n, int64_t lda,
+                       const id_opts* o, void* work, size_t work_bytes, int32_t* perm, double* R,
+                       int64_t ldr, int64_t* k_out, int32_t* info, hipStream_t s);
 
 void last_profile(id_profile* out);
 

@@ -119,3 +119,28 @@ def test_options_validation():
         make_opts(k=3, prec="fp8")
     with pytest.raises(ValueError):
         make_opts(k=3, rule="nope")
+
+
+def test_noalloc_host_checks(lib):
+    """id_factor_noalloc refuses, before any device call, what does not fit
+    its static scratch and the flags it does not take."""
+    from paper_2012_00706_amd import C, make_opts
+    assert lib.id_noalloc_scratch_bytes() == C["ID_NOALLOC_SCRATCH_MB"] << 20
+    k = ctypes.c_int64(0)
+    info = ctypes.c_int32(0)
+    fake = ctypes.c_void_p(0x1000)
+    o = make_opts(tol=1e-3, prec="mixed_bf16x3")
+    # 20000 x 2000 fp32 needs about 362 MiB of workspace
+    assert lib.id_workspace_size(20000, 2000, C["ID_F32"], ctypes.byref(o)) > \
+        lib.id_noalloc_scratch_bytes()
+    rc = lib.id_factor_noalloc(fake, C["ID_F32"], 20000, 2000, 20000, ctypes.byref(o), fake, fake,
+                               2000, ctypes.byref(k), ctypes.byref(info), None)
+    assert rc == C["ID_ERR_SCRATCH"]
+    assert lib.id_status_string(rc).decode() != "unknown code"
+    g = make_opts(tol=1e-3, gram=True)
+    rc = lib.id_factor_noalloc(fake, C["ID_F64"], 100, 10, 100, ctypes.byref(g), fake, fake, 10,
+                               ctypes.byref(k), ctypes.byref(info), None)
+    assert rc == C["ID_ERR_UNSUPPORTED"]
+    rc = lib.id_factor_noalloc(fake, 9, 100, 10, 100, ctypes.byref(o), fake, fake, 10,
+                               ctypes.byref(k), ctypes.byref(info), None)
+    assert rc == C["ID_ERR_DTYPE"]
