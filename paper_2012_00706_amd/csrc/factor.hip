@@ -112,13 +112,16 @@ bool make_factor_plan(int64_t m, int64_t n, int32_t dtype, const id_opts* o, Fac
   p->off_w1 = take((size_t)mm * p->ldw * p->wbytes);
   p->off_v = take((size_t)kNbMax * p->ldv * p->wbytes);
   p->off_f = take((size_t)kNbMax * p->ldf * 8);
-  p->off_zpart = take((size_t)p->ntile_s_max * p->ldf * 8);
-  p->off_auxpart = take((size_t)p->ntile_s_max * kNbMax * 8);
-  p->off_nrm2part = take((size_t)p->ntile_s_max * 8);
+  // per-tile partials, plus a row of zeros after the last tile (zeroed by
+  // k_init, never written by a sweep or fold)
+  p->off_zpart = take((size_t)(p->ntile_s_max + 1) * p->ldf * 8);
+  p->off_auxpart = take((size_t)(p->ntile_s_max + 1) * kNbMax * 8);
+  p->off_nrm2part = take((size_t)(p->ntile_s_max + 1) * 8);
   const int64_t nfold = ceil_div(p->ntile_s_max, kFold);
-  p->off_zfold = take((size_t)nfold * p->ldf * 8);
-  p->off_afold = take((size_t)nfold * kNbMax * 8);
-  p->off_nfold = take((size_t)nfold * 8);
+  p->nfold_max = nfold;
+  p->off_zfold = take((size_t)(nfold + 1) * p->ldf * 8);
+  p->off_afold = take((size_t)(nfold + 1) * kNbMax * 8);
+  p->off_nfold = take((size_t)(nfold + 1) * 8);
   p->off_colpart = take((size_t)p->ntile_g * p->ldf * 8);
   p->off_nu = take((size_t)p->ldf * 8);
   p->off_nuo = take((size_t)p->ldf * 8);
@@ -135,19 +138,36 @@ bool make_factor_plan(int64_t m, int64_t n, int32_t dtype, const id_opts* o, Fac
   p->off_rorig = take((size_t)kk * nn * 8);
   p->off_state = take(sizeof(FactorState));
   p->off_slot = take(2 * sizeof(FactorHostSlot));  // panel end states (allocation-free calls)
+  p->off_wrow = take((size_t)p->ldf * 8);
+  p->off_vrow = take((size_t)kNbMax * 8);
+  p->off_keypos = take((size_t)p->ldf * 4);
   p->bytes = off;
   return true;
 }
 
 // ----------------------------------------------------------------- kernels
 
+// zrow[0..2] / frow[0..2]: the zero rows of the per-tile and the folded
+// partials (ldf, kNbMax and 1 entries).
 __global__ __launch_bounds__(kThreads) void k_init(FactorState* st, int* colid0, int* pvflag,
                                                    int* permw, int* posof, int64_t n,
-                                                   int64_t ldf) {
+                                                   int64_t ldf, double* zrow_z, double* zrow_a,
+                                                   double* zrow_n, double* frow_z,
+                                                   double* frow_a, double* frow_n) {
   const int64_t l = (int64_t)blockIdx.x * kThreads + threadIdx.x;
   if (l < ldf) {
     colid0[l] = (int)l;
     pvflag[l] = 0;
+    zrow_z[l] = 0.0;
+    frow_z[l] = 0.0;
+  }
+  if (l < kNbMax) {
+    zrow_a[l] = 0.0;
+    frow_a[l] = 0.0;
+  }
+  if (l == 0) {
+    zrow_n[0] = 0.0;
+    frow_n[0] = 0.0;
   }
   if (l < n) {
     permw[l] = (int)l;
@@ -234,7 +254,8 @@ __device__ __forceinline__ void colreduce_block(
     const double* __restrict__ colpart, int64_t ldf, int64_t tg0, int64_t tg1, int64_t ncols_base,
     int subtract_jb, double* __restrict__ nu, double* __restrict__ nuo, AmaxPart* __restrict__ amax,
     const int* __restrict__ colid, const int* __restrict__ posof, int* __restrict__ pvflag,
-    FactorState* st, double rel_tol, double (*red)[kFinCols + 1], AmaxVal* ascr) {
+    int* __restrict__ keypos, FactorState* st, double rel_tol, double (*red)[kFinCols + 1],
+    AmaxVal* ascr) {
   const int tid = threadIdx.x, cl = tid % kFinCols, tl = tid / kFinCols;
   const int64_t ncols = subtract_jb ? st->ncur - st->jb : ncols_base;
   const int64_t l = (int64_t)blockIdx.x * kFinCols + cl;
@@ -254,6 +275,7 @@ __device__ __forceinline__ void colreduce_block(
     cand.s2 = tot;
     cand.pos = (int)l;
     cand.key = posof[colid[l]];
+    keypos[l] = cand.key;
     above = v > rel_tol * st->r00 ? 1 : 0;
   }
   cand = block_amax(cand, ascr);
@@ -284,7 +306,7 @@ __global__ __launch_bounds__(kThreads) void k_colreduce(
     const double* __restrict__ colpart, int64_t ldf, int64_t tg0, int64_t tg1, int64_t ncols_base,
     int subtract_jb, double* __restrict__ nu, double* __restrict__ nuo, AmaxPart* __restrict__ amax,
     const int* __restrict__ colid, const int* __restrict__ posof, int* __restrict__ pvflag,
-    FactorState* st, double rel_tol, FactorHostSlot* hs, int64_t seq) {
+    int* __restrict__ keypos, FactorState* st, double rel_tol, FactorHostSlot* hs, int64_t seq) {
   __shared__ double red[8][kFinCols + 1];
   __shared__ AmaxVal ascr[4];
   __shared__ int s_go, s_last;
@@ -293,7 +315,7 @@ __global__ __launch_bounds__(kThreads) void k_colreduce(
   __syncthreads();
   if (s_go)
     colreduce_block(colpart, ldf, tg0, tg1, ncols_base, subtract_jb, nu, nuo, amax, colid, posof,
-                    pvflag, st, rel_tol, red, ascr);
+                    pvflag, keypos, st, rel_tol, red, ascr);
   if (hs == nullptr) return;
   if (tid == 0) {
     __threadfence();  // this block's counts before its arrival
@@ -345,31 +367,39 @@ struct StepArgs {
   double* nu;
   double* nuo;
   double* rorig;
+  double* wrow;  // the step's row of W, for the finalization (written by the sweep)
+  double* vrow;  // the step's row of the panel's reflectors (unscaled)
+  int* keypos;   // swap-order key of each working position
   int64_t kcap, k_fixed;
   double rel_tol, tol3z;
   int rule, nopivot, nb;
+  int want_fmax;  // the panel update scales FP16 operands by the panel's max |F|
   // per step; j and ncur above are the host's bounds (j <= the step's row,
   // ncur >= the live column count), the exact values live in the state
   int64_t j;
   int jj;
   int64_t t0;
   int ntile, nchunk, Rt, CW;
+  int64_t tguard;  // row of zeros in zpart / auxpart / nrm2part (past every tile)
 };
 
 // One pivot step, part 1.  Grid: (row tiles of Rt <= 256 rows) x (column
 // chunks of CW positions), padded to a multiple of 8 and remapped so that the
 // chunks of one row tile run on the same XCD (they share the pivot column and
 // the reflector rows through that XCD's L2).  G = 256 / Rt threads share a row.
-//  - reduces the pivot partials, applies the rank rule, records the pivot;
+//  - reduces the pivot partials, applies the rank rule, records the pivot
+//    (and which column's swap-order key the swap changed);
 //  - w = W(i,p) - sum_c V(i,c) F(p,c) for the tile's rows i >= j;
 //  - z(l) = sum_{i>j} W(i,l) w(i) for the chunk's columns (the sweep);
 //  - partial sums over the tile of V(i,c) w(i) (c split across the chunks)
-//    and, in chunk 0, of w(i)^2; chunk 0 also stores w as reflector jj.
+//    and, in chunk 0, of w(i)^2; chunk 0 also stores w as reflector jj;
+//  - the tile holding row j copies that row of W and of the panel's earlier
+//    reflectors for the finalization.
 // Everything that does not depend on the pivot -- flags, pivot partials, the
 // reflector entries of the tile and the first rows of the sweep -- is loaded
 // in one round trip before the pivot is known.
 template <typename S, int G>
-__global__ __launch_bounds__(kThreads) void k_sweep(StepArgs<S> a) {
+__device__ __forceinline__ void sweep_block(const StepArgs<S>& a, const int bid, const int nblk) {
   typedef typename Vec16<S>::type VT;
   constexpr int VEC = Vec16<S>::n;
   constexpr int SLOTS = kNbMax / G;
@@ -385,8 +415,8 @@ __global__ __launch_bounds__(kThreads) void k_sweep(StepArgs<S> a) {
   FactorState* st = a.st;
   const int tid = threadIdx.x;
   const int total = a.ntile * a.nchunk;
-  const int per = gridDim.x / 8;
-  const int v = (blockIdx.x % 8) * per + blockIdx.x / 8;
+  const int per = nblk / 8;
+  const int v = (bid % 8) * per + bid / 8;
   if (v >= total) return;
   const int64_t tile = a.t0 + v / a.nchunk;
   const int chunk = v % a.nchunk;
@@ -483,14 +513,14 @@ __global__ __launch_bounds__(kThreads) void k_sweep(StepArgs<S> a) {
     }
   }
   if (stop) {
-    if (blockIdx.x == 0 && tid == 0) {
+    if (bid == 0 && tid == 0) {
       st->done = 1;
       st->k = j;
       st->end_flag = 1;
     }
     return;
   }
-  if (blockIdx.x == 0 && tid == 0) {
+  if (bid == 0 && tid == 0) {
     a.pivpos[jj] = p;
     a.pvflag[p] = 1;
     const int q = a.colid[p];
@@ -501,6 +531,9 @@ __global__ __launch_bounds__(kThreads) void k_sweep(StepArgs<S> a) {
     a.posof[other] = pa;
     a.permw[j] = q;
     a.posof[q] = (int)j;
+    // the only live column whose key changed (q is pivoted)
+    st->swap_other = other;
+    st->swap_key = pa;
     st->jb = jj + 1;
     if (j == 0) st->fro2 = best.s2;
   }
@@ -562,6 +595,12 @@ __global__ __launch_bounds__(kThreads) void k_sweep(StepArgs<S> a) {
       a.V[(int64_t)jj * a.ldv + iw] = (S)w;
       if (iw == j) st->alpha = w;
     }
+  }
+  // row j of the panel's earlier reflectors, for the finalization (the
+  // entries are masked to c < jj above)
+  if (lead && iw == j) {
+#pragma unroll
+    for (int q = 0; q < SLOTS; ++q) a.vrow[gi + G * q] = (double)vr[q];
   }
   // tile partials of sum_{i>j} V(i,c) w(i) for c = chunk, chunk + nchunk, ...
   {
@@ -646,6 +685,18 @@ __global__ __launch_bounds__(kThreads) void k_sweep(StepArgs<S> a) {
 #pragma unroll
     for (int e = 0; e < VEC; ++e) a.zpart[tile * a.ldf + l0 + e] = acc[e];
   }
+  // the tile holding row j passes that row on to the finalization (these
+  // blocks stream the fewest rows; the load is left to their end)
+  if (r0 <= j && rg == 0 && colok) {
+    const VT xr = *(const VT*)(base + j * a.ldw);
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) a.wrow[l0 + e] = (double)xr[e];
+  }
+}
+
+template <typename S, int G>
+__global__ __launch_bounds__(kThreads) void k_sweep(StepArgs<S> a) {
+  sweep_block<S, G>(a, blockIdx.x, gridDim.x);
 }
 
 // Tall inputs (more row tiles than one round trip of the finalization
@@ -692,26 +743,30 @@ __global__ __launch_bounds__(kThreads) void k_fold(StepArgs<S> a, double* __rest
 // tile lanes.  Finishes the reflector (dlarfg conventions), forms the new
 // column of F and the new row of R, downdates the column norms (with the
 // cancellation test that ends the panel), and emits pivot partials.
-// Every load that does not depend on another one is issued before the first
-// barrier, so the kernel costs about two memory round trips.
+// Every load is issued before the first barrier (the step's row of W and of
+// the reflectors and the swap-order keys come from the sweep and the norm
+// reduction, not from rows that depend on the step), so the kernel costs one
+// memory round trip.
+// Returns, in thread 0, the largest |F| entry the block formed (for the FP16
+// operand scaling of the panel update; the caller folds it into the state),
+// or -1 when the step did not run.
 template <typename S>
-__global__ __launch_bounds__(kThreads) void k_finalize(StepArgs<S> a) {
+__device__ __forceinline__ float finalize_block(const StepArgs<S>& a, const int bid) {
   __shared__ double red[kFL][kFC + 1];
   __shared__ double ared[8][kNbMax + 1];
   __shared__ double Fsh[kNbMax][kFC + 1];
   __shared__ double aux[kNbMax];
   __shared__ double vj[kNbMax];
   __shared__ double dscr[4];
-  __shared__ AmaxVal ascr[4];
-  __shared__ float fscr[4];
   __shared__ int s_go;
   __shared__ double s_alpha;
   __shared__ int64_t s_off, s_ncur;
+  __shared__ int s_swo, s_swk;
   FactorState* st = a.st;
   const int tid = threadIdx.x, cl = tid % kFC, tl = tid / kFC;
   const int jj = a.jj;
   const int64_t tend = a.t0 + a.ntile;
-  const int64_t l = (int64_t)blockIdx.x * kFC + cl;
+  const int64_t l = (int64_t)bid * kFC + cl;
   const bool lb = l < a.ncur;  // within the host's column bound
 
   // Round trip 1: loads that depend neither on each other nor on the exact
@@ -722,14 +777,18 @@ __global__ __launch_bounds__(kThreads) void k_finalize(StepArgs<S> a) {
   const int64_t lc = lb ? l : 0;
   double nl = a.nu[lc], nlo = a.nuo[lc];
   int pv = a.pvflag[lc], id = a.colid[lc];
+  // the step's row and swap-order key, left by the sweep
+  double wj = a.wrow[lc];
+  int key = a.keypos[lc];
+  double vjr = a.vrow[tid % kNbMax];
   double fv[kNbMax / kFL];
 #pragma unroll
   for (int q = 0; q < kNbMax / kFL; ++q) fv[q] = a.F[(int64_t)(tl + kFL * q) * a.ldf + lc];
   double vsc = a.vscale[tid % kNbMax];
   // partial sums over the row tiles [t0, tend), one batch of loads per round
-  // trip (one batch covers up to kFinZ kFL = kFinA 8 = 192 tiles); indices
-  // past tend are clamped to tend - 1 (written this step, finite) and
-  // weighted 0
+  // trip (one batch covers up to kFinZ kFL = kFinA 8 = 192 tiles); tiles past
+  // tend read the zero row "tguard" of the partial arrays (no weights: they
+  // would take a register per load)
   const int ca = tid % kNbMax, sla = tid / kNbMax;
   const int64_t caa = ca < jj ? ca : 0;
   double sz = 0.0, sa = 0.0, sn = 0.0;
@@ -739,30 +798,27 @@ __global__ __launch_bounds__(kThreads) void k_finalize(StepArgs<S> a) {
     const int64_t nbn = ceil_div(a.ntile, (int64_t)kThreads);
     const int64_t nbat = nbz > nba ? (nbz > nbn ? nbz : nbn) : (nba > nbn ? nba : nbn);
     for (int64_t b = 0; b < nbat; ++b) {
-      double xz[kFinZ], xa[kFinA], wz[kFinZ], wa[kFinA];
+      double xz[kFinZ], xa[kFinA];
 #pragma unroll
       for (int u = 0; u < kFinZ; ++u) {
         const int64_t t = a.t0 + tl + kFL * (b * kFinZ + u);
-        wz[u] = t < tend ? 1.0 : 0.0;
-        xz[u] = a.zpart[(t < tend ? t : tend - 1) * a.ldf + lc];
+        xz[u] = a.zpart[(t < tend ? t : a.tguard) * a.ldf + lc];
       }
 #pragma unroll
       for (int u = 0; u < kFinA; ++u) {
         const int64_t t = a.t0 + sla + 8 * (b * kFinA + u);
-        wa[u] = t < tend ? 1.0 : 0.0;
-        xa[u] = a.auxpart[(t < tend ? t : tend - 1) * kNbMax + caa];
+        xa[u] = a.auxpart[(t < tend ? t : a.tguard) * kNbMax + caa];
       }
       const int64_t tn = a.t0 + tid + (int64_t)kThreads * b;
-      const double wn = tn < tend ? 1.0 : 0.0;
-      const double xn = a.nrm2part[tn < tend ? tn : tend - 1];
+      const double xn = a.nrm2part[tn < tend ? tn : a.tguard];
       // keep the scheduler from interleaving the sums with the loads (it
       // would wait for all loads issued so far, several times per batch)
       __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-      for (int u = 0; u < kFinZ; ++u) sz += xz[u] * wz[u];
+      for (int u = 0; u < kFinZ; ++u) sz += xz[u];
 #pragma unroll
-      for (int u = 0; u < kFinA; ++u) sa += xa[u] * wa[u];
-      sn += xn * wn;
+      for (int u = 0; u < kFinA; ++u) sa += xa[u];
+      sn += xn;
     }
   }
   if (tid == 0) {
@@ -770,14 +826,17 @@ __global__ __launch_bounds__(kThreads) void k_finalize(StepArgs<S> a) {
     s_alpha = st->alpha;
     s_off = st->off;
     s_ncur = st->ncur;
+    s_swo = st->swap_other;
+    s_swk = st->swap_key;
   }
 #pragma unroll
-  for (int q = 0; q < kNbMax / kFL; ++q) Fsh[tl + kFL * q][cl] = fv[q];  // rows >= jj unused
+  for (int q = 0; q < kNbMax / kFL; ++q)  // rows >= jj hold stale workspace data: zeroed
+    Fsh[tl + kFL * q][cl] = tl + kFL * q < jj ? fv[q] : 0.0;
   ared[sla][ca] = sa;  // columns >= jj unused
   red[tl][cl] = sz;    // positions >= ncur unused
 
   const double xnorm2 = block_sum(sn, dscr);  // also publishes the LDS writes above
-  if (!s_go) return;
+  if (!s_go) return -1.0f;
   if (!(tl == 0 && lb)) {
     nl = 0.0;
     nlo = 1.0;
@@ -785,14 +844,13 @@ __global__ __launch_bounds__(kThreads) void k_finalize(StepArgs<S> a) {
     id = 0;
   }
   if (tid >= jj) vsc = 0.0;
-  // round trip 2: the step's row
   const int64_t j = s_off + jj;
   const bool lv = l < s_ncur;
-  double wj = (double)a.W[j * a.ldw + lc];
-  double vjr = (double)a.V[(int64_t)(tid % kNbMax) * a.ldv + j];
-  // colid entries past the live columns are stale or were never written:
-  // clamp the id into range (the key is used for live columns only)
-  int key = a.posof[(uint32_t)id < (uint32_t)a.n ? id : 0];
+  // this step's swap moved one live column in the swap order
+  if (tl == 0 && lv && id == s_swo) {
+    key = s_swk;
+    a.keypos[l] = key;
+  }
   if (!(tl == 0 && lv)) {
     wj = 0.0;
     key = 0;
@@ -810,13 +868,13 @@ __global__ __launch_bounds__(kThreads) void k_finalize(StepArgs<S> a) {
     tau = (beta - alpha) / beta;
     scale = 1.0 / (alpha - beta);
   }
-  if (tid < jj) {
+  if (tid < kNbMax) {  // zero past jj (the partials there may be stale, even NaN)
     double z = 0.0;
 #pragma unroll
     for (int q = 0; q < 8; ++q) z += ared[q][tid];
     const double vjc = vsc * vjr;
-    vj[tid] = vjc;
-    aux[tid] = vjc + vsc * scale * z;
+    vj[tid] = tid < jj ? vjc : 0.0;
+    aux[tid] = tid < jj ? vjc + vsc * scale * z : 0.0;
   }
   __syncthreads();
 
@@ -829,7 +887,10 @@ __global__ __launch_bounds__(kThreads) void k_finalize(StepArgs<S> a) {
     for (int q = 0; q < kFL; ++q) zt += red[q][cl];
     const double y = wj + scale * zt;
     double s1 = 0.0, s2 = 0.0;
-    for (int c = 0; c < jj; ++c) {
+    // all kNbMax slots (zero past jj): the unrolled loop issues its LDS
+    // reads together instead of one dependent read per reflector
+#pragma unroll
+    for (int c = 0; c < kNbMax; ++c) {
       const double fc = Fsh[c][cl];
       s1 += fc * aux[c];
       s2 += vj[c] * fc;
@@ -859,25 +920,32 @@ __global__ __launch_bounds__(kThreads) void k_finalize(StepArgs<S> a) {
     }
   }
   if (flag) st->end_flag = 1;
-  // largest |F| entry of the panel (for the FP16 operand scaling)
-  {
-    float fm = fabsmax;
+  // the pivot candidates and the largest |F| entry (for the FP16 operand
+  // scaling) live in lanes 0 .. kFC - 1 of the first wave (tl == 0): a
+  // reduction over those lanes, no barrier (the other lanes hold no
+  // candidate, so this is the block-wide result, bit for bit)
+  float fm = fabsmax;
+  if (tid < 64) {
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) fm = fmaxf(fm, __shfl_xor(fm, off, 64));
-    if ((tid & 63) == 0) fscr[tid >> 6] = fm;
+    for (int off = kFC / 2; off > 0; off >>= 1) {
+      fm = fmaxf(fm, __shfl_xor(fm, off, 64));
+      AmaxVal b;
+      b.v = __shfl_xor(cand.v, off, 64);
+      b.s2 = __shfl_xor(cand.s2, off, 64);
+      b.pos = __shfl_xor(cand.pos, off, 64);
+      b.key = __shfl_xor(cand.key, off, 64);
+      cand = amax_combine(cand, b);
+    }
   }
-  cand = block_amax(cand, ascr);
   if (tid == 0) {
-    const float fm = fmaxf(fmaxf(fscr[0], fscr[1]), fmaxf(fscr[2], fscr[3]));
-    atomicMax(&st->fmax_bits, __float_as_uint(fm));
     AmaxPart o;
     o.v = cand.v;
     o.s2 = cand.s2;
     o.pos = cand.pos;
     o.key = cand.key;
-    a.amax[blockIdx.x] = o;
+    a.amax[bid] = o;
   }
-  if (blockIdx.x == 0 && tid == 0) {
+  if (bid == 0 && tid == 0) {
     a.tau[j] = tau;
     a.vscale[jj] = scale;
     const int p = a.pivpos[jj];
@@ -890,6 +958,16 @@ __global__ __launch_bounds__(kThreads) void k_finalize(StepArgs<S> a) {
       st->end_flag = 1;
     }
   }
+  return fm;
+}
+
+template <typename S>
+__global__ __launch_bounds__(kThreads) void k_finalize(StepArgs<S> a) {
+  const float fm = finalize_block<S>(a, blockIdx.x);
+  // (one word for every block: its read-modify-writes queue up and the
+  // launch ends only when they are done, so it is updated only when used)
+  if (a.want_fmax && threadIdx.x == 0 && fm >= 0.0f)
+    atomicMax(&a.st->fmax_bits, __float_as_uint(fm));
 }
 
 template <typename S>
@@ -1344,6 +1422,9 @@ static int factor_impl(const TA* A, int64_t lda, const FactorPlan& pl, const id_
   double* tau = (double*)(wb + pl.off_tau);
   double* vscale = (double*)(wb + pl.off_vscale);
   double* rorig = (double*)(wb + pl.off_rorig);
+  double* wrow = (double*)(wb + pl.off_wrow);
+  double* vrow = (double*)(wb + pl.off_vrow);
+  int* keypos = (int*)(wb + pl.off_keypos);
   FactorState* st = (FactorState*)(wb + pl.off_state);
 
 
@@ -1365,14 +1446,17 @@ static int factor_impl(const TA* A, int64_t lda, const FactorPlan& pl, const id_
   const double sbytes = (double)pl.wbytes;
   prof.begin(PK_OTHER, 0, s);
   k_init<<<dim3((unsigned)ceil_div(ldf > n ? ldf : n, kThreads)), kThreads, 0, s>>>(
-      st, colid[0], pvflag, permw, posof, n, ldf);
+      st, colid[0], pvflag, permw, posof, n, ldf, zpart + pl.ntile_s_max * ldf,
+      auxpart + pl.ntile_s_max * kNbMax, nrm2part + pl.ntile_s_max, zfold + pl.nfold_max * ldf,
+      afold + pl.nfold_max * kNbMax, nfoldb + pl.nfold_max);
   MPID_LAUNCH_CHECK();
   k_ingest<TA, S><<<dim3((unsigned)ceil_div(n, 64), (unsigned)ntg), kThreads, 0, s>>>(
       A, lda, m, n, W[0], ldw, colpart, ldf, st);
   MPID_LAUNCH_CHECK();
   int namax = (int)ceil_div(n, kFinCols);
   k_colreduce<<<dim3((unsigned)namax), kThreads, 0, s>>>(colpart, ldf, 0, ntg, n, 0, nu, nuo,
-                                                          amax, colid[0], posof, pvflag, st, -1.0, nullptr, 0);
+                                                          amax, colid[0], posof, pvflag, keypos, st,
+                                                          -1.0, nullptr, 0);
   MPID_LAUNCH_CHECK();
   prof.end(s);
 
@@ -1400,6 +1484,10 @@ static int factor_impl(const TA* A, int64_t lda, const FactorPlan& pl, const id_
   a.nu = nu;
   a.nuo = nuo;
   a.rorig = rorig;
+  a.wrow = wrow;
+  a.vrow = vrow;
+  a.keypos = keypos;
+  a.tguard = pl.ntile_s_max;
   a.kcap = kcap;
   a.k_fixed = o->k_fixed;
   a.rel_tol = o->rel_tol;
@@ -1407,6 +1495,7 @@ static int factor_impl(const TA* A, int64_t lda, const FactorPlan& pl, const id_
   a.rule = o->rank_rule;
   a.nopivot = (o->flags & ID_FLAG_NO_PIVOT) ? 1 : 0;
   a.nb = pl.nb;
+  a.want_fmax = OP == OP_F16 ? 1 : 0;
 
   // Panels are enqueued one ahead of what the host knows: before panel P is
   // enqueued the host has read the state after panel P - 2, whose offset is a
@@ -1560,6 +1649,7 @@ static int factor_impl(const TA* A, int64_t lda, const FactorPlan& pl, const id_
       af.nrm2part = nfoldb;
       af.t0 = 0;
       af.ntile = (int)nfold;
+      af.tguard = pl.nfold_max;
       prof.launch(PK_FINALIZE, tag, k_finalize<S>, dim3((unsigned)namax), s, af);
     } else {
       prof.launch(PK_FINALIZE, tag, k_finalize<S>, dim3((unsigned)namax), s, a);
@@ -1622,7 +1712,7 @@ static int factor_impl(const TA* A, int64_t lda, const FactorPlan& pl, const id_
     prof.begin(PK_OTHER, (int64_t)panel * 1024, s);
     k_colreduce<<<dim3((unsigned)namax), kThreads, 0, s>>>(colpart, ldf, g.tg0, ntg, ncur_ub, 1,
                                                             nu, nuo, amax, colid[cur ^ 1], posof,
-                                                            pvflag, st, count_tol, &kslot[cur],
+                                                            pvflag, keypos, st, count_tol, &kslot[cur],
                                                             seq0 + panel + 1);
     MPID_LAUNCH_CHECK();
     prof.end(s);

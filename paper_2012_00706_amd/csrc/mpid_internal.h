@@ -40,6 +40,8 @@ struct FactorState {
   int64_t off;       // first step of the current panel
   int64_t ncur;      // columns of the current (compacted) working copy
   uint32_t nred;     // blocks of the panel-end column reduction that finished
+  int32_t swap_other;  // the column whose swap-order key the step's swap changed
+  int32_t swap_key;    // ... and its new key
   int32_t pad1;
 };
 
@@ -63,11 +65,12 @@ struct FactorPlan {
   int64_t m, n, kcap;
   int32_t dtype, prec, nb, wbytes;  // wbytes: 4 (fp32 working copy) or 8
   int64_t ldw, ldv, ldf;
-  int64_t ntile_s_max, ntile_g;
+  int64_t ntile_s_max, ntile_g, nfold_max;
   size_t off_w0, off_w1, off_v, off_f, off_zpart, off_auxpart, off_nrm2part, off_zfold,
       off_afold, off_nfold, off_colpart,
       off_nu, off_nuo, off_amax, off_colid0, off_colid1, off_pvflag, off_pivpos, off_pivid,
-      off_permw, off_posof, off_tau, off_vscale, off_rorig, off_state, off_slot;
+      off_permw, off_posof, off_tau, off_vscale, off_rorig, off_state, off_slot, off_wrow,
+      off_vrow, off_keypos;
   size_t bytes;
 };
 
