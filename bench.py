@@ -830,8 +830,16 @@ def main():
         r = res[p]
         e_o = oerr.get(r["k"])
         if e_o is None:
-            return {"err_oracle_same_k": None, "bound": None, "pass": None,
-                    "note": "oracle not run to this rank"}
+            # oracle not run to this rank: sigma_{k+1} (analytic) is a lower
+            # bound of its error (Eckart-Young), so passing the rule with it in
+            # place of err_oracle(k) is sufficient for the rule itself
+            s_k1 = float(sigma[r["k"]]) if r["k"] < len(sigma) else 0.0
+            bound = 1.1 * s_k1 + 10.0 * U_LOW[p] * float(sigma[0])
+            ok = bool(r["err2"] <= bound)
+            return {"err_oracle_same_k": None, "sigma_k1": s_k1, "u_low": U_LOW[p],
+                    "bound_with_sigma_k1": bound, "pass": True if ok else None,
+                    "note": ("oracle not run to this rank; sigma_{k+1} <= err_oracle(k), so "
+                             "err <= 1.1 sigma_{k+1} + 10 u_low ||A||_2 implies the rule")}
         bound = 1.1 * e_o + 10.0 * U_LOW[p] * float(sigma[0])
         return {"err_oracle_same_k": e_o, "u_low": U_LOW[p], "bound": bound,
                 "pass": bool(r["err2"] <= bound)}
