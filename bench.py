@@ -147,8 +147,9 @@ SWEEP_SOURCES = [os.path.join(ROOT, "paper_2012_00706_amd", "csrc", f)
 
 
 def sweep_source_hash() -> str:
-    """Hash of the reflector sweep's own source: the k_sweep kernel, its
-    argument struct and constants in factor.hip, and the device helpers."""
+    """Hash of the reflector sweep's own source: the k_sweep kernel and its
+    body (sweep_block), its argument struct and constants in factor.hip, and
+    the device helpers."""
     import hashlib
     import re
     h = hashlib.sha256()
@@ -157,6 +158,8 @@ def sweep_source_hash() -> str:
     for pat in (r"constexpr int kPrefetch[^\n]*\n", r"constexpr int kSweepU[^\n]*\n",
                 r"template <typename S, int G>\nconstexpr int overlap_rows\(\) \{.*?\n\}\n",
                 r"template <typename S>\nstruct StepArgs \{.*?\n\};\n",
+                r"template <typename S, int G>\n__device__ __forceinline__ void "
+                r"sweep_block\(.*?\n\}\n",
                 r"template <typename S, int G>\n__global__ __launch_bounds__\(kThreads\) void "
                 r"k_sweep\(.*?\n\}\n"):
         mt = re.search(pat, text, flags=re.S)
