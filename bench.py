@@ -623,6 +623,10 @@ def run_accuracy(args):
       mixed_half    A stored in fp16 (no scaling), mixed FP16 path, skeleton from A
       half          same, skeleton from the fp16 matrix
       mixed_half_scaled  A scaled by a power of two before the fp16 storage
+      *_literal     the simulated single / half precision of the paper: every
+                    value the factorization keeps, and T, rounded to binary32 /
+                    binary16 (ID_FLAG_ROUND_F32 / ID_FLAG_ROUND_F16; no FP16
+                    operand scaling)
     A variant "breaks" when its R11 is numerically singular (recorded as null)."""
     import numpy as np
     import torch
@@ -657,16 +661,20 @@ def run_accuracy(args):
         y = (x * sc).to(dt).to(torch.float64) / sc
         return y.numpy().astype(np.float32)
 
-    variants = [  # (name, storage dtype, scaled, prec, skeleton from the stored matrix)
-        ("double", None, False, "f64", False),
-        ("mixed_single", torch.float32, False, "mixed_f32", False),
-        ("single", torch.float32, False, "mixed_f32", True),
-        ("mixed_single_bf16x3", torch.float32, False, "mixed_bf16x3", False),
-        ("mixed_bf16", torch.bfloat16, False, "mixed_bf16", False),
-        ("bf16", torch.bfloat16, False, "mixed_bf16", True),
-        ("mixed_half", torch.float16, False, "mixed_f16", False),
-        ("half", torch.float16, False, "mixed_f16", True),
-        ("mixed_half_scaled", torch.float16, True, "mixed_f16", False),
+    variants = [  # (name, storage dtype, scaled, prec, skeleton from the stored matrix, rounding)
+        ("double", None, False, "f64", False, None),
+        ("mixed_single", torch.float32, False, "mixed_f32", False, None),
+        ("single", torch.float32, False, "mixed_f32", True, None),
+        ("mixed_single_literal", torch.float32, False, "mixed_f32", False, "f32"),
+        ("single_literal", torch.float32, False, "mixed_f32", True, "f32"),
+        ("mixed_single_bf16x3", torch.float32, False, "mixed_bf16x3", False, None),
+        ("mixed_bf16", torch.bfloat16, False, "mixed_bf16", False, None),
+        ("bf16", torch.bfloat16, False, "mixed_bf16", True, None),
+        ("mixed_half", torch.float16, False, "mixed_f16", False, None),
+        ("half", torch.float16, False, "mixed_f16", True, None),
+        ("mixed_half_scaled", torch.float16, True, "mixed_f16", False, None),
+        ("mixed_half_literal", torch.float16, False, "mixed_f16", False, "f16"),
+        ("half_literal", torch.float16, False, "mixed_f16", True, "f16"),
     ]
     ks = [1, 2, 4, 6, 8, 10, 12, 15, 18, 20, 21, 22, 25, 30, 35, 40, 50]
     ns = [50, 100, 200, 300, 400, 500, 600, 700, 800, 900, 1000]
@@ -681,11 +689,11 @@ def run_accuracy(args):
                 Ad = dev(A)
                 nA = norm2(Ad)
                 ref = None
-                for name, dt, scaled, prec, low_skel in variants:
+                for name, dt, scaled, prec, low_skel, rnd in variants:
                     As = A if dt is None else stored(A, dt, scaled)
                     Asd = dev(As)
                     try:
-                        r = mp.column_id(Asd, k=k, prec=prec)
+                        r = mp.column_id(Asd, k=k, prec=prec, round_to=rnd)
                         Y = mp.reconstruct(Asd if low_skel else Ad, r.perm, r.k, r.T)
                     except mp.MpidError:
                         table.setdefault(kind, {}).setdefault(sweep, {}).setdefault(name, []).append(

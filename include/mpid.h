@@ -87,6 +87,17 @@ extern "C" {
 #define ID_FLAG_PROFILE 2  /* time every kernel with HIP events (see id_last_profile) */
 #define ID_FLAG_GRAM 4     /* tall-skinny front end: pivots and R from the FP64 Gram
                               matrix A^T A (one pivoted Cholesky); see id_factor */
+/* Simulated low precision (Section 3: variables held in single or half
+ * precision while arithmetic accumulates in higher precision): every value the
+ * factorization keeps -- the working copy, the reflectors, F, the rows of R,
+ * the column norms, beta / tau -- is rounded to the nearest binary32
+ * (ID_FLAG_ROUND_F32) or binary16 (ID_FLAG_ROUND_F16) number; sums and
+ * products still accumulate in the kernels' precision.  With ID_FLAG_ROUND_F16
+ * the FP16 update (ID_PREC_MIXED_F16) drops its power-of-two operand scaling,
+ * so tiny values underflow as in the paper's simulation.  id_round then gives
+ * the coefficients T the same precision.  Not with ID_FLAG_GRAM. */
+#define ID_FLAG_ROUND_F32 8
+#define ID_FLAG_ROUND_F16 16
 
 typedef struct {
   int32_t prec;      /* ID_PREC_* */
@@ -178,6 +189,13 @@ int id_factor_noalloc(const void* A, int32_t dtype, int64_t m, int64_t n, int64_
  * Asynchronous on "stream". */
 int id_solve_T(const double* R, int64_t ldr, int64_t k, int64_t n, double* T, int64_t ldt,
                int32_t* info, void* stream);
+
+/* X (rows x cols, column-major, ld >= max(1, rows), float64, device) rounded in
+ * place to the nearest binary32 (mode 1) or binary16 (mode 2) values -- the
+ * low-precision coefficient matrix of the simulated single / half precision ID
+ * (Section 3).  cols <= 65535.  ID_ERR_ARG for other modes or sizes.
+ * Asynchronous on "stream". */
+int id_round(double* X, int64_t rows, int64_t cols, int64_t ld, int32_t mode, void* stream);
 
 /* Reconstruction Y = A(:, J) P in float64 (eq. (4)-(5) with P from eq. (8),
  * products in double precision as in the remark after Lemma 1):

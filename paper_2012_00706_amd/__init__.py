@@ -22,6 +22,7 @@ from .api import (  # noqa: F401
     make_opts,
     SketchIDResult,
     reconstruct,
+    round_,
     sketch,
     sketch_id,
     solve_T,

@@ -87,6 +87,7 @@ SIGNATURES = {
     "id_factor_noalloc": (ctypes.c_int, [_vp, _i32, _i64, _i64, _i64, _P(IdOpts), _vp, _vp, _i64,
                                          _P(_i64), _P(_i32), _vp]),
     "id_solve_T": (ctypes.c_int, [_vp, _i64, _i64, _i64, _vp, _i64, _vp, _vp]),
+    "id_round": (ctypes.c_int, [_vp, _i64, _i64, _i64, _i32, _vp]),
     "id_reconstruct": (ctypes.c_int, [_vp, _i32, _i64, _i64, _i64, _vp, _i64, _vp, _i64, _vp,
                                       _i64, _i32, _vp]),
     "id_backward_workspace_size": (_sz, [_i64, _i64, _i64]),

@@ -49,12 +49,19 @@ def _stream(device=None):
     return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
 
 
+ROUND = {None: 0, "f32": 1, "f16": 2}
+
+
 def make_opts(k=None, tol=None, prec="f64", rule="pivot_rel", k_max=0, nb=0, no_pivot=False,
-              profile=False, gram=False):
+              profile=False, gram=False, round_to=None):
+    """round_to: None, "f32" or "f16" -- the simulated single / half precision
+    of the paper's Section 3 (ID_FLAG_ROUND_F32 / ID_FLAG_ROUND_F16)."""
     if prec not in PREC:
         raise ValueError(f"prec must be one of {sorted(PREC)}")
     if rule not in RULE:
         raise ValueError(f"rule must be one of {sorted(RULE)}")
+    if round_to not in ROUND:
+        raise ValueError('round_to must be None, "f32" or "f16"')
     if k is None and tol is None:
         raise ValueError("give k (fixed rank) or tol (adaptive rank)")
     o = _lib.IdOpts()
@@ -65,7 +72,9 @@ def make_opts(k=None, tol=None, prec="f64", rule="pivot_rel", k_max=0, nb=0, no_
     o.k_max = int(k_max)
     o.nb = int(nb)
     o.flags = ((C["ID_FLAG_NO_PIVOT"] if no_pivot else 0) | (C["ID_FLAG_PROFILE"] if profile else 0)
-               | (C["ID_FLAG_GRAM"] if gram else 0))
+               | (C["ID_FLAG_GRAM"] if gram else 0)
+               | (C["ID_FLAG_ROUND_F32"] if round_to == "f32" else 0)
+               | (C["ID_FLAG_ROUND_F16"] if round_to == "f16" else 0))
     if k is not None and int(k) == 0:
         o.k_max = 0
     return o
@@ -95,7 +104,7 @@ class FactorResult:
 def factor(A: torch.Tensor, k=None, tol=None, prec="f64", rule="pivot_rel", k_max=0, nb=0,
            no_pivot=False, work: torch.Tensor | None = None, R_buf: torch.Tensor | None = None,
            perm_buf: torch.Tensor | None = None, profile: bool = False,
-           gram: bool = False) -> FactorResult:
+           gram: bool = False, round_to=None) -> FactorResult:
     """Rank-k column-pivoted QR (id_factor).  k=0 gives k = 0.  gram=True takes
     the tall-skinny front end (pivots and R from the FP64 Gram matrix)."""
     lib = _lib.load()
@@ -104,7 +113,7 @@ def factor(A: torch.Tensor, k=None, tol=None, prec="f64", rule="pivot_rel", k_ma
     if k is not None and int(k) == 0:
         return FactorResult(torch.arange(n, dtype=torch.int32, device=A.device),
                             empty_colmajor(0, n, device=A.device), 0, 0)
-    o = make_opts(k, tol, prec, rule, k_max, nb, no_pivot, profile, gram)
+    o = make_opts(k, tol, prec, rule, k_max, nb, no_pivot, profile, gram, round_to)
     ws = workspace_size(m, n, A.dtype, o)
     if ws == 0:
         raise ValueError("invalid factorization arguments")
@@ -259,13 +268,32 @@ class ColumnIDResult:
     info: int = 0       # id_factor's info (e.g. ID_INFO_GRAM_LIMIT)
 
 
+def round_(X: torch.Tensor, mode: str) -> torch.Tensor:
+    """id_round: X (float64, column-major view) rounded in place to binary32
+    ("f32") or binary16 ("f16") values."""
+    if X.numel() == 0:
+        return X
+    rows, cols = X.shape
+    ld = X.stride(1) if cols > 1 else max(rows, 1)
+    if X.dtype != torch.float64 or X.stride(0) != 1:
+        raise ValueError("id_round takes a float64 column-major matrix")
+    with torch.cuda.device(X.device):
+        _lib.check(_lib.load().id_round(X.data_ptr(), rows, cols, ld, ROUND[mode],
+                                        _stream(X.device)), "id_round")
+    return X
+
+
 def column_id(A: torch.Tensor, k=None, tol=None, prec="f64", rule="pivot_rel", k_max=0, nb=0,
-              gram=False):
+              gram=False, round_to=None):
     """Algorithm 1 (prec="f64") or Algorithm 2's mixed variant end to end
-    (gram=True: the Gram-matrix front end for tall inputs)."""
-    fr = factor(A, k=k, tol=tol, prec=prec, rule=rule, k_max=k_max, nb=nb, gram=gram)
+    (gram=True: the Gram-matrix front end for tall inputs; round_to="f32" /
+    "f16": the simulated single / half precision ID, T rounded too)."""
+    fr = factor(A, k=k, tol=tol, prec=prec, rule=rule, k_max=k_max, nb=nb, gram=gram,
+                round_to=round_to)
     n = A.shape[1]
     T, _ = solve_T(fr.R, fr.k, n)
+    if round_to is not None:
+        round_(T, round_to)
     return ColumnIDResult(fr.perm[:fr.k].long(), T, fr.perm, fr.k, fr.R, fr.info)
 
 

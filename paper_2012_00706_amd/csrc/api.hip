@@ -34,6 +34,10 @@ int id_solve_T(const double* R, int64_t ldr, int64_t k, int64_t n, double* T, in
   return mpid::solve_T_run(R, ldr, k, n, T, ldt, info, (hipStream_t)stream);
 }
 
+int id_round(double* X, int64_t rows, int64_t cols, int64_t ld, int32_t mode, void* stream) {
+  return mpid::round_run(X, rows, cols, ld, mode, (hipStream_t)stream);
+}
+
 int id_reconstruct(const void* A, int32_t dtype, int64_t m, int64_t n, int64_t lda,
                    const int32_t* perm, int64_t k, const double* T, int64_t ldt, double* Y,
                    int64_t ldy, int32_t residual, void* stream) {

@@ -56,6 +56,21 @@ struct Vec16<double> {
 
 enum { OP_F64 = 0, OP_F16 = 1, OP_BF16 = 2, OP_BF16X3 = 3, OP_F32 = 4 };
 
+// Storage rounding of the simulated low precision (ID_FLAG_ROUND_F32 /
+// ID_FLAG_ROUND_F16): a value the factorization keeps (working copy,
+// reflectors, F, R, column norms) is rounded to the nearest binary32 or
+// binary16 number; arithmetic on it stays in the kernel's precision.
+enum { RM_NONE = 0, RM_F32 = 1, RM_F16 = 2 };
+__device__ __forceinline__ double rnd(double x, int mode) {
+  if (mode == RM_F32) return (double)(float)x;
+  if (mode == RM_F16) return (double)(_Float16)x;
+  return x;
+}
+template <typename S>
+__device__ __forceinline__ S rnd_store(double x, int mode) {
+  return (S)rnd(x, mode);
+}
+
 constexpr int kPrefetch = 4;  // sweep rows per thread loaded ahead of the pivot search
 constexpr int kFinZ = (192 + kFL - 1) / kFL;  // column partials per lane and round trip in the finalization
 constexpr int kFinA = 24;     // reflector-product partials per thread and round trip
@@ -78,6 +93,7 @@ bool make_factor_plan(int64_t m, int64_t n, int32_t dtype, const id_opts* o, Fac
     return false;
   if (o->rank_rule != ID_RANK_PIVOT_REL && o->rank_rule != ID_RANK_FROB_REL) return false;
   if (o->k_fixed < 0 || o->k_max < 0 || !(o->rel_tol >= 0.0)) return false;
+  if ((o->flags & ID_FLAG_ROUND_F32) && (o->flags & ID_FLAG_ROUND_F16)) return false;
   const int nb = o->nb == 0 ? kNbMax : o->nb;
   if (nb < 1 || nb > kNbMax) return false;
   if (m > (int64_t)1 << 31 || n > (int64_t)1 << 30) return false;
@@ -199,7 +215,7 @@ template <typename TA, typename S>
 __global__ __launch_bounds__(kThreads) void k_ingest(const TA* __restrict__ A, int64_t lda,
                                                      int64_t m, int64_t n, S* __restrict__ W,
                                                      int64_t ldw, double* __restrict__ colpart,
-                                                     int64_t ldf, FactorState* st) {
+                                                     int64_t ldf, FactorState* st, int rmode) {
   __shared__ S tile[64][65];
   __shared__ double ssq[4][64];
   const int tid = threadIdx.x;
@@ -225,7 +241,7 @@ __global__ __launch_bounds__(kThreads) void k_ingest(const TA* __restrict__ A, i
       const int cc = q * 4 + tid / 64, rr = tid % 64;
       const int64_t r = rs + rr, c = c0 + cc;
       if (r < re && c < n && !isfinite((double)xv[q])) bad = true;
-      tile[cc][rr] = (S)xv[q];
+      tile[cc][rr] = rmode ? rnd_store<S>((double)xv[q], rmode) : (S)xv[q];
     }
     __syncthreads();
 #pragma unroll 4
@@ -254,8 +270,8 @@ __device__ __forceinline__ void colreduce_block(
     const double* __restrict__ colpart, int64_t ldf, int64_t tg0, int64_t tg1, int64_t ncols_base,
     int subtract_jb, double* __restrict__ nu, double* __restrict__ nuo, AmaxPart* __restrict__ amax,
     const int* __restrict__ colid, const int* __restrict__ posof, int* __restrict__ pvflag,
-    int* __restrict__ keypos, FactorState* st, double rel_tol, double (*red)[kFinCols + 1],
-    AmaxVal* ascr) {
+    int* __restrict__ keypos, FactorState* st, double rel_tol, int rmode,
+    double (*red)[kFinCols + 1], AmaxVal* ascr) {
   const int tid = threadIdx.x, cl = tid % kFinCols, tl = tid / kFinCols;
   const int64_t ncols = subtract_jb ? st->ncur - st->jb : ncols_base;
   const int64_t l = (int64_t)blockIdx.x * kFinCols + cl;
@@ -267,7 +283,7 @@ __device__ __forceinline__ void colreduce_block(
     double tot = 0.0;
 #pragma unroll
     for (int q = 0; q < 8; ++q) tot += red[q][cl];
-    const double v = sqrt(tot);
+    const double v = rnd(sqrt(tot), rmode);
     nu[l] = v;
     nuo[l] = v;
     pvflag[l] = 0;
@@ -306,7 +322,8 @@ __global__ __launch_bounds__(kThreads) void k_colreduce(
     const double* __restrict__ colpart, int64_t ldf, int64_t tg0, int64_t tg1, int64_t ncols_base,
     int subtract_jb, double* __restrict__ nu, double* __restrict__ nuo, AmaxPart* __restrict__ amax,
     const int* __restrict__ colid, const int* __restrict__ posof, int* __restrict__ pvflag,
-    int* __restrict__ keypos, FactorState* st, double rel_tol, FactorHostSlot* hs, int64_t seq) {
+    int* __restrict__ keypos, FactorState* st, double rel_tol, int rmode, FactorHostSlot* hs,
+    int64_t seq) {
   __shared__ double red[8][kFinCols + 1];
   __shared__ AmaxVal ascr[4];
   __shared__ int s_go, s_last;
@@ -315,7 +332,7 @@ __global__ __launch_bounds__(kThreads) void k_colreduce(
   __syncthreads();
   if (s_go)
     colreduce_block(colpart, ldf, tg0, tg1, ncols_base, subtract_jb, nu, nuo, amax, colid, posof,
-                    pvflag, keypos, st, rel_tol, red, ascr);
+                    pvflag, keypos, st, rel_tol, rmode, red, ascr);
   if (hs == nullptr) return;
   if (tid == 0) {
     __threadfence();  // this block's counts before its arrival
@@ -374,6 +391,7 @@ struct StepArgs {
   double rel_tol, tol3z;
   int rule, nopivot, nb;
   int want_fmax;  // the panel update scales FP16 operands by the panel's max |F|
+  int rmode;      // storage rounding (RM_*)
   // per step; j and ncur above are the host's bounds (j <= the step's row,
   // ncur >= the live column count), the exact values live in the state
   int64_t j;
@@ -587,7 +605,7 @@ __device__ __forceinline__ void sweep_block(const StepArgs<S>& a, const int bid,
   for (int off = 1; off < G; off <<= 1) part += __shfl_xor(part, off, 64);
   // valid on all G lanes of the row; rows below the step (loaded from the
   // lower bound jlb on) and past the matrix contribute nothing
-  const double w = rowok ? wp - part : 0.0;
+  const double w = rowok ? (a.rmode ? rnd(wp - part, a.rmode) : wp - part) : 0.0;
   const bool lead = chunk == 0;
   if (gi == 0 && rsub < a.Rt) {
     wsh[rsub] = iw == j ? 0.0 : w;  // row j holds alpha, kept apart
@@ -864,9 +882,9 @@ __device__ __forceinline__ float finalize_block(const StepArgs<S>& a, const int 
     scale = 0.0;
   } else {
     const double h = hypot(alpha, sqrt(xnorm2));
-    beta = alpha >= 0.0 ? -h : h;
-    tau = (beta - alpha) / beta;
-    scale = 1.0 / (alpha - beta);
+    beta = rnd(alpha >= 0.0 ? -h : h, a.rmode);
+    tau = rnd((beta - alpha) / beta, a.rmode);
+    scale = rnd(1.0 / (alpha - beta), a.rmode);
   }
   if (tid < kNbMax) {  // zero past jj (the partials there may be stale, even NaN)
     double z = 0.0;
@@ -895,10 +913,10 @@ __device__ __forceinline__ float finalize_block(const StepArgs<S>& a, const int 
       s1 += fc * aux[c];
       s2 += vj[c] * fc;
     }
-    const double f = tau * (y - s1);
+    const double f = rnd(tau * (y - s1), a.rmode);
     a.F[(int64_t)jj * a.ldf + l] = f;
     if (!pv) {
-      const double r = wj - s2 - f;
+      const double r = rnd(wj - s2 - f, a.rmode);
       a.rorig[(int64_t)id * a.kcap + j] = r;
       if (nl != 0.0) {
         double t = fabs(r) / nl;
@@ -908,7 +926,7 @@ __device__ __forceinline__ float finalize_block(const StepArgs<S>& a, const int 
         if (t * ratio * ratio <= a.tol3z) {
           flag = true;
         } else {
-          nl = nl * sqrt(t);
+          nl = rnd(nl * sqrt(t), a.rmode);
           a.nu[l] = nl;
         }
       }
@@ -985,6 +1003,7 @@ struct GemmArgs {
   const int* colid;
   int* colid_n;
   double* colpart;
+  int rmode;  // storage rounding (RM_*); RM_F16 also drops the FP16 operand scaling
   int64_t off, tg0;
   int64_t gx, gy;  // column blocks and row tiles of the grid
 };
@@ -1072,7 +1091,7 @@ __global__ __launch_bounds__(kThreads) void k_panel_gemm(GemmArgs<S> a) {
   const int cc = tid % 64, rq = tid / 64;  // write-out mapping: column cc, rows rq + 4q
   const int myout = cidx[cc];
   int sF = 0, sV = 0;
-  if (OP == OP_F16) {
+  if (OP == OP_F16 && a.rmode != RM_F16) {
     const float fmax = __uint_as_float(s_fmax);
     int e = 0;
     if (fmax > 0.0f) frexpf(fmax, &e);
@@ -1255,7 +1274,8 @@ __global__ __launch_bounds__(kThreads) void k_panel_gemm(GemmArgs<S> a) {
           const int rr = rq + 4 * q;
           const int64_t r = rs + rr;
           if (r >= rbeg && r < rend) {
-            const S v = (S)((double)wt[sl][q] - (double)accs[rr][cc] * descale);
+            const double vd = (double)wt[sl][q] - (double)accs[rr][cc] * descale;
+            const S v = a.rmode ? rnd_store<S>(vd, a.rmode) : (S)vd;
             outb[(uint32_t)(rr * a.ldw + myout)] = v;
             ss += (double)v * (double)v;
           }
@@ -1444,6 +1464,8 @@ static int factor_impl(const TA* A, int64_t lda, const FactorPlan& pl, const id_
     MPID_HIP(hipEventRecord(ev_t0, s));
   }
   const double sbytes = (double)pl.wbytes;
+  const int rmode = (o->flags & ID_FLAG_ROUND_F16) ? RM_F16
+                    : (o->flags & ID_FLAG_ROUND_F32) ? RM_F32 : RM_NONE;
   prof.begin(PK_OTHER, 0, s);
   k_init<<<dim3((unsigned)ceil_div(ldf > n ? ldf : n, kThreads)), kThreads, 0, s>>>(
       st, colid[0], pvflag, permw, posof, n, ldf, zpart + pl.ntile_s_max * ldf,
@@ -1451,12 +1473,12 @@ static int factor_impl(const TA* A, int64_t lda, const FactorPlan& pl, const id_
       afold + pl.nfold_max * kNbMax, nfoldb + pl.nfold_max);
   MPID_LAUNCH_CHECK();
   k_ingest<TA, S><<<dim3((unsigned)ceil_div(n, 64), (unsigned)ntg), kThreads, 0, s>>>(
-      A, lda, m, n, W[0], ldw, colpart, ldf, st);
+      A, lda, m, n, W[0], ldw, colpart, ldf, st, rmode);
   MPID_LAUNCH_CHECK();
   int namax = (int)ceil_div(n, kFinCols);
   k_colreduce<<<dim3((unsigned)namax), kThreads, 0, s>>>(colpart, ldf, 0, ntg, n, 0, nu, nuo,
                                                           amax, colid[0], posof, pvflag, keypos, st,
-                                                          -1.0, nullptr, 0);
+                                                          -1.0, rmode, nullptr, 0);
   MPID_LAUNCH_CHECK();
   prof.end(s);
 
@@ -1495,7 +1517,8 @@ static int factor_impl(const TA* A, int64_t lda, const FactorPlan& pl, const id_
   a.rule = o->rank_rule;
   a.nopivot = (o->flags & ID_FLAG_NO_PIVOT) ? 1 : 0;
   a.nb = pl.nb;
-  a.want_fmax = OP == OP_F16 ? 1 : 0;
+  a.want_fmax = (OP == OP_F16 && rmode != RM_F16) ? 1 : 0;
+  a.rmode = rmode;
 
   // Panels are enqueued one ahead of what the host knows: before panel P is
   // enqueued the host has read the state after panel P - 2, whose offset is a
@@ -1701,6 +1724,7 @@ static int factor_impl(const TA* A, int64_t lda, const FactorPlan& pl, const id_
     g.colid = colid[cur];
     g.colid_n = colid[cur ^ 1];
     g.colpart = colpart;
+    g.rmode = rmode;
     g.off = off_lb;
     g.tg0 = off_lb / kRowTileG;
     g.gx = ceil_div(ncur_ub, 64);
@@ -1712,7 +1736,8 @@ static int factor_impl(const TA* A, int64_t lda, const FactorPlan& pl, const id_
     prof.begin(PK_OTHER, (int64_t)panel * 1024, s);
     k_colreduce<<<dim3((unsigned)namax), kThreads, 0, s>>>(colpart, ldf, g.tg0, ntg, ncur_ub, 1,
                                                             nu, nuo, amax, colid[cur ^ 1], posof,
-                                                            pvflag, keypos, st, count_tol, &kslot[cur],
+                                                            pvflag, keypos, st, count_tol, rmode,
+                                                            &kslot[cur],
                                                             seq0 + panel + 1);
     MPID_LAUNCH_CHECK();
     prof.end(s);

@@ -507,7 +507,8 @@ int gram_factor_run(const void* A, int32_t dtype, int64_t m, int64_t n, int64_t 
                     int64_t ldr, int64_t* k_out, int32_t* info, hipStream_t s) {
   GramPlan pl;
   if (!make_gram_plan(m, n, dtype, o, &pl)) return ID_ERR_ARG;
-  if (o->flags & (ID_FLAG_NO_PIVOT | ID_FLAG_PROFILE)) return ID_ERR_UNSUPPORTED;
+  if (o->flags & (ID_FLAG_NO_PIVOT | ID_FLAG_PROFILE | ID_FLAG_ROUND_F32 | ID_FLAG_ROUND_F16))
+    return ID_ERR_UNSUPPORTED;
   if (!k_out || !info) return ID_ERR_ARG;
   if (n > 0 && !perm) return ID_ERR_ARG;
   if (m > 0 && n > 0 && !A) return ID_ERR_ARG;

@@ -98,6 +98,7 @@ int gram_factor_run(const void* A, int32_t dtype, int64_t m, int64_t n, int64_t 
 
 int solve_T_run(const double* R, int64_t ldr, int64_t k, int64_t n, double* T, int64_t ldt,
                 int32_t* info, hipStream_t s);
+int round_run(double* X, int64_t rows, int64_t cols, int64_t ld, int32_t mode, hipStream_t s);
 
 // X = op(R)^{-1} B for upper-triangular R (k x k, ldr); trans = 0 solves R X = B,
 // trans = 1 solves R^T X = B.  B (k x ncols, ldb) and X (ldx) may alias.

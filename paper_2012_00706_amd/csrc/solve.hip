@@ -211,4 +211,26 @@ int solve_T_run(const double* R, int64_t ldr, int64_t k, int64_t n, double* T, i
   return ID_OK;
 }
 
+// X (rows x cols, column-major, ld) rounded in place to the nearest binary32
+// (mode 1) or binary16 (mode 2) values: the low-precision coefficients of
+// the simulated single / half precision ID.
+__global__ __launch_bounds__(kThreads) void k_round(double* X, int64_t rows, int64_t cols,
+                                                    int64_t ld, int mode) {
+  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  const int64_t c = blockIdx.y;
+  if (i >= rows || c >= cols) return;
+  double* p = X + c * ld + i;
+  *p = mode == 1 ? (double)(float)*p : (double)(_Float16)*p;
+}
+
+int round_run(double* X, int64_t rows, int64_t cols, int64_t ld, int32_t mode, hipStream_t s) {
+  if (rows < 0 || cols < 0 || (mode != 1 && mode != 2)) return ID_ERR_ARG;
+  if (rows == 0 || cols == 0) return ID_OK;
+  if (!X || ld < rows || cols > 65535) return ID_ERR_ARG;
+  k_round<<<dim3((unsigned)ceil_div(rows, kThreads), (unsigned)cols), kThreads, 0, s>>>(X, rows, cols,
+                                                                                       ld, mode);
+  MPID_LAUNCH_CHECK();
+  return ID_OK;
+}
+
 }  // namespace mpid

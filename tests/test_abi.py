@@ -144,3 +144,25 @@ def test_noalloc_host_checks(lib):
     rc = lib.id_factor_noalloc(fake, 9, 100, 10, 100, ctypes.byref(o), fake, fake, 10,
                                ctypes.byref(k), ctypes.byref(info), None)
     assert rc == C["ID_ERR_DTYPE"]
+
+
+def test_round_and_flag_host_checks(lib):
+    """id_round and the simulated-precision flags: argument errors before any
+    device call."""
+    from paper_2012_00706_amd import C, make_opts
+    fake = ctypes.c_void_p(0x1000)
+    assert lib.id_round(fake, 4, 4, 4, 3, None) == C["ID_ERR_ARG"]      # unknown mode
+    assert lib.id_round(fake, 4, 4, 3, 1, None) == C["ID_ERR_ARG"]      # ld < rows
+    assert lib.id_round(None, 0, 5, 1, 2, None) == C["ID_OK"]           # empty
+    both = make_opts(k=3)
+    both.flags = C["ID_FLAG_ROUND_F32"] | C["ID_FLAG_ROUND_F16"]
+    assert lib.id_workspace_size(10, 10, C["ID_F32"], ctypes.byref(both)) == 0
+    g = make_opts(tol=1e-3, gram=True, round_to="f32")
+    k = ctypes.c_int64(0)
+    info = ctypes.c_int32(0)
+    ws = lib.id_workspace_size(100, 10, C["ID_F64"], ctypes.byref(g))
+    rc = lib.id_factor(fake, C["ID_F64"], 100, 10, 100, ctypes.byref(g), fake, ws, fake, fake, 10,
+                       ctypes.byref(k), ctypes.byref(info), None)
+    assert rc == C["ID_ERR_UNSUPPORTED"]
+    with pytest.raises(ValueError):
+        make_opts(k=3, round_to="f8")
