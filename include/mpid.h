@@ -95,7 +95,9 @@ extern "C" {
  * products still accumulate in the kernels' precision.  With ID_FLAG_ROUND_F16
  * the FP16 update (ID_PREC_MIXED_F16) drops its power-of-two operand scaling,
  * so tiny values underflow as in the paper's simulation.  id_round then gives
- * the coefficients T the same precision.  Not with ID_FLAG_GRAM. */
+ * the coefficients T the same precision.  ID_FLAG_ROUND_F32 takes
+ * ID_PREC_MIXED_F32 and ID_FLAG_ROUND_F16 takes ID_PREC_MIXED_F16 (other
+ * combinations are invalid arguments); not with ID_FLAG_GRAM. */
 #define ID_FLAG_ROUND_F32 8
 #define ID_FLAG_ROUND_F16 16
 

@@ -70,6 +70,14 @@ template <typename S>
 __device__ __forceinline__ S rnd_store(double x, int mode) {
   return (S)rnd(x, mode);
 }
+// the same with the mode fixed at compile time (kernels whose registers are
+// tight: the run-time branch raised their register count)
+template <int RM>
+__device__ __forceinline__ double rndc(double x) {
+  if (RM == RM_F32) return (double)(float)x;
+  if (RM == RM_F16) return (double)(_Float16)x;
+  return x;
+}
 
 constexpr int kPrefetch = 4;  // sweep rows per thread loaded ahead of the pivot search
 constexpr int kFinZ = (192 + kFL - 1) / kFL;  // column partials per lane and round trip in the finalization
@@ -93,7 +101,10 @@ bool make_factor_plan(int64_t m, int64_t n, int32_t dtype, const id_opts* o, Fac
     return false;
   if (o->rank_rule != ID_RANK_PIVOT_REL && o->rank_rule != ID_RANK_FROB_REL) return false;
   if (o->k_fixed < 0 || o->k_max < 0 || !(o->rel_tol >= 0.0)) return false;
+  // the simulated single / half precision pairs with its own update
   if ((o->flags & ID_FLAG_ROUND_F32) && (o->flags & ID_FLAG_ROUND_F16)) return false;
+  if ((o->flags & ID_FLAG_ROUND_F32) && o->prec != ID_PREC_MIXED_F32) return false;
+  if ((o->flags & ID_FLAG_ROUND_F16) && o->prec != ID_PREC_MIXED_F16) return false;
   const int nb = o->nb == 0 ? kNbMax : o->nb;
   if (nb < 1 || nb > kNbMax) return false;
   if (m > (int64_t)1 << 31 || n > (int64_t)1 << 30) return false;
@@ -768,7 +779,7 @@ __global__ __launch_bounds__(kThreads) void k_fold(StepArgs<S> a, double* __rest
 // Returns, in thread 0, the largest |F| entry the block formed (for the FP16
 // operand scaling of the panel update; the caller folds it into the state),
 // or -1 when the step did not run.
-template <typename S>
+template <typename S, int RM>
 __device__ __forceinline__ float finalize_block(const StepArgs<S>& a, const int bid) {
   __shared__ double red[kFL][kFC + 1];
   __shared__ double ared[8][kNbMax + 1];
@@ -882,9 +893,9 @@ __device__ __forceinline__ float finalize_block(const StepArgs<S>& a, const int 
     scale = 0.0;
   } else {
     const double h = hypot(alpha, sqrt(xnorm2));
-    beta = rnd(alpha >= 0.0 ? -h : h, a.rmode);
-    tau = rnd((beta - alpha) / beta, a.rmode);
-    scale = rnd(1.0 / (alpha - beta), a.rmode);
+    beta = rndc<RM>(alpha >= 0.0 ? -h : h);
+    tau = rndc<RM>((beta - alpha) / beta);
+    scale = rndc<RM>(1.0 / (alpha - beta));
   }
   if (tid < kNbMax) {  // zero past jj (the partials there may be stale, even NaN)
     double z = 0.0;
@@ -913,10 +924,10 @@ __device__ __forceinline__ float finalize_block(const StepArgs<S>& a, const int 
       s1 += fc * aux[c];
       s2 += vj[c] * fc;
     }
-    const double f = rnd(tau * (y - s1), a.rmode);
+    const double f = rndc<RM>(tau * (y - s1));
     a.F[(int64_t)jj * a.ldf + l] = f;
     if (!pv) {
-      const double r = rnd(wj - s2 - f, a.rmode);
+      const double r = rndc<RM>(wj - s2 - f);
       a.rorig[(int64_t)id * a.kcap + j] = r;
       if (nl != 0.0) {
         double t = fabs(r) / nl;
@@ -926,7 +937,7 @@ __device__ __forceinline__ float finalize_block(const StepArgs<S>& a, const int 
         if (t * ratio * ratio <= a.tol3z) {
           flag = true;
         } else {
-          nl = rnd(nl * sqrt(t), a.rmode);
+          nl = rndc<RM>(nl * sqrt(t));
           a.nu[l] = nl;
         }
       }
@@ -979,9 +990,9 @@ __device__ __forceinline__ float finalize_block(const StepArgs<S>& a, const int 
   return fm;
 }
 
-template <typename S>
+template <typename S, int RM>
 __global__ __launch_bounds__(kThreads) void k_finalize(StepArgs<S> a) {
-  const float fm = finalize_block<S>(a, blockIdx.x);
+  const float fm = finalize_block<S, RM>(a, blockIdx.x);
   // (one word for every block: its read-modify-writes queue up and the
   // launch ends only when they are done, so it is updated only when used)
   if (a.want_fmax && threadIdx.x == 0 && fm >= 0.0f)
@@ -1003,7 +1014,6 @@ struct GemmArgs {
   const int* colid;
   int* colid_n;
   double* colpart;
-  int rmode;  // storage rounding (RM_*); RM_F16 also drops the FP16 operand scaling
   int64_t off, tg0;
   int64_t gx, gy;  // column blocks and row tiles of the grid
 };
@@ -1017,7 +1027,7 @@ struct GemmArgs {
 // the waves form the 64 x 64 product as 16x16 MFMA blocks (positions along
 // the MFMA rows) and park it in LDS, then each thread writes its column of the
 // refreshed tile to the compacted position.
-template <typename S, int OP>
+template <typename S, int OP, int RM>
 __global__ __launch_bounds__(kThreads) void k_panel_gemm(GemmArgs<S> a) {
   typedef typename std::conditional<OP == OP_F64, double, float>::type AccT;
   __shared__ int spiv[kNbMax];
@@ -1091,7 +1101,7 @@ __global__ __launch_bounds__(kThreads) void k_panel_gemm(GemmArgs<S> a) {
   const int cc = tid % 64, rq = tid / 64;  // write-out mapping: column cc, rows rq + 4q
   const int myout = cidx[cc];
   int sF = 0, sV = 0;
-  if (OP == OP_F16 && a.rmode != RM_F16) {
+  if (OP == OP_F16 && RM != RM_F16) {
     const float fmax = __uint_as_float(s_fmax);
     int e = 0;
     if (fmax > 0.0f) frexpf(fmax, &e);
@@ -1275,7 +1285,7 @@ __global__ __launch_bounds__(kThreads) void k_panel_gemm(GemmArgs<S> a) {
           const int64_t r = rs + rr;
           if (r >= rbeg && r < rend) {
             const double vd = (double)wt[sl][q] - (double)accs[rr][cc] * descale;
-            const S v = a.rmode ? rnd_store<S>(vd, a.rmode) : (S)vd;
+            const S v = (S)rndc<RM>(vd);
             outb[(uint32_t)(rr * a.ldw + myout)] = v;
             ss += (double)v * (double)v;
           }
@@ -1415,7 +1425,7 @@ static int await_slot(const FactorHostSlot* hs, int64_t seq) {
   return ID_ERR_HIP;
 }
 
-template <typename TA, typename S, int OP>
+template <typename TA, typename S, int OP, int RM>
 static int factor_impl(const TA* A, int64_t lda, const FactorPlan& pl, const id_opts* o,
                        char* wb, int32_t* perm, double* R, int64_t ldr, int64_t* k_out,
                        int32_t* info, bool noalloc, hipStream_t s) {
@@ -1464,8 +1474,7 @@ static int factor_impl(const TA* A, int64_t lda, const FactorPlan& pl, const id_
     MPID_HIP(hipEventRecord(ev_t0, s));
   }
   const double sbytes = (double)pl.wbytes;
-  const int rmode = (o->flags & ID_FLAG_ROUND_F16) ? RM_F16
-                    : (o->flags & ID_FLAG_ROUND_F32) ? RM_F32 : RM_NONE;
+  const int rmode = RM;
   prof.begin(PK_OTHER, 0, s);
   k_init<<<dim3((unsigned)ceil_div(ldf > n ? ldf : n, kThreads)), kThreads, 0, s>>>(
       st, colid[0], pvflag, permw, posof, n, ldf, zpart + pl.ntile_s_max * ldf,
@@ -1673,9 +1682,9 @@ static int factor_impl(const TA* A, int64_t lda, const FactorPlan& pl, const id_
       af.t0 = 0;
       af.ntile = (int)nfold;
       af.tguard = pl.nfold_max;
-      prof.launch(PK_FINALIZE, tag, k_finalize<S>, dim3((unsigned)namax), s, af);
+      prof.launch(PK_FINALIZE, tag, k_finalize<S, RM>, dim3((unsigned)namax), s, af);
     } else {
-      prof.launch(PK_FINALIZE, tag, k_finalize<S>, dim3((unsigned)namax), s, a);
+      prof.launch(PK_FINALIZE, tag, k_finalize<S, RM>, dim3((unsigned)namax), s, a);
     }
     MPID_LAUNCH_CHECK();
     return ID_OK;
@@ -1724,12 +1733,11 @@ static int factor_impl(const TA* A, int64_t lda, const FactorPlan& pl, const id_
     g.colid = colid[cur];
     g.colid_n = colid[cur ^ 1];
     g.colpart = colpart;
-    g.rmode = rmode;
     g.off = off_lb;
     g.tg0 = off_lb / kRowTileG;
     g.gx = ceil_div(ncur_ub, 64);
     g.gy = ntg - g.tg0;
-    prof.launch(PK_GEMM, (int64_t)panel * 1024, k_panel_gemm<S, OP>,
+    prof.launch(PK_GEMM, (int64_t)panel * 1024, k_panel_gemm<S, OP, RM>,
                 dim3((unsigned)round_up(g.gx * g.gy, 8)), s, g);
     MPID_LAUNCH_CHECK();
     namax = (int)ceil_div(ncur_ub, kFinCols);
@@ -1800,39 +1808,29 @@ static int factor_dispatch(const void* A, int32_t dtype, int64_t m, int64_t n, i
     return ID_OK;
   }
   char* wb = (char*)work;
-  if (pl.prec == ID_PREC_F64) {
-    if (dtype == ID_F64)
-      return factor_impl<double, double, OP_F64>((const double*)A, lda, pl, o, wb, perm, R, ldr,
-                                                  k_out, info, noalloc, s);
-    return factor_impl<float, double, OP_F64>((const float*)A, lda, pl, o, wb, perm, R, ldr, k_out,
-                                              info, noalloc, s);
+  const bool f64in = dtype == ID_F64;
+  const int32_t rflags = o->flags & (ID_FLAG_ROUND_F32 | ID_FLAG_ROUND_F16);
+#define MPID_IMPL(S, OP, RM)                                                                      \
+  (f64in ? factor_impl<double, S, OP, RM>((const double*)A, lda, pl, o, wb, perm, R, ldr, k_out,  \
+                                          info, noalloc, s)                                       \
+         : factor_impl<float, S, OP, RM>((const float*)A, lda, pl, o, wb, perm, R, ldr, k_out,    \
+                                         info, noalloc, s))
+  // the simulated precisions pair with their own update (checked by the plan)
+  if (rflags == ID_FLAG_ROUND_F32) return MPID_IMPL(float, OP_F32, RM_F32);
+  if (rflags == ID_FLAG_ROUND_F16) return MPID_IMPL(float, OP_F16, RM_F16);
+  switch (pl.prec) {
+    case ID_PREC_F64:
+      return MPID_IMPL(double, OP_F64, RM_NONE);
+    case ID_PREC_MIXED_F16:
+      return MPID_IMPL(float, OP_F16, RM_NONE);
+    case ID_PREC_MIXED_F32:
+      return MPID_IMPL(float, OP_F32, RM_NONE);
+    case ID_PREC_MIXED_BF16X3:
+      return MPID_IMPL(float, OP_BF16X3, RM_NONE);
+    default:
+      return MPID_IMPL(float, OP_BF16, RM_NONE);
   }
-  if (pl.prec == ID_PREC_MIXED_F16) {
-    if (dtype == ID_F64)
-      return factor_impl<double, float, OP_F16>((const double*)A, lda, pl, o, wb, perm, R, ldr,
-                                                k_out, info, noalloc, s);
-    return factor_impl<float, float, OP_F16>((const float*)A, lda, pl, o, wb, perm, R, ldr, k_out,
-                                             info, noalloc, s);
-  }
-  if (pl.prec == ID_PREC_MIXED_F32) {
-    if (dtype == ID_F64)
-      return factor_impl<double, float, OP_F32>((const double*)A, lda, pl, o, wb, perm, R, ldr,
-                                                k_out, info, noalloc, s);
-    return factor_impl<float, float, OP_F32>((const float*)A, lda, pl, o, wb, perm, R, ldr, k_out,
-                                             info, noalloc, s);
-  }
-  if (pl.prec == ID_PREC_MIXED_BF16X3) {
-    if (dtype == ID_F64)
-      return factor_impl<double, float, OP_BF16X3>((const double*)A, lda, pl, o, wb, perm, R, ldr,
-                                                   k_out, info, noalloc, s);
-    return factor_impl<float, float, OP_BF16X3>((const float*)A, lda, pl, o, wb, perm, R, ldr,
-                                                k_out, info, noalloc, s);
-  }
-  if (dtype == ID_F64)
-    return factor_impl<double, float, OP_BF16>((const double*)A, lda, pl, o, wb, perm, R, ldr,
-                                               k_out, info, noalloc, s);
-  return factor_impl<float, float, OP_BF16>((const float*)A, lda, pl, o, wb, perm, R, ldr, k_out,
-                                            info, noalloc, s);
+#undef MPID_IMPL
 }
 
 int factor_run(const void* A, int32_t dtype, int64_t m, int64_t n, int64_t lda,

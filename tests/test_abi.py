@@ -157,7 +157,7 @@ def test_round_and_flag_host_checks(lib):
     both = make_opts(k=3)
     both.flags = C["ID_FLAG_ROUND_F32"] | C["ID_FLAG_ROUND_F16"]
     assert lib.id_workspace_size(10, 10, C["ID_F32"], ctypes.byref(both)) == 0
-    g = make_opts(tol=1e-3, gram=True, round_to="f32")
+    g = make_opts(tol=1e-3, prec="mixed_f32", gram=True, round_to="f32")
     k = ctypes.c_int64(0)
     info = ctypes.c_int32(0)
     ws = lib.id_workspace_size(100, 10, C["ID_F64"], ctypes.byref(g))
@@ -166,3 +166,14 @@ def test_round_and_flag_host_checks(lib):
     assert rc == C["ID_ERR_UNSUPPORTED"]
     with pytest.raises(ValueError):
         make_opts(k=3, round_to="f8")
+
+
+def test_round_flags_pair_with_their_update(lib):
+    from paper_2012_00706_amd import C, make_opts
+    for prec, rnd in (("mixed_bf16x3", "f32"), ("f64", "f32"), ("mixed_f32", "f16"),
+                      ("mixed_bf16", "f16")):
+        o = make_opts(k=3, prec=prec, round_to=rnd)
+        assert lib.id_workspace_size(10, 10, C["ID_F32"], ctypes.byref(o)) == 0, (prec, rnd)
+    for prec, rnd in (("mixed_f32", "f32"), ("mixed_f16", "f16")):
+        o = make_opts(k=3, prec=prec, round_to=rnd)
+        assert lib.id_workspace_size(10, 10, C["ID_F32"], ctypes.byref(o)) > 0, (prec, rnd)
