@@ -55,5 +55,35 @@ def build_library(verbose: bool = False, jobs: int | None = None) -> str:
     return LIB_PATH
 
 
+# host code under AddressSanitizer and UndefinedBehaviorSanitizer (the device
+# code is built as usual); "-Xarch_host" keeps each sanitizer off the GPU side
+HOST_SANITIZE = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+                 "-Xarch_host", "-fno-omit-frame-pointer", "-g"]
+HOST_CHECK_SRC = os.path.join(REPO_DIR, "tests", "host_check", "host_check.cpp")
+
+
+def build_host_check(outdir: str | None = None) -> str:
+    """A sanitizer build of the library's host code (libmpid_host_check.so)
+    and of the host-side ABI checker linked against it; returns the checker's
+    path.  Runs without a GPU."""
+    hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+    outdir = outdir or os.path.join(REPO_DIR, "_build", "host_check")
+    os.makedirs(outdir, exist_ok=True)
+    inc = ["-I", os.path.join(REPO_DIR, "include")]
+    srcs = sources()
+    objs = [os.path.join(outdir, os.path.basename(src) + ".o") for src in srcs]
+    flags = [f for f in HIPCC_FLAGS if f != "-O3"] + ["-O1"] + HOST_SANITIZE
+    cmds = [[hipcc, *flags, *inc, "-c", src, "-o", obj] for src, obj in zip(srcs, objs)]
+    with ThreadPoolExecutor(max_workers=min(len(srcs), os.cpu_count() or 1)) as pool:
+        list(pool.map(_run, cmds))
+    lib = os.path.join(outdir, "libmpid_host_check.so")
+    _run([hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", lib, *objs])
+    exe = os.path.join(outdir, "host_check")
+    _run([hipcc, "-O1", "--offload-arch=gfx950", *HOST_SANITIZE, *inc, HOST_CHECK_SRC, "-o", exe,
+          "-L", outdir,
+          "-lmpid_host_check", "-Wl,-rpath," + outdir])
+    return exe
+
+
 if __name__ == "__main__":
     print(build_library(verbose=False))

@@ -1,8 +1,30 @@
 // extern "C" entry points of libmpid (declared in include/mpid.h).
 #include <hip/hip_runtime.h>
 
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+
 #include "mpid.h"
 #include "mpid_internal.h"
+
+namespace mpid {
+
+int log_level() {
+  const char* v = std::getenv("MPID_LOG");
+  return (v && *v) ? std::atoi(v) : 0;
+}
+
+void log_printf(const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  std::fputs("[mpid] ", stderr);
+  std::vfprintf(stderr, fmt, ap);
+  std::fputc('\n', stderr);
+  va_end(ap);
+}
+
+}  // namespace mpid
 
 extern "C" {
 

@@ -1475,6 +1475,11 @@ static int factor_impl(const TA* A, int64_t lda, const FactorPlan& pl, const id_
   }
   const double sbytes = (double)pl.wbytes;
   const int rmode = RM;
+  MPID_LOG(1, "id_factor: m=%lld n=%lld dtype=%s prec=%d flags=%d kcap=%lld nb=%d k_fixed=%lld "
+              "rel_tol=%g rule=%d workspace=%zu bytes%s",
+           (long long)m, (long long)n, sizeof(TA) == 8 ? "f64" : "f32", o->prec, o->flags,
+           (long long)kcap, pl.nb, (long long)o->k_fixed, o->rel_tol, o->rank_rule, pl.bytes,
+           noalloc ? " (static scratch)" : "");
   prof.begin(PK_OTHER, 0, s);
   k_init<<<dim3((unsigned)ceil_div(ldf > n ? ldf : n, kThreads)), kThreads, 0, s>>>(
       st, colid[0], pvflag, permw, posof, n, ldf, zpart + pl.ntile_s_max * ldf,
@@ -1619,6 +1624,14 @@ static int factor_impl(const TA* A, int64_t lda, const FactorPlan& pl, const id_
       }
       const FactorState& h = hs->s;
       settle(settled, known_off, h);
+      {
+        float vm;
+        std::memcpy(&vm, &h.vmax_bits, sizeof(float));
+        MPID_LOG(1, "panel %d settled: start %lld, steps %d, done %d (k %lld), live norms above "
+                    "the rank threshold %u, largest norm %.4g, drain %d",
+                 settled, (long long)known_off, h.done ? (int)(h.k - known_off) : h.last_jb,
+                 h.done, (long long)h.k, h.nabove, (double)vm, (int)drain);
+      }
       ++settled;
       if (h.done) {
         *done_state = &h;
@@ -1658,6 +1671,10 @@ static int factor_impl(const TA* A, int64_t lda, const FactorPlan& pl, const id_
     a.namax = namax;
     const int64_t total = (int64_t)a.ntile * a.nchunk;
     const dim3 sgrid((unsigned)round_up(total, 8));
+    MPID_LOG(2, "step: panel %d, jj %d, rows from %lld, columns <= %lld: %lld-row tiles x "
+                "%d-column chunks = %lld blocks%s",
+             panel, jj, (long long)jlb, (long long)ncur_b, (long long)sh.Rt, sh.CW,
+             (long long)total, a.ntile > kFinZ * kFL ? " (partials folded)" : "");
     const int64_t tag = (int64_t)panel * 1024 + jj;
     if (sh.Rt >= 256)
       prof.launch(PK_SWEEP, tag, k_sweep<S, 1>, sgrid, s, a);
@@ -1771,6 +1788,7 @@ static int factor_impl(const TA* A, int64_t lda, const FactorPlan& pl, const id_
   const int64_t k = fin->k;
   *k_out = k;
   *info = fin->info;
+  MPID_LOG(1, "id_factor: k=%lld info=%d after %d panels", (long long)k, fin->info, settled);
   k_finish<<<dim3((unsigned)n, (unsigned)(k > 0 ? ceil_div(k, kThreads) : 1)), kThreads, 0, s>>>(
       permw, perm, rorig, kcap, n, k, R, ldr);
   MPID_LAUNCH_CHECK();

@@ -136,6 +136,16 @@ int sketch_run(const void* A, int32_t dtype, int64_t m, int64_t n, int64_t lda, 
 __host__ __device__ inline int64_t round_up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
 __host__ __device__ inline int64_t ceil_div(int64_t x, int64_t a) { return (x + a - 1) / a; }
 
+// Host-side diagnostics on stderr, switched on by the environment variable
+// MPID_LOG (1: a line per factorization call and per settled panel; 2: also
+// the geometry of every pivot step's launches).  Read at each use.
+int log_level();
+void log_printf(const char* fmt, ...) __attribute__((format(printf, 1, 2)));
+#define MPID_LOG(level, ...)                                         \
+  do {                                                               \
+    if (::mpid::log_level() >= (level)) ::mpid::log_printf(__VA_ARGS__); \
+  } while (0)
+
 // Returns ID_ERR_HIP from the enclosing function when a HIP call fails.
 #define MPID_HIP(expr)                              \
   do {                                              \
