@@ -29,6 +29,13 @@ struct G64Args {
   double* C;  // C(i, cmap[j])
   int64_t ldc;
   const int32_t* cmap;
+  // optional second output of the large-tile kernel (no split K):
+  // E(i, j) = (Ein ? Ein(i, einmap[j]) : 0) - C(i, cmap[j])
+  double* E;
+  int64_t lde;
+  const double* Ein;
+  int64_t ldein;
+  const int32_t* einmap;
 };
 
 // C = alpha op(A) op(B) + beta Cin, 64 x 64 tile per block, K chunks of 16
@@ -173,12 +180,221 @@ __global__ __launch_bounds__(kThreads) void k_gemm64(G64Args<TA, TC> a) {
     }
 }
 
+// Larger products: a 128 x 128 tile per block, the four waves as 2 x 2 each
+// computing a 64 x 64 part from 4 x 4 FP64 16x16x4 MFMA blocks (four times the
+// matrix-core work of k_gemm64 between two barriers), K in chunks of 16
+// through LDS with the next chunk loaded into registers during the products.
+// Operand and output lane layouts are those of k_gemm64.  With gridDim.z > 1
+// (split K) block z sums the K range [z kc, (z + 1) kc) into its own partial
+// P + z M N (column-major, ld M) and k_gemm64_reduce applies the epilogue.
+// Two waves per SIMD: the register budget (236 of 256) keeps the 64 accumulators
+// in VGPRs without spilling.
 template <typename TA, typename TC>
-static int gemm_launch(const G64Args<TA, TC>& a, hipStream_t s) {
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_gemm64t(
+    G64Args<TA, TC> a, int64_t kc,
+                                                      double* __restrict__ P) {
+  __shared__ double As[16][128 + 2];  // As[kk][i] = op(A)(m0 + i, k0 + kk)
+  __shared__ double Bs[16][128 + 2];  // Bs[kk][j] = op(B)(k0 + kk, n0 + j)
+  __shared__ int32_t smap[3][128];    // the tile's output, Cin and Ein columns
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wv = tid >> 6, g = lane >> 4, li = lane & 15;
+  const int64_t m0 = (int64_t)blockIdx.x * 128, n0 = (int64_t)blockIdx.y * 128;
+  const int wr = (wv & 1) * 64, wc = (wv >> 1) * 64;
+  const int64_t kb = (int64_t)blockIdx.z * kc;
+  const int64_t ke = kb + kc < a.K ? kb + kc : a.K;
+  f64x4 acc[4][4];
+#pragma unroll
+  for (int x = 0; x < 4; ++x)
+#pragma unroll
+    for (int y = 0; y < 4; ++y) acc[x][y] = (f64x4){0.0, 0.0, 0.0, 0.0};
+
+  // Loads are unconditional from indices clamped into the operands and issued
+  // as one group; entries outside the product are zeroed when they go to LDS
+  // (a clamped entry is a real entry of the same operand row or column).
+  double ra[8], rb[8];
+  auto load = [&](int64_t k0) {
+    int64_t col[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int64_t gk = k0 + tid / 128 + 2 * q;
+      const int64_t gkc = gk < ke ? gk : ke - 1;
+      col[q] = (a.ta == 0 && a.amap) ? (int64_t)a.amap[gkc] : gkc;
+    }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      if (a.ta == 0) {  // op(A)(i, kk): 128 consecutive rows of one column per half-block
+        const int64_t gi = m0 + tid % 128;
+        ra[q] = (double)a.A[col[q] * a.lda + (gi < a.M ? gi : a.M - 1)];
+      } else {          // A(kk, i) row-major in the contraction
+        const int64_t gi = m0 + tid / 16 + 16 * q, gk = k0 + tid % 16;
+        ra[q] = (double)a.A[(gi < a.M ? gi : a.M - 1) * a.lda + (gk < ke ? gk : ke - 1)];
+      }
+      if (a.tb == 0) {  // B(kk, j) = B[j ldb + kk]
+        const int64_t gj = n0 + tid / 16 + 16 * q, gk = k0 + tid % 16;
+        rb[q] = a.B[(gj < a.N ? gj : a.N - 1) * a.ldb + (gk < ke ? gk : ke - 1)];
+      } else {          // B(kk, j) = B[kk ldb + j]
+        const int64_t gj = n0 + tid % 128, gk = k0 + tid / 128 + 2 * q;
+        rb[q] = a.B[(gk < ke ? gk : ke - 1) * a.ldb + (gj < a.N ? gj : a.N - 1)];
+      }
+    }
+  };
+  if (kb < ke) load(kb);
+  // the epilogue's column maps, ready by its time (the main loop's barriers
+  // publish them)
+  if (tid < 128) {
+    const int64_t j = n0 + tid;
+    const int64_t jc = j < a.N ? j : a.N - 1;
+    smap[0][tid] = a.cmap ? a.cmap[jc] : (int32_t)jc;
+    smap[1][tid] = a.cinmap ? a.cinmap[jc] : (int32_t)jc;
+    smap[2][tid] = a.einmap ? a.einmap[jc] : (int32_t)jc;
+  }
+  if (kb >= ke) __syncthreads();
+  for (int64_t k0 = kb; k0 < ke; k0 += 16) {
+    __syncthreads();  // the previous chunk's products are done with LDS
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      if (a.ta == 0) {
+        const int i = tid % 128, kk = tid / 128 + 2 * q;
+        As[kk][i] = (m0 + i < a.M && k0 + kk < ke) ? ra[q] : 0.0;
+      } else {
+        const int kk = tid % 16, i = tid / 16 + 16 * q;
+        As[kk][i] = (m0 + i < a.M && k0 + kk < ke) ? ra[q] : 0.0;
+      }
+      if (a.tb == 0) {
+        const int kk = tid % 16, j = tid / 16 + 16 * q;
+        Bs[kk][j] = (n0 + j < a.N && k0 + kk < ke) ? rb[q] : 0.0;
+      } else {
+        const int j = tid % 128, kk = tid / 128 + 2 * q;
+        Bs[kk][j] = (n0 + j < a.N && k0 + kk < ke) ? rb[q] : 0.0;
+      }
+    }
+    __syncthreads();
+    if (k0 + 16 < ke) load(k0 + 16);
+#pragma unroll
+    for (int ks = 0; ks < 4; ++ks) {
+      double af[4], bf[4];
+#pragma unroll
+      for (int x = 0; x < 4; ++x) af[x] = As[4 * ks + g][wr + 16 * x + li];
+#pragma unroll
+      for (int y = 0; y < 4; ++y) bf[y] = Bs[4 * ks + g][wc + 16 * y + li];
+      // operands fed swapped (the product comes out transposed): a lane's
+      // four results are then four columns of C at one row, and the 16 lanes
+      // of a lane group hold 16 consecutive rows -- 128-byte segments of the
+      // column-major output instead of 32-byte ones
+#pragma unroll
+      for (int x = 0; x < 4; ++x)
+#pragma unroll
+        for (int y = 0; y < 4; ++y)
+          acc[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(bf[y], af[x], acc[x][y], 0, 0, 0);
+    }
+  }
+  // acc[x][y][r] = product(m0 + wr + 16x + li, n0 + wc + 16y + g + 4r)
+  const int64_t ib = m0 + wr + li;
+  if (gridDim.z > 1) {
+    double* Pz = P + (int64_t)blockIdx.z * a.M * a.N;
+#pragma unroll
+    for (int x = 0; x < 4; ++x)
+#pragma unroll
+      for (int y = 0; y < 4; ++y)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int64_t i = ib + 16 * x, j = n0 + wc + 16 * y + g + 4 * r;
+          if (i < a.M && j < a.N) Pz[j * a.M + i] = acc[x][y][r];
+        }
+    return;
+  }
+  // per group y: every Cin / Ein load of its 16 outputs issued before any of
+  // them is used (one memory round trip per group, not one per output row)
+  const bool hasc = a.beta != 0.0, hase = a.E && a.Ein;
+#pragma unroll
+  for (int y = 0; y < 4; ++y) {
+    double cin[4][4], ein[4][4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int jl = wc + 16 * y + g + 4 * r;
+      const int64_t ij = smap[1][jl], ej = smap[2][jl];
+#pragma unroll
+      for (int x = 0; x < 4; ++x) {
+        const int64_t i = ib + 16 * x;
+        const int64_t icl = i < a.M ? i : a.M - 1;
+        cin[r][x] = hasc ? (double)a.Cin[ij * a.ldcin + icl] : 0.0;
+        ein[r][x] = hase ? a.Ein[ej * a.ldein + icl] : 0.0;
+      }
+    }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int jl = wc + 16 * y + g + 4 * r;
+      const int64_t j = n0 + jl;
+      if (j >= a.N) continue;
+      const int64_t cj = smap[0][jl];
+#pragma unroll
+      for (int x = 0; x < 4; ++x) {
+        const int64_t i = ib + 16 * x;
+        if (i >= a.M) continue;
+        double v = a.alpha * acc[x][y][r];
+        if (hasc) v += a.beta * cin[r][x];
+        a.C[cj * a.ldc + i] = v;
+        if (a.E) a.E[j * a.lde + i] = ein[r][x] - v;
+      }
+    }
+  }
+}
+
+// Split-K epilogue: C(i, cmap[j]) = alpha sum_z P_z(i, j) + beta Cin(i, cinmap[j]),
+// the partials summed in z order.
+template <typename TA, typename TC>
+__global__ __launch_bounds__(kThreads) void k_gemm64_reduce(G64Args<TA, TC> a, int nz,
+                                                            const double* __restrict__ P) {
+  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  const int64_t j = blockIdx.y;
+  if (i >= a.M) return;
+  double s = 0.0;
+  for (int z = 0; z < nz; ++z) s += P[((int64_t)z * a.N + j) * a.M + i];
+  double v = a.alpha * s;
+  if (a.beta != 0.0) v += a.beta * (double)a.Cin[(a.cinmap ? (int64_t)a.cinmap[j] : j) * a.ldcin + i];
+  a.C[(a.cmap ? (int64_t)a.cmap[j] : j) * a.ldc + i] = v;
+}
+
+// Split-K plan of the large-tile product: with few output tiles and a long
+// contraction the K range is split so that the grid has about two blocks per
+// compute unit; P must then hold nz M N doubles.
+static int gemm_splits(int64_t M, int64_t N, int64_t K) {
+  const int64_t tiles = ceil_div(M, 128) * ceil_div(N, 128);
+  int nz = 1;
+  while (nz < 16 && tiles * nz * 2 <= 512 && K / (nz * 2) >= 128) nz *= 2;
+  return nz;
+}
+
+size_t gemm64_split_workspace(int64_t M, int64_t N, int64_t K) {
+  const int nz = gemm_splits(M, N, K);
+  return nz > 1 ? (size_t)nz * M * N * 8 : 0;
+}
+
+template <typename TA, typename TC>
+static int gemm_launch(const G64Args<TA, TC>& a, hipStream_t s, double* P = nullptr,
+                       size_t p_bytes = 0) {
   if (a.M <= 0 || a.N <= 0) return ID_OK;
-  k_gemm64<TA, TC><<<dim3((unsigned)ceil_div(a.M, 64), (unsigned)ceil_div(a.N, 64)), kThreads, 0,
-                     s>>>(a);
+  // small products take the 64 x 64 tile (which has no second output)
+  if (!a.E && (a.M < 128 || a.N < 64 || a.K < 16)) {
+    k_gemm64<TA, TC><<<dim3((unsigned)ceil_div(a.M, 64), (unsigned)ceil_div(a.N, 64)), kThreads,
+                       0, s>>>(a);
+    MPID_LAUNCH_CHECK();
+    return ID_OK;
+  }
+  int nz = gemm_splits(a.M, a.N, a.K);
+  if (nz > 1 && (a.E || !P || p_bytes < (size_t)nz * a.M * a.N * 8)) nz = 1;
+  const int64_t kc = round_up(ceil_div(a.K, nz), 16);
+  k_gemm64t<TA, TC><<<dim3((unsigned)ceil_div(a.M, 128), (unsigned)ceil_div(a.N, 128),
+                           (unsigned)nz),
+                      kThreads, 0, s>>>(a, kc, P);
   MPID_LAUNCH_CHECK();
+  if (nz > 1) {
+    k_gemm64_reduce<TA, TC><<<dim3((unsigned)ceil_div(a.M, kThreads), (unsigned)a.N), kThreads, 0,
+                              s>>>(a, nz, P);
+    MPID_LAUNCH_CHECK();
+  }
   return ID_OK;
 }
 
@@ -285,10 +501,15 @@ int reconstruct_run(const void* A, int32_t dtype, int64_t m, int64_t n, int64_t 
 
 // ---------------------------------------------------------------- adjoint
 
+// B^T gY(:, Jc) has few output tiles: its contraction is split for about this
+// many blocks (fewer, longer chunks than a sketch of the whole input: less
+// partial-sum traffic)
+constexpr int kBwdSketchBlocks = 1024;
+
 struct BwdPlan {
-  size_t off_b, off_c, off_gyj, off_gyc, off_tbar, off_wt, off_rq, off_permq, off_info, off_fws,
-      off_btg, off_sk;
-  size_t fws_bytes, sk_bytes, bytes;
+  size_t off_b, off_de, off_xt, off_tbar, off_rq, off_permq, off_info, off_fws, off_btg, off_sk,
+      off_p;
+  size_t fws_bytes, sk_bytes, p_bytes, bytes;
 };
 
 static bool make_bwd_plan(int64_t m, int64_t n, int64_t k, BwdPlan* p) {
@@ -301,12 +522,10 @@ static bool make_bwd_plan(int64_t m, int64_t n, int64_t k, BwdPlan* p) {
     off += (bytes + 255) / 256 * 256;
     return at;
   };
-  p->off_b = take((size_t)mm * kk * 8);
-  p->off_c = take((size_t)mm * cc * 8);
-  p->off_gyj = take((size_t)mm * kk * 8);
-  p->off_gyc = take((size_t)mm * cc * 8);
+  p->off_b = take((size_t)mm * kk * 8);       // B = A(:, J) in FP64
+  p->off_de = take((size_t)mm * 2 * cc * 8);  // [D | E], m x 2(n-k)
+  p->off_xt = take((size_t)kk * 2 * cc * 8);  // [X | T], k x 2(n-k)
   p->off_tbar = take((size_t)kk * cc * 8);
-  p->off_wt = take((size_t)mm * cc * 8);
   p->off_rq = take((size_t)kk * kk * 8);
   p->off_permq = take((size_t)kk * 4);
   p->off_info = take(64);
@@ -322,8 +541,11 @@ static bool make_bwd_plan(int64_t m, int64_t n, int64_t k, BwdPlan* p) {
   // B^T gY(:, Jc): k x (n-k) with a contraction over all m rows, split over
   // row chunks (few output tiles, long contraction)
   p->off_btg = take((size_t)kk * cc * 8);
-  p->sk_bytes = sketch_workspace(kk, mm, cc);
+  p->sk_bytes = sketch_workspace_target(kk, mm, cc, kBwdSketchBlocks);
   p->off_sk = take(p->sk_bytes);
+  // split-K partials of the m x k product with the 2(n-k) contraction
+  p->p_bytes = gemm64_split_workspace(mm, kk, 2 * cc);
+  p->off_p = take(p->p_bytes > 0 ? p->p_bytes : 8);
   p->bytes = off;
   return true;
 }
@@ -333,6 +555,16 @@ size_t backward_workspace(int64_t m, int64_t n, int64_t k) {
   return make_bwd_plan(m, n, k, &p) ? p.bytes : 0;
 }
 
+// With B = A(:, J), C = A(:, Jc), T = B^+ C and X = (B^T B)^{-1} Tbar,
+// Tbar = gT + B^T gY(:, Jc):
+//   gA(:, Jc) = W = B X
+//   gA(:, J)  = gY(:, J) + (C - B T) X^T + (gY(:, Jc) - W) T^T
+//             = gY(:, J) + [D | E] [X | T]^T,  D = C - B T, E = gY(:, Jc) - W.
+// A and gY are read through column maps (no gathered copies but B); the two
+// products with B share nothing but their operand, the last one is a single
+// product over the 2 (n - k) contraction, split over K when its output has few
+// tiles.  The singularity check of B's R factor is read at the end (one host
+// synchronization per call).
 template <typename TA>
 static int backward_impl(const TA* A, int64_t m, int64_t n, int64_t lda, const int32_t* perm,
                          int64_t k, const double* T, int64_t ldt, const double* Rb, int64_t ldrb,
@@ -341,11 +573,9 @@ static int backward_impl(const TA* A, int64_t m, int64_t n, int64_t lda, const i
                          hipStream_t s) {
   const int64_t nc = n - k;
   double* Bm = (double*)(wb + p.off_b);
-  double* Cm = (double*)(wb + p.off_c);
-  double* gYJ = (double*)(wb + p.off_gyj);
-  double* gYc = (double*)(wb + p.off_gyc);
+  double* DE = (double*)(wb + p.off_de);
+  double* XT = (double*)(wb + p.off_xt);
   double* Tb = (double*)(wb + p.off_tbar);
-  double* Wt = (double*)(wb + p.off_wt);
   double* Rq = (double*)(wb + p.off_rq);
   int32_t* permq = (int32_t*)(wb + p.off_permq);
   int32_t* dinfo = (int32_t*)(wb + p.off_info);
@@ -353,82 +583,94 @@ static int backward_impl(const TA* A, int64_t m, int64_t n, int64_t lda, const i
   *info = 0;
   // gA = 0 when there is no skeleton
   if (k == 0) return gather<double>(nullptr, 1, m, nullptr, n, gA, ldga, nullptr, 1, s);
-  if ((rc = gather<TA>(A, lda, m, perm, k, Bm, m, nullptr, 0, s))) return rc;
-  if (nc > 0 && (rc = gather<TA>(A, lda, m, perm + k, nc, Cm, m, nullptr, 0, s))) return rc;
-  if (gY) {
-    if ((rc = gather<double>(gY, ldgy, m, perm, k, gYJ, m, nullptr, 0, s))) return rc;
-    if (nc > 0 && (rc = gather<double>(gY, ldgy, m, perm + k, nc, gYc, m, nullptr, 0, s)))
-      return rc;
-  } else {
-    if ((rc = gather<double>(nullptr, 1, m, nullptr, k, gYJ, m, nullptr, 1, s))) return rc;
-  }
-  if (nc > 0) {
-    // R factor of B: the caller's (any R with R^T R = B^T B, e.g. R11 of the
-    // FP64 factorization that chose J), else an unpivoted FP64 Householder QR
-    const double* Rf = Rb;
-    int64_t ldrf = ldrb;
-    if (!Rf) {
-      id_opts o;
-      std::memset(&o, 0, sizeof(o));
-      o.prec = ID_PREC_F64;
-      o.k_fixed = k;
-      o.flags = ID_FLAG_NO_PIVOT;
-      int64_t kq = 0;
-      int32_t iq = 0;
-      rc = factor_run(Bm, ID_F64, m, k, m, &o, wb + p.off_fws, p.fws_bytes, permq, Rq, k, &kq,
-                      &iq, s);
-      if (rc) return rc;
-      if (iq != 0 || kq != k) {
-        *info = ID_INFO_SINGULAR;
-        return ID_OK;
-      }
-      Rf = Rq;
-      ldrf = k;
-    }
-    if ((rc = solve_T_run(Rf, ldrf, k, k, nullptr, 1, dinfo, s))) return rc;
-    int32_t hinfo = 0;
-    MPID_HIP(hipMemcpyAsync(&hinfo, dinfo, 4, hipMemcpyDeviceToHost, s));
+  if (nc == 0) {  // the skeleton is every column: Y = A, gA = gY
+    rc = gY ? gather<double>(gY, ldgy, m, perm, k, gA, ldga, perm, 0, s)
+            : gather<double>(nullptr, 1, m, nullptr, k, gA, ldga, perm, 1, s);
+    if (rc) return rc;
     MPID_HIP(hipStreamSynchronize(s));
-    if (hinfo == ID_INFO_SINGULAR) {
+    return ID_OK;
+  }
+  if ((rc = gather<TA>(A, lda, m, perm, k, Bm, m, nullptr, 0, s))) return rc;
+  // R factor of B: the caller's (any R with R^T R = B^T B, e.g. R11 of the
+  // FP64 factorization that chose J), else an unpivoted FP64 Householder QR
+  const double* Rf = Rb;
+  int64_t ldrf = ldrb;
+  if (!Rf) {
+    id_opts o;
+    std::memset(&o, 0, sizeof(o));
+    o.prec = ID_PREC_F64;
+    o.k_fixed = k;
+    o.flags = ID_FLAG_NO_PIVOT;
+    int64_t kq = 0;
+    int32_t iq = 0;
+    rc = factor_run(Bm, ID_F64, m, k, m, &o, wb + p.off_fws, p.fws_bytes, permq, Rq, k, &kq, &iq,
+                    s);
+    if (rc) return rc;
+    if (iq != 0 || kq != k) {
       *info = ID_INFO_SINGULAR;
       return ID_OK;
     }
-    // Tbar = gT + B^T gY(:, Jc)
-    if (gT) {
-      if ((rc = gather<double>(gT, ldgt, k, nullptr, nc, Tb, k, nullptr, 0, s))) return rc;
-    } else {
-      if ((rc = gather<double>(nullptr, 1, k, nullptr, nc, Tb, k, nullptr, 1, s))) return rc;
-    }
-    if (gY) {
-      // B^T as a row-major k x m matrix is B's column-major storage
-      double* btg = (double*)(wb + p.off_btg);
-      if ((rc = sketch_run(gYc, ID_F64, m, nc, m, Bm, k, m, btg, k, wb + p.off_sk, p.sk_bytes, s)))
-        return rc;
-      k_axpy_cols<<<dim3((unsigned)ceil_div(k, kThreads), (unsigned)nc), kThreads, 0, s>>>(
-          Tb, k, btg, k, k, 1.0);
-      MPID_LAUNCH_CHECK();
-    }
-    // X = (B^T B)^{-1} Tbar = R^{-1} R^{-T} Tbar
-    if ((rc = trsm_upper_run(Rf, ldrf, k, Tb, k, nc, Tb, k, 1, s))) return rc;
-    if ((rc = trsm_upper_run(Rf, ldrf, k, Tb, k, nc, Tb, k, 0, s))) return rc;
-    // Wt = B X  (= dL/dC)
-    if ((rc = gemm64_run(0, 0, m, nc, k, 1.0, Bm, m, Tb, k, 0.0, Wt, m, s))) return rc;
-    // Rres = C - B T (in place in Cm)
-    if ((rc = gemm64_run(0, 0, m, nc, k, -1.0, Bm, m, T, ldt, 1.0, Cm, m, s))) return rc;
-    // Bbar = gY(:, J) + Rres X^T + (gY(:, Jc) - Wt) T^T
-    if ((rc = gemm64_run(0, 1, m, k, nc, 1.0, Cm, m, Tb, k, 1.0, gYJ, m, s))) return rc;
-    if (gY) {
-      k_axpy_cols<<<dim3((unsigned)ceil_div(m, kThreads), (unsigned)nc), kThreads, 0, s>>>(
-          gYc, m, Wt, m, m, -1.0);
-      MPID_LAUNCH_CHECK();
-      if ((rc = gemm64_run(0, 1, m, k, nc, 1.0, gYc, m, T, ldt, 1.0, gYJ, m, s))) return rc;
-    } else {
-      if ((rc = gemm64_run(0, 1, m, k, nc, -1.0, Wt, m, T, ldt, 1.0, gYJ, m, s))) return rc;
-    }
-    if ((rc = gather<double>(Wt, m, m, nullptr, nc, gA, ldga, perm + k, 0, s))) return rc;
+    Rf = Rq;
+    ldrf = k;
   }
-  if ((rc = gather<double>(gYJ, m, m, nullptr, k, gA, ldga, perm, 0, s))) return rc;
+  // the diagonal check of Rf (read at the end)
+  if ((rc = solve_T_run(Rf, ldrf, k, k, nullptr, 1, dinfo, s))) return rc;
+  // Tbar = gT + B^T gY(:, Jc)
+  if (gT) {
+    if ((rc = gather<double>(gT, ldgt, k, nullptr, nc, Tb, k, nullptr, 0, s))) return rc;
+  } else {
+    if ((rc = gather<double>(nullptr, 1, k, nullptr, nc, Tb, k, nullptr, 1, s))) return rc;
+  }
+  if (gY) {
+    // B^T as a row-major k x m matrix is B's column-major storage
+    double* btg = (double*)(wb + p.off_btg);
+    if ((rc = sketch_run_cols(gY, ID_F64, m, nc, ldgy, perm + k, Bm, k, m, btg, k, wb + p.off_sk,
+                              p.sk_bytes, kBwdSketchBlocks, s)))
+      return rc;
+    k_axpy_cols<<<dim3((unsigned)ceil_div(k, kThreads), (unsigned)nc), kThreads, 0, s>>>(
+        Tb, k, btg, k, k, 1.0);
+    MPID_LAUNCH_CHECK();
+  }
+  // X = (B^T B)^{-1} Tbar = R^{-1} R^{-T} Tbar into the left half of [X | T]
+  double* X = XT;
+  if ((rc = trsm_upper_run(Rf, ldrf, k, Tb, k, nc, Tb, k, 1, s))) return rc;
+  if ((rc = trsm_upper_run(Rf, ldrf, k, Tb, k, nc, X, k, 0, s))) return rc;
+  if ((rc = gather<double>(T, ldt, k, nullptr, nc, XT + k * nc, k, nullptr, 0, s))) return rc;
+  // gA(:, Jc) = W = B X, and E = gY(:, Jc) - W beside it
+  {
+    G64Args<double, double> a;
+    std::memset(&a, 0, sizeof(a));
+    a.M = m, a.N = nc, a.K = k, a.alpha = 1.0;
+    a.A = Bm, a.lda = m, a.B = X, a.ldb = k;
+    a.C = gA, a.ldc = ldga, a.cmap = perm + k;
+    a.E = DE + m * nc, a.lde = m, a.Ein = gY, a.ldein = ldgy, a.einmap = perm + k;
+    if ((rc = gemm_launch(a, s))) return rc;
+  }
+  // D = A(:, Jc) - B T
+  {
+    G64Args<double, TA> a;
+    std::memset(&a, 0, sizeof(a));
+    a.M = m, a.N = nc, a.K = k, a.alpha = -1.0, a.beta = 1.0;
+    a.A = Bm, a.lda = m, a.B = XT + k * nc, a.ldb = k;
+    a.Cin = A, a.ldcin = lda, a.cinmap = perm + k;
+    a.C = DE, a.ldc = m;
+    if ((rc = gemm_launch(a, s))) return rc;
+  }
+  // gA(:, J) = gY(:, J) + [D | E] [X | T]^T
+  {
+    G64Args<double, double> a;
+    std::memset(&a, 0, sizeof(a));
+    a.tb = 1;
+    a.M = m, a.N = k, a.K = 2 * nc, a.alpha = 1.0, a.beta = gY ? 1.0 : 0.0;
+    a.A = DE, a.lda = m, a.B = XT, a.ldb = k;
+    a.Cin = gY, a.ldcin = ldgy, a.cinmap = perm;
+    a.C = gA, a.ldc = ldga, a.cmap = perm;
+    if ((rc = gemm_launch(a, s, (double*)(wb + p.off_p), p.p_bytes))) return rc;
+  }
+  int32_t hinfo = 0;
+  MPID_HIP(hipMemcpyAsync(&hinfo, dinfo, 4, hipMemcpyDeviceToHost, s));
   MPID_HIP(hipStreamSynchronize(s));
+  if (hinfo == ID_INFO_SINGULAR) *info = ID_INFO_SINGULAR;  // gA is then undefined
   return ID_OK;
 }
 

@@ -106,6 +106,9 @@ int trsm_upper_run(const double* R, int64_t ldr, int64_t k, const double* B, int
                    int64_t ncols, double* X, int64_t ldx, int trans, hipStream_t s);
 
 // C = alpha * op(A) op(B) + beta * C (column-major float64; ta/tb: 0 = N, 1 = T).
+// Bytes of split-K partials gemm64 uses for an M x N product with contraction K
+// when given them (0: no split).
+size_t gemm64_split_workspace(int64_t M, int64_t N, int64_t K);
 int gemm64_run(int ta, int tb, int64_t M, int64_t N, int64_t K, double alpha, const double* A,
                int64_t lda, const double* B, int64_t ldb, double beta, double* C, int64_t ldc,
                hipStream_t s);
@@ -129,6 +132,12 @@ int backward_run(const void* A, int32_t dtype, int64_t m, int64_t n, int64_t lda
                  hipStream_t s);
 
 size_t sketch_workspace(int64_t l, int64_t m, int64_t n);
+// sketch_run with column j of A taken from A(:, acols[j]) (acols may be null)
+// and the contraction split for about target_blocks blocks (0: the default)
+size_t sketch_workspace_target(int64_t l, int64_t m, int64_t n, int target_blocks);
+int sketch_run_cols(const void* A, int32_t dtype, int64_t m, int64_t n, int64_t lda,
+                    const int32_t* acols, const double* Om, int64_t l, int64_t ldo, double* Y,
+                    int64_t ldy, void* work, size_t work_bytes, int target_blocks, hipStream_t s);
 int sketch_run(const void* A, int32_t dtype, int64_t m, int64_t n, int64_t lda, const double* Om,
                int64_t l, int64_t ldo, double* Y, int64_t ldy, void* work, size_t work_bytes,
                hipStream_t s);

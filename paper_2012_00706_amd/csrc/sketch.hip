@@ -43,7 +43,7 @@ struct SketchPlan {
   size_t bytes;
 };
 
-bool make_sketch_plan(int64_t l, int64_t m, int64_t n, SketchPlan* p) {
+bool make_sketch_plan(int64_t l, int64_t m, int64_t n, SketchPlan* p, int target = 0) {
   if (l < 0 || m < 0 || n < 0 || l > ((int64_t)1 << 20) || n > ((int64_t)1 << 30)) return false;
   std::memset(p, 0, sizeof(*p));
   const int64_t mm = m > 0 ? m : 1;
@@ -51,7 +51,7 @@ bool make_sketch_plan(int64_t l, int64_t m, int64_t n, SketchPlan* p) {
   p->ntn = ceil_div(n > 0 ? n : 1, 64);
   p->ntiles = p->ntl * p->ntn;
   // many short chunks: ~16 resident blocks per CU and a short tail
-  int64_t S = ceil_div(env_int("MPID_SKETCH_BLOCKS", 4096), p->ntiles);
+  int64_t S = ceil_div(target > 0 ? target : env_int("MPID_SKETCH_BLOCKS", 4096), p->ntiles);
   const int64_t smax = ceil_div(mm, 8 * kSK);
   if (S > smax) S = smax;
   if (S < 1) S = 1;
@@ -85,8 +85,8 @@ struct Vec2x<double> {
 template <typename TA, bool VEC>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4, 4))) void
 k_sketch_partial(const double* __restrict__ Om, int64_t ldo, const TA* __restrict__ A, int64_t lda,
-                 int64_t l, int64_t m, int64_t n, int64_t ntn, int64_t ntiles, int64_t S,
-                 int64_t chunk, double* __restrict__ P) {
+                 const int32_t* __restrict__ acols, int64_t l, int64_t m, int64_t n, int64_t ntn,
+                 int64_t ntiles, int64_t S, int64_t chunk, double* __restrict__ P) {
   __shared__ double Os[kSK][64 + 1];  // Os[kk][x] = Omega(i0 + x, r0 + kk)
   __shared__ double As[kSK][64 + 1];  // As[kk][y] = A(r0 + kk, j0 + y)
   const int tid = threadIdx.x;
@@ -108,7 +108,9 @@ k_sketch_partial(const double* __restrict__ Om, int64_t ldo, const TA* __restric
   const int lc = tid / kTH, lr = (tid % kTH) * kOR;
   const bool okO = i0 + lc < l, okA = j0 + lc < n;
   const double* orow = Om + (okO ? (i0 + lc) * ldo : 0) + lr;
-  const TA* acol = A + (okA ? (j0 + lc) * lda : 0) + lr;
+  // column j of A is A(:, acols[j]) when a column map is given
+  const int64_t ac = okA ? (acols ? (int64_t)acols[j0 + lc] : j0 + lc) : 0;
+  const TA* acol = A + ac * lda + lr;
   f64x4 acc[2][2];
 #pragma unroll
   for (int x = 0; x < 2; ++x)
@@ -209,19 +211,19 @@ __global__ __launch_bounds__(kThreads) void k_sketch_reduce(const double* __rest
 }
 
 template <typename TA>
-int sketch_impl(const TA* A, int64_t m, int64_t n, int64_t lda, const double* Om, int64_t l,
-                int64_t ldo, double* Y, int64_t ldy, const SketchPlan& p, double* P,
-                hipStream_t s) {
+int sketch_impl(const TA* A, int64_t m, int64_t n, int64_t lda, const int32_t* acols,
+                const double* Om, int64_t l, int64_t ldo, double* Y, int64_t ldy,
+                const SketchPlan& p, double* P, hipStream_t s) {
   const dim3 grid((unsigned)round_up(p.S * p.ntiles, 8));
   // 16-byte loads need 16-byte aligned rows of Omega and columns of A
   const bool vec = ((uintptr_t)Om % 16 == 0) && (ldo % 2 == 0) && ((uintptr_t)A % 16 == 0) &&
                    ((lda * (int64_t)sizeof(TA)) % 16 == 0);
   if (vec)
-    k_sketch_partial<TA, true><<<grid, kThreads, 0, s>>>(Om, ldo, A, lda, l, m, n, p.ntn,
+    k_sketch_partial<TA, true><<<grid, kThreads, 0, s>>>(Om, ldo, A, lda, acols, l, m, n, p.ntn,
                                                          p.ntiles, p.S, p.chunk, P);
   else
-    k_sketch_partial<TA, false><<<grid, kThreads, 0, s>>>(Om, ldo, A, lda, l, m, n, p.ntn,
-                                                          p.ntiles, p.S, p.chunk, P);
+    k_sketch_partial<TA, false><<<grid, kThreads, 0, s>>>(Om, ldo, A, lda, acols, l, m, n,
+                                                          p.ntn, p.ntiles, p.S, p.chunk, P);
   MPID_LAUNCH_CHECK();
   k_sketch_reduce<<<dim3((unsigned)ceil_div(p.ntiles * 4096, kThreads)), kThreads, 0, s>>>(
       P, p.S, p.ntiles, p.ntn, l, n, Y, ldy);
@@ -240,17 +242,30 @@ size_t sketch_workspace(int64_t l, int64_t m, int64_t n) {
 int sketch_run(const void* A, int32_t dtype, int64_t m, int64_t n, int64_t lda, const double* Om,
                int64_t l, int64_t ldo, double* Y, int64_t ldy, void* work, size_t work_bytes,
                hipStream_t s) {
+  return sketch_run_cols(A, dtype, m, n, lda, nullptr, Om, l, ldo, Y, ldy, work, work_bytes, 0,
+                         s);
+}
+
+size_t sketch_workspace_target(int64_t l, int64_t m, int64_t n, int target_blocks) {
+  SketchPlan p;
+  if (!make_sketch_plan(l, m, n, &p, target_blocks)) return 0;
+  return p.bytes;
+}
+
+int sketch_run_cols(const void* A, int32_t dtype, int64_t m, int64_t n, int64_t lda,
+                    const int32_t* acols, const double* Om, int64_t l, int64_t ldo, double* Y,
+                    int64_t ldy, void* work, size_t work_bytes, int target_blocks, hipStream_t s) {
   if (dtype != ID_F32 && dtype != ID_F64) return ID_ERR_DTYPE;
   SketchPlan p;
-  if (!make_sketch_plan(l, m, n, &p)) return ID_ERR_ARG;
+  if (!make_sketch_plan(l, m, n, &p, target_blocks)) return ID_ERR_ARG;
   if (l == 0 || n == 0) return ID_OK;
   if (!Y || ldy < l) return ID_ERR_ARG;
   if (m > 0 && (!A || !Om || lda < m || ldo < m)) return ID_ERR_ARG;
   if (!work || work_bytes < p.bytes) return ID_ERR_WORKSPACE;
   double* P = (double*)work;
   if (dtype == ID_F64)
-    return sketch_impl<double>((const double*)A, m, n, lda, Om, l, ldo, Y, ldy, p, P, s);
-  return sketch_impl<float>((const float*)A, m, n, lda, Om, l, ldo, Y, ldy, p, P, s);
+    return sketch_impl<double>((const double*)A, m, n, lda, acols, Om, l, ldo, Y, ldy, p, P, s);
+  return sketch_impl<float>((const float*)A, m, n, lda, acols, Om, l, ldo, Y, ldy, p, P, s);
 }
 
 }  // namespace mpid
