@@ -527,11 +527,17 @@ def run_config4(args):
     log(f"[bench] {len(mats)} matrices generated in {time.perf_counter() - t0:.1f} s")
     As = [torch.from_numpy(np.ascontiguousarray(a.T)).cuda().t() for a in mats]
     import paper_2012_00706_amd as mp
+    # the lock-step launches (every step of all unfinished items in one launch)
+    lock = mp.LockstepID(As, tol=1e-4, prec=args.prec)
+    ms, _ = _timed(lock.run, max(args.steps // 5, 2), 1)
+    res = lock.results()
+    ks = [r.k for r in res]
+    # the persistent graph-capturable launch, for comparison
     plan = mp.BatchedID(As, tol=1e-4, prec=args.prec)
     tune = mp.autotune(plan, use_cache=False)
-    ms, _ = _timed(plan.run, max(args.steps // 5, 2), 1)
-    res = plan.results()
-    ks = [r.k for r in res]
+    pers_ms, _ = _timed(plan.run, max(args.steps // 5, 2), 1)
+    pres = plan.results()
+    same_k = sum(int(a.k == b.k) for a, b in zip(res, pres))
     flops = sum(useful_flops(a.shape[0], a.shape[1], k) for a, k in zip(mats, ks))
     sweep_bytes = sum(4.0 * sum((a.shape[0] - j) * (a.shape[1] - j - 1) for j in range(k))
                       for a, k in zip(mats, ks))
@@ -540,8 +546,9 @@ def run_config4(args):
         for A in As:
             mp.column_id(A, tol=1e-4, prec=args.prec)
     loop_ms, _ = _timed(loop, 1, 1)
-    log(f"[bench] batched {ms:.1f} ms, loop of single IDs {loop_ms:.1f} ms")
-    out = _line(args, "batched rank-k IDs: aggregate TFLOP/s (one persistent launch)",
+    log(f"[bench] lock-step {ms:.1f} ms, persistent {pers_ms:.1f} ms, "
+        f"loop of single IDs {loop_ms:.1f} ms")
+    out = _line(args, "batched rank-k IDs: aggregate TFLOP/s (lock-step launches)",
                 flops / (ms * 1e-3) / 1e12, "TFLOP/s", ms, True,
                 {"mixed_bf16": "f32+bf16", "mixed_bf16x3": "f32+bf16x3", "mixed_f16": "f32+f16",
                  "f64": "f64"}.get(args.prec, args.prec),
@@ -550,8 +557,10 @@ def run_config4(args):
                  "prec": args.prec},
                 {"sum_k": int(sum(ks)), "ids_per_s": len(mats) / (ms * 1e-3),
                  "loop_of_single_ids_ms": loop_ms, "speedup_vs_loop": loop_ms / ms,
+                 "persistent_launch_ms": pers_ms,
+                 "persistent_same_k_items": same_k,
                  "autotune": {k_: v for k_, v in tune.items() if k_ != "table"},
-                 "roofline": {"kernel": "k_batched_factor (whole launch)", "bound": "hbm",
+                 "roofline": {"kernel": "lock-step batch (whole call)", "bound": "hbm",
                               "achieved": sweep_bytes / (ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
                               "unit": "GB/s", "frac": sweep_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
                               "traffic": None,

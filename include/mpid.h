@@ -329,6 +329,39 @@ int id_factor_batched(id_batch_item* items, int32_t batch, const int32_t* slots,
                       int32_t* queue, int64_t max_n, int32_t dtype, const id_opts* opts,
                       int32_t block_threads, int32_t num_groups, void* stream);
 
+/* ---- lock-step batches ----------------------------------------------------
+ * Many column IDs (the factorization of Algorithms 1 and 2 plus
+ * T = R11^{-1} R12, per item) advanced together: every launch runs one kernel
+ * of a pivot step (the sweep over the trailing block, the step's finalization)
+ * or of a panel end (the blocked update, the column norms) for all unfinished
+ * items at once, so each launch streams the trailing blocks of the whole batch
+ * and the per-step latencies are shared.  Every item is computed exactly as
+ * by id_factor with the same options (the same kernels on its own workspace;
+ * only the sweep's tile shapes may differ, which changes rounding order).
+ * The host reads every item's state after each panel, so the call
+ * synchronizes the stream and cannot be captured in a graph (id_factor_batched
+ * can).
+ *
+ *   items       [in/out] HOST array of "batch" descriptors.  In: A, m, n, lda,
+ *               work (device, id_workspace_size(m, n, dtype, opts) bytes, the
+ *               same workspace id_factor uses), perm, R, ldr, T, ldt (device
+ *               outputs as in id_factor_batched; T untouched when info != 0).
+ *               Out: k and info (ID_INFO_NONFINITE, ID_INFO_SINGULAR,
+ *               ID_INFO_RANK_FULL or 0, as id_factor then id_solve_T report).
+ *               "groups" is ignored.
+ *   dtype, opts as in id_factor (ID_FLAG_GRAM and ID_FLAG_PROFILE refused:
+ *               ID_ERR_UNSUPPORTED).
+ *   work        shared device workspace of id_lockstep_workspace_size bytes
+ *               (item tables and block maps).
+ * Returns ID_ERR_ARG / ID_ERR_WORKSPACE / ID_ERR_DTYPE for invalid arguments,
+ * ID_ERR_UNSUPPORTED for an item with more than 49152 rows (one finalization
+ * round trip covers 192 row tiles of at most 256 rows), ID_ERR_HIP on a HIP
+ * failure.  Calls that share "work" or an item's workspace must not overlap. */
+size_t id_lockstep_workspace_size(const id_batch_item* items, int32_t batch, int32_t dtype,
+                                  const id_opts* opts);
+int id_factor_lockstep(id_batch_item* items, int32_t batch, int32_t dtype, const id_opts* opts,
+                       void* work, size_t work_bytes, void* stream);
+
 /* Per-kernel timing of the calling thread's last id_factor call made with
  * ID_FLAG_PROFILE (instrumentation, not part of the method).  Times come from
  * HIP events recorded around each launch on the call's stream; "bytes" are the

@@ -29,4 +29,11 @@ from .api import (  # noqa: F401
     workspace_size,
 )
 from ._lib import C, MpidError, load  # noqa: F401
-from .batched import BatchedID, BatchItemResult, autotune, factor_batched  # noqa: F401
+from .batched import (  # noqa: F401
+    BatchedID,
+    BatchItemResult,
+    LockstepID,
+    autotune,
+    factor_batched,
+    factor_lockstep,
+)

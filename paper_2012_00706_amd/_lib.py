@@ -99,6 +99,8 @@ SIGNATURES = {
     "id_batch_item_workspace_size": (_sz, [_i64, _i64, _P(IdOpts)]),
     "id_factor_batched": (ctypes.c_int, [_vp, _i32, _vp, _i32, _vp, _i64, _i32, _P(IdOpts), _i32,
                                          _i32, _vp]),
+    "id_lockstep_workspace_size": (_sz, [_P(IdBatchItem), _i32, _i32, _P(IdOpts)]),
+    "id_factor_lockstep": (ctypes.c_int, [_P(IdBatchItem), _i32, _i32, _P(IdOpts), _vp, _sz, _vp]),
     "id_last_profile": (ctypes.c_int, [_P(IdProfile)]),
     "id_status_string": (ctypes.c_char_p, [ctypes.c_int]),
 }

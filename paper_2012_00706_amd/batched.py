@@ -1,4 +1,5 @@
-"""Many column IDs of uneven sizes in one persistent launch (id_factor_batched).
+"""Many column IDs of uneven sizes: one persistent launch (id_factor_batched), or
+all items advanced in lock step (id_factor_lockstep).
 
 A :class:`BatchedID` plan binds a list of device matrices, owns every
 workspace and output buffer, and launches the batched factorization plus the
@@ -18,7 +19,7 @@ from dataclasses import dataclass
 import torch
 
 from . import _lib
-from .api import DTYPE, _stream, colmajor, kcap_of, make_opts
+from .api import DTYPE, _stream, colmajor, kcap_of, make_opts, round_
 
 C = _lib.C
 _ALIGN = 256
@@ -31,6 +32,68 @@ def _round_up(x: int, a: int) -> int:
 def _colmajor_view(buf: torch.Tensor, off: int, rows: int, cols: int, ld: int) -> torch.Tensor:
     """rows x cols column-major view (leading dimension ld) of buf[off:]."""
     return buf[off:off + ld * cols].view(cols, ld).t()[:rows]
+
+
+def _bind_items(inputs, ldas, shapes, ws, kcs, dev):
+    """Workspaces and output buffers of a batch, and its host descriptors."""
+    w_off, r_off, p_off = [], [], []
+    tw = tr = tp = 0
+    for (m, n), w, kc in zip(shapes, ws, kcs):
+        w_off.append(tw)
+        tw += _round_up(w, _ALIGN)
+        r_off.append(tr)
+        tr += _round_up(max(kc, 1) * max(n, 1), 32)
+        p_off.append(tp)
+        tp += _round_up(max(n, 1), 64)
+    bufs = {"work": torch.empty(tw + _ALIGN, dtype=torch.uint8, device=dev),
+            "R": torch.zeros(tr, dtype=torch.float64, device=dev),
+            "T": torch.zeros(tr, dtype=torch.float64, device=dev),
+            "perm": torch.zeros(tp, dtype=torch.int32, device=dev)}
+    wbase = _round_up(bufs["work"].data_ptr(), _ALIGN) - bufs["work"].data_ptr()
+    items = (_lib.IdBatchItem * len(shapes))()
+    for i, ((m, n), kc) in enumerate(zip(shapes, kcs)):
+        it = items[i]
+        it.A = inputs[i].data_ptr()
+        it.m, it.n, it.lda = m, n, ldas[i]
+        it.work = bufs["work"].data_ptr() + wbase + w_off[i]
+        it.perm = bufs["perm"].data_ptr() + 4 * p_off[i]
+        it.R = bufs["R"].data_ptr() + 8 * r_off[i]
+        it.ldr = max(kc, 1)
+        it.T = bufs["T"].data_ptr() + 8 * r_off[i]
+        it.ldt = max(kc, 1)
+    return items, bufs, r_off, p_off
+
+
+def _item_results(items, shapes, kcaps, bufs, r_off, p_off):
+    out = []
+    for i, (m, n) in enumerate(shapes):
+        k, info = int(items[i].k), int(items[i].info)
+        ld = max(kcaps[i], 1)
+        perm = bufs["perm"][p_off[i]:p_off[i] + n]
+        R = _colmajor_view(bufs["R"], r_off[i], k, n, ld)
+        solved = info in (0, C["ID_INFO_RANK_FULL"])
+        T = _colmajor_view(bufs["T"], r_off[i], k if solved else 0, n - k if solved else 0, ld)
+        out.append(BatchItemResult(perm, k, R, T, info))
+    return out
+
+
+def _bind_inputs(As):
+    """(dtype, device, column-major inputs, their leading dimensions)."""
+    if len(As) == 0:
+        raise ValueError("empty batch")
+    dtypes = {A.dtype for A in As}
+    devices = {A.device for A in As}
+    if len(dtypes) != 1 or len(devices) != 1:
+        raise ValueError("all matrices must share dtype and device")
+    dtype = dtypes.pop()
+    if dtype not in DTYPE:
+        raise TypeError("matrices must be float32 or float64")
+    inputs, ldas = [], []
+    for A in As:
+        Ac, lda = colmajor(A)
+        inputs.append(Ac)
+        ldas.append(lda)
+    return dtype, devices.pop(), inputs, ldas
 
 
 @dataclass
@@ -56,27 +119,13 @@ class BatchedID:
 
     def __init__(self, As, k=None, tol=None, prec="f64", rule="pivot_rel", k_max=0, nb=0,
                  block_threads=0, num_groups=0, order="lpt", groups="auto"):
-        if len(As) == 0:
-            raise ValueError("empty batch")
-        dtypes = {A.dtype for A in As}
-        devices = {A.device for A in As}
-        if len(dtypes) != 1 or len(devices) != 1:
-            raise ValueError("all matrices must share dtype and device")
         if k is not None and int(k) <= 0:
             raise ValueError("fixed rank must be >= 1")
-        self.dtype = dtypes.pop()
-        self.device = devices.pop()
-        if self.dtype not in DTYPE:
-            raise TypeError("matrices must be float32 or float64")
+        self.dtype, self.device, self.inputs, ldas = _bind_inputs(As)
         self.opts = make_opts(k, tol, prec, rule, k_max, nb)
         self.block_threads = int(block_threads)
         self.num_groups = int(num_groups)
         lib = _lib.load()
-        self.inputs, ldas = [], []
-        for A in As:
-            Ac, lda = colmajor(A)
-            self.inputs.append(Ac)
-            ldas.append(lda)
         shapes = [tuple(A.shape) for A in self.inputs]
         self.shapes = shapes
         self.batch = len(shapes)
@@ -89,37 +138,14 @@ class BatchedID:
             ws.append(w)
             kcs.append(kcap_of(m, n, self.opts))
         self.kcaps = kcs
-        dev = self.device
-        w_off, r_off, p_off = [], [], []
-        tw = tr = tp = 0
-        for (m, n), w, kc in zip(shapes, ws, kcs):
-            w_off.append(tw)
-            tw += _round_up(w, _ALIGN)
-            r_off.append(tr)
-            tr += _round_up(max(kc, 1) * max(n, 1), 32)
-            p_off.append(tp)
-            tp += _round_up(max(n, 1), 64)
-        self.work = torch.empty(tw + _ALIGN, dtype=torch.uint8, device=dev)
-        wbase = _round_up(self.work.data_ptr(), _ALIGN) - self.work.data_ptr()
-        self.R_buf = torch.zeros(tr, dtype=torch.float64, device=dev)
-        self.T_buf = torch.zeros(tr, dtype=torch.float64, device=dev)
-        self.perm_buf = torch.zeros(tp, dtype=torch.int32, device=dev)
-        self._r_off, self._p_off = r_off, p_off
-        items = (_lib.IdBatchItem * self.batch)()
-        for i, ((m, n), kc) in enumerate(zip(shapes, kcs)):
-            it = items[i]
-            it.A = self.inputs[i].data_ptr()
-            it.m, it.n, it.lda = m, n, ldas[i]
-            it.work = self.work.data_ptr() + wbase + w_off[i]
-            it.perm = self.perm_buf.data_ptr() + 4 * p_off[i]
-            it.R = self.R_buf.data_ptr() + 8 * r_off[i]
-            it.ldr = max(kc, 1)
-            it.T = self.T_buf.data_ptr() + 8 * r_off[i]
-            it.ldt = max(kc, 1)
+        items, self._bufs, self._r_off, self._p_off = _bind_items(self.inputs, ldas, shapes, ws,
+                                                                  kcs, self.device)
+        self.work, self.R_buf = self._bufs["work"], self._bufs["R"]
+        self.T_buf, self.perm_buf = self._bufs["T"], self._bufs["perm"]
         self._items_host = items
         self._order = order
-        self.cus = torch.cuda.get_device_properties(dev).multi_processor_count
-        self.queue = torch.zeros(1, dtype=torch.int32, device=dev)
+        self.cus = torch.cuda.get_device_properties(self.device).multi_processor_count
+        self.queue = torch.zeros(1, dtype=torch.int32, device=self.device)
         self._plan_slots(groups, [None] * self.batch)
 
     @staticmethod
@@ -211,17 +237,74 @@ class BatchedID:
         torch.cuda.synchronize(self.device)
         raw = self.items.cpu().numpy().tobytes()
         items = (_lib.IdBatchItem * self.batch).from_buffer_copy(raw)
-        out = []
-        for i, (m, n) in enumerate(self.shapes):
-            k, info = int(items[i].k), int(items[i].info)
-            ld = max(self.kcaps[i], 1)
-            perm = self.perm_buf[self._p_off[i]:self._p_off[i] + n]
-            R = _colmajor_view(self.R_buf, self._r_off[i], k, n, ld)
-            solved = info in (0, C["ID_INFO_RANK_FULL"])
-            T = _colmajor_view(self.T_buf, self._r_off[i], k if solved else 0,
-                               n - k if solved else 0, ld)
-            out.append(BatchItemResult(perm, k, R, T, info))
-        return out
+        return _item_results(items, self.shapes, self.kcaps, self._bufs, self._r_off,
+                             self._p_off)
+
+
+class LockstepID:
+    """Plan for the column IDs of the matrices ``As`` advanced in lock step
+    (id_factor_lockstep): every launch runs one pivot step, or one panel end,
+    of all unfinished items, so each launch streams the whole batch's trailing
+    blocks.  Each item is the single-matrix algorithm with the same options
+    (``k`` or ``tol`` and ``rule``, ``prec``, ``nb``) on its own workspace.
+    ``run()`` synchronizes the stream (use :class:`BatchedID` for a launch
+    that can be captured in a graph).  ``round_to`` ("f32" / "f16") selects the
+    simulated single / half precision of id_factor."""
+
+    def __init__(self, As, k=None, tol=None, prec="f64", rule="pivot_rel", k_max=0, nb=0,
+                 round_to=None):
+        if k is not None and int(k) <= 0:
+            raise ValueError("fixed rank must be >= 1")
+        self.dtype, self.device, self.inputs, ldas = _bind_inputs(As)
+        self.opts = make_opts(k, tol, prec, rule, k_max, nb, round_to=round_to)
+        lib = _lib.load()
+        self.shapes = [tuple(A.shape) for A in self.inputs]
+        self.batch = len(self.shapes)
+        dt = DTYPE[self.dtype]
+        ws = []
+        for m, n in self.shapes:
+            w = int(lib.id_workspace_size(m, n, dt, ctypes.byref(self.opts)))
+            if w == 0:
+                raise ValueError(f"invalid item shape {m} x {n} or options")
+            ws.append(w)
+        self.kcaps = [kcap_of(m, n, self.opts) for m, n in self.shapes]
+        self._items, self._bufs, self._r_off, self._p_off = _bind_items(
+            self.inputs, ldas, self.shapes, ws, self.kcaps, self.device)
+        sb = int(lib.id_lockstep_workspace_size(self._items, self.batch, dt,
+                                                ctypes.byref(self.opts)))
+        if sb == 0:
+            raise ValueError("unsupported batch for the lock-step path (an item with more "
+                             "than 49152 rows, or invalid options)")
+        self.shared = torch.empty(sb, dtype=torch.uint8, device=self.device)
+        self.round_to = round_to
+
+    def run(self):
+        """Factor every item and solve for T (returns when done)."""
+        lib = _lib.load()
+        with torch.cuda.device(self.device):
+            rc = lib.id_factor_lockstep(self._items, self.batch, DTYPE[self.dtype],
+                                        ctypes.byref(self.opts), self.shared.data_ptr(),
+                                        self.shared.numel(), _stream(self.device))
+        _lib.check(rc, "id_factor_lockstep")
+        if self.round_to is not None:
+            # the simulated low-precision ID keeps T rounded too (as column_id)
+            for r in self.results():
+                if r.T.numel():
+                    round_(r.T, self.round_to)
+
+    def results(self):
+        """Per-item results of the last run()."""
+        return _item_results(self._items, self.shapes, self.kcaps, self._bufs, self._r_off,
+                             self._p_off)
+
+
+def factor_lockstep(As, k=None, tol=None, prec="f64", rule="pivot_rel", k_max=0, nb=0,
+                    round_to=None):
+    """Column IDs of every matrix in As advanced in lock step; list of BatchItemResult."""
+    plan = LockstepID(As, k=k, tol=tol, prec=prec, rule=rule, k_max=k_max, nb=nb,
+                      round_to=round_to)
+    plan.run()
+    return plan.results()
 
 
 def factor_batched(As, k=None, tol=None, prec="f64", rule="pivot_rel", k_max=0, nb=0,

@@ -102,6 +102,16 @@ int id_factor_batched(id_batch_item* items, int32_t batch, const int32_t* slots,
                                   block_threads, num_groups, (hipStream_t)stream);
 }
 
+size_t id_lockstep_workspace_size(const id_batch_item* items, int32_t batch, int32_t dtype,
+                                  const id_opts* opts) {
+  return mpid::lockstep_workspace(items, batch, dtype, opts);
+}
+
+int id_factor_lockstep(id_batch_item* items, int32_t batch, int32_t dtype, const id_opts* opts,
+                       void* work, size_t work_bytes, void* stream) {
+  return mpid::lockstep_run(items, batch, dtype, opts, work, work_bytes, (hipStream_t)stream);
+}
+
 int id_last_profile(id_profile* out) {
   if (!out) return ID_ERR_ARG;
   mpid::last_profile(out);

@@ -84,6 +84,9 @@ constexpr int kFinZ = (192 + kFL - 1) / kFL;  // column partials per lane and ro
 constexpr int kFinA = 24;     // reflector-product partials per thread and round trip
 constexpr int kFold = 32;     // row tiles summed per folded partial (tall inputs)
 constexpr int kSweepU = 4;    // sweep rows per thread in flight in the main loop
+// the same where the step's trailing block is far larger than the caches (the
+// loop is bound by bytes in flight over memory latency, which is longer there)
+constexpr int kSweepUDeep = 8;
 // main-loop rows per thread loaded with the second round trip: 8 where the
 // registers allow it without lowering occupancy (fp32, row tiles <= 128)
 template <typename S, int G>
@@ -176,12 +179,20 @@ bool make_factor_plan(int64_t m, int64_t n, int32_t dtype, const id_opts* o, Fac
 
 // zrow[0..2] / frow[0..2]: the zero rows of the per-tile and the folded
 // partials (ldf, kNbMax and 1 entries).
-__global__ __launch_bounds__(kThreads) void k_init(FactorState* st, int* colid0, int* pvflag,
-                                                   int* permw, int* posof, int64_t n,
-                                                   int64_t ldf, double* zrow_z, double* zrow_a,
-                                                   double* zrow_n, double* frow_z,
-                                                   double* frow_a, double* frow_n) {
-  const int64_t l = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+struct InitArgs {
+  FactorState* st;
+  int *colid0, *pvflag, *permw, *posof;
+  int64_t n, ldf;
+  double *zrow_z, *zrow_a, *zrow_n, *frow_z, *frow_a, *frow_n;
+};
+
+__device__ __forceinline__ void init_block(const InitArgs& a, const int64_t bx) {
+  FactorState* st = a.st;
+  int *colid0 = a.colid0, *pvflag = a.pvflag, *permw = a.permw, *posof = a.posof;
+  const int64_t n = a.n, ldf = a.ldf;
+  double *zrow_z = a.zrow_z, *zrow_a = a.zrow_a, *zrow_n = a.zrow_n;
+  double *frow_z = a.frow_z, *frow_a = a.frow_a, *frow_n = a.frow_n;
+  const int64_t l = bx * kThreads + threadIdx.x;
   if (l < ldf) {
     colid0[l] = (int)l;
     pvflag[l] = 0;
@@ -219,19 +230,35 @@ __global__ __launch_bounds__(kThreads) void k_init(FactorState* st, int* colid0,
   }
 }
 
+__global__ __launch_bounds__(kThreads) void k_init(InitArgs a) { init_block(a, blockIdx.x); }
+
 // A (column-major, lda) -> W (row-major, ldw) in the working precision, with
 // the per-row-tile partial sums of squares of every column (FP64) and a
 // NaN/Inf check.  Block: 64 columns x kRowTileG rows, LDS transpose.
 template <typename TA, typename S>
-__global__ __launch_bounds__(kThreads) void k_ingest(const TA* __restrict__ A, int64_t lda,
-                                                     int64_t m, int64_t n, S* __restrict__ W,
-                                                     int64_t ldw, double* __restrict__ colpart,
-                                                     int64_t ldf, FactorState* st, int rmode) {
+struct IngestArgs {
+  const TA* A;
+  int64_t lda, m, n;
+  S* W;
+  int64_t ldw;
+  double* colpart;
+  int64_t ldf;
+  FactorState* st;
+  int rmode;
+};
+
+template <typename TA, typename S>
+__device__ __forceinline__ void ingest_block(const IngestArgs<TA, S>& ia, const int64_t bx,
+                                             const int64_t tg) {
+  const TA* __restrict__ A = ia.A;
+  S* __restrict__ W = ia.W;
+  double* __restrict__ colpart = ia.colpart;
+  const int64_t lda = ia.lda, m = ia.m, n = ia.n, ldw = ia.ldw, ldf = ia.ldf;
+  const int rmode = ia.rmode;
   __shared__ S tile[64][65];
   __shared__ double ssq[4][64];
   const int tid = threadIdx.x;
-  const int64_t c0 = (int64_t)blockIdx.x * 64;
-  const int64_t tg = blockIdx.y;
+  const int64_t c0 = bx * 64;
   const int64_t rb = tg * kRowTileG;
   const int64_t re = rb + kRowTileG < m ? rb + kRowTileG : m;
   double ss = 0.0;
@@ -273,7 +300,12 @@ __global__ __launch_bounds__(kThreads) void k_ingest(const TA* __restrict__ A, i
     const int64_t c = c0 + tid;
     if (c < n) colpart[tg * ldf + c] = ssq[0][tid] + ssq[1][tid] + ssq[2][tid] + ssq[3][tid];
   }
-  if (bad) st->info = ID_INFO_NONFINITE;
+  if (bad) ia.st->info = ID_INFO_NONFINITE;
+}
+
+template <typename TA, typename S>
+__global__ __launch_bounds__(kThreads) void k_ingest(IngestArgs<TA, S> a) {
+  ingest_block<TA, S>(a, blockIdx.x, blockIdx.y);
 }
 
 // One block of the column-norm reduction (see k_colreduce).
@@ -282,10 +314,10 @@ __device__ __forceinline__ void colreduce_block(
     int subtract_jb, double* __restrict__ nu, double* __restrict__ nuo, AmaxPart* __restrict__ amax,
     const int* __restrict__ colid, const int* __restrict__ posof, int* __restrict__ pvflag,
     int* __restrict__ keypos, FactorState* st, double rel_tol, int rmode,
-    double (*red)[kFinCols + 1], AmaxVal* ascr) {
+    double (*red)[kFinCols + 1], AmaxVal* ascr, const int bid) {
   const int tid = threadIdx.x, cl = tid % kFinCols, tl = tid / kFinCols;
   const int64_t ncols = subtract_jb ? st->ncur - st->jb : ncols_base;
-  const int64_t l = (int64_t)blockIdx.x * kFinCols + cl;
+  const int64_t l = (int64_t)bid * kFinCols + cl;
   red[tl][cl] = l < ncols ? strided_sum(colpart + l, ldf, tg0 + tl, tg1, 8) : 0.0;
   __syncthreads();
   AmaxVal cand = amax_none();
@@ -314,7 +346,7 @@ __device__ __forceinline__ void colreduce_block(
     o.s2 = cand.s2;
     o.pos = cand.pos;
     o.key = cand.key;
-    amax[blockIdx.x] = o;
+    amax[bid] = o;
     // the host's view of how close the rank rule is (norms are >= 0)
     if (cand.v > 0.0) atomicMax(&st->vmax_bits, __float_as_uint((float)cand.v));
   }
@@ -329,25 +361,38 @@ __device__ __forceinline__ void colreduce_block(
 // At a panel's end (hs != nullptr) the last block to finish also advances the
 // state to the next panel and publishes it to the host slot hs with tag seq.
 // Block: 32 columns x 8 tile lanes.
-__global__ __launch_bounds__(kThreads) void k_colreduce(
-    const double* __restrict__ colpart, int64_t ldf, int64_t tg0, int64_t tg1, int64_t ncols_base,
-    int subtract_jb, double* __restrict__ nu, double* __restrict__ nuo, AmaxPart* __restrict__ amax,
-    const int* __restrict__ colid, const int* __restrict__ posof, int* __restrict__ pvflag,
-    int* __restrict__ keypos, FactorState* st, double rel_tol, int rmode, FactorHostSlot* hs,
-    int64_t seq) {
+struct ColArgs {
+  const double* colpart;
+  int64_t ldf, tg0, tg1, ncols_base;
+  int subtract_jb;
+  double *nu, *nuo;
+  AmaxPart* amax;
+  const int *colid, *posof;
+  int *pvflag, *keypos;
+  FactorState* st;
+  double rel_tol;
+  int rmode;
+  FactorHostSlot* hs;
+  int64_t seq;
+};
+
+__device__ __forceinline__ void colreduce_body(const ColArgs& c, const int bid, const int nblk) {
   __shared__ double red[8][kFinCols + 1];
   __shared__ AmaxVal ascr[4];
   __shared__ int s_go, s_last;
+  FactorState* st = c.st;
+  FactorHostSlot* hs = c.hs;
   const int tid = threadIdx.x;
   if (tid == 0) s_go = (st->done == 0);
   __syncthreads();
   if (s_go)
-    colreduce_block(colpart, ldf, tg0, tg1, ncols_base, subtract_jb, nu, nuo, amax, colid, posof,
-                    pvflag, keypos, st, rel_tol, rmode, red, ascr);
+    colreduce_block(c.colpart, c.ldf, c.tg0, c.tg1, c.ncols_base, c.subtract_jb, c.nu, c.nuo,
+                    c.amax, c.colid, c.posof, c.pvflag, c.keypos, st, c.rel_tol, c.rmode, red,
+                    ascr, bid);
   if (hs == nullptr) return;
   if (tid == 0) {
     __threadfence();  // this block's counts before its arrival
-    s_last = atomicAdd(&st->nred, 1u) == gridDim.x - 1;
+    s_last = atomicAdd(&st->nred, 1u) == (uint32_t)nblk - 1u;
   }
   __syncthreads();
   if (s_last && tid == 0) {
@@ -366,8 +411,12 @@ __global__ __launch_bounds__(kThreads) void k_colreduce(
     }
     hs->s = *st;
     __threadfence_system();  // the state before its tag
-    __hip_atomic_store(&hs->seq, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+    __hip_atomic_store(&hs->seq, c.seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
   }
+}
+
+__global__ __launch_bounds__(kThreads) void k_colreduce(ColArgs c) {
+  colreduce_body(c, blockIdx.x, gridDim.x);
 }
 
 template <typename S>
@@ -427,7 +476,7 @@ struct StepArgs {
 // Everything that does not depend on the pivot -- flags, pivot partials, the
 // reflector entries of the tile and the first rows of the sweep -- is loaded
 // in one round trip before the pivot is known.
-template <typename S, int G>
+template <typename S, int G, int U = kSweepU>
 __device__ __forceinline__ void sweep_block(const StepArgs<S>& a, const int bid, const int nblk) {
   typedef typename Vec16<S>::type VT;
   constexpr int VEC = Vec16<S>::n;
@@ -482,12 +531,16 @@ __device__ __forceinline__ void sweep_block(const StepArgs<S>& a, const int bid,
   const int rsub = tid / G, gi = tid % G;
   const int64_t iw = r0 + rsub;
   // (masked after the pivot search: a select next to its load is turned
-  // back into a conditional load)
+  // back into a conditional load; reflectors the panel has not generated yet
+  // are read from reflector 0's cached line instead of from memory)
   S vr[SLOTS];
   {
     const int64_t iwc = iw < a.m ? iw : a.m - 1;
 #pragma unroll
-    for (int q = 0; q < SLOTS; ++q) vr[q] = a.V[(int64_t)(gi + G * q) * a.ldv + iwc];
+    for (int q = 0; q < SLOTS; ++q) {
+      const int c = gi + G * q;
+      vr[q] = a.V[(int64_t)(c < jj ? c : 0) * a.ldv + iwc];
+    }
   }
   // the step state, after the vector loads are on their way
   if (tid == 0) {
@@ -680,14 +733,14 @@ __device__ __forceinline__ void sweep_block(const StepArgs<S>& a, const int bid,
       }
     }
     int64_t i = i1 + (int64_t)kOverlap * RG;
-    // kSweepU independent row loads in flight per thread: the loop is bound
-    // by memory latency times the number of its iterations
-    for (; i + (kSweepU - 1) * RG < r1; i += kSweepU * RG) {
-      VT x[kSweepU];
+    // U independent row loads in flight per thread: the loop is bound by
+    // memory latency times the number of its iterations
+    for (; i + (U - 1) * RG < r1; i += U * RG) {
+      VT x[U];
 #pragma unroll
-      for (int u = 0; u < kSweepU; ++u) x[u] = *(const VT*)(base + (i + u * RG) * a.ldw);
+      for (int u = 0; u < U; ++u) x[u] = *(const VT*)(base + (i + u * RG) * a.ldw);
 #pragma unroll
-      for (int u = 0; u < kSweepU; ++u) {
+      for (int u = 0; u < U; ++u) {
         const double wu = wsh[i + u * RG - r0];
 #pragma unroll
         for (int e = 0; e < VEC; ++e) acc[e] += (double)x[u][e] * wu;
@@ -1028,7 +1081,8 @@ struct GemmArgs {
 // the MFMA rows) and park it in LDS, then each thread writes its column of the
 // refreshed tile to the compacted position.
 template <typename S, int OP, int RM>
-__global__ __launch_bounds__(kThreads) void k_panel_gemm(GemmArgs<S> a) {
+__device__ __forceinline__ void panel_gemm_block(const GemmArgs<S>& a, const uint32_t bid,
+                                                 const uint32_t nblk) {
   typedef typename std::conditional<OP == OP_F64, double, float>::type AccT;
   __shared__ int spiv[kNbMax];
   __shared__ double svs[kNbMax];
@@ -1056,8 +1110,8 @@ __global__ __launch_bounds__(kThreads) void k_panel_gemm(GemmArgs<S> a) {
   // indices are uniform and kept in scalar registers (the division is
   // expanded into vector instructions, which would move everything derived
   // from them into vector registers).
-  const uint32_t per = gridDim.x / 8u;
-  const uint32_t vb = (blockIdx.x % 8u) * per + blockIdx.x / 8u;
+  const uint32_t per = nblk / 8u;
+  const uint32_t vb = (bid % 8u) * per + bid / 8u;
   if (vb >= (uint32_t)(a.gx * a.gy)) return;
   const int64_t bx = __builtin_amdgcn_readfirstlane((int)(vb % (uint32_t)a.gx));
   const int64_t by = __builtin_amdgcn_readfirstlane((int)(vb / (uint32_t)a.gx));
@@ -1302,19 +1356,33 @@ __global__ __launch_bounds__(kThreads) void k_panel_gemm(GemmArgs<S> a) {
   }
 }
 
+template <typename S, int OP, int RM>
+__global__ __launch_bounds__(kThreads) void k_panel_gemm(GemmArgs<S> a) {
+  panel_gemm_block<S, OP, RM>(a, blockIdx.x, gridDim.x);
+}
+
 // perm (swap order) and R gathered into pivot order: R(i, c) = Rorig(i, perm[c])
 // for i < k, zero below the diagonal of the first k columns.
-__global__ __launch_bounds__(kThreads) void k_finish(const int* __restrict__ permw,
-                                                     int32_t* __restrict__ perm_out,
-                                                     const double* __restrict__ rorig,
-                                                     int64_t kcap, int64_t n, int64_t k,
-                                                     double* __restrict__ R, int64_t ldr) {
-  const int64_t c = blockIdx.x;
-  const int64_t i = (int64_t)blockIdx.y * kThreads + threadIdx.x;
-  if (c >= n) return;
-  const int id = permw[c];
-  if (blockIdx.y == 0 && threadIdx.x == 0) perm_out[c] = id;
-  if (i < k) R[c * ldr + i] = (c >= k || i <= c) ? rorig[(int64_t)id * kcap + i] : 0.0;
+struct FinishArgs {
+  const int* permw;
+  int32_t* perm_out;
+  const double* rorig;
+  int64_t kcap, n, k;
+  double* R;
+  int64_t ldr;
+};
+
+__device__ __forceinline__ void finish_block(const FinishArgs& a, const int64_t c,
+                                             const int64_t by) {
+  const int64_t i = by * kThreads + threadIdx.x;
+  if (c >= a.n) return;
+  const int id = a.permw[c];
+  if (by == 0 && threadIdx.x == 0) a.perm_out[c] = id;
+  if (i < a.k) a.R[c * a.ldr + i] = (c >= a.k || i <= c) ? a.rorig[(int64_t)id * a.kcap + i] : 0.0;
+}
+
+__global__ __launch_bounds__(kThreads) void k_finish(FinishArgs a) {
+  finish_block(a, blockIdx.x, blockIdx.y);
 }
 
 __global__ void k_iota(int32_t* perm, int64_t n) {
@@ -1329,6 +1397,165 @@ static int env_int(const char* name, int dflt) {
   if (!s || !*s) return dflt;
   return std::atoi(s);
 }
+
+// ---- argument blocks of one factorization's kernels, from its plan and
+// workspace (shared by the single-matrix driver and the lock-step batches)
+
+static InitArgs make_init_args(const FactorPlan& pl, char* wb) {
+  InitArgs a;
+  a.st = (FactorState*)(wb + pl.off_state);
+  a.colid0 = (int*)(wb + pl.off_colid0);
+  a.pvflag = (int*)(wb + pl.off_pvflag);
+  a.permw = (int*)(wb + pl.off_permw);
+  a.posof = (int*)(wb + pl.off_posof);
+  a.n = pl.n;
+  a.ldf = pl.ldf;
+  a.zrow_z = (double*)(wb + pl.off_zpart) + pl.ntile_s_max * pl.ldf;
+  a.zrow_a = (double*)(wb + pl.off_auxpart) + pl.ntile_s_max * kNbMax;
+  a.zrow_n = (double*)(wb + pl.off_nrm2part) + pl.ntile_s_max;
+  a.frow_z = (double*)(wb + pl.off_zfold) + pl.nfold_max * pl.ldf;
+  a.frow_a = (double*)(wb + pl.off_afold) + pl.nfold_max * kNbMax;
+  a.frow_n = (double*)(wb + pl.off_nfold) + pl.nfold_max;
+  return a;
+}
+static int64_t init_blocks(const FactorPlan& pl) {
+  return ceil_div(pl.ldf > pl.n ? pl.ldf : pl.n, kThreads);
+}
+
+template <typename TA, typename S>
+static IngestArgs<TA, S> make_ingest_args(const FactorPlan& pl, char* wb, const TA* A, int64_t lda,
+                                          int rmode) {
+  IngestArgs<TA, S> a;
+  a.A = A;
+  a.lda = lda;
+  a.m = pl.m;
+  a.n = pl.n;
+  a.W = (S*)(wb + pl.off_w0);
+  a.ldw = pl.ldw;
+  a.colpart = (double*)(wb + pl.off_colpart);
+  a.ldf = pl.ldf;
+  a.st = (FactorState*)(wb + pl.off_state);
+  a.rmode = rmode;
+  return a;
+}
+
+// The norm reduction after the ingest (buf 0, all n columns) or at the end of
+// a panel that wrote buffer buf (row tile groups from tg0, at most ncols_ub
+// live columns, the count of columns above rel_tol |R_00| when rel_tol >= 0,
+// the state published to hs with tag seq).
+static ColArgs make_col_args(const FactorPlan& pl, char* wb, int buf, int64_t tg0,
+                             int64_t ncols_ub, int subtract_jb, double rel_tol, int rmode,
+                             FactorHostSlot* hs, int64_t seq) {
+  ColArgs c;
+  c.colpart = (double*)(wb + pl.off_colpart);
+  c.ldf = pl.ldf;
+  c.tg0 = tg0;
+  c.tg1 = ceil_div(pl.m, kRowTileG);
+  c.ncols_base = ncols_ub;
+  c.subtract_jb = subtract_jb;
+  c.nu = (double*)(wb + pl.off_nu);
+  c.nuo = (double*)(wb + pl.off_nuo);
+  c.amax = (AmaxPart*)(wb + pl.off_amax);
+  c.colid = (int*)(wb + (buf ? pl.off_colid1 : pl.off_colid0));
+  c.posof = (int*)(wb + pl.off_posof);
+  c.pvflag = (int*)(wb + pl.off_pvflag);
+  c.keypos = (int*)(wb + pl.off_keypos);
+  c.st = (FactorState*)(wb + pl.off_state);
+  c.rel_tol = rel_tol;
+  c.rmode = rmode;
+  c.hs = hs;
+  c.seq = seq;
+  return c;
+}
+
+// The fields of a pivot step's arguments that stay fixed over the call.
+template <typename S>
+static StepArgs<S> make_step_args(const FactorPlan& pl, char* wb, const id_opts* o, int rmode,
+                                  int want_fmax) {
+  StepArgs<S> a;
+  std::memset(&a, 0, sizeof(a));
+  a.ldw = pl.ldw;
+  a.m = pl.m;
+  a.n = pl.n;
+  a.V = (S*)(wb + pl.off_v);
+  a.ldv = pl.ldv;
+  a.F = (double*)(wb + pl.off_f);
+  a.ldf = pl.ldf;
+  a.vscale = (double*)(wb + pl.off_vscale);
+  a.tau = (double*)(wb + pl.off_tau);
+  a.st = (FactorState*)(wb + pl.off_state);
+  a.amax = (AmaxPart*)(wb + pl.off_amax);
+  a.pvflag = (int*)(wb + pl.off_pvflag);
+  a.pivpos = (int*)(wb + pl.off_pivpos);
+  a.pivid = (int*)(wb + pl.off_pivid);
+  a.permw = (int*)(wb + pl.off_permw);
+  a.posof = (int*)(wb + pl.off_posof);
+  a.zpart = (double*)(wb + pl.off_zpart);
+  a.auxpart = (double*)(wb + pl.off_auxpart);
+  a.nrm2part = (double*)(wb + pl.off_nrm2part);
+  a.nu = (double*)(wb + pl.off_nu);
+  a.nuo = (double*)(wb + pl.off_nuo);
+  a.rorig = (double*)(wb + pl.off_rorig);
+  a.wrow = (double*)(wb + pl.off_wrow);
+  a.vrow = (double*)(wb + pl.off_vrow);
+  a.keypos = (int*)(wb + pl.off_keypos);
+  a.tguard = pl.ntile_s_max;
+  a.kcap = pl.kcap;
+  a.k_fixed = o->k_fixed;
+  a.rel_tol = o->rel_tol;
+  a.tol3z = std::sqrt(pl.wbytes == 8 ? std::ldexp(1.0, -53) : std::ldexp(1.0, -24));
+  a.rule = o->rank_rule;
+  a.nopivot = (o->flags & ID_FLAG_NO_PIVOT) ? 1 : 0;
+  a.nb = pl.nb;
+  a.want_fmax = want_fmax;
+  a.rmode = rmode;
+  return a;
+}
+
+// The panel update of buffer cur into cur ^ 1, grid sized from the offset
+// lower bound off_lb.
+template <typename S>
+static GemmArgs<S> make_gemm_args(const FactorPlan& pl, char* wb, int cur, int64_t off_lb) {
+  GemmArgs<S> g;
+  S* W[2] = {(S*)(wb + pl.off_w0), (S*)(wb + pl.off_w1)};
+  int* colid[2] = {(int*)(wb + pl.off_colid0), (int*)(wb + pl.off_colid1)};
+  const int64_t ncur_ub = pl.n - off_lb;
+  g.W = W[cur];
+  g.Wn = W[cur ^ 1];
+  g.ldw = pl.ldw;
+  g.m = pl.m;
+  g.ncur = ncur_ub;
+  g.V = (S*)(wb + pl.off_v);
+  g.ldv = pl.ldv;
+  g.F = (double*)(wb + pl.off_f);
+  g.ldf = pl.ldf;
+  g.vscale = (double*)(wb + pl.off_vscale);
+  g.st = (FactorState*)(wb + pl.off_state);
+  g.pivpos = (int*)(wb + pl.off_pivpos);
+  g.colid = colid[cur];
+  g.colid_n = colid[cur ^ 1];
+  g.colpart = (double*)(wb + pl.off_colpart);
+  g.off = off_lb;
+  g.tg0 = off_lb / kRowTileG;
+  g.gx = ceil_div(ncur_ub, 64);
+  g.gy = ceil_div(pl.m, kRowTileG) - g.tg0;
+  return g;
+}
+
+static FinishArgs make_finish_args(const FactorPlan& pl, char* wb, int32_t* perm, double* R,
+                                   int64_t ldr, int64_t k) {
+  FinishArgs f;
+  f.permw = (int*)(wb + pl.off_permw);
+  f.perm_out = perm;
+  f.rorig = (double*)(wb + pl.off_rorig);
+  f.kcap = pl.kcap;
+  f.n = pl.n;
+  f.k = k;
+  f.R = R;
+  f.ldr = ldr;
+  return f;
+}
+
 
 struct SweepShape {
   int Rt, CW;
@@ -1431,34 +1658,10 @@ static int factor_impl(const TA* A, int64_t lda, const FactorPlan& pl, const id_
                        int32_t* info, bool noalloc, hipStream_t s) {
   const int64_t m = pl.m, n = pl.n, kcap = pl.kcap;
   S* W[2] = {(S*)(wb + pl.off_w0), (S*)(wb + pl.off_w1)};
-  S* V = (S*)(wb + pl.off_v);
-  double* F = (double*)(wb + pl.off_f);
-  double* zpart = (double*)(wb + pl.off_zpart);
-  double* auxpart = (double*)(wb + pl.off_auxpart);
-  double* nrm2part = (double*)(wb + pl.off_nrm2part);
   double* zfold = (double*)(wb + pl.off_zfold);
   double* afold = (double*)(wb + pl.off_afold);
   double* nfoldb = (double*)(wb + pl.off_nfold);
-  double* colpart = (double*)(wb + pl.off_colpart);
-  double* nu = (double*)(wb + pl.off_nu);
-  double* nuo = (double*)(wb + pl.off_nuo);
-  AmaxPart* amax = (AmaxPart*)(wb + pl.off_amax);
   int* colid[2] = {(int*)(wb + pl.off_colid0), (int*)(wb + pl.off_colid1)};
-  int* pvflag = (int*)(wb + pl.off_pvflag);
-  int* pivpos = (int*)(wb + pl.off_pivpos);
-  int* pivid = (int*)(wb + pl.off_pivid);
-  int* permw = (int*)(wb + pl.off_permw);
-  int* posof = (int*)(wb + pl.off_posof);
-  double* tau = (double*)(wb + pl.off_tau);
-  double* vscale = (double*)(wb + pl.off_vscale);
-  double* rorig = (double*)(wb + pl.off_rorig);
-  double* wrow = (double*)(wb + pl.off_wrow);
-  double* vrow = (double*)(wb + pl.off_vrow);
-  int* keypos = (int*)(wb + pl.off_keypos);
-  FactorState* st = (FactorState*)(wb + pl.off_state);
-
-
-  const int64_t ldw = pl.ldw, ldf = pl.ldf;
   const int64_t ntg = ceil_div(m, kRowTileG);
   static thread_local std::vector<hipEvent_t> ev_pool;
   Profiler prof;
@@ -1481,58 +1684,19 @@ static int factor_impl(const TA* A, int64_t lda, const FactorPlan& pl, const id_
            (long long)kcap, pl.nb, (long long)o->k_fixed, o->rel_tol, o->rank_rule, pl.bytes,
            noalloc ? " (static scratch)" : "");
   prof.begin(PK_OTHER, 0, s);
-  k_init<<<dim3((unsigned)ceil_div(ldf > n ? ldf : n, kThreads)), kThreads, 0, s>>>(
-      st, colid[0], pvflag, permw, posof, n, ldf, zpart + pl.ntile_s_max * ldf,
-      auxpart + pl.ntile_s_max * kNbMax, nrm2part + pl.ntile_s_max, zfold + pl.nfold_max * ldf,
-      afold + pl.nfold_max * kNbMax, nfoldb + pl.nfold_max);
+  k_init<<<dim3((unsigned)init_blocks(pl)), kThreads, 0, s>>>(make_init_args(pl, wb));
   MPID_LAUNCH_CHECK();
   k_ingest<TA, S><<<dim3((unsigned)ceil_div(n, 64), (unsigned)ntg), kThreads, 0, s>>>(
-      A, lda, m, n, W[0], ldw, colpart, ldf, st, rmode);
+      make_ingest_args<TA, S>(pl, wb, A, lda, rmode));
   MPID_LAUNCH_CHECK();
   int namax = (int)ceil_div(n, kFinCols);
-  k_colreduce<<<dim3((unsigned)namax), kThreads, 0, s>>>(colpart, ldf, 0, ntg, n, 0, nu, nuo,
-                                                          amax, colid[0], posof, pvflag, keypos, st,
-                                                          -1.0, rmode, nullptr, 0);
+  k_colreduce<<<dim3((unsigned)namax), kThreads, 0, s>>>(
+      make_col_args(pl, wb, 0, 0, n, 0, -1.0, rmode, nullptr, 0));
   MPID_LAUNCH_CHECK();
   prof.end(s);
 
-  StepArgs<S> a;
-  std::memset(&a, 0, sizeof(a));
-  a.ldw = ldw;
-  a.m = m;
-  a.n = n;
-  a.V = V;
-  a.ldv = pl.ldv;
-  a.F = F;
-  a.ldf = ldf;
-  a.vscale = vscale;
-  a.tau = tau;
-  a.st = st;
-  a.amax = amax;
-  a.pvflag = pvflag;
-  a.pivpos = pivpos;
-  a.pivid = pivid;
-  a.permw = permw;
-  a.posof = posof;
-  a.zpart = zpart;
-  a.auxpart = auxpart;
-  a.nrm2part = nrm2part;
-  a.nu = nu;
-  a.nuo = nuo;
-  a.rorig = rorig;
-  a.wrow = wrow;
-  a.vrow = vrow;
-  a.keypos = keypos;
-  a.tguard = pl.ntile_s_max;
-  a.kcap = kcap;
-  a.k_fixed = o->k_fixed;
-  a.rel_tol = o->rel_tol;
-  a.tol3z = std::sqrt(pl.wbytes == 8 ? std::ldexp(1.0, -53) : std::ldexp(1.0, -24));
-  a.rule = o->rank_rule;
-  a.nopivot = (o->flags & ID_FLAG_NO_PIVOT) ? 1 : 0;
-  a.nb = pl.nb;
-  a.want_fmax = (OP == OP_F16 && rmode != RM_F16) ? 1 : 0;
-  a.rmode = rmode;
+  StepArgs<S> a =
+      make_step_args<S>(pl, wb, o, rmode, (OP == OP_F16 && rmode != RM_F16) ? 1 : 0);
 
   // Panels are enqueued one ahead of what the host knows: before panel P is
   // enqueued the host has read the state after panel P - 2, whose offset is a
@@ -1734,36 +1898,15 @@ static int factor_impl(const TA* A, int64_t lda, const FactorPlan& pl, const id_
       if (rl < 0) return rl;
       if (rl != ID_OK) break;
     }
-    GemmArgs<S> g;
-    g.W = W[cur];
-    g.Wn = W[cur ^ 1];
-    g.ldw = ldw;
-    g.m = m;
-    g.ncur = ncur_ub;
-    g.V = V;
-    g.ldv = pl.ldv;
-    g.F = F;
-    g.ldf = ldf;
-    g.vscale = vscale;
-    g.st = st;
-    g.pivpos = pivpos;
-    g.colid = colid[cur];
-    g.colid_n = colid[cur ^ 1];
-    g.colpart = colpart;
-    g.off = off_lb;
-    g.tg0 = off_lb / kRowTileG;
-    g.gx = ceil_div(ncur_ub, 64);
-    g.gy = ntg - g.tg0;
+    const GemmArgs<S> g = make_gemm_args<S>(pl, wb, cur, off_lb);
     prof.launch(PK_GEMM, (int64_t)panel * 1024, k_panel_gemm<S, OP, RM>,
                 dim3((unsigned)round_up(g.gx * g.gy, 8)), s, g);
     MPID_LAUNCH_CHECK();
     namax = (int)ceil_div(ncur_ub, kFinCols);
     prof.begin(PK_OTHER, (int64_t)panel * 1024, s);
-    k_colreduce<<<dim3((unsigned)namax), kThreads, 0, s>>>(colpart, ldf, g.tg0, ntg, ncur_ub, 1,
-                                                            nu, nuo, amax, colid[cur ^ 1], posof,
-                                                            pvflag, keypos, st, count_tol, rmode,
-                                                            &kslot[cur],
-                                                            seq0 + panel + 1);
+    k_colreduce<<<dim3((unsigned)namax), kThreads, 0, s>>>(
+        make_col_args(pl, wb, cur ^ 1, g.tg0, ncur_ub, 1, count_tol, rmode, &kslot[cur],
+                      seq0 + panel + 1));
     MPID_LAUNCH_CHECK();
     prof.end(s);
     if (!noalloc) MPID_HIP(hipEventRecord(pev[cur], s));
@@ -1790,7 +1933,7 @@ static int factor_impl(const TA* A, int64_t lda, const FactorPlan& pl, const id_
   *info = fin->info;
   MPID_LOG(1, "id_factor: k=%lld info=%d after %d panels", (long long)k, fin->info, settled);
   k_finish<<<dim3((unsigned)n, (unsigned)(k > 0 ? ceil_div(k, kThreads) : 1)), kThreads, 0, s>>>(
-      permw, perm, rorig, kcap, n, k, R, ldr);
+      make_finish_args(pl, wb, perm, R, ldr, k));
   MPID_LAUNCH_CHECK();
   if (prof.on) {
     MPID_HIP(hipEventRecord(ev_t1, s));
@@ -1865,5 +2008,668 @@ int factor_run_noalloc(const void* A, int32_t dtype, int64_t m, int64_t n, int64
   return factor_dispatch(A, dtype, m, n, lda, o, work, work_bytes, perm, R, ldr, k_out, info,
                          true, s);
 }
+
+// ----------------------------------------------------------------- lock-step batches
+//
+// Many factorizations advanced together, each the single-matrix algorithm on
+// its own workspace: every launch runs one kernel of a pivot step or of a
+// panel end for all unfinished items at once, so a step's launch streams the
+// trailing blocks of every item (the per-step latencies of one matrix are paid
+// once per batch, not once per item).  All items start each panel together;
+// an item whose panel ended early, or that finished, leaves the rest of the
+// panel's launches at once.  The host reads every item's state after each
+// panel, one panel behind the GPU as in the single-matrix driver, to size the
+// next panel's grids and to drop finished items.
+//
+// Block b of a launch belongs to table entry map[b]; its index inside the
+// item is b minus the entry's first block of that launch kind.
+
+enum { LK_SWEEP = 0, LK_FIN, LK_GEMM, LK_COL, LK_INIT, LK_INGEST, LK_FINISH, LK_KINDS };
+
+template <typename S>
+struct ManyItem {
+  StepArgs<S> step;  // j: the panel's offset lower bound (a step adds jj)
+  GemmArgs<S> gemm;
+  ColArgs col;
+  InitArgs init;
+  FinishArgs finish;
+  const void* A;  // ingest: the input, its working copy and norm partials
+  int64_t lda;
+  S* w0;
+  double* colpart;
+  int64_t ingest_gx;
+  int namax0, namax1;  // pivot partials of the panel's first / later sweeps
+  int first[LK_KINDS];
+  int nblk[LK_KINDS];
+  int user;  // index of the item in the caller's array
+};
+
+// Argument blocks read from an item table in device memory, field by field
+// through the constant address space: a pointer loaded that way is known to
+// address global memory, so every access derived from it is a global (not a
+// flat) memory instruction -- flat accesses also count as LDS accesses, and
+// the waits they force would serialize the kernels' round trips.  The field
+// lists name every member of the structs above.
+template <typename T>
+using ConstPtr = const T __attribute__((address_space(4)))*;
+
+#define MPID_STEP_FIELDS(X)                                                                      \
+  X(W) X(ldw) X(m) X(n) X(ncur) X(V) X(ldv) X(F) X(ldf) X(vscale) X(tau) X(st) X(amax) X(namax) \
+  X(pvflag) X(colid) X(pivpos) X(pivid) X(permw) X(posof) X(zpart) X(auxpart) X(nrm2part) X(nu) \
+  X(nuo) X(rorig) X(wrow) X(vrow) X(keypos) X(kcap) X(k_fixed) X(rel_tol) X(tol3z) X(rule)       \
+  X(nopivot) X(nb) X(want_fmax) X(rmode) X(j) X(jj) X(t0) X(ntile) X(nchunk) X(Rt) X(CW)        \
+  X(tguard)
+#define MPID_GEMM_FIELDS(X)                                                                      \
+  X(W) X(Wn) X(ldw) X(m) X(ncur) X(V) X(ldv) X(F) X(ldf) X(vscale) X(st) X(pivpos) X(colid)     \
+  X(colid_n) X(colpart) X(off) X(tg0) X(gx) X(gy)
+#define MPID_COL_FIELDS(X)                                                                       \
+  X(colpart) X(ldf) X(tg0) X(tg1) X(ncols_base) X(subtract_jb) X(nu) X(nuo) X(amax) X(colid)   \
+  X(posof) X(pvflag) X(keypos) X(st) X(rel_tol) X(rmode) X(hs) X(seq)
+#define MPID_INIT_FIELDS(X)                                                                      \
+  X(st) X(colid0) X(pvflag) X(permw) X(posof) X(n) X(ldf) X(zrow_z) X(zrow_a) X(zrow_n)         \
+  X(frow_z) X(frow_a) X(frow_n)
+#define MPID_FINISH_FIELDS(X) X(permw) X(perm_out) X(rorig) X(kcap) X(n) X(k) X(R) X(ldr)
+#define MPID_COPY_FIELD(f) d.f = s->f;
+
+template <typename S>
+__device__ __forceinline__ StepArgs<S> load_args(ConstPtr<StepArgs<S>> s) {
+  StepArgs<S> d;
+  MPID_STEP_FIELDS(MPID_COPY_FIELD)
+  return d;
+}
+template <typename S>
+__device__ __forceinline__ GemmArgs<S> load_args(ConstPtr<GemmArgs<S>> s) {
+  GemmArgs<S> d;
+  MPID_GEMM_FIELDS(MPID_COPY_FIELD)
+  return d;
+}
+__device__ __forceinline__ ColArgs load_args(ConstPtr<ColArgs> s) {
+  ColArgs d;
+  MPID_COL_FIELDS(MPID_COPY_FIELD)
+  return d;
+}
+__device__ __forceinline__ InitArgs load_args(ConstPtr<InitArgs> s) {
+  InitArgs d;
+  MPID_INIT_FIELDS(MPID_COPY_FIELD)
+  return d;
+}
+__device__ __forceinline__ FinishArgs load_args(ConstPtr<FinishArgs> s) {
+  FinishArgs d;
+  MPID_FINISH_FIELDS(MPID_COPY_FIELD)
+  return d;
+}
+
+// The table entry of this block of a lock-step launch.
+template <typename S>
+__device__ __forceinline__ ConstPtr<ManyItem<S>> many_entry(const ManyItem<S>* it, const int* map) {
+  return (ConstPtr<ManyItem<S>>)it + ((ConstPtr<int>)map)[blockIdx.x];
+}
+
+template <typename S, int G>
+__global__ __launch_bounds__(kThreads) void k_sweep_many(const ManyItem<S>* __restrict__ it,
+                                                         const int* __restrict__ map, int jj) {
+  const ConstPtr<ManyItem<S>> q = many_entry(it, map);
+  StepArgs<S> a = load_args<S>(&q->step);
+  a.j += jj;
+  a.jj = jj;
+  a.namax = jj == 0 ? q->namax0 : q->namax1;
+  sweep_block<S, G, kSweepUDeep>(a, (int)blockIdx.x - q->first[LK_SWEEP], q->nblk[LK_SWEEP]);
+}
+
+template <typename S, int RM>
+__global__ __launch_bounds__(kThreads) void k_finalize_many(const ManyItem<S>* __restrict__ it,
+                                                            const int* __restrict__ map, int jj) {
+  const ConstPtr<ManyItem<S>> q = many_entry(it, map);
+  StepArgs<S> a = load_args<S>(&q->step);
+  a.j += jj;
+  a.jj = jj;
+  const float fm = finalize_block<S, RM>(a, (int)blockIdx.x - q->first[LK_FIN]);
+  if (a.want_fmax && threadIdx.x == 0 && fm >= 0.0f)
+    atomicMax(&a.st->fmax_bits, __float_as_uint(fm));
+}
+
+template <typename S, int OP, int RM>
+__global__ __launch_bounds__(kThreads) void k_panel_gemm_many(const ManyItem<S>* __restrict__ it,
+                                                              const int* __restrict__ map) {
+  const ConstPtr<ManyItem<S>> q = many_entry(it, map);
+  const GemmArgs<S> g = load_args<S>(&q->gemm);
+  panel_gemm_block<S, OP, RM>(g, blockIdx.x - (uint32_t)q->first[LK_GEMM],
+                              (uint32_t)q->nblk[LK_GEMM]);
+}
+
+template <typename S>
+__global__ __launch_bounds__(kThreads) void k_colreduce_many(const ManyItem<S>* __restrict__ it,
+                                                             const int* __restrict__ map) {
+  const ConstPtr<ManyItem<S>> q = many_entry(it, map);
+  const ColArgs c = load_args(&q->col);
+  colreduce_body(c, (int)blockIdx.x - q->first[LK_COL], q->nblk[LK_COL]);
+}
+
+template <typename S>
+__global__ __launch_bounds__(kThreads) void k_init_many(const ManyItem<S>* __restrict__ it,
+                                                        const int* __restrict__ map) {
+  const ConstPtr<ManyItem<S>> q = many_entry(it, map);
+  const InitArgs a = load_args(&q->init);
+  init_block(a, (int64_t)blockIdx.x - q->first[LK_INIT]);
+}
+
+template <typename TA, typename S>
+__global__ __launch_bounds__(kThreads) void k_ingest_many(const ManyItem<S>* __restrict__ it,
+                                                          const int* __restrict__ map) {
+  const ConstPtr<ManyItem<S>> q = many_entry(it, map);
+  IngestArgs<TA, S> a;
+  a.A = (const TA*)q->A;
+  a.lda = q->lda;
+  a.m = q->step.m;
+  a.n = q->step.n;
+  a.W = q->w0;
+  a.ldw = q->step.ldw;
+  a.colpart = q->colpart;
+  a.ldf = q->step.ldf;
+  a.st = q->step.st;
+  a.rmode = q->step.rmode;
+  const int64_t gx = q->ingest_gx;
+  const int64_t lb = (int64_t)blockIdx.x - q->first[LK_INGEST];
+  ingest_block<TA, S>(a, lb % gx, lb / gx);
+}
+
+template <typename S>
+__global__ __launch_bounds__(kThreads) void k_finish_many(const ManyItem<S>* __restrict__ it,
+                                                          const int* __restrict__ map) {
+  const ConstPtr<ManyItem<S>> q = many_entry(it, map);
+  const FinishArgs f = load_args(&q->finish);
+  const int64_t lb = (int64_t)blockIdx.x - q->first[LK_FINISH];
+  finish_block(f, lb % f.n, lb / f.n);
+}
+
+// k and info of every item (one block per table entry, in the caller's
+// order): the factorization's own info (non-finite input) if set, else
+// ID_INFO_SINGULAR when some |R_ii| <= n 2^-53 |R_00| (or R_00 = 0),
+// ID_INFO_RANK_FULL when k == n, else 0 -- the conditions of id_solve_T.
+template <typename S>
+__global__ __launch_bounds__(kThreads) void k_check_many(const ManyItem<S>* __restrict__ it,
+                                                         id_batch_item* __restrict__ items) {
+  __shared__ double dscr[4];
+  const ManyItem<S>& q = it[blockIdx.x];
+  id_batch_item& bi = items[q.user];
+  const FactorState* st = q.step.st;
+  const int64_t k = q.finish.k, n = q.finish.n;
+  const int32_t finfo = st->info;
+  const double* R = bi.R;
+  const int64_t ldr = bi.ldr;
+  const int tid = threadIdx.x;
+  const double r00 = (finfo == 0 && k > 0) ? fabs(R[0]) : 0.0;
+  const double thr = (double)n * ldexp(1.0, -53) * r00;
+  double bad = 0.0;
+  if (finfo == 0)
+    for (int64_t i = tid; i < k; i += kThreads)
+      if (!(fabs(R[i * ldr + i]) > thr)) bad += 1.0;
+  bad = block_sum(bad, dscr);
+  if (tid == 0) {
+    bi.k = k;
+    if (finfo != 0)
+      bi.info = finfo;
+    else if (k > 0 && (bad > 0.0 || r00 == 0.0))
+      bi.info = ID_INFO_SINGULAR;
+    else
+      bi.info = (k == n) ? ID_INFO_RANK_FULL : 0;
+  }
+}
+
+namespace {
+
+// Pinned host memory of the calling thread, grown on demand and kept.
+struct PinnedBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+};
+int pinned_reserve(PinnedBuf& b, size_t bytes) {
+  if (b.bytes >= bytes) return ID_OK;
+  if (b.p) MPID_HIP(hipHostFree(b.p));
+  b.p = nullptr;
+  b.bytes = 0;
+  MPID_HIP(hipHostMalloc(&b.p, bytes, hipHostMallocDefault));
+  b.bytes = bytes;
+  return ID_OK;
+}
+
+struct LockPlan {
+  int Rt = 128;
+  std::vector<FactorPlan> pl;   // per item
+  std::vector<int> cw;          // sweep column chunk per item
+  int64_t cap[LK_KINDS] = {0};  // map capacity per launch kind (blocks)
+  int64_t max_n = 0;
+  size_t off_items = 0, off_ditems = 0, off_slots = 0, off_map[LK_KINDS] = {0};
+  size_t bytes = 0;
+};
+
+constexpr int kManyTileMax = kFinZ * kFL;  // row tiles one finalization round trip covers
+constexpr int kManyBlocks = 4096;          // sweep blocks that fill the chip several times over
+
+int lockstep_sweep_blocks(const FactorPlan& pl, int Rt, int cw, int64_t off) {
+  const int64_t ntile = ceil_div(pl.m, Rt) - off / Rt;
+  return (int)round_up(ntile * ceil_div(pl.n - off, cw), 8);
+}
+
+}  // namespace
+
+// Validates the batch and lays out the shared workspace.
+static int make_lock_plan(const id_batch_item* items, int32_t batch, int32_t dtype,
+                          const id_opts* o, LockPlan* lp) {
+  if (!items || batch < 0 || !o) return ID_ERR_ARG;
+  if (dtype != ID_F32 && dtype != ID_F64) return ID_ERR_DTYPE;
+  if (o->flags & (ID_FLAG_GRAM | ID_FLAG_PROFILE)) return ID_ERR_UNSUPPORTED;
+  lp->pl.resize(batch);
+  lp->cw.resize(batch);
+  int64_t max_m = 0;
+  for (int32_t i = 0; i < batch; ++i) {
+    const id_batch_item& it = items[i];
+    FactorPlan& pl = lp->pl[i];
+    if (!make_factor_plan(it.m, it.n, dtype, o, &pl)) return ID_ERR_ARG;
+    if (it.m > 0 && it.n > 0 && !it.A) return ID_ERR_ARG;
+    if (it.lda < (it.m > 1 ? it.m : 1)) return ID_ERR_ARG;
+    if (it.n > 0 && !it.perm) return ID_ERR_ARG;
+    if (pl.kcap > 0 && (!it.R || it.ldr < pl.kcap)) return ID_ERR_ARG;
+    if (pl.kcap > 0 && it.n > pl.kcap && (!it.T || it.ldt < pl.kcap)) return ID_ERR_ARG;
+    if (!it.work) return ID_ERR_WORKSPACE;
+    max_m = std::max<int64_t>(max_m, it.m);
+    lp->max_n = std::max<int64_t>(lp->max_n, it.n);
+  }
+  // one row-tile height for the batch, every item's tiles within one round
+  // trip of the finalization (no folding): the tallest tiles (the fixed
+  // latencies of a block are shared by the most rows) unless the batch then
+  // has too few blocks to fill the chip
+  if (ceil_div(max_m, kRtMax) > kManyTileMax) return ID_ERR_UNSUPPORTED;
+  const int cw_env = env_int("MPID_LOCKSTEP_CW", 0);
+  for (int32_t i = 0; i < batch; ++i) {
+    const FactorPlan& pl = lp->pl[i];
+    const int v = pl.wbytes == 8 ? 2 : 4;  // values per 16-byte load
+    // the chunk (64, 128 or 256 lanes per row) that leaves the fewest idle
+    // lanes over the item's columns, the wider one on ties
+    int cw = 64 * v;
+    for (int c = 128 * v; c <= 256 * v; c *= 2)
+      if (ceil_div(pl.n, c) * c <= ceil_div(pl.n, cw) * cw) cw = c;
+    if (cw_env == 64 * v || cw_env == 128 * v || cw_env == 256 * v) cw = cw_env;
+    lp->cw[i] = cw;
+  }
+  int rt = env_int("MPID_LOCKSTEP_RT", 0);
+  if (rt <= 0) {
+    const int64_t target = env_int("MPID_LOCKSTEP_BLOCKS", kManyBlocks);
+    rt = kRtMax;
+    while (rt > kRtMin && ceil_div(max_m, rt / 2) <= kManyTileMax) {
+      int64_t blocks = 0;
+      for (int32_t i = 0; i < batch; ++i)
+        blocks += lockstep_sweep_blocks(lp->pl[i], rt, lp->cw[i], 0);
+      if (blocks >= target) break;
+      rt /= 2;
+    }
+  }
+  if (rt != 64 && rt != 128 && rt != 256) return ID_ERR_ARG;
+  if (ceil_div(max_m, rt) > kManyTileMax) return ID_ERR_UNSUPPORTED;
+  lp->Rt = rt;
+  for (int32_t i = 0; i < batch; ++i) {
+    const FactorPlan& pl = lp->pl[i];
+    // the grids of the first panel (offset 0) are the largest
+    lp->cap[LK_SWEEP] += lockstep_sweep_blocks(pl, rt, lp->cw[i], 0);
+    lp->cap[LK_FIN] += ceil_div(pl.n, kFC);
+    lp->cap[LK_GEMM] += round_up(ceil_div(pl.n, 64) * ceil_div(pl.m, kRowTileG), 8);
+    lp->cap[LK_COL] += ceil_div(pl.n, kFinCols);
+    lp->cap[LK_INIT] += init_blocks(pl);
+    lp->cap[LK_INGEST] += ceil_div(pl.n, 64) * ceil_div(pl.m, kRowTileG);
+    lp->cap[LK_FINISH] += pl.n * (pl.kcap > 0 ? ceil_div(pl.kcap, kThreads) : 1);
+  }
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o2 = off;
+    off += (bytes + 255) / 256 * 256;
+    return o2;
+  };
+  static_assert(sizeof(ManyItem<float>) == sizeof(ManyItem<double>), "item table layout");
+  lp->off_items = take(sizeof(ManyItem<float>) * (size_t)std::max(batch, 1));
+  lp->off_ditems = take(sizeof(id_batch_item) * (size_t)std::max(batch, 1));
+  lp->off_slots = take(sizeof(FactorHostSlot) * (size_t)std::max(batch, 1));
+  for (int kd = 0; kd < LK_KINDS; ++kd) lp->off_map[kd] = take(4 * (size_t)std::max<int64_t>(lp->cap[kd], 1));
+  lp->bytes = off;
+  return ID_OK;
+}
+
+size_t lockstep_workspace(const id_batch_item* items, int32_t batch, int32_t dtype,
+                          const id_opts* o) {
+  LockPlan lp;
+  if (make_lock_plan(items, batch, dtype, o, &lp) != ID_OK) return 0;
+  return lp.bytes;
+}
+
+template <typename TA, typename S, int OP, int RM, int G>
+static int lockstep_impl(id_batch_item* items, int32_t batch, const id_opts* o, const LockPlan& lp,
+                         char* shared, hipStream_t s) {
+  const int rmode = RM;
+  const int Rt = lp.Rt;
+  const int want_fmax = (OP == OP_F16 && RM != RM_F16) ? 1 : 0;
+  // the batch's working set is far beyond the caches: the deeper sweep loop
+  ManyItem<S>* d_items = (ManyItem<S>*)(shared + lp.off_items);
+  id_batch_item* d_bi = (id_batch_item*)(shared + lp.off_ditems);
+  FactorHostSlot* d_slots = (FactorHostSlot*)(shared + lp.off_slots);
+  int* d_map[LK_KINDS];
+  for (int kd = 0; kd < LK_KINDS; ++kd) d_map[kd] = (int*)(shared + lp.off_map[kd]);
+
+  static thread_local PinnedBuf stage[2], hslots[2];
+  static thread_local hipEvent_t ev_stage[2] = {nullptr, nullptr};
+  static thread_local hipEvent_t ev_slot[2] = {nullptr, nullptr};
+  static thread_local int64_t ncalls = 0;
+  for (int q = 0; q < 2; ++q) {
+    if (!ev_stage[q]) MPID_HIP(hipEventCreateWithFlags(&ev_stage[q], hipEventDisableTiming));
+    if (!ev_slot[q]) MPID_HIP(hipEventCreateWithFlags(&ev_slot[q], hipEventDisableTiming));
+  }
+  const size_t tbl_bytes = sizeof(ManyItem<S>) * (size_t)batch;
+  int64_t map_total = 0;
+  for (int kd = 0; kd < LK_KINDS; ++kd) map_total += lp.cap[kd];
+  const size_t stage_bytes = tbl_bytes + 4 * (size_t)map_total;
+  for (int q = 0; q < 2; ++q) {
+    int rc = pinned_reserve(stage[q], stage_bytes);
+    if (rc) return rc;
+    rc = pinned_reserve(hslots[q], sizeof(FactorHostSlot) * (size_t)batch);
+    if (rc) return rc;
+  }
+  int upload = 0;  // uploads so far (staging buffer upload & 1)
+  // staging buffer for the next upload: its table and per-kind maps
+  struct Stage {
+    ManyItem<S>* tbl;
+    int* map[LK_KINDS];
+  };
+  auto begin_stage = [&](Stage* st) -> int {
+    const int q = upload & 1;
+    MPID_HIP(hipEventSynchronize(ev_stage[q]));  // its last copy has been read
+    char* b = (char*)stage[q].p;
+    st->tbl = (ManyItem<S>*)b;
+    size_t off = tbl_bytes;
+    for (int kd = 0; kd < LK_KINDS; ++kd) {
+      st->map[kd] = (int*)(b + off);
+      off += 4 * (size_t)lp.cap[kd];
+    }
+    return ID_OK;
+  };
+  // copies the table (entries) and the maps of the given kinds (blocks used)
+  auto end_stage = [&](const Stage& st, int entries, const int64_t* used) -> int {
+    const int q = upload & 1;
+    MPID_HIP(hipMemcpyAsync(d_items, st.tbl, sizeof(ManyItem<S>) * (size_t)entries,
+                            hipMemcpyHostToDevice, s));
+    for (int kd = 0; kd < LK_KINDS; ++kd)
+      if (used[kd] > 0)
+        MPID_HIP(hipMemcpyAsync(d_map[kd], st.map[kd], 4 * (size_t)used[kd],
+                                hipMemcpyHostToDevice, s));
+    MPID_HIP(hipEventRecord(ev_stage[q], s));
+    ++upload;
+    return ID_OK;
+  };
+
+  // per-item host view
+  std::vector<int64_t> known_off(batch, 0), k(batch, 0);
+  std::vector<int32_t> finfo(batch, 0);
+  std::vector<char> done(batch, 0);
+  std::vector<int> namax_cr(batch, 0);
+  std::vector<StepArgs<S>> base(batch);
+  for (int32_t i = 0; i < batch; ++i) {
+    char* wb = (char*)items[i].work;
+    base[i] = make_step_args<S>(lp.pl[i], wb, o, rmode, want_fmax);
+    namax_cr[i] = (int)ceil_div(lp.pl[i].n, kFinCols);
+    // nothing to factor: k = 0 (the initialization still runs for perm)
+    if (items[i].m == 0 || items[i].n == 0 || lp.pl[i].kcap == 0) done[i] = 1;
+  }
+  MPID_LOG(1, "id_factor_lockstep: %d items, %d-row tiles, shared workspace %zu bytes", (int)batch,
+           Rt, lp.bytes);
+
+  // ---- prologue: initialization, ingest, column norms of every item
+  MPID_HIP(hipMemcpyAsync(d_bi, items, sizeof(id_batch_item) * (size_t)batch,
+                          hipMemcpyHostToDevice, s));
+  {
+    Stage st;
+    int rc = begin_stage(&st);
+    if (rc) return rc;
+    int64_t used[LK_KINDS] = {0};
+    for (int32_t i = 0; i < batch; ++i) {
+      const FactorPlan& pl = lp.pl[i];
+      char* wb = (char*)items[i].work;
+      ManyItem<S>& q = st.tbl[i];
+      std::memset(&q, 0, sizeof(q));
+      q.user = i;
+      q.step = base[i];
+      q.init = make_init_args(pl, wb);
+      q.A = items[i].A;
+      q.lda = items[i].lda;
+      q.w0 = (S*)(wb + pl.off_w0);
+      q.colpart = (double*)(wb + pl.off_colpart);
+      q.ingest_gx = ceil_div(pl.n, 64);
+      q.col = make_col_args(pl, wb, 0, 0, pl.n, 0, -1.0, rmode, nullptr, 0);
+      const int64_t nb_kind[3] = {init_blocks(pl),
+                                  done[i] ? 0 : q.ingest_gx * ceil_div(pl.m, kRowTileG),
+                                  done[i] ? 0 : ceil_div(pl.n, kFinCols)};
+      const int kinds[3] = {LK_INIT, LK_INGEST, LK_COL};
+      for (int t = 0; t < 3; ++t) {
+        const int kd = kinds[t];
+        q.first[kd] = (int)used[kd];
+        q.nblk[kd] = (int)nb_kind[t];
+        for (int64_t b = 0; b < nb_kind[t]; ++b) st.map[kd][used[kd] + b] = i;
+        used[kd] += nb_kind[t];
+      }
+    }
+    rc = end_stage(st, batch, used);
+    if (rc) return rc;
+    if (used[LK_INIT] > 0)
+      k_init_many<S><<<dim3((unsigned)used[LK_INIT]), kThreads, 0, s>>>(d_items, d_map[LK_INIT]);
+    MPID_LAUNCH_CHECK();
+    if (used[LK_INGEST] > 0)
+      k_ingest_many<TA, S><<<dim3((unsigned)used[LK_INGEST]), kThreads, 0, s>>>(
+          d_items, d_map[LK_INGEST]);
+    MPID_LAUNCH_CHECK();
+    if (used[LK_COL] > 0)
+      k_colreduce_many<S><<<dim3((unsigned)used[LK_COL]), kThreads, 0, s>>>(d_items,
+                                                                            d_map[LK_COL]);
+    MPID_LAUNCH_CHECK();
+  }
+
+  // ---- panels
+  const bool count_rule = o->k_fixed == 0 && o->rank_rule == ID_RANK_PIVOT_REL;
+  const double count_tol = count_rule ? o->rel_tol : -1.0;
+  const int64_t seq0 = (++ncalls) << 24;
+  std::vector<int> in_panel[2];  // items (caller's index) of the last two panels
+  std::vector<int> order;
+  std::vector<int64_t> lim;
+  auto settle = [&](int panel) -> int {
+    const int q = panel & 1;
+    MPID_HIP(hipEventSynchronize(ev_slot[q]));
+    const FactorHostSlot* hs = (const FactorHostSlot*)hslots[q].p;
+    for (const int i : in_panel[q]) {
+      if (done[i]) continue;
+      const FactorHostSlot& sl = hs[i];
+      if (sl.seq != seq0 + panel + 1) return ID_ERR_HIP;
+      const FactorState& h = sl.s;
+      if (h.done) {
+        done[i] = 1;
+        k[i] = h.k;
+        finfo[i] = h.info;
+        continue;
+      }
+      if (h.last_jb <= 0) return ID_ERR_HIP;  // a live panel always makes progress
+      known_off[i] += h.last_jb;
+    }
+    return ID_OK;
+  };
+  int panel = 0;
+  for (;; ++panel) {
+    const int cur = panel & 1;
+    // live items, most steps first (a step's launch covers a prefix of them)
+    order.clear();
+    for (int32_t i = 0; i < batch; ++i)
+      if (!done[i]) order.push_back(i);
+    if (order.empty()) break;
+    lim.assign(batch, 0);
+    for (const int i : order) {
+      const FactorPlan& pl = lp.pl[i];
+      lim[i] = std::min<int64_t>({(int64_t)pl.nb, pl.kcap - known_off[i], pl.n - known_off[i]});
+    }
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return lim[x] > lim[y]; });
+    Stage st;
+    int rc = begin_stage(&st);
+    if (rc) return rc;
+    int64_t used[LK_KINDS] = {0};
+    std::vector<int64_t> sw_end(order.size()), fin_end(order.size());
+    for (size_t t = 0; t < order.size(); ++t) {
+      const int i = order[t];
+      const FactorPlan& pl = lp.pl[i];
+      char* wb = (char*)items[i].work;
+      const int64_t off_lb = known_off[i];
+      const int64_t ncur_b = pl.n - off_lb;
+      ManyItem<S>& q = st.tbl[t];
+      std::memset(&q, 0, sizeof(q));
+      q.user = i;
+      StepArgs<S>& a = q.step;
+      a = base[i];
+      a.W = (const S*)(wb + (cur ? pl.off_w1 : pl.off_w0));
+      a.colid = (const int*)(wb + (cur ? pl.off_colid1 : pl.off_colid0));
+      a.ncur = ncur_b;
+      a.j = off_lb;
+      a.Rt = Rt;
+      a.CW = lp.cw[i];
+      a.t0 = off_lb / Rt;
+      a.ntile = (int)(ceil_div(pl.m, Rt) - a.t0);
+      a.nchunk = (int)ceil_div(ncur_b, a.CW);
+      q.namax0 = namax_cr[i];
+      q.namax1 = (int)ceil_div(ncur_b, kFC);
+      q.gemm = make_gemm_args<S>(pl, wb, cur, off_lb);
+      q.col = make_col_args(pl, wb, cur ^ 1, q.gemm.tg0, ncur_b, 1, count_tol, rmode,
+                            &d_slots[i], seq0 + panel + 1);
+      const int64_t nb_kind[4] = {round_up((int64_t)a.ntile * a.nchunk, 8), q.namax1,
+                                  round_up(q.gemm.gx * q.gemm.gy, 8), ceil_div(ncur_b, kFinCols)};
+      for (int kd = 0; kd < 4; ++kd) {
+        q.first[kd] = (int)used[kd];
+        q.nblk[kd] = (int)nb_kind[kd];
+        int* mp = st.map[kd] + used[kd];
+        for (int64_t b = 0; b < nb_kind[kd]; ++b) mp[b] = (int)t;
+        used[kd] += nb_kind[kd];
+      }
+      sw_end[t] = used[LK_SWEEP];
+      fin_end[t] = used[LK_FIN];
+      namax_cr[i] = (int)nb_kind[LK_COL];
+    }
+    rc = end_stage(st, (int)order.size(), used);
+    if (rc) return rc;
+    MPID_LOG(2, "lock-step panel %d: %zu items, %lld sweep blocks, %lld update blocks", panel,
+             order.size(), (long long)used[LK_SWEEP], (long long)used[LK_GEMM]);
+    const int64_t lmax = lim[order[0]];
+    size_t live = order.size();
+    for (int jj = 0; jj < lmax; ++jj) {
+      while (live > 0 && lim[order[live - 1]] <= jj) --live;
+      if (live == 0) break;
+      const unsigned gs = (unsigned)sw_end[live - 1], gf = (unsigned)fin_end[live - 1];
+      k_sweep_many<S, G><<<dim3(gs), kThreads, 0, s>>>(d_items, d_map[LK_SWEEP], jj);
+      MPID_LAUNCH_CHECK();
+      k_finalize_many<S, RM><<<dim3(gf), kThreads, 0, s>>>(d_items, d_map[LK_FIN], jj);
+      MPID_LAUNCH_CHECK();
+    }
+    k_panel_gemm_many<S, OP, RM><<<dim3((unsigned)used[LK_GEMM]), kThreads, 0, s>>>(
+        d_items, d_map[LK_GEMM]);
+    MPID_LAUNCH_CHECK();
+    k_colreduce_many<S><<<dim3((unsigned)used[LK_COL]), kThreads, 0, s>>>(d_items,
+                                                                          d_map[LK_COL]);
+    MPID_LAUNCH_CHECK();
+    MPID_HIP(hipMemcpyAsync(hslots[cur].p, d_slots, sizeof(FactorHostSlot) * (size_t)batch,
+                            hipMemcpyDeviceToHost, s));
+    MPID_HIP(hipEventRecord(ev_slot[cur], s));
+    in_panel[cur] = order;
+    // the previous panel's end states (this panel keeps the GPU busy)
+    if (panel > 0) {
+      rc = settle(panel - 1);
+      if (rc) return rc;
+    }
+  }
+  // the last enqueued panel (if any) only found finished items
+  if (panel > 0) {
+    const int rc = settle(panel - 1);
+    if (rc) return rc;
+  }
+  MPID_HIP(hipStreamSynchronize(s));
+  for (int32_t i = 0; i < batch; ++i)
+    if (!done[i]) return ID_ERR_HIP;
+
+  // ---- R, perm, k and info of every item, then T = R11^{-1} R12
+  {
+    Stage st;
+    int rc = begin_stage(&st);
+    if (rc) return rc;
+    int64_t used[LK_KINDS] = {0};
+    for (int32_t i = 0; i < batch; ++i) {
+      const FactorPlan& pl = lp.pl[i];
+      char* wb = (char*)items[i].work;
+      ManyItem<S>& q = st.tbl[i];
+      std::memset(&q, 0, sizeof(q));
+      q.user = i;
+      q.step = base[i];
+      q.finish = make_finish_args(pl, wb, items[i].perm, items[i].R, items[i].ldr, k[i]);
+      const int64_t nbk = pl.n * (k[i] > 0 ? ceil_div(k[i], kThreads) : 1);
+      q.first[LK_FINISH] = (int)used[LK_FINISH];
+      q.nblk[LK_FINISH] = (int)nbk;
+      for (int64_t b = 0; b < nbk; ++b) st.map[LK_FINISH][used[LK_FINISH] + b] = i;
+      used[LK_FINISH] += nbk;
+    }
+    rc = end_stage(st, batch, used);
+    if (rc) return rc;
+    if (used[LK_FINISH] > 0)
+      k_finish_many<S><<<dim3((unsigned)used[LK_FINISH]), kThreads, 0, s>>>(d_items,
+                                                                            d_map[LK_FINISH]);
+    MPID_LAUNCH_CHECK();
+    k_check_many<S><<<dim3((unsigned)batch), kThreads, 0, s>>>(d_items, d_bi);
+    MPID_LAUNCH_CHECK();
+  }
+  {
+    const int rc = trsm_batched_run(d_bi, batch, lp.max_n, s);
+    if (rc) return rc;
+  }
+  std::vector<id_batch_item> out(batch);
+  MPID_HIP(hipMemcpyAsync(out.data(), d_bi, sizeof(id_batch_item) * (size_t)batch,
+                          hipMemcpyDeviceToHost, s));
+  MPID_HIP(hipStreamSynchronize(s));
+  for (int32_t i = 0; i < batch; ++i) {
+    items[i].k = out[i].k;
+    items[i].info = out[i].info;
+  }
+  MPID_LOG(1, "id_factor_lockstep: done after %d panels", panel);
+  return ID_OK;
+}
+
+int lockstep_run(id_batch_item* items, int32_t batch, int32_t dtype, const id_opts* o, void* work,
+                 size_t work_bytes, hipStream_t s) {
+  LockPlan lp;
+  const int rc = make_lock_plan(items, batch, dtype, o, &lp);
+  if (rc) return rc;
+  if (batch == 0) return ID_OK;
+  if (!work || work_bytes < lp.bytes) return ID_ERR_WORKSPACE;
+  char* sh = (char*)work;
+  const bool f64in = dtype == ID_F64;
+  const int32_t rflags = o->flags & (ID_FLAG_ROUND_F32 | ID_FLAG_ROUND_F16);
+#define MPID_LS(S, OP, RM)                                                                     \
+  (lp.Rt == 256   ? (f64in ? lockstep_impl<double, S, OP, RM, 1>(items, batch, o, lp, sh, s)    \
+                           : lockstep_impl<float, S, OP, RM, 1>(items, batch, o, lp, sh, s))    \
+   : lp.Rt == 128 ? (f64in ? lockstep_impl<double, S, OP, RM, 2>(items, batch, o, lp, sh, s)    \
+                           : lockstep_impl<float, S, OP, RM, 2>(items, batch, o, lp, sh, s))    \
+                  : (f64in ? lockstep_impl<double, S, OP, RM, 4>(items, batch, o, lp, sh, s)    \
+                           : lockstep_impl<float, S, OP, RM, 4>(items, batch, o, lp, sh, s)))
+  if (rflags == ID_FLAG_ROUND_F32) return MPID_LS(float, OP_F32, RM_F32);
+  if (rflags == ID_FLAG_ROUND_F16) return MPID_LS(float, OP_F16, RM_F16);
+  switch (o->prec) {
+    case ID_PREC_F64:
+      return MPID_LS(double, OP_F64, RM_NONE);
+    case ID_PREC_MIXED_F16:
+      return MPID_LS(float, OP_F16, RM_NONE);
+    case ID_PREC_MIXED_F32:
+      return MPID_LS(float, OP_F32, RM_NONE);
+    case ID_PREC_MIXED_BF16X3:
+      return MPID_LS(float, OP_BF16X3, RM_NONE);
+    default:
+      return MPID_LS(float, OP_BF16, RM_NONE);
+  }
+#undef MPID_LS
+}
+
 
 }  // namespace mpid

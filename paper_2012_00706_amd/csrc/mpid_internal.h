@@ -124,6 +124,12 @@ int factor_batched_run(id_batch_item* items, int32_t batch, const int32_t* slots
 // T of every item (after the batched factorization, same stream).
 int trsm_batched_run(const id_batch_item* items, int32_t batch, int64_t max_n, hipStream_t s);
 
+// Lock-step batches (items: host array; see id_factor_lockstep).
+size_t lockstep_workspace(const id_batch_item* items, int32_t batch, int32_t dtype,
+                          const id_opts* o);
+int lockstep_run(id_batch_item* items, int32_t batch, int32_t dtype, const id_opts* o, void* work,
+                 size_t work_bytes, hipStream_t s);
+
 size_t backward_workspace(int64_t m, int64_t n, int64_t k);
 int backward_run(const void* A, int32_t dtype, int64_t m, int64_t n, int64_t lda,
                  const int32_t* perm, int64_t k, const double* T, int64_t ldt, const double* Rb,

@@ -177,3 +177,59 @@ def test_round_flags_pair_with_their_update(lib):
     for prec, rnd in (("mixed_f32", "f32"), ("mixed_f16", "f16")):
         o = make_opts(k=3, prec=prec, round_to=rnd)
         assert lib.id_workspace_size(10, 10, C["ID_F32"], ctypes.byref(o)) > 0, (prec, rnd)
+
+
+def _lock_items(shapes, fake):
+    from paper_2012_00706_amd import _lib
+    items = (_lib.IdBatchItem * len(shapes))()
+    for i, (m, n) in enumerate(shapes):
+        it = items[i]
+        it.A, it.m, it.n, it.lda = fake, m, n, max(m, 1)
+        it.work, it.perm, it.R, it.T = fake, fake, fake, fake
+        it.ldr = it.ldt = max(min(m, n), 1)
+    return items
+
+
+def test_lockstep_host_checks(lib):
+    """id_lockstep_workspace_size / id_factor_lockstep: sizes and argument
+    errors before any device call."""
+    from paper_2012_00706_amd import C, make_opts
+    fake = 0x1000
+    o = make_opts(tol=1e-3, prec="mixed_bf16x3")
+    items = _lock_items([(300, 150), (2000, 800), (1, 1)], fake)
+    ws = lib.id_lockstep_workspace_size(items, 3, C["ID_F32"], ctypes.byref(o))
+    assert ws > 0 and ws % 256 == 0
+    # more items or larger items need more
+    items4 = _lock_items([(300, 150), (2000, 800), (1, 1), (20000, 800)], fake)
+    assert lib.id_lockstep_workspace_size(items4, 4, C["ID_F32"], ctypes.byref(o)) > ws
+    # invalid: negative batch, a null input, ldr below kcap, an unknown dtype,
+    # more than 49152 rows, refused flags
+    assert lib.id_lockstep_workspace_size(items, -1, C["ID_F32"], ctypes.byref(o)) == 0
+    bad = _lock_items([(300, 150)], fake)
+    bad[0].A = None
+    assert lib.id_lockstep_workspace_size(bad, 1, C["ID_F32"], ctypes.byref(o)) == 0
+    bad = _lock_items([(300, 150)], fake)
+    bad[0].ldr = 10
+    assert lib.id_lockstep_workspace_size(bad, 1, C["ID_F32"], ctypes.byref(o)) == 0
+    assert lib.id_lockstep_workspace_size(items, 3, 7, ctypes.byref(o)) == 0
+    tall = _lock_items([(49153, 4)], fake)
+    assert lib.id_lockstep_workspace_size(tall, 1, C["ID_F32"], ctypes.byref(o)) == 0
+    assert lib.id_factor_lockstep(tall, 1, C["ID_F32"], ctypes.byref(o), fake, 1 << 30,
+                                  None) == C["ID_ERR_UNSUPPORTED"]
+    ok = _lock_items([(49152, 4)], fake)
+    assert lib.id_lockstep_workspace_size(ok, 1, C["ID_F32"], ctypes.byref(o)) > 0
+    g = make_opts(tol=1e-3, gram=True)
+    assert lib.id_factor_lockstep(items, 3, C["ID_F32"], ctypes.byref(g), fake, ws,
+                                  None) == C["ID_ERR_UNSUPPORTED"]
+    # workspace too small or missing, and an item without a workspace
+    assert lib.id_factor_lockstep(items, 3, C["ID_F32"], ctypes.byref(o), fake, ws - 256,
+                                  None) == C["ID_ERR_WORKSPACE"]
+    assert lib.id_factor_lockstep(items, 3, C["ID_F32"], ctypes.byref(o), None, ws,
+                                  None) == C["ID_ERR_WORKSPACE"]
+    nowork = _lock_items([(300, 150)], fake)
+    nowork[0].work = None
+    assert lib.id_factor_lockstep(nowork, 1, C["ID_F32"], ctypes.byref(o), fake, ws,
+                                  None) == C["ID_ERR_WORKSPACE"]
+    # an empty batch does nothing
+    assert lib.id_factor_lockstep(items, 0, C["ID_F32"], ctypes.byref(o), None, 0,
+                                  None) == C["ID_OK"]
