@@ -145,7 +145,10 @@ size_t id_workspace_size(int64_t m, int64_t n, int32_t dtype, const id_opts* opt
  * Pivoting follows the largest remaining column norm with ties going to the
  * first column in the current (LAPACK swap) order.  The call enqueues work on
  * "stream" and synchronizes it before returning: the number of pivot steps is
- * data dependent.  Concurrent calls must use distinct workspaces. */
+ * data dependent.  Concurrent calls must use distinct workspaces.  A single
+ * ID that can be captured in a graph (k and info left in device memory, no
+ * host synchronization) is id_factor_batched with a batch of one item, whose
+ * workgroups share it (up to ID_BATCH_MAX_GROUPS). */
 int id_factor(const void* A, int32_t dtype, int64_t m, int64_t n, int64_t lda,
               const id_opts* opts, void* work, size_t work_bytes, int32_t* perm, double* R,
               int64_t ldr, int64_t* k_out, int32_t* info, void* stream);

@@ -188,17 +188,20 @@ __global__ __launch_bounds__(kThreads) void k_gemm64(G64Args<TA, TC> a) {
 // (split K) block z sums the K range [z kc, (z + 1) kc) into its own partial
 // P + z M N (column-major, ld M) and k_gemm64_reduce applies the epilogue.
 // Two waves per SIMD: the register budget (236 of 256) keeps the 64 accumulators
-// in VGPRs without spilling.
+// in VGPRs without spilling.  One launch may run two products that share M
+// and K: the blocks with blockIdx.y >= ny0 compute the second (a1).
 template <typename TA, typename TC>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_gemm64t(
-    G64Args<TA, TC> a, int64_t kc,
-                                                      double* __restrict__ P) {
+    G64Args<TA, TC> a0, G64Args<TA, TC> a1, unsigned ny0, int64_t kc, double* __restrict__ P) {
+  const bool second = blockIdx.y >= ny0;
+  const G64Args<TA, TC>& a = second ? a1 : a0;
+  const unsigned by = second ? blockIdx.y - ny0 : blockIdx.y;
   __shared__ double As[16][128 + 2];  // As[kk][i] = op(A)(m0 + i, k0 + kk)
   __shared__ double Bs[16][128 + 2];  // Bs[kk][j] = op(B)(k0 + kk, n0 + j)
   __shared__ int32_t smap[3][128];    // the tile's output, Cin and Ein columns
   const int tid = threadIdx.x;
   const int lane = tid & 63, wv = tid >> 6, g = lane >> 4, li = lane & 15;
-  const int64_t m0 = (int64_t)blockIdx.x * 128, n0 = (int64_t)blockIdx.y * 128;
+  const int64_t m0 = (int64_t)blockIdx.x * 128, n0 = (int64_t)by * 128;
   const int wr = (wv & 1) * 64, wc = (wv >> 1) * 64;
   const int64_t kb = (int64_t)blockIdx.z * kc;
   const int64_t ke = kb + kc < a.K ? kb + kc : a.K;
@@ -386,15 +389,28 @@ static int gemm_launch(const G64Args<TA, TC>& a, hipStream_t s, double* P = null
   int nz = gemm_splits(a.M, a.N, a.K);
   if (nz > 1 && (a.E || !P || p_bytes < (size_t)nz * a.M * a.N * 8)) nz = 1;
   const int64_t kc = round_up(ceil_div(a.K, nz), 16);
-  k_gemm64t<TA, TC><<<dim3((unsigned)ceil_div(a.M, 128), (unsigned)ceil_div(a.N, 128),
-                           (unsigned)nz),
-                      kThreads, 0, s>>>(a, kc, P);
+  const unsigned ny = (unsigned)ceil_div(a.N, 128);
+  k_gemm64t<TA, TC><<<dim3((unsigned)ceil_div(a.M, 128), ny, (unsigned)nz), kThreads, 0, s>>>(
+      a, a, ny, kc, P);
   MPID_LAUNCH_CHECK();
   if (nz > 1) {
     k_gemm64_reduce<TA, TC><<<dim3((unsigned)ceil_div(a.M, kThreads), (unsigned)a.N), kThreads, 0,
                               s>>>(a, nz, P);
     MPID_LAUNCH_CHECK();
   }
+  return ID_OK;
+}
+
+// Two large-tile products with the same M and K (and A operand layout) in one
+// launch: one grid, so the blocks of both fill the chip together.
+template <typename TA, typename TC>
+static int gemm_launch2(const G64Args<TA, TC>& a0, const G64Args<TA, TC>& a1, hipStream_t s) {
+  if (a0.M != a1.M || a0.K != a1.K) return ID_ERR_ARG;
+  if (a0.M <= 0 || (a0.N <= 0 && a1.N <= 0)) return ID_OK;
+  const unsigned ny0 = (unsigned)ceil_div(a0.N, 128), ny1 = (unsigned)ceil_div(a1.N, 128);
+  k_gemm64t<TA, TC><<<dim3((unsigned)ceil_div(a0.M, 128), ny0 + ny1, 1), kThreads, 0, s>>>(
+      a0, a1, ny0, round_up(a0.K, 16), nullptr);
+  MPID_LAUNCH_CHECK();
   return ID_OK;
 }
 
@@ -636,25 +652,21 @@ static int backward_impl(const TA* A, int64_t m, int64_t n, int64_t lda, const i
   if ((rc = trsm_upper_run(Rf, ldrf, k, Tb, k, nc, Tb, k, 1, s))) return rc;
   if ((rc = trsm_upper_run(Rf, ldrf, k, Tb, k, nc, X, k, 0, s))) return rc;
   if ((rc = gather<double>(T, ldt, k, nullptr, nc, XT + k * nc, k, nullptr, 0, s))) return rc;
-  // gA(:, Jc) = W = B X, and E = gY(:, Jc) - W beside it
+  // gA(:, Jc) = W = B X with E = gY(:, Jc) - W beside it, and D = A(:, Jc) - B T:
+  // two products with the operand B, one launch
   {
-    G64Args<double, double> a;
-    std::memset(&a, 0, sizeof(a));
-    a.M = m, a.N = nc, a.K = k, a.alpha = 1.0;
-    a.A = Bm, a.lda = m, a.B = X, a.ldb = k;
-    a.C = gA, a.ldc = ldga, a.cmap = perm + k;
-    a.E = DE + m * nc, a.lde = m, a.Ein = gY, a.ldein = ldgy, a.einmap = perm + k;
-    if ((rc = gemm_launch(a, s))) return rc;
-  }
-  // D = A(:, Jc) - B T
-  {
-    G64Args<double, TA> a;
-    std::memset(&a, 0, sizeof(a));
-    a.M = m, a.N = nc, a.K = k, a.alpha = -1.0, a.beta = 1.0;
-    a.A = Bm, a.lda = m, a.B = XT + k * nc, a.ldb = k;
-    a.Cin = A, a.ldcin = lda, a.cinmap = perm + k;
-    a.C = DE, a.ldc = m;
-    if ((rc = gemm_launch(a, s))) return rc;
+    G64Args<double, TA> w, d;
+    std::memset(&w, 0, sizeof(w));
+    w.M = m, w.N = nc, w.K = k, w.alpha = 1.0;
+    w.A = Bm, w.lda = m, w.B = X, w.ldb = k;
+    w.C = gA, w.ldc = ldga, w.cmap = perm + k;
+    w.E = DE + m * nc, w.lde = m, w.Ein = gY, w.ldein = ldgy, w.einmap = perm + k;
+    std::memset(&d, 0, sizeof(d));
+    d.M = m, d.N = nc, d.K = k, d.alpha = -1.0, d.beta = 1.0;
+    d.A = Bm, d.lda = m, d.B = XT + k * nc, d.ldb = k;
+    d.Cin = A, d.ldcin = lda, d.cinmap = perm + k;
+    d.C = DE, d.ldc = m;
+    if ((rc = gemm_launch2(w, d, s))) return rc;
   }
   // gA(:, J) = gY(:, J) + [D | E] [X | T]^T
   {

@@ -340,3 +340,29 @@ def test_item_needing_more_workgroups_than_launched_is_abandoned_at_once():
     assert time.perf_counter() - t0 < 5.0
     assert res[0].info == mp.C["ID_INFO_ABORTED"] and res[0].k == 0
     _check_item_f64(As[1], res[1], k_req=30)
+
+
+def test_single_matrix_graph_capture():
+    """The graph-capturable single ID: a batch of one matrix (its workgroups
+    sharing the item, k and info written on the device) captured once and
+    replayed with new data and eager work in between; every replay gives the
+    oracle's pivots, R and T and the rank of id_factor."""
+    need_gpu()
+    import paper_2012_00706_amd as mp
+    A1 = _inputs([(1000, 257)], seed0=1500)[0]
+    A2 = _inputs([(1000, 257)], decay=8.0, seed0=1600)[0]
+    k1 = mp.column_id(to_dev(A1), tol=1e-6, prec="f64").k
+    k2 = mp.column_id(to_dev(A2), tol=1e-6, prec="f64").k
+    plan = mp.BatchedID([to_dev(A1)], tol=1e-6, prec="f64")
+    assert plan.groups[0] > 1  # the item is shared by several workgroups
+    g = plan.capture()
+    junk = torch.randn(256, 256, device="cuda", dtype=torch.float64)
+    for rep, (A, k) in enumerate([(A1, k1), (A2, k2), (A1, k1), (A2, k2)]):
+        plan.inputs[0].copy_(to_dev(A))
+        plan.R_buf.fill_(float("nan"))
+        plan.T_buf.fill_(float("nan"))
+        g.replay()
+        junk = junk @ junk.t() / 256.0
+        r = plan.results()[0]
+        assert r.k == k, rep
+        _check_item_f64(A, r, tol=1e-6)
