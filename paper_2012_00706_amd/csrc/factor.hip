@@ -821,8 +821,9 @@ __global__ __launch_bounds__(kThreads) void k_fold(StepArgs<S> a, double* __rest
     nf[gidx] = t;
 }
 
-// One pivot step, part 2.  Grid: ceil(ncur / kFC) blocks of kFC columns x kFL
-// tile lanes.  Finishes the reflector (dlarfg conventions), forms the new
+// One pivot step, part 2.  Grid: ceil(ncur / FC) blocks of FC columns x
+// 256 / FC tile lanes (FC = 16 for one matrix, 32 in lock-step launches).
+// Finishes the reflector (dlarfg conventions), forms the new
 // column of F and the new row of R, downdates the column norms (with the
 // cancellation test that ends the panel), and emits pivot partials.
 // Every load is issued before the first barrier (the step's row of W and of
@@ -832,11 +833,13 @@ __global__ __launch_bounds__(kThreads) void k_fold(StepArgs<S> a, double* __rest
 // Returns, in thread 0, the largest |F| entry the block formed (for the FP16
 // operand scaling of the panel update; the caller folds it into the state),
 // or -1 when the step did not run.
-template <typename S, int RM>
+template <typename S, int RM, int FC = kFC>
 __device__ __forceinline__ float finalize_block(const StepArgs<S>& a, const int bid) {
-  __shared__ double red[kFL][kFC + 1];
+  constexpr int FL = kThreads / FC;             // tile lanes per column
+  constexpr int FZ = (192 + FL - 1) / FL;      // column partials per lane and round trip
+  __shared__ double red[FL][FC + 1];
   __shared__ double ared[8][kNbMax + 1];
-  __shared__ double Fsh[kNbMax][kFC + 1];
+  __shared__ double Fsh[kNbMax][FC + 1];
   __shared__ double aux[kNbMax];
   __shared__ double vj[kNbMax];
   __shared__ double dscr[4];
@@ -845,10 +848,10 @@ __device__ __forceinline__ float finalize_block(const StepArgs<S>& a, const int 
   __shared__ int64_t s_off, s_ncur;
   __shared__ int s_swo, s_swk;
   FactorState* st = a.st;
-  const int tid = threadIdx.x, cl = tid % kFC, tl = tid / kFC;
+  const int tid = threadIdx.x, cl = tid % FC, tl = tid / FC;
   const int jj = a.jj;
   const int64_t tend = a.t0 + a.ntile;
-  const int64_t l = (int64_t)bid * kFC + cl;
+  const int64_t l = (int64_t)bid * FC + cl;
   const bool lb = l < a.ncur;  // within the host's column bound
 
   // Round trip 1: loads that depend neither on each other nor on the exact
@@ -863,27 +866,27 @@ __device__ __forceinline__ float finalize_block(const StepArgs<S>& a, const int 
   double wj = a.wrow[lc];
   int key = a.keypos[lc];
   double vjr = a.vrow[tid % kNbMax];
-  double fv[kNbMax / kFL];
+  double fv[kNbMax / FL];
 #pragma unroll
-  for (int q = 0; q < kNbMax / kFL; ++q) fv[q] = a.F[(int64_t)(tl + kFL * q) * a.ldf + lc];
+  for (int q = 0; q < kNbMax / FL; ++q) fv[q] = a.F[(int64_t)(tl + FL * q) * a.ldf + lc];
   double vsc = a.vscale[tid % kNbMax];
   // partial sums over the row tiles [t0, tend), one batch of loads per round
-  // trip (one batch covers up to kFinZ kFL = kFinA 8 = 192 tiles); tiles past
+  // trip (one batch covers up to FZ FL = kFinA 8 = 192 tiles); tiles past
   // tend read the zero row "tguard" of the partial arrays (no weights: they
   // would take a register per load)
   const int ca = tid % kNbMax, sla = tid / kNbMax;
   const int64_t caa = ca < jj ? ca : 0;
   double sz = 0.0, sa = 0.0, sn = 0.0;
   {
-    const int64_t nbz = ceil_div(a.ntile, (int64_t)kFinZ * kFL);
+    const int64_t nbz = ceil_div(a.ntile, (int64_t)FZ * FL);
     const int64_t nba = ceil_div(a.ntile, (int64_t)kFinA * 8);
     const int64_t nbn = ceil_div(a.ntile, (int64_t)kThreads);
     const int64_t nbat = nbz > nba ? (nbz > nbn ? nbz : nbn) : (nba > nbn ? nba : nbn);
     for (int64_t b = 0; b < nbat; ++b) {
-      double xz[kFinZ], xa[kFinA];
+      double xz[FZ], xa[kFinA];
 #pragma unroll
-      for (int u = 0; u < kFinZ; ++u) {
-        const int64_t t = a.t0 + tl + kFL * (b * kFinZ + u);
+      for (int u = 0; u < FZ; ++u) {
+        const int64_t t = a.t0 + tl + FL * (b * FZ + u);
         xz[u] = a.zpart[(t < tend ? t : a.tguard) * a.ldf + lc];
       }
 #pragma unroll
@@ -897,7 +900,7 @@ __device__ __forceinline__ float finalize_block(const StepArgs<S>& a, const int 
       // would wait for all loads issued so far, several times per batch)
       __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-      for (int u = 0; u < kFinZ; ++u) sz += xz[u];
+      for (int u = 0; u < FZ; ++u) sz += xz[u];
 #pragma unroll
       for (int u = 0; u < kFinA; ++u) sa += xa[u];
       sn += xn;
@@ -912,8 +915,8 @@ __device__ __forceinline__ float finalize_block(const StepArgs<S>& a, const int 
     s_swk = st->swap_key;
   }
 #pragma unroll
-  for (int q = 0; q < kNbMax / kFL; ++q)  // rows >= jj hold stale workspace data: zeroed
-    Fsh[tl + kFL * q][cl] = tl + kFL * q < jj ? fv[q] : 0.0;
+  for (int q = 0; q < kNbMax / FL; ++q)  // rows >= jj hold stale workspace data: zeroed
+    Fsh[tl + FL * q][cl] = tl + FL * q < jj ? fv[q] : 0.0;
   ared[sla][ca] = sa;  // columns >= jj unused
   red[tl][cl] = sz;    // positions >= ncur unused
 
@@ -966,7 +969,7 @@ __device__ __forceinline__ float finalize_block(const StepArgs<S>& a, const int 
   if (tl == 0 && lv) {
     double zt = 0.0;
 #pragma unroll
-    for (int q = 0; q < kFL; ++q) zt += red[q][cl];
+    for (int q = 0; q < FL; ++q) zt += red[q][cl];
     const double y = wj + scale * zt;
     double s1 = 0.0, s2 = 0.0;
     // all kNbMax slots (zero past jj): the unrolled loop issues its LDS
@@ -1003,13 +1006,13 @@ __device__ __forceinline__ float finalize_block(const StepArgs<S>& a, const int 
   }
   if (flag) st->end_flag = 1;
   // the pivot candidates and the largest |F| entry (for the FP16 operand
-  // scaling) live in lanes 0 .. kFC - 1 of the first wave (tl == 0): a
+  // scaling) live in lanes 0 .. FC - 1 of the first wave (tl == 0): a
   // reduction over those lanes, no barrier (the other lanes hold no
   // candidate, so this is the block-wide result, bit for bit)
   float fm = fabsmax;
   if (tid < 64) {
 #pragma unroll
-    for (int off = kFC / 2; off > 0; off >>= 1) {
+    for (int off = FC / 2; off > 0; off >>= 1) {
       fm = fmaxf(fm, __shfl_xor(fm, off, 64));
       AmaxVal b;
       b.v = __shfl_xor(cand.v, off, 64);
@@ -2026,6 +2029,11 @@ int factor_run_noalloc(const void* A, int32_t dtype, int64_t m, int64_t n, int64
 
 enum { LK_SWEEP = 0, LK_FIN, LK_GEMM, LK_COL, LK_INIT, LK_INGEST, LK_FINISH, LK_KINDS };
 
+// columns per finalization block in lock-step launches: a step's launch has
+// blocks for every item's columns, and each block is one memory round trip, so
+// wider blocks (fewer rounds of blocks) shorten the launch
+constexpr int kFCMany = 32;
+
 template <typename S>
 struct ManyItem {
   StepArgs<S> step;  // j: the panel's offset lower bound (a step adds jj)
@@ -2123,7 +2131,7 @@ __global__ __launch_bounds__(kThreads) void k_finalize_many(const ManyItem<S>* _
   StepArgs<S> a = load_args<S>(&q->step);
   a.j += jj;
   a.jj = jj;
-  const float fm = finalize_block<S, RM>(a, (int)blockIdx.x - q->first[LK_FIN]);
+  const float fm = finalize_block<S, RM, kFCMany>(a, (int)blockIdx.x - q->first[LK_FIN]);
   if (a.want_fmax && threadIdx.x == 0 && fm >= 0.0f)
     atomicMax(&a.st->fmax_bits, __float_as_uint(fm));
 }
@@ -2311,7 +2319,7 @@ static int make_lock_plan(const id_batch_item* items, int32_t batch, int32_t dty
     const FactorPlan& pl = lp->pl[i];
     // the grids of the first panel (offset 0) are the largest
     lp->cap[LK_SWEEP] += lockstep_sweep_blocks(pl, rt, lp->cw[i], 0);
-    lp->cap[LK_FIN] += ceil_div(pl.n, kFC);
+    lp->cap[LK_FIN] += ceil_div(pl.n, kFCMany);
     lp->cap[LK_GEMM] += round_up(ceil_div(pl.n, 64) * ceil_div(pl.m, kRowTileG), 8);
     lp->cap[LK_COL] += ceil_div(pl.n, kFinCols);
     lp->cap[LK_INIT] += init_blocks(pl);
@@ -2535,7 +2543,7 @@ static int lockstep_impl(id_batch_item* items, int32_t batch, const id_opts* o, 
       a.ntile = (int)(ceil_div(pl.m, Rt) - a.t0);
       a.nchunk = (int)ceil_div(ncur_b, a.CW);
       q.namax0 = namax_cr[i];
-      q.namax1 = (int)ceil_div(ncur_b, kFC);
+      q.namax1 = (int)ceil_div(ncur_b, kFCMany);
       q.gemm = make_gemm_args<S>(pl, wb, cur, off_lb);
       q.col = make_col_args(pl, wb, cur ^ 1, q.gemm.tg0, ncur_b, 1, count_tol, rmode,
                             &d_slots[i], seq0 + panel + 1);
