@@ -87,6 +87,7 @@ constexpr int kSweepU = 4;    // sweep rows per thread in flight in the main loo
 // the same where the step's trailing block is far larger than the caches (the
 // loop is bound by bytes in flight over memory latency, which is longer there)
 constexpr int kSweepUDeep = 8;
+constexpr double kDeepBytes = 256.0 * 1024 * 1024;  // the Infinity Cache
 // main-loop rows per thread loaded with the second round trip: 8 where the
 // registers allow it without lowering occupancy (fp32, row tiles <= 128)
 template <typename S, int G>
@@ -776,9 +777,9 @@ __device__ __forceinline__ void sweep_block(const StepArgs<S>& a, const int bid,
   }
 }
 
-template <typename S, int G>
+template <typename S, int G, int U>
 __global__ __launch_bounds__(kThreads) void k_sweep(StepArgs<S> a) {
-  sweep_block<S, G>(a, blockIdx.x, gridDim.x);
+  sweep_block<S, G, U>(a, blockIdx.x, gridDim.x);
 }
 
 // Tall inputs (more row tiles than one round trip of the finalization
@@ -1729,6 +1730,7 @@ static int factor_impl(const TA* A, int64_t lda, const FactorPlan& pl, const id_
     kslot = hslot;
   }
   const int64_t seq0 = (++ncalls) << 24;
+  const int sweep_u = env_int("MPID_SWEEP_U", 0);
   int64_t off_lb = 0;     // lower bound of the offset of the panel being enqueued
   int64_t known_off = 0;  // exact offset at the start of the first unsettled panel
   const FactorState* fin = nullptr;
@@ -1843,12 +1845,19 @@ static int factor_impl(const TA* A, int64_t lda, const FactorPlan& pl, const id_
              panel, jj, (long long)jlb, (long long)ncur_b, (long long)sh.Rt, sh.CW,
              (long long)total, a.ntile > kFinZ * kFL ? " (partials folded)" : "");
     const int64_t tag = (int64_t)panel * 1024 + jj;
+    // a trailing block beyond the Infinity Cache streams from HBM at its
+    // longer latency: more row loads in flight per thread
+    const bool deep = sweep_u > 0 ? sweep_u == kSweepUDeep
+                                  : (double)(m - jlb) * (double)ncur_b * pl.wbytes > kDeepBytes;
     if (sh.Rt >= 256)
-      prof.launch(PK_SWEEP, tag, k_sweep<S, 1>, sgrid, s, a);
+      prof.launch(PK_SWEEP, tag, deep ? k_sweep<S, 1, kSweepUDeep> : k_sweep<S, 1, kSweepU>,
+                  sgrid, s, a);
     else if (sh.Rt >= 128)
-      prof.launch(PK_SWEEP, tag, k_sweep<S, 2>, sgrid, s, a);
+      prof.launch(PK_SWEEP, tag, deep ? k_sweep<S, 2, kSweepUDeep> : k_sweep<S, 2, kSweepU>,
+                  sgrid, s, a);
     else
-      prof.launch(PK_SWEEP, tag, k_sweep<S, 4>, sgrid, s, a);
+      prof.launch(PK_SWEEP, tag, deep ? k_sweep<S, 4, kSweepUDeep> : k_sweep<S, 4, kSweepU>,
+                  sgrid, s, a);
     MPID_LAUNCH_CHECK();
     // the finalization's grid sets how many pivot partials the next sweep reads
     namax = (int)ceil_div(ncur_b, kFC);
