@@ -155,15 +155,18 @@ def sweep_source_hash() -> str:
     h = hashlib.sha256()
     text = open(SWEEP_SOURCES[0]).read()
     parts = []
-    for pat in (r"constexpr int kPrefetch[^\n]*\n", r"constexpr int kSweepU[^\n]*\n",
+    for pat in (r"constexpr int kPrefetch[^\n]*\n", r"constexpr int kSweepU [^\n]*\n",
+                r"constexpr int kSweepUDeep[^\n]*\n", r"constexpr double kDeepBytes[^\n]*\n",
                 r"template <typename S, int G>\nconstexpr int overlap_rows\(\) \{.*?\n\}\n",
                 r"template <typename S>\nstruct StepArgs \{.*?\n\};\n",
-                r"template <typename S, int G>\n__device__ __forceinline__ void "
+                r"template <typename S, int G, int U = kSweepU>\n__device__ __forceinline__ void "
                 r"sweep_block\(.*?\n\}\n",
-                r"template <typename S, int G>\n__global__ __launch_bounds__\(kThreads\) void "
-                r"k_sweep\(.*?\n\}\n"):
+                r"template <typename S, int G, int U>\n__global__ __launch_bounds__\(kThreads\) "
+                r"void k_sweep\(.*?\n\}\n"):
         mt = re.search(pat, text, flags=re.S)
-        parts.append(mt.group(0) if mt else "")
+        if not mt:  # the hash must cover the whole kernel, never a part of it
+            raise RuntimeError(f"sweep source pattern not found: {pat[:40]}")
+        parts.append(mt.group(0))
     h.update("".join(parts).encode())
     with open(SWEEP_SOURCES[1], "rb") as fh:
         h.update(fh.read())
