@@ -1047,9 +1047,9 @@ __device__ __forceinline__ float finalize_block(const StepArgs<S>& a, const int 
   return fm;
 }
 
-template <typename S, int RM>
+template <typename S, int RM, int FC>
 __global__ __launch_bounds__(kThreads) void k_finalize(StepArgs<S> a) {
-  const float fm = finalize_block<S, RM>(a, blockIdx.x);
+  const float fm = finalize_block<S, RM, FC>(a, blockIdx.x);
   // (one word for every block: its read-modify-writes queue up and the
   // launch ends only when they are done, so it is updated only when used)
   if (a.want_fmax && threadIdx.x == 0 && fm >= 0.0f)
@@ -1588,6 +1588,50 @@ static SweepShape choose_sweep_shape(int64_t rows, int64_t ncur, int wbytes) {
   return sh;
 }
 
+// ---- host resources of the calling thread
+
+// Pinned host memory, grown on demand.
+struct PinnedBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+};
+static int pinned_reserve(PinnedBuf& b, size_t bytes, unsigned flags) {
+  if (b.bytes >= bytes) return ID_OK;
+  if (b.p) MPID_HIP(hipHostFree(b.p));
+  b.p = nullptr;
+  b.bytes = 0;
+  MPID_HIP(hipHostMalloc(&b.p, bytes, flags));
+  b.bytes = bytes;
+  return ID_OK;
+}
+
+// What a thread's calls keep between calls -- pinned slots and staging
+// buffers, events -- released when the thread ends (every call has
+// synchronized its stream before returning, so nothing is in flight).
+struct ThreadRes {
+  PinnedBuf slot;                 // the single-matrix driver's two panel-end slots
+  hipEvent_t pev[2] = {nullptr, nullptr};
+  std::vector<hipEvent_t> prof_events;  // ID_FLAG_PROFILE
+  PinnedBuf stage[2], lslots[2];  // lock-step tables and panel-end states
+  hipEvent_t ev_stage[2] = {nullptr, nullptr}, ev_slot[2] = {nullptr, nullptr};
+  int64_t ncalls = 0;             // tags the panel-end states of this thread's calls
+  ThreadRes() = default;
+  ThreadRes(const ThreadRes&) = delete;
+  ThreadRes& operator=(const ThreadRes&) = delete;
+  ~ThreadRes() {
+    for (PinnedBuf* b : {&slot, &stage[0], &stage[1], &lslots[0], &lslots[1]})
+      if (b->p) (void)hipHostFree(b->p);
+    for (hipEvent_t e : {pev[0], pev[1], ev_stage[0], ev_stage[1], ev_slot[0], ev_slot[1]})
+      if (e) (void)hipEventDestroy(e);
+    for (hipEvent_t e : prof_events)
+      if (e) (void)hipEventDestroy(e);
+  }
+};
+static ThreadRes& thread_res() {
+  static thread_local ThreadRes r;
+  return r;
+}
+
 // ---- opt-in per-kernel event timing (ID_FLAG_PROFILE)
 
 static thread_local id_profile g_last_profile;
@@ -1667,10 +1711,10 @@ static int factor_impl(const TA* A, int64_t lda, const FactorPlan& pl, const id_
   double* nfoldb = (double*)(wb + pl.off_nfold);
   int* colid[2] = {(int*)(wb + pl.off_colid0), (int*)(wb + pl.off_colid1)};
   const int64_t ntg = ceil_div(m, kRowTileG);
-  static thread_local std::vector<hipEvent_t> ev_pool;
+  ThreadRes& tr = thread_res();
   Profiler prof;
   prof.on = (o->flags & ID_FLAG_PROFILE) != 0;
-  prof.pool = &ev_pool;
+  prof.pool = &tr.prof_events;
   id_profile acc;
   std::memset(&acc, 0, sizeof(acc));
   hipEvent_t ev_t0 = nullptr, ev_t1 = nullptr;
@@ -1714,22 +1758,24 @@ static int factor_impl(const TA* A, int64_t lda, const FactorPlan& pl, const id_
   // (allocated on a thread's first call, read after the panel's event), or,
   // in an allocation-free call, two slots in the workspace that the host
   // copies into host memory of its own (the copy waits for the stream).
-  static thread_local FactorHostSlot* hslot = nullptr;
-  static thread_local hipEvent_t pev[2] = {nullptr, nullptr};
-  static thread_local FactorHostSlot mirror[2];
-  static thread_local int64_t ncalls = 0;
+  FactorHostSlot mirror[2];
+  FactorHostSlot* hslot = nullptr;
+  hipEvent_t* pev = tr.pev;
   FactorHostSlot* dslot = (FactorHostSlot*)(wb + pl.off_slot);
   FactorHostSlot* kslot = dslot;  // the slots the kernels write
   if (!noalloc) {
-    if (!hslot) {
-      MPID_HIP(hipHostMalloc((void**)&hslot, 2 * sizeof(FactorHostSlot), hipHostMallocCoherent));
-      hslot[0].seq = hslot[1].seq = 0;
+    if (!tr.slot.p) {
+      const int rs = pinned_reserve(tr.slot, 2 * sizeof(FactorHostSlot), hipHostMallocCoherent);
+      if (rs) return rs;
+      FactorHostSlot* h = (FactorHostSlot*)tr.slot.p;
+      h[0].seq = h[1].seq = 0;
     }
+    hslot = (FactorHostSlot*)tr.slot.p;
     for (int q = 0; q < 2; ++q)
       if (!pev[q]) MPID_HIP(hipEventCreateWithFlags(&pev[q], hipEventDisableTiming));
     kslot = hslot;
   }
-  const int64_t seq0 = (++ncalls) << 24;
+  const int64_t seq0 = (++tr.ncalls) << 24;
   const int sweep_u = env_int("MPID_SWEEP_U", 0);
   int64_t off_lb = 0;     // lower bound of the offset of the panel being enqueued
   int64_t known_off = 0;  // exact offset at the start of the first unsettled panel
@@ -1860,6 +1906,9 @@ static int factor_impl(const TA* A, int64_t lda, const FactorPlan& pl, const id_
                   sgrid, s, a);
     MPID_LAUNCH_CHECK();
     // the finalization's grid sets how many pivot partials the next sweep reads
+    // (16 columns per block: with 32 the benchmark took 12.02-12.08 instead of
+    // 11.87-11.91 ms per ID -- one matrix's step wants more, smaller blocks)
+    const auto kfin = k_finalize<S, RM, kFC>;
     namax = (int)ceil_div(ncur_b, kFC);
     if (a.ntile > kFinZ * kFL) {
       // tall input: fold the partials so that one round trip reads them
@@ -1875,9 +1924,9 @@ static int factor_impl(const TA* A, int64_t lda, const FactorPlan& pl, const id_
       af.t0 = 0;
       af.ntile = (int)nfold;
       af.tguard = pl.nfold_max;
-      prof.launch(PK_FINALIZE, tag, k_finalize<S, RM>, dim3((unsigned)namax), s, af);
+      prof.launch(PK_FINALIZE, tag, kfin, dim3((unsigned)namax), s, af);
     } else {
-      prof.launch(PK_FINALIZE, tag, k_finalize<S, RM>, dim3((unsigned)namax), s, a);
+      prof.launch(PK_FINALIZE, tag, kfin, dim3((unsigned)namax), s, a);
     }
     MPID_LAUNCH_CHECK();
     return ID_OK;
@@ -2235,21 +2284,6 @@ __global__ __launch_bounds__(kThreads) void k_check_many(const ManyItem<S>* __re
 
 namespace {
 
-// Pinned host memory of the calling thread, grown on demand and kept.
-struct PinnedBuf {
-  void* p = nullptr;
-  size_t bytes = 0;
-};
-int pinned_reserve(PinnedBuf& b, size_t bytes) {
-  if (b.bytes >= bytes) return ID_OK;
-  if (b.p) MPID_HIP(hipHostFree(b.p));
-  b.p = nullptr;
-  b.bytes = 0;
-  MPID_HIP(hipHostMalloc(&b.p, bytes, hipHostMallocDefault));
-  b.bytes = bytes;
-  return ID_OK;
-}
-
 struct LockPlan {
   int Rt = 128;
   std::vector<FactorPlan> pl;   // per item
@@ -2370,10 +2404,11 @@ static int lockstep_impl(id_batch_item* items, int32_t batch, const id_opts* o, 
   int* d_map[LK_KINDS];
   for (int kd = 0; kd < LK_KINDS; ++kd) d_map[kd] = (int*)(shared + lp.off_map[kd]);
 
-  static thread_local PinnedBuf stage[2], hslots[2];
-  static thread_local hipEvent_t ev_stage[2] = {nullptr, nullptr};
-  static thread_local hipEvent_t ev_slot[2] = {nullptr, nullptr};
-  static thread_local int64_t ncalls = 0;
+  ThreadRes& tr = thread_res();
+  PinnedBuf* stage = tr.stage;
+  PinnedBuf* hslots = tr.lslots;
+  hipEvent_t* ev_stage = tr.ev_stage;
+  hipEvent_t* ev_slot = tr.ev_slot;
   for (int q = 0; q < 2; ++q) {
     if (!ev_stage[q]) MPID_HIP(hipEventCreateWithFlags(&ev_stage[q], hipEventDisableTiming));
     if (!ev_slot[q]) MPID_HIP(hipEventCreateWithFlags(&ev_slot[q], hipEventDisableTiming));
@@ -2383,9 +2418,9 @@ static int lockstep_impl(id_batch_item* items, int32_t batch, const id_opts* o, 
   for (int kd = 0; kd < LK_KINDS; ++kd) map_total += lp.cap[kd];
   const size_t stage_bytes = tbl_bytes + 4 * (size_t)map_total;
   for (int q = 0; q < 2; ++q) {
-    int rc = pinned_reserve(stage[q], stage_bytes);
+    int rc = pinned_reserve(stage[q], stage_bytes, hipHostMallocDefault);
     if (rc) return rc;
-    rc = pinned_reserve(hslots[q], sizeof(FactorHostSlot) * (size_t)batch);
+    rc = pinned_reserve(hslots[q], sizeof(FactorHostSlot) * (size_t)batch, hipHostMallocDefault);
     if (rc) return rc;
   }
   int upload = 0;  // uploads so far (staging buffer upload & 1)
@@ -2488,7 +2523,7 @@ static int lockstep_impl(id_batch_item* items, int32_t batch, const id_opts* o, 
   // ---- panels
   const bool count_rule = o->k_fixed == 0 && o->rank_rule == ID_RANK_PIVOT_REL;
   const double count_tol = count_rule ? o->rel_tol : -1.0;
-  const int64_t seq0 = (++ncalls) << 24;
+  const int64_t seq0 = (++tr.ncalls) << 24;
   std::vector<int> in_panel[2];  // items (caller's index) of the last two panels
   std::vector<int> order;
   std::vector<int64_t> lim;
