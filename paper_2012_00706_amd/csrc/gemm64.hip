@@ -4,6 +4,7 @@
 // the reconstruction with the skeleton held fixed.
 #include <hip/hip_runtime.h>
 
+#include <cstdlib>
 #include <cstring>
 
 #include "mpid_internal.h"
@@ -515,6 +516,244 @@ int reconstruct_run(const void* A, int32_t dtype, int64_t m, int64_t n, int64_t 
                                  s);
 }
 
+// ---------------------------------------------------------------- fused adjoint products
+
+typedef double f64x4v __attribute__((ext_vector_type(4)));
+
+// Padded copies of the coefficient blocks for the fused kernel: Xp / Tp are X
+// and T (k x nc) with the leading dimension kq = k rounded up to 16 and rows
+// k..kq-1 zero; Xq / Tq are their transposes (nc x k) with the leading
+// dimension nq = nc rounded up to 16 and rows nc..nq-1 zero.  Every 32-byte
+// group of four contraction entries a lane reads is then aligned and in range.
+__global__ __launch_bounds__(kThreads) void k_adj_prep(const double* __restrict__ X, int64_t ldx,
+                                                       const double* __restrict__ T, int64_t ldt,
+                                                       int64_t k, int64_t nc, int64_t kq,
+                                                       int64_t nq, double* __restrict__ Xp,
+                                                       double* __restrict__ Tp,
+                                                       double* __restrict__ Xq,
+                                                       double* __restrict__ Tq) {
+  __shared__ double tx[32][33], tt[32][33];
+  const int lx = threadIdx.x % 32, ly = threadIdx.x / 32;  // 32 x 8
+  const int64_t r0 = (int64_t)blockIdx.x * 32, c0 = (int64_t)blockIdx.y * 32;  // r: k, c: nc
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int64_t r = r0 + lx, c = c0 + ly + 8 * q;
+    const bool in = r < k && c < nc;
+    const double x = in ? X[c * ldx + r] : 0.0, t = in ? T[c * ldt + r] : 0.0;
+    if (r < kq && c < nc) {
+      Xp[c * kq + r] = x;
+      Tp[c * kq + r] = t;
+    }
+    tx[ly + 8 * q][lx] = x;
+    tt[ly + 8 * q][lx] = t;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int64_t c = c0 + lx, r = r0 + ly + 8 * q;  // Xq(c, r) = X(r, c)
+    if (r < k && c < nq) {
+      Xq[r * nq + c] = tx[lx][ly + 8 * q];
+      Tq[r * nq + c] = tt[lx][ly + 8 * q];
+    }
+  }
+}
+
+template <typename TA>
+struct AdjArgs {
+  int64_t m, k, nc, kq, nq;
+  const double* Bm;  // B = A(:, J), m x k, ld m
+  const double* Xp;  // X, kq x nc (rows past k zero)
+  const double* Tp;  // T, kq x nc
+  const double* Xq;  // X^T, nq x k (rows past nc zero)
+  const double* Tq;  // T^T, nq x k
+  const TA* A;
+  int64_t lda;
+  const double* gY;  // may be null
+  int64_t ldgy;
+  const int32_t* perm;  // J = perm[0:k], Jc = perm[k:n]
+  double* gA;
+  int64_t ldga;
+};
+
+constexpr int kAdjRows = 16;    // rows of A per block (one matrix-core row block)
+constexpr int kAdjChunk = 128;  // coefficient columns per pass
+constexpr int kAdjKMax = 256;   // largest k the fused kernel takes
+
+// The adjoint's products for a strip of 16 rows i, without D and E in memory.
+// For each chunk of 128 columns j of the n - k coefficient columns:
+//   phase 1: P_X = B(i, :) X(:, j), P_T = B(i, :) T(:, j)        (K = k)
+//            gA(i, Jc[j]) = P_X,  E = gY(i, Jc[j]) - P_X,  D = A(i, Jc[j]) - P_T
+//            (E and D go to LDS)
+//   phase 2: acc(i, c) += sum_j D(i, j) X(c, j) + E(i, j) T(c, j)   (K = 2 x 128)
+// and finally gA(i, J[c]) = gY(i, J[c]) + acc(i, c).  Wave w owns columns
+// [32 w, 32 w + 32) of each chunk in phase 1 and NB2 blocks of 16 columns c
+// of k in phase 2 (4 NB2 16 >= k).  Operand lanes: a lane supplies A(row li,
+// kk) and B(kk, col li) and receives C(row li, col g + 4 r) (operands fed
+// swapped, as in k_gemm64t).  The contraction runs in groups of 16 in which
+// lane group g takes the four consecutive entries 4 g .. 4 g + 3, so a lane
+// reads each B operand as one aligned 32-byte load per group (from the padded
+// copies, L2-resident), two groups ahead of their products; the A operands
+// come from LDS in the same order.  Columns past nc or k read clamped
+// in-range columns and are never stored; rows past m are zero in LDS and not
+// stored.
+template <typename TA, int NB2>
+__global__ __launch_bounds__(kThreads) void k_adj_fused(AdjArgs<TA> a) {
+  constexpr int KB = 64 * NB2;                  // largest k of this instantiation
+  __shared__ double Bs[KB][kAdjRows];           // Bs[kk][i] = B(i0 + i, kk)
+  __shared__ double Es[kAdjChunk][kAdjRows];    // Es[j][i] = E(i0 + i, c0 + j)
+  __shared__ double Ds[kAdjChunk][kAdjRows];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wv = tid >> 6, g = lane >> 4, li = lane & 15;
+  const int64_t m = a.m, k = a.k, nc = a.nc;
+  const int64_t i0 = (int64_t)blockIdx.x * kAdjRows;
+  const int64_t i = i0 + li;  // this lane's output row
+  const int64_t ic = i < m ? i : m - 1;
+  const int ng1 = (int)(a.kq / 16);  // contraction groups of phase 1
+  // the strip of B (rows past m and columns past k zero)
+  for (int e = tid; e < KB * kAdjRows; e += kThreads) {
+    const int r = e % kAdjRows, kk = e / kAdjRows;
+    const int64_t gi = i0 + r;
+    Bs[kk][r] = (gi < m && kk < k) ? a.Bm[(int64_t)kk * m + gi] : 0.0;
+  }
+  f64x4 acc2[NB2], acc3[NB2];
+#pragma unroll
+  for (int nb = 0; nb < NB2; ++nb) {
+    acc2[nb] = (f64x4){0.0, 0.0, 0.0, 0.0};
+    acc3[nb] = acc2[nb];
+  }
+  for (int64_t c0 = 0; c0 < nc; c0 += kAdjChunk) {
+    // the epilogue's inputs: rows i, columns Jc[j] for the lane's outputs
+    // j = c0 + 32 w + 16 nb + g + 4 r (loaded ahead of the products)
+    double ein[2][4], cin[2][4];
+#pragma unroll
+    for (int nb = 0; nb < 2; ++nb)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t j = c0 + 32 * wv + 16 * nb + g + 4 * r;
+        const int64_t col = a.perm[k + (j < nc ? j : nc - 1)];
+        ein[nb][r] = a.gY ? a.gY[col * a.ldgy + ic] : 0.0;
+        cin[nb][r] = (double)a.A[col * a.lda + ic];
+      }
+    __syncthreads();  // Bs ready (first pass); Es / Ds free (later passes)
+    // ---- phase 1, one 16-column block nb at a time: the B operands are
+    // columns j = c0 + 32 w + 16 nb + li of X and T, two groups in flight
+    f64x4 px[2], pt[2];
+#pragma unroll
+    for (int nb = 0; nb < 2; ++nb) {
+      const int64_t j = c0 + 32 * wv + 16 * nb + li;
+      const int64_t jc = j < nc ? j : nc - 1;
+      const double* xcol = a.Xp + jc * a.kq + 4 * g;
+      const double* tcol = a.Tp + jc * a.kq + 4 * g;
+      f64x4 ax = (f64x4){0.0, 0.0, 0.0, 0.0}, at = ax;
+      f64x4v x0 = *(const f64x4v*)xcol, t0 = *(const f64x4v*)tcol, x1 = x0, t1 = t0;
+      if (ng1 > 1) {
+        x1 = *(const f64x4v*)(xcol + 16);
+        t1 = *(const f64x4v*)(tcol + 16);
+      }
+      for (int q = 0; q < ng1; q += 2) {
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+          const double af = Bs[16 * q + 4 * g + s][li];
+          ax = __builtin_amdgcn_mfma_f64_16x16x4f64(x0[s], af, ax, 0, 0, 0);
+          at = __builtin_amdgcn_mfma_f64_16x16x4f64(t0[s], af, at, 0, 0, 0);
+        }
+        if (q + 2 < ng1) {
+          x0 = *(const f64x4v*)(xcol + 16 * (q + 2));
+          t0 = *(const f64x4v*)(tcol + 16 * (q + 2));
+        }
+        if (q + 1 < ng1) {
+#pragma unroll
+          for (int s = 0; s < 4; ++s) {
+            const double af = Bs[16 * (q + 1) + 4 * g + s][li];
+            ax = __builtin_amdgcn_mfma_f64_16x16x4f64(x1[s], af, ax, 0, 0, 0);
+            at = __builtin_amdgcn_mfma_f64_16x16x4f64(t1[s], af, at, 0, 0, 0);
+          }
+          if (q + 3 < ng1) {
+            x1 = *(const f64x4v*)(xcol + 16 * (q + 3));
+            t1 = *(const f64x4v*)(tcol + 16 * (q + 3));
+          }
+        }
+      }
+      px[nb] = ax;
+      pt[nb] = at;
+    }
+    // ---- epilogue: gA(i, Jc[j]) = P_X; E and D to LDS (zero past nc / m)
+#pragma unroll
+    for (int nb = 0; nb < 2; ++nb)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int jl = 32 * wv + 16 * nb + g + 4 * r;
+        const int64_t j = c0 + jl;
+        const bool ok = j < nc && i < m;
+        const double w = px[nb][r];
+        if (ok) a.gA[(int64_t)a.perm[k + j] * a.ldga + i] = w;
+        Es[jl][li] = ok ? ein[nb][r] - w : 0.0;
+        Ds[jl][li] = ok ? cin[nb][r] - pt[nb][r] : 0.0;
+      }
+    __syncthreads();
+    // ---- phase 2, one 16-column block nb of k at a time: acc2 += D X(c, j)^T
+    // and acc3 += E T(c, j)^T over the chunk's j (two independent chains), the
+    // B operands read from the transposed copies (j consecutive)
+    {
+      const int64_t jn = nc - c0 < kAdjChunk ? nc - c0 : kAdjChunk;
+      const int ng2 = (int)ceil_div(jn, (int64_t)16);
+#pragma unroll
+      for (int nb = 0; nb < NB2; ++nb) {
+        const int64_t c = (int64_t)16 * (NB2 * wv + nb) + li;
+        const int64_t cc = c < k ? c : k - 1;
+        const double* xrow = a.Xq + cc * a.nq + c0 + 4 * g;
+        const double* trow = a.Tq + cc * a.nq + c0 + 4 * g;
+        f64x4 ax = acc2[nb], at = acc3[nb];
+        f64x4v x0 = *(const f64x4v*)xrow, t0 = *(const f64x4v*)trow, x1 = x0, t1 = t0;
+        if (ng2 > 1) {
+          x1 = *(const f64x4v*)(xrow + 16);
+          t1 = *(const f64x4v*)(trow + 16);
+        }
+        for (int q = 0; q < ng2; q += 2) {
+#pragma unroll
+          for (int s = 0; s < 4; ++s) {
+            const int jl = 16 * q + 4 * g + s;
+            ax = __builtin_amdgcn_mfma_f64_16x16x4f64(x0[s], Ds[jl][li], ax, 0, 0, 0);
+            at = __builtin_amdgcn_mfma_f64_16x16x4f64(t0[s], Es[jl][li], at, 0, 0, 0);
+          }
+          if (q + 2 < ng2) {
+            x0 = *(const f64x4v*)(xrow + 16 * (q + 2));
+            t0 = *(const f64x4v*)(trow + 16 * (q + 2));
+          }
+          if (q + 1 < ng2) {
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+              const int jl = 16 * (q + 1) + 4 * g + s;
+              ax = __builtin_amdgcn_mfma_f64_16x16x4f64(x1[s], Ds[jl][li], ax, 0, 0, 0);
+              at = __builtin_amdgcn_mfma_f64_16x16x4f64(t1[s], Es[jl][li], at, 0, 0, 0);
+            }
+            if (q + 3 < ng2) {
+              x1 = *(const f64x4v*)(xrow + 16 * (q + 3));
+              t1 = *(const f64x4v*)(trow + 16 * (q + 3));
+            }
+          }
+        }
+        acc2[nb] = ax;
+        acc3[nb] = at;
+      }
+    }
+  }
+  // ---- gA(i, J[c]) = gY(i, J[c]) + acc2
+  if (i < m) {
+#pragma unroll
+    for (int nb = 0; nb < NB2; ++nb)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t c = (int64_t)16 * (NB2 * wv + nb) + g + 4 * r;
+        if (c < k) {
+          const int64_t col = a.perm[c];
+          const double y = a.gY ? a.gY[col * a.ldgy + i] : 0.0;
+          a.gA[col * a.ldga + i] = y + (acc2[nb][r] + acc3[nb][r]);
+        }
+      }
+  }
+}
+
 // ---------------------------------------------------------------- adjoint
 
 // B^T gY(:, Jc) has few output tiles: its contraction is split for about this
@@ -524,7 +763,7 @@ constexpr int kBwdSketchBlocks = 1024;
 
 struct BwdPlan {
   size_t off_b, off_de, off_xt, off_tbar, off_rq, off_permq, off_info, off_fws, off_btg, off_sk,
-      off_p;
+      off_p, off_pad;
   size_t fws_bytes, sk_bytes, p_bytes, bytes;
 };
 
@@ -562,6 +801,9 @@ static bool make_bwd_plan(int64_t m, int64_t n, int64_t k, BwdPlan* p) {
   // split-K partials of the m x k product with the 2(n-k) contraction
   p->p_bytes = gemm64_split_workspace(mm, kk, 2 * cc);
   p->off_p = take(p->p_bytes > 0 ? p->p_bytes : 8);
+  // the fused products' padded coefficient copies: X, T (k rounded up to 16
+  // rows) and their transposes (n - k rounded up to 16 rows)
+  p->off_pad = take((size_t)4 * round_up(kk, 16) * round_up(cc, 16) * 8);
   p->bytes = off;
   return true;
 }
@@ -569,6 +811,52 @@ static bool make_bwd_plan(int64_t m, int64_t n, int64_t k, BwdPlan* p) {
 size_t backward_workspace(int64_t m, int64_t n, int64_t k) {
   BwdPlan p;
   return make_bwd_plan(m, n, k, &p) ? p.bytes : 0;
+}
+
+static int env_flag(const char* name, int dflt) {
+  const char* v = std::getenv(name);
+  return (v && *v) ? std::atoi(v) : dflt;
+}
+
+// The products of the adjoint as separate launches (any k): W with E beside
+// it and D in one launch of the large-tile kernel, then gA(:, J) over the
+// 2 (n - k) contraction with split K.
+template <typename TA>
+static int products_unfused(const TA* A, int64_t m, int64_t k, int64_t nc, int64_t lda,
+                            const int32_t* perm, const double* T, int64_t ldt, const double* gY,
+                            int64_t ldgy, double* gA, int64_t ldga, const double* Bm, double* DE,
+                            double* XT, double* P, size_t p_bytes, hipStream_t s) {
+  int rc;
+  const double* X = XT;
+  if ((rc = gather<double>(T, ldt, k, nullptr, nc, XT + k * nc, k, nullptr, 0, s))) return rc;
+  // gA(:, Jc) = W = B X with E = gY(:, Jc) - W beside it, and D = A(:, Jc) - B T:
+  // two products with the operand B, one launch
+  {
+    G64Args<double, TA> w, d;
+    std::memset(&w, 0, sizeof(w));
+    w.M = m, w.N = nc, w.K = k, w.alpha = 1.0;
+    w.A = Bm, w.lda = m, w.B = X, w.ldb = k;
+    w.C = gA, w.ldc = ldga, w.cmap = perm + k;
+    w.E = DE + m * nc, w.lde = m, w.Ein = gY, w.ldein = ldgy, w.einmap = perm + k;
+    std::memset(&d, 0, sizeof(d));
+    d.M = m, d.N = nc, d.K = k, d.alpha = -1.0, d.beta = 1.0;
+    d.A = Bm, d.lda = m, d.B = XT + k * nc, d.ldb = k;
+    d.Cin = A, d.ldcin = lda, d.cinmap = perm + k;
+    d.C = DE, d.ldc = m;
+    if ((rc = gemm_launch2(w, d, s))) return rc;
+  }
+  // gA(:, J) = gY(:, J) + [D | E] [X | T]^T
+  {
+    G64Args<double, double> a;
+    std::memset(&a, 0, sizeof(a));
+    a.tb = 1;
+    a.M = m, a.N = k, a.K = 2 * nc, a.alpha = 1.0, a.beta = gY ? 1.0 : 0.0;
+    a.A = DE, a.lda = m, a.B = XT, a.ldb = k;
+    a.Cin = gY, a.ldcin = ldgy, a.cinmap = perm;
+    a.C = gA, a.ldc = ldga, a.cmap = perm;
+    if ((rc = gemm_launch(a, s, P, p_bytes))) return rc;
+  }
+  return ID_OK;
 }
 
 // With B = A(:, J), C = A(:, Jc), T = B^+ C and X = (B^T B)^{-1} Tbar,
@@ -651,33 +939,30 @@ static int backward_impl(const TA* A, int64_t m, int64_t n, int64_t lda, const i
   double* X = XT;
   if ((rc = trsm_upper_run(Rf, ldrf, k, Tb, k, nc, Tb, k, 1, s))) return rc;
   if ((rc = trsm_upper_run(Rf, ldrf, k, Tb, k, nc, X, k, 0, s))) return rc;
-  if ((rc = gather<double>(T, ldt, k, nullptr, nc, XT + k * nc, k, nullptr, 0, s))) return rc;
-  // gA(:, Jc) = W = B X with E = gY(:, Jc) - W beside it, and D = A(:, Jc) - B T:
-  // two products with the operand B, one launch
-  {
-    G64Args<double, TA> w, d;
-    std::memset(&w, 0, sizeof(w));
-    w.M = m, w.N = nc, w.K = k, w.alpha = 1.0;
-    w.A = Bm, w.lda = m, w.B = X, w.ldb = k;
-    w.C = gA, w.ldc = ldga, w.cmap = perm + k;
-    w.E = DE + m * nc, w.lde = m, w.Ein = gY, w.ldein = ldgy, w.einmap = perm + k;
-    std::memset(&d, 0, sizeof(d));
-    d.M = m, d.N = nc, d.K = k, d.alpha = -1.0, d.beta = 1.0;
-    d.A = Bm, d.lda = m, d.B = XT + k * nc, d.ldb = k;
-    d.Cin = A, d.ldcin = lda, d.cinmap = perm + k;
-    d.C = DE, d.ldc = m;
-    if ((rc = gemm_launch2(w, d, s))) return rc;
-  }
-  // gA(:, J) = gY(:, J) + [D | E] [X | T]^T
-  {
-    G64Args<double, double> a;
-    std::memset(&a, 0, sizeof(a));
-    a.tb = 1;
-    a.M = m, a.N = k, a.K = 2 * nc, a.alpha = 1.0, a.beta = gY ? 1.0 : 0.0;
-    a.A = DE, a.lda = m, a.B = XT, a.ldb = k;
-    a.Cin = gY, a.ldcin = ldgy, a.cinmap = perm;
-    a.C = gA, a.ldc = ldga, a.cmap = perm;
-    if ((rc = gemm_launch(a, s, (double*)(wb + p.off_p), p.p_bytes))) return rc;
+  double* pad = (double*)(wb + p.off_pad);
+  // (the fused kernel reads the padded copies in aligned 32-byte groups)
+  if (k <= kAdjKMax && (uintptr_t)pad % 32 == 0 && env_flag("MPID_ADJ_FUSED", 1)) {
+    // all three products in one pass over 16-row strips (D and E stay in LDS)
+    const int64_t kq = round_up(k, 16), nq = round_up(nc, 16);
+    double *Xp = pad, *Tp = pad + kq * nq, *Xq = pad + 2 * kq * nq, *Tq = pad + 3 * kq * nq;
+    k_adj_prep<<<dim3((unsigned)ceil_div(kq, 32), (unsigned)ceil_div(nq, 32)), kThreads, 0, s>>>(
+        X, k, T, ldt, k, nc, kq, nq, Xp, Tp, Xq, Tq);
+    MPID_LAUNCH_CHECK();
+    AdjArgs<TA> fa;
+    fa.m = m, fa.k = k, fa.nc = nc, fa.kq = kq, fa.nq = nq;
+    fa.Bm = Bm, fa.Xp = Xp, fa.Tp = Tp, fa.Xq = Xq, fa.Tq = Tq;
+    fa.A = A, fa.lda = lda, fa.gY = gY, fa.ldgy = ldgy, fa.perm = perm;
+    fa.gA = gA, fa.ldga = ldga;
+    const dim3 fg((unsigned)ceil_div(m, kAdjRows));
+    if (k <= 128)
+      k_adj_fused<TA, 2><<<fg, kThreads, 0, s>>>(fa);
+    else
+      k_adj_fused<TA, 4><<<fg, kThreads, 0, s>>>(fa);
+    MPID_LAUNCH_CHECK();
+  } else {
+    if ((rc = products_unfused<TA>(A, m, k, nc, lda, perm, T, ldt, gY, ldgy, gA, ldga, Bm, DE, XT,
+                                   (double*)(wb + p.off_p), p.p_bytes, s)))
+      return rc;
   }
   int32_t hinfo = 0;
   MPID_HIP(hipMemcpyAsync(&hinfo, dinfo, 4, hipMemcpyDeviceToHost, s));
@@ -685,6 +970,7 @@ static int backward_impl(const TA* A, int64_t m, int64_t n, int64_t lda, const i
   if (hinfo == ID_INFO_SINGULAR) *info = ID_INFO_SINGULAR;  // gA is then undefined
   return ID_OK;
 }
+
 
 int backward_run(const void* A, int32_t dtype, int64_t m, int64_t n, int64_t lda,
                  const int32_t* perm, int64_t k, const double* T, int64_t ldt, const double* Rb,

@@ -120,3 +120,27 @@ def test_backward_with_forward_R_factor():
     assert rel_err(g1, g0) <= 1e-12
     ref = orc.adjoint(A, host(res.perm).astype(np.int64), 40, host(res.T), gT=host(gT), gY=host(gY))
     assert rel_err(g1, ref) <= 1e-10
+
+
+@pytest.mark.parametrize("m,n,k,fused", [(600, 300, 200, "1"), (531, 190, 129, "1"),
+                                         (300, 80, 20, "0"), (700, 330, 270, "1"),
+                                         (1000, 400, 150, "0")])
+def test_backward_product_paths(monkeypatch, m, n, k, fused):
+    """Both product paths of id_backward against the oracle's adjoint: the
+    fused pass over 16-row strips (skeletons up to 256 columns; 129..256 use
+    four column blocks per wave) and the separate large-tile launches (forced,
+    or k > 256), with ragged strips and coefficient chunks."""
+    need_gpu()
+    import paper_2012_00706_amd as mp
+    monkeypatch.setenv("MPID_ADJ_FUSED", fused)
+    rng = np.random.default_rng(m + 7 * k)
+    A = synth.spectrum_matrix(m, n, synth.sigma_exp(min(m, n), 40.0), m + 1, n + 1)
+    res = mp.column_id(to_dev(A), k=k)
+    perm = host(res.perm).astype(np.int64)
+    T = host(res.T)
+    gT = rng.standard_normal(T.shape)
+    gY = rng.standard_normal((m, n))
+    gA = host(mp.backward(to_dev(A), res.perm, k, res.T, gT=to_dev(gT), gY=to_dev(gY),
+                          R11=res.R[:, :k]))
+    ref = orc.adjoint(A, perm, k, T, gT=gT, gY=gY)
+    assert rel_err(gA, ref) <= 1e-10
