@@ -610,8 +610,9 @@ def run_config5(args):
                  {"forward_ms": fwd_ms, "rel_err_vs_oracle_adjoint": err,
                   "backward_with_forward_R_ms": bwdR_ms,
                   "roofline": {"kernel": "id_backward reusing R11 (whole call: the skeleton "
-                                         "gather, two triangular solves, four FP64 MFMA "
-                                         "product launches of 10 m k (n-k) flops)",
+                                         "gather, the split-K product B^T gY, two triangular "
+                                         "solves, the fused pass of the three remaining "
+                                         "products; 10 m k (n-k) FP64 MFMA flops)",
                                "bound": "mfma",
                                "achieved": gemm_flops / (bwdR_ms * 1e-3) / 1e12, "peak": 78.6,
                                "unit": "TFLOP/s",
