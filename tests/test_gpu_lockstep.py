@@ -209,3 +209,58 @@ def test_lockstep_workload_full_size_properties():
         ref = orc.cpqr(A, k=r.k)
         e_ref = orc.id_error(A, ref.perm, r.k, orc.solve_T(ref.R, r.k))[0]
         assert e <= 1.1 * e_ref + 10 * U_LOW["mixed_bf16x3"] * 1.0  # sigma_1 = 1
+
+
+def test_lockstep_simulated_single_matches_single_path():
+    """The simulated single precision ID (every kept value rounded to binary32,
+    the FP32 update) in lock step gives each item the rank, pivots and
+    (rounded) T of column_id with the same options."""
+    need_gpu()
+    import paper_2012_00706_amd as mp
+    As = [to_dev(A.astype(np.float32)) for A in _inputs([(1500, 300), (800, 120)], seed0=980)]
+    res = mp.factor_lockstep(As, tol=1e-4, prec="mixed_f32", round_to="f32")
+    for A, r in zip(As, res):
+        one = mp.column_id(A, tol=1e-4, prec="mixed_f32", round_to="f32")
+        assert r.k == one.k
+        assert np.array_equal(host(r.perm), host(one.perm))
+        T1 = np.asarray(host(one.T))
+        Tl = np.asarray(host(r.T))
+        # T rounded to binary32 on both sides
+        assert np.array_equal(Tl.astype(np.float32).astype(np.float64), Tl)
+        assert np.max(np.abs(Tl - T1)) <= 1e-5 * max(np.max(np.abs(T1)), 1.0)
+
+
+def test_concurrent_calls_from_two_threads():
+    """Two host threads factoring on their own streams at the same time (each
+    with its own pinned panel-end slots) get the results of sequential calls."""
+    need_gpu()
+    import threading
+    import paper_2012_00706_amd as mp
+    As = [to_dev(A) for A in _inputs([(3000, 400), (2500, 350)], seed0=990)]
+    ref = [mp.column_id(A, tol=1e-8, prec="f64") for A in As]
+    torch.cuda.synchronize()
+    out = [None, None]
+    errs = []
+
+    def work(idx):
+        try:
+            s = torch.cuda.Stream()
+            with torch.cuda.stream(s):
+                for _ in range(3):
+                    r = mp.column_id(As[idx], tol=1e-8, prec="f64")
+                s.synchronize()
+                out[idx] = r
+        except Exception as e:  # noqa: BLE001 -- reported below
+            errs.append(e)
+
+    ts = [threading.Thread(target=work, args=(i,)) for i in range(2)]
+    for t in ts:
+        t.start()
+    for t in ts:
+        t.join()
+    assert not errs, errs
+    for r, q in zip(out, ref):
+        assert r.k == q.k
+        assert np.array_equal(host(r.perm), host(q.perm))
+        assert np.array_equal(host(r.R), host(q.R))
+        assert np.array_equal(host(r.T), host(q.T))
