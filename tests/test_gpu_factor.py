@@ -270,3 +270,43 @@ def test_tall_input_folded_partials(prec):
         ref = orc.cpqr(A32.astype(np.float64), k=40)
         assert k == 40 and perm[:40].tolist() == ref.perm[:40].tolist()
         assert rel_err(T, orc.solve_T(ref.R, 40)) <= 1e-4
+
+
+# ---------------------------------------------------------------- metamorphic invariances
+
+@pytest.mark.parametrize("prec", ["f64", "mixed_bf16x3", "mixed_f32"])
+def test_power_of_two_scaling_is_exact(prec):
+    """Scaling A by 2^s scales every floating-point value the factorization
+    forms by exactly 2^s (no rounding changes; no value reaches the FP16
+    scaling's range limits here), so pivots, k and T are bitwise unchanged and
+    R is exactly 2^s times R."""
+    need_gpu()
+    A = synth.spectrum_matrix(1500, 260, synth.sigma_exp(260, 30.0), 61, 62).astype(np.float32)
+    p1, k1, R1, T1 = gpu_id(A, tol=1e-4, prec=prec)
+    for s in (-7, 5):
+        As = (A * np.float32(2.0 ** s)).astype(np.float32)
+        p2, k2, R2, T2 = gpu_id(As, tol=1e-4, prec=prec)
+        assert k1 == k2 and np.array_equal(p1, p2), (prec, s)
+        assert np.array_equal(R1 * 2.0 ** s, R2), (prec, s)
+        assert np.array_equal(T1, T2), (prec, s)
+
+
+def test_row_and_column_permutations():
+    """FP64 path: permuting the rows of A leaves the pivots, |R| and T
+    unchanged (to rounding); permuting its columns permutes the pivots the
+    same way (gap-separated input: no near-ties)."""
+    need_gpu()
+    rng = np.random.default_rng(63)
+    A = synth.spectrum_matrix(900, 180, synth.sigma_geom10(180, 10.0), 63, 64)
+    k = 40
+    p1, _, R1, T1 = gpu_id(A, k=k, prec="f64")
+    rows = rng.permutation(A.shape[0])
+    p2, _, R2, T2 = gpu_id(np.asfortranarray(A[rows]), k=k, prec="f64")
+    assert np.array_equal(p1, p2)
+    assert np.max(np.abs(np.abs(R2) - np.abs(R1))) <= 1e-12 * np.max(np.abs(R1))
+    assert np.max(np.abs(T2 - T1)) <= 1e-10 * max(np.max(np.abs(T1)), 1.0)
+    cols = rng.permutation(A.shape[1])
+    p3, _, R3, _ = gpu_id(np.asfortranarray(A[:, cols]), k=k, prec="f64")
+    assert np.array_equal(cols[p3[:k]], p1[:k])
+    assert np.max(np.abs(np.abs(np.diag(R3[:, :k])) - np.abs(np.diag(R1[:, :k])))) <= \
+        1e-12 * abs(R1[0, 0])
