@@ -486,7 +486,8 @@ def run_config3(args):
         pt = PathTimer(A, prec, tol=1e-3)
         ms, wall, fr, T = pt.timed(max(args.steps // 5, 2), 1)
         prof = pt.profiled(1)
-        res[prec] = dict(ms=ms, k=fr.k, prof=prof, tflops=useful_flops(m, n, fr.k) / (ms * 1e-3) / 1e12)
+        res[prec] = dict(ms=ms, k=fr.k, prof=prof, perm=fr.perm[:fr.k].cpu(),
+                         tflops=useful_flops(m, n, fr.k) / (ms * 1e-3) / 1e12)
         log(f"[bench] {prec}: k={fr.k} {ms:.2f} ms/ID")
         del pt
         torch.cuda.empty_cache()
@@ -494,6 +495,9 @@ def run_config3(args):
     import paper_2012_00706_amd as mp
     gms, gres = _timed(lambda: mp.column_id(A, tol=1e-3, gram=True), 3, 1)
     log(f"[bench] gram front end: k={gres.k} {gms:.2f} ms/ID")
+    # the CholeskyQR3 front end (FP64 Householder pivots of the n x n R factor)
+    cms, cres = _timed(lambda: mp.column_id(A, tol=1e-3, cholqr=True), 3, 1)
+    log(f"[bench] cholqr front end: k={cres.k} info={cres.info} {cms:.2f} ms/ID")
     sk = _sketch_front_end(A, 320, 1e-3, 3)
     log(f"[bench] sketch front end (l=320): k={sk['k']} {sk['ms_per_id']:.2f} ms/ID "
         f"(sketch {sk['sketch_kernel_ms']:.2f} ms, {sk['sketch_roofline']['achieved']:.1f} TFLOP/s)")
@@ -508,6 +512,11 @@ def run_config3(args):
                  "speedup_vs_fp64": res["f64"]["ms"] / mx["ms"],
                  "gram_front_end": {"ms_per_id": gms, "k": gres.k,
                                     "speedup_vs_mixed": mx["ms"] / gms},
+                 "cholqr_front_end": {"ms_per_id": cms, "k": cres.k, "info": cres.info,
+                                      "speedup_vs_mixed": mx["ms"] / cms,
+                                      "same_pivots_as_fp64": bool(
+                                          cres.k == res["f64"]["k"] and torch.equal(
+                                              cres.J.cpu().int(), res["f64"]["perm"]))},
                  "sketch_front_end": sk,
                  "roofline": _sweep_roofline(mx["prof"]),
                  "kernel_ms_per_id": {key: mx["prof"][key] for key in

@@ -42,6 +42,7 @@ extern "C" {
 #define ID_INFO_RANK_FULL 3     /* k = n: T has no columns, P is a permutation */
 #define ID_INFO_ABORTED 4       /* batched item abandoned (see id_factor_batched) */
 #define ID_INFO_GRAM_LIMIT 5    /* ID_FLAG_GRAM stopped at its resolution floor (see id_factor) */
+#define ID_INFO_CHOLQR_BREAKDOWN 6 /* ID_FLAG_CHOLQR: A lacks full numerical column rank (k = 0) */
 
 /* Most workgroups that may share one batched item. */
 #define ID_BATCH_MAX_GROUPS 16
@@ -87,6 +88,8 @@ extern "C" {
 #define ID_FLAG_PROFILE 2  /* time every kernel with HIP events (see id_last_profile) */
 #define ID_FLAG_GRAM 4     /* tall-skinny front end: pivots and R from the FP64 Gram
                               matrix A^T A (one pivoted Cholesky); see id_factor */
+#define ID_FLAG_CHOLQR 32  /* tall-skinny front end: the pivoted factorization of the
+                              n x n R factor of a shifted CholeskyQR3; see id_factor */
 /* Simulated low precision (Section 3: variables held in single or half
  * precision while arithmetic accumulates in higher precision): every value the
  * factorization keeps -- the working copy, the reflectors, F, the rows of R,
@@ -97,7 +100,7 @@ extern "C" {
  * so tiny values underflow as in the paper's simulation.  id_round then gives
  * the coefficients T the same precision.  ID_FLAG_ROUND_F32 takes
  * ID_PREC_MIXED_F32 and ID_FLAG_ROUND_F16 takes ID_PREC_MIXED_F16 (other
- * combinations are invalid arguments); not with ID_FLAG_GRAM. */
+ * combinations are invalid arguments); not with ID_FLAG_GRAM or ID_FLAG_CHOLQR. */
 #define ID_FLAG_ROUND_F32 8
 #define ID_FLAG_ROUND_F16 16
 
@@ -129,8 +132,8 @@ size_t id_workspace_size(int64_t m, int64_t n, int32_t dtype, const id_opts* opt
  *                factor in pivot order are written (zeros below the diagonal);
  *                rows k..kcap-1 are left untouched.
  *   k_out  [host,out] the rank k.
- *   info   [host,out] 0, ID_INFO_NONFINITE, or (ID_FLAG_GRAM only)
- *          ID_INFO_GRAM_LIMIT.
+ *   info   [host,out] 0, ID_INFO_NONFINITE, or ID_INFO_GRAM_LIMIT
+ *          (ID_FLAG_GRAM) / ID_INFO_CHOLQR_BREAKDOWN (ID_FLAG_CHOLQR).
  *
  * ID_FLAG_GRAM (tall inputs): pivots and R come from a pivoted Cholesky
  * factorization of the FP64 Gram matrix A^T A (equal to the Householder
@@ -141,6 +144,23 @@ size_t id_workspace_size(int64_t m, int64_t n, int32_t dtype, const id_opts* opt
  * included, with info = ID_INFO_GRAM_LIMIT and k the steps completed (R and T
  * of those steps are valid).  The flag supports k <= 2048 and no
  * ID_FLAG_NO_PIVOT / ID_FLAG_PROFILE.
+ *
+ * ID_FLAG_CHOLQR (tall inputs, m >= n): A = Q R0 from three CholeskyQR passes
+ * (the first with a shift of 11 (m n + n (n + 1)) 2^-53 ||A||_F^2, each pass a
+ * Gram product and a right multiplication by the inverse factor on the FP64
+ * matrix cores), then the FP64 pivoted factorization of the n x n R0, whose
+ * pivots and R are those of A: residual norms resolved down to about
+ * 2^-53 ||A|| (the Gram front end: about 2^-26.5 ||A||).  Needs full
+ * numerical column rank: the shifted pass leaves A R1^{-1} with a condition
+ * number of about kappa(A) sqrt(11 (m n + n^2) 2^-53), which the plain
+ * passes take only below about 2^26.5, so kappa(A) must stay below about
+ * 2^53 / sqrt(11 (m n + n^2)) (2e12 at 3000 x 200).  Beyond that a Cholesky
+ * pivot fails or R3 is not near the identity: info = ID_INFO_CHOLQR_BREAKDOWN
+ * and k = 0 (nothing factored; perm = identity).  A = 0 gives k = 0, info 0.
+ * The workspace holds two m x n FP64 copies.  opts->prec is ignored (the
+ * factorization of R0 is FP64); ID_FLAG_GRAM, ID_FLAG_NO_PIVOT,
+ * ID_FLAG_PROFILE and the ROUND flags are refused (ID_ERR_UNSUPPORTED), as is
+ * m < n.
  *
  * Pivoting follows the largest remaining column norm with ties going to the
  * first column in the current (LAPACK swap) order.  The call enqueues work on
@@ -167,7 +187,7 @@ int id_factor(const void* A, int32_t dtype, int64_t m, int64_t n, int64_t lda,
  *   Arguments as in id_factor, without work / work_bytes.
  *   Returns ID_ERR_SCRATCH when id_workspace_size(m, n, dtype, opts) exceeds
  *   id_noalloc_scratch_bytes() (nothing is enqueued), ID_ERR_UNSUPPORTED for
- *   ID_FLAG_GRAM or ID_FLAG_PROFILE, ID_ERR_ARG when "stream" does not belong
+ *   ID_FLAG_GRAM, ID_FLAG_CHOLQR or ID_FLAG_PROFILE, ID_ERR_ARG when "stream" does not belong
  *   to the current device (whose scratch is used).
  * Every call on one GPU shares that GPU's scratch, which keeps the last
  * call's contents (each call initializes what it reads before reading it):
@@ -352,8 +372,8 @@ int id_factor_batched(id_batch_item* items, int32_t batch, const int32_t* slots,
  *               Out: k and info (ID_INFO_NONFINITE, ID_INFO_SINGULAR,
  *               ID_INFO_RANK_FULL or 0, as id_factor then id_solve_T report).
  *               "groups" is ignored.
- *   dtype, opts as in id_factor (ID_FLAG_GRAM and ID_FLAG_PROFILE refused:
- *               ID_ERR_UNSUPPORTED).
+ *   dtype, opts as in id_factor (ID_FLAG_GRAM, ID_FLAG_CHOLQR and
+ *               ID_FLAG_PROFILE refused: ID_ERR_UNSUPPORTED).
  *   work        shared device workspace of id_lockstep_workspace_size bytes
  *               (item tables and block maps).
  * Returns ID_ERR_ARG / ID_ERR_WORKSPACE / ID_ERR_DTYPE for invalid arguments,

@@ -53,7 +53,7 @@ ROUND = {None: 0, "f32": 1, "f16": 2}
 
 
 def make_opts(k=None, tol=None, prec="f64", rule="pivot_rel", k_max=0, nb=0, no_pivot=False,
-              profile=False, gram=False, round_to=None):
+              profile=False, gram=False, round_to=None, cholqr=False):
     """round_to: None, "f32" or "f16" -- the simulated single / half precision
     of the paper's Section 3 (ID_FLAG_ROUND_F32 / ID_FLAG_ROUND_F16)."""
     if prec not in PREC:
@@ -73,6 +73,7 @@ def make_opts(k=None, tol=None, prec="f64", rule="pivot_rel", k_max=0, nb=0, no_
     o.nb = int(nb)
     o.flags = ((C["ID_FLAG_NO_PIVOT"] if no_pivot else 0) | (C["ID_FLAG_PROFILE"] if profile else 0)
                | (C["ID_FLAG_GRAM"] if gram else 0)
+               | (C["ID_FLAG_CHOLQR"] if cholqr else 0)
                | (C["ID_FLAG_ROUND_F32"] if round_to == "f32" else 0)
                | (C["ID_FLAG_ROUND_F16"] if round_to == "f16" else 0))
     if k is not None and int(k) == 0:
@@ -104,16 +105,18 @@ class FactorResult:
 def factor(A: torch.Tensor, k=None, tol=None, prec="f64", rule="pivot_rel", k_max=0, nb=0,
            no_pivot=False, work: torch.Tensor | None = None, R_buf: torch.Tensor | None = None,
            perm_buf: torch.Tensor | None = None, profile: bool = False,
-           gram: bool = False, round_to=None) -> FactorResult:
+           gram: bool = False, round_to=None, cholqr: bool = False) -> FactorResult:
     """Rank-k column-pivoted QR (id_factor).  k=0 gives k = 0.  gram=True takes
-    the tall-skinny front end (pivots and R from the FP64 Gram matrix)."""
+    the tall-skinny front end (pivots and R from the FP64 Gram matrix);
+    cholqr=True the one through a shifted CholeskyQR3 R factor (full
+    numerical column rank required; info ID_INFO_CHOLQR_BREAKDOWN otherwise)."""
     lib = _lib.load()
     A, lda = colmajor(A)
     m, n = A.shape
     if k is not None and int(k) == 0:
         return FactorResult(torch.arange(n, dtype=torch.int32, device=A.device),
                             empty_colmajor(0, n, device=A.device), 0, 0)
-    o = make_opts(k, tol, prec, rule, k_max, nb, no_pivot, profile, gram, round_to)
+    o = make_opts(k, tol, prec, rule, k_max, nb, no_pivot, profile, gram, round_to, cholqr)
     ws = workspace_size(m, n, A.dtype, o)
     if ws == 0:
         raise ValueError("invalid factorization arguments")
@@ -284,12 +287,12 @@ def round_(X: torch.Tensor, mode: str) -> torch.Tensor:
 
 
 def column_id(A: torch.Tensor, k=None, tol=None, prec="f64", rule="pivot_rel", k_max=0, nb=0,
-              gram=False, round_to=None):
+              gram=False, round_to=None, cholqr=False):
     """Algorithm 1 (prec="f64") or Algorithm 2's mixed variant end to end
     (gram=True: the Gram-matrix front end for tall inputs; round_to="f32" /
     "f16": the simulated single / half precision ID, T rounded too)."""
     fr = factor(A, k=k, tol=tol, prec=prec, rule=rule, k_max=k_max, nb=nb, gram=gram,
-                round_to=round_to)
+                round_to=round_to, cholqr=cholqr)
     n = A.shape[1]
     T, _ = solve_T(fr.R, fr.k, n)
     if round_to is not None:

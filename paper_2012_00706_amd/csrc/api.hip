@@ -29,7 +29,9 @@ void log_printf(const char* fmt, ...) {
 extern "C" {
 
 size_t id_workspace_size(int64_t m, int64_t n, int32_t dtype, const id_opts* opts) {
+  if (opts && (opts->flags & ID_FLAG_GRAM) && (opts->flags & ID_FLAG_CHOLQR)) return 0;
   if (opts && (opts->flags & ID_FLAG_GRAM)) return mpid::gram_workspace(m, n, dtype, opts);
+  if (opts && (opts->flags & ID_FLAG_CHOLQR)) return mpid::cholqr_workspace(m, n, dtype, opts);
   mpid::FactorPlan p;
   if (!mpid::make_factor_plan(m, n, dtype, opts, &p)) return 0;
   return p.bytes;
@@ -44,9 +46,13 @@ int id_factor(const void* A, int32_t dtype, int64_t m, int64_t n, int64_t lda,
       opts->prec != ID_PREC_MIXED_BF16 && opts->prec != ID_PREC_MIXED_BF16X3 &&
       opts->prec != ID_PREC_MIXED_F32)
     return ID_ERR_DTYPE;
+  if ((opts->flags & ID_FLAG_GRAM) && (opts->flags & ID_FLAG_CHOLQR)) return ID_ERR_ARG;
   if (opts->flags & ID_FLAG_GRAM)
     return mpid::gram_factor_run(A, dtype, m, n, lda, opts, work, work_bytes, perm, R, ldr, k_out,
                                  info, (hipStream_t)stream);
+  if (opts->flags & ID_FLAG_CHOLQR)
+    return mpid::cholqr_factor_run(A, dtype, m, n, lda, opts, work, work_bytes, perm, R, ldr,
+                                   k_out, info, (hipStream_t)stream);
   return mpid::factor_run(A, dtype, m, n, lda, opts, work, work_bytes, perm, R, ldr, k_out, info,
                           (hipStream_t)stream);
 }
@@ -144,6 +150,8 @@ const char* id_status_string(int code) {
       return "batched item abandoned: a workgroup sharing it did not arrive in time";
     case ID_INFO_GRAM_LIMIT:
       return "Gram front end stopped at its resolution floor (k is the steps completed)";
+    case ID_INFO_CHOLQR_BREAKDOWN:
+      return "CholeskyQR front end: A lacks full numerical column rank (nothing factored)";
     default:
       return "unknown code";
   }

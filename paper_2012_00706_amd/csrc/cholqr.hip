@@ -1,0 +1,293 @@
+// Tall-skinny front end through a shifted CholeskyQR3 R factor
+// (ID_FLAG_CHOLQR).
+//
+// The column-pivoted QR of A and of any R0 with A = Q R0 (Q with orthonormal
+// columns) are the same factorization: the column norms and every Householder
+// step agree (Section 1.1, eq. (6)-(7)), so the pivots and R of A are those of
+// the n x n matrix R0.  R0 comes from three CholeskyQR passes (shifted
+// CholeskyQR3, Fukaya, Kannan, Nakatsukasa, Yamamoto and Yanagisawa 2020):
+//   R1 = chol(A^T A + s I),  s = 11 (m n + n (n + 1)) u_64 ||A||_F^2,
+//   A1 = A R1^{-1},  R2 = chol(A1^T A1),  A2 = A1 R2^{-1},  R3 = chol(A2^T A2),
+//   R0 = R3 R2 R1.
+// The shift keeps the first Cholesky factorization defined; the two plain
+// passes restore A = Q R0 to working precision.  Each pass reads its matrix
+// twice on the FP64 matrix cores (the Gram product and the right
+// multiplication by R^{-1}); the pivoted factorization (FP64 Householder, the
+// single-matrix path) then runs on R0.  Unlike the Gram front end, residual
+// norms are resolved down to about u_64 ||A|| instead of sqrt(u_64) ||A||.
+// The route needs A to have full numerical column rank: the shift leaves A1
+// with a condition number of about kappa(A) sqrt(11 (m n + n^2) u_64), and
+// the plain passes need it below about u_64^{-1/2}.  When a plain pass breaks
+// down, or R3 is not close to the identity (A2 not orthonormal), the call
+// reports ID_INFO_CHOLQR_BREAKDOWN and factors nothing (k = 0).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+
+#include "device_util.h"
+#include "mpid_internal.h"
+
+namespace mpid {
+
+namespace {
+
+constexpr int kCB = 64;  // Cholesky panel width
+
+// Flags written by the device (int32 each): [0] A non-finite, [1] a Cholesky
+// pivot not positive / not finite, [2] R3 far from the identity, [3] A = 0.
+enum { CF_NONFINITE = 0, CF_BREAKDOWN = 1, CF_NOT_ORTHO = 2, CF_ZERO = 3, CF_COUNT = 4 };
+
+__global__ void k_cq_zero_flags(int32_t* f) {
+  if (threadIdx.x < CF_COUNT) f[threadIdx.x] = 0;
+}
+
+// X = I (n x n, ld n).
+__global__ __launch_bounds__(kThreads) void k_cq_eye(double* __restrict__ X, int64_t n) {
+  const int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (e >= n * n) return;
+  X[e] = (e / n == e % n) ? 1.0 : 0.0;
+}
+
+// G_ii += c trace(G), one block; flags a zero A (trace 0).
+__global__ __launch_bounds__(kThreads) void k_cq_shift(double* __restrict__ G, int64_t n,
+                                                       double c, int32_t* __restrict__ flags) {
+  __shared__ double dscr[4];
+  double t = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += kThreads) t += G[i * n + i];
+  t = block_sum(t, dscr);
+  if (threadIdx.x == 0 && t == 0.0) flags[CF_ZERO] = 1;
+  const double s = c * t;
+  for (int64_t i = threadIdx.x; i < n; i += kThreads) G[i * n + i] += s;
+}
+
+// Cholesky factorization of the diagonal block G(p0 : p0 + nb, same) after
+// the earlier panels' updates (upper factor R_pp with R_pp^T R_pp = G_pp), in
+// LDS; writes R(p0 + i, p0 + j) for j >= i, zeros the block's rows left of
+// its diagonal (R is upper triangular throughout), and flags a pivot that is
+// not positive and finite (replaced by 1 so that nothing becomes NaN).
+__global__ __launch_bounds__(kThreads) void k_cq_chol_diag(const double* __restrict__ G, int64_t n,
+                                                           int64_t p0, int nb,
+                                                           double* __restrict__ R,
+                                                           int32_t* __restrict__ flags) {
+  __shared__ double Gs[kCB][kCB + 1];
+  __shared__ double s_r;
+  const int tid = threadIdx.x;
+  for (int e = tid; e < kCB * kCB; e += kThreads) {
+    const int i = e % kCB, j = e / kCB;
+    // the upper triangle (j >= i), read as G(p0 + i, p0 + j)
+    Gs[i][j] = (i < nb && j < nb && j >= i) ? G[(p0 + j) * n + p0 + i] : 0.0;
+  }
+  __syncthreads();
+  for (int c = 0; c < nb; ++c) {
+    if (tid == 0) {
+      double d = Gs[c][c];
+      if (!(d > 0.0) || !isfinite(d)) {
+        flags[CF_BREAKDOWN] = 1;
+        d = 1.0;
+      }
+      s_r = sqrt(d);
+      Gs[c][c] = s_r;
+    }
+    __syncthreads();
+    const double rinv = 1.0 / s_r;
+    for (int j = c + 1 + tid; j < nb; j += kThreads) Gs[c][j] *= rinv;
+    __syncthreads();
+    // trailing update of the upper triangle: G(i, j) -= R(c, i) R(c, j), c < i <= j
+    const int w = nb - c - 1;
+    for (int e = tid; e < w * w; e += kThreads) {
+      const int i = c + 1 + e % w, j = c + 1 + e / w;
+      if (j >= i) Gs[i][j] -= Gs[c][i] * Gs[c][j];
+    }
+    __syncthreads();
+  }
+  for (int e = tid; e < kCB * kCB; e += kThreads) {
+    const int i = e % kCB, j = e / kCB;
+    if (i < nb && j < nb) R[(p0 + j) * n + p0 + i] = j >= i ? Gs[i][j] : 0.0;
+  }
+  // rows of the block left of it
+  for (int64_t e = tid; e < (int64_t)nb * p0; e += kThreads) {
+    const int64_t i = e % nb, j = e / nb;
+    R[j * n + p0 + i] = 0.0;
+  }
+}
+
+// flags[CF_NOT_ORTHO] when some |R3(i, j) - delta_ij| > 1/4 (the last pass
+// should have met an orthonormal A2), one block.
+__global__ __launch_bounds__(kThreads) void k_cq_check_identity(const double* __restrict__ R,
+                                                                int64_t n,
+                                                                int32_t* __restrict__ flags) {
+  __shared__ double dscr[4];
+  double bad = 0.0;
+  for (int64_t e = threadIdx.x; e < n * n; e += kThreads) {
+    const int64_t i = e % n, j = e / n;
+    const double v = R[e] - (i == j ? 1.0 : 0.0);
+    if (!(fabs(v) <= 0.25)) bad = 1.0;
+  }
+  bad = block_sum(bad, dscr);
+  if (threadIdx.x == 0 && bad > 0.0) flags[CF_NOT_ORTHO] = 1;
+}
+
+__global__ void k_cq_iota(int32_t* perm, int64_t n) {
+  const int64_t l = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (l < n) perm[l] = (int32_t)l;
+}
+
+struct CqPlan {
+  int64_t m, n;
+  size_t off_g, off_r[3], off_rinv, off_r0, off_tmp, off_part, off_a[2], off_flags, off_inner;
+  size_t part_bytes, inner_bytes, bytes;
+  id_opts inner;  // the pivoted factorization of R0 (FP64)
+};
+
+bool make_cq_plan(int64_t m, int64_t n, int32_t dtype, const id_opts* o, CqPlan* p) {
+  if (!o || !p || m < 0 || n < 0) return false;
+  if (dtype != ID_F32 && dtype != ID_F64) return false;
+  std::memset(p, 0, sizeof(*p));
+  p->m = m;
+  p->n = n;
+  p->inner = *o;
+  p->inner.prec = ID_PREC_F64;
+  p->inner.flags = 0;
+  FactorPlan fp;
+  const int64_t nn = n > 0 ? n : 1, mm = m > 0 ? m : 1;
+  if (!make_factor_plan(nn, nn, ID_F64, &p->inner, &fp)) return false;
+  p->inner_bytes = fp.bytes;
+  p->part_bytes = gram_matrix_workspace(mm, nn);
+  if (p->part_bytes == 0) return false;
+  size_t off = 0;
+  auto take = [&](size_t b) {
+    const size_t at = off;
+    off += (b + 255) / 256 * 256;
+    return at;
+  };
+  const size_t n2 = (size_t)nn * nn * 8;
+  p->off_g = take(n2);
+  for (int q = 0; q < 3; ++q) p->off_r[q] = take(n2);
+  p->off_rinv = take(n2);
+  p->off_r0 = take(n2);
+  p->off_tmp = take(n2);
+  p->off_part = take(p->part_bytes);
+  p->off_a[0] = take((size_t)mm * nn * 8);
+  p->off_a[1] = take((size_t)mm * nn * 8);
+  p->off_flags = take(CF_COUNT * 4);
+  p->off_inner = take(p->inner_bytes);
+  p->bytes = off;
+  return true;
+}
+
+// R = chol(G) by 64-column panels: the diagonal block in LDS, the block row
+// right of it by a triangular solve with its transpose, the trailing matrix
+// updated on the matrix cores.  G is overwritten.
+int cholesky_run(double* G, int64_t n, double* R, int32_t* flags, hipStream_t s) {
+  for (int64_t p0 = 0; p0 < n; p0 += kCB) {
+    const int nb = (int)(n - p0 < kCB ? n - p0 : kCB);
+    k_cq_chol_diag<<<1, kThreads, 0, s>>>(G, n, p0, nb, R, flags);
+    MPID_LAUNCH_CHECK();
+    const int64_t r0 = p0 + nb, nr = n - r0;
+    if (nr <= 0) continue;
+    // R(p0 : r0, r0 : n) = R_pp^{-T} G(p0 : r0, r0 : n)
+    int rc = trsm_upper_run(R + p0 * n + p0, n, nb, G + r0 * n + p0, n, nr, R + r0 * n + p0, n, 1,
+                            s);
+    if (rc) return rc;
+    // G(r0 : n, r0 : n) -= R(p0 : r0, r0 : n)^T R(p0 : r0, r0 : n)
+    rc = gemm64_run(1, 0, nr, nr, nb, -1.0, R + r0 * n + p0, n, R + r0 * n + p0, n, 1.0,
+                    G + r0 * n + r0, n, s);
+    if (rc) return rc;
+  }
+  return ID_OK;
+}
+
+}  // namespace
+
+size_t cholqr_workspace(int64_t m, int64_t n, int32_t dtype, const id_opts* o) {
+  CqPlan p;
+  if (!make_cq_plan(m, n, dtype, o, &p)) return 0;
+  return p.bytes;
+}
+
+int cholqr_factor_run(const void* A, int32_t dtype, int64_t m, int64_t n, int64_t lda,
+                      const id_opts* o, void* work, size_t work_bytes, int32_t* perm, double* R,
+                      int64_t ldr, int64_t* k_out, int32_t* info, hipStream_t s) {
+  if (!o) return ID_ERR_ARG;
+  if (o->flags & (ID_FLAG_GRAM | ID_FLAG_NO_PIVOT | ID_FLAG_PROFILE | ID_FLAG_ROUND_F32 |
+                  ID_FLAG_ROUND_F16))
+    return ID_ERR_UNSUPPORTED;
+  CqPlan pl;
+  if (!make_cq_plan(m, n, dtype, o, &pl)) return ID_ERR_ARG;
+  if (!k_out || !info) return ID_ERR_ARG;
+  if (n > 0 && !perm) return ID_ERR_ARG;
+  if (m > 0 && n > 0 && !A) return ID_ERR_ARG;
+  if (lda < (m > 1 ? m : 1)) return ID_ERR_ARG;
+  FactorPlan fp;
+  if (!make_factor_plan(m, n, dtype, o, &fp)) return ID_ERR_ARG;
+  if (fp.kcap > 0 && (!R || ldr < fp.kcap)) return ID_ERR_ARG;
+  if (m < n) return ID_ERR_UNSUPPORTED;  // R0 needs full column rank: a tall A
+  if (!work || work_bytes < pl.bytes) return ID_ERR_WORKSPACE;
+  *info = 0;
+  *k_out = 0;
+  if (m == 0 || n == 0 || fp.kcap == 0) {
+    if (n > 0) {
+      k_cq_iota<<<dim3((unsigned)ceil_div(n, kThreads)), kThreads, 0, s>>>(perm, n);
+      MPID_LAUNCH_CHECK();
+    }
+    return ID_OK;
+  }
+  char* wb = (char*)work;
+  double* G = (double*)(wb + pl.off_g);
+  double* Rk[3] = {(double*)(wb + pl.off_r[0]), (double*)(wb + pl.off_r[1]),
+                   (double*)(wb + pl.off_r[2])};
+  double* Rinv = (double*)(wb + pl.off_rinv);
+  double* R0 = (double*)(wb + pl.off_r0);
+  double* Tmp = (double*)(wb + pl.off_tmp);
+  double* Ab[2] = {(double*)(wb + pl.off_a[0]), (double*)(wb + pl.off_a[1])};
+  int32_t* flags = (int32_t*)(wb + pl.off_flags);
+  int rc;
+  k_cq_zero_flags<<<1, 64, 0, s>>>(flags);
+  MPID_LAUNCH_CHECK();
+  const unsigned eye_blocks = (unsigned)ceil_div(n * n, kThreads);
+  for (int q = 0; q < 3; ++q) {
+    // this pass's matrix: A, then A1, A2 (float64, ld m)
+    const void* Aq = q == 0 ? A : (const void*)Ab[q - 1];
+    const int32_t dq = q == 0 ? dtype : ID_F64;
+    const int64_t ldq = q == 0 ? lda : m;
+    if ((rc = gram_matrix_run(Aq, dq, m, n, ldq, G, wb + pl.off_part, pl.part_bytes,
+                              &flags[CF_NONFINITE], s)))
+      return rc;
+    if (q == 0) {
+      const double c = 11.0 * ((double)m * (double)n + (double)n * (double)(n + 1)) *
+                       std::ldexp(1.0, -53);
+      k_cq_shift<<<1, kThreads, 0, s>>>(G, n, c, flags);
+      MPID_LAUNCH_CHECK();
+    }
+    if ((rc = cholesky_run(G, n, Rk[q], flags, s))) return rc;
+    if (q < 2) {
+      // the next pass's matrix: Aq R_q^{-1}
+      k_cq_eye<<<eye_blocks, kThreads, 0, s>>>(Rinv, n);
+      MPID_LAUNCH_CHECK();
+      if ((rc = trsm_upper_run(Rk[q], n, n, Rinv, n, n, Rinv, n, 0, s))) return rc;
+      if ((rc = gemm64_typed_run(Aq, dq, m, n, n, ldq, Rinv, n, Ab[q], m, s))) return rc;
+    }
+  }
+  k_cq_check_identity<<<1, kThreads, 0, s>>>(Rk[2], n, flags);
+  MPID_LAUNCH_CHECK();
+  // R0 = R3 R2 R1
+  if ((rc = gemm64_run(0, 0, n, n, n, 1.0, Rk[2], n, Rk[1], n, 0.0, Tmp, n, s))) return rc;
+  if ((rc = gemm64_run(0, 0, n, n, n, 1.0, Tmp, n, Rk[0], n, 0.0, R0, n, s))) return rc;
+  int32_t hf[CF_COUNT];
+  MPID_HIP(hipMemcpyAsync(hf, flags, sizeof(hf), hipMemcpyDeviceToHost, s));
+  MPID_HIP(hipStreamSynchronize(s));
+  if (hf[CF_NONFINITE] || hf[CF_ZERO] || hf[CF_BREAKDOWN] || hf[CF_NOT_ORTHO]) {
+    // a zero A has rank 0 (k = 0, info 0), like the other routes
+    *info = hf[CF_NONFINITE] ? ID_INFO_NONFINITE : hf[CF_ZERO] ? 0 : ID_INFO_CHOLQR_BREAKDOWN;
+    k_cq_iota<<<dim3((unsigned)ceil_div(n, kThreads)), kThreads, 0, s>>>(perm, n);
+    MPID_LAUNCH_CHECK();
+    return ID_OK;
+  }
+  // the pivoted factorization of the n x n R0 (same rank rule and options)
+  return factor_run(R0, ID_F64, n, n, n, &pl.inner, wb + pl.off_inner, pl.inner_bytes, perm, R,
+                    ldr, k_out, info, s);
+}
+
+}  // namespace mpid

@@ -2065,7 +2065,7 @@ int factor_run(const void* A, int32_t dtype, int64_t m, int64_t n, int64_t lda,
 int factor_run_noalloc(const void* A, int32_t dtype, int64_t m, int64_t n, int64_t lda,
                        const id_opts* o, void* work, size_t work_bytes, int32_t* perm, double* R,
                        int64_t ldr, int64_t* k_out, int32_t* info, hipStream_t s) {
-  if (o && (o->flags & (ID_FLAG_GRAM | ID_FLAG_PROFILE))) return ID_ERR_UNSUPPORTED;
+  if (o && (o->flags & (ID_FLAG_GRAM | ID_FLAG_CHOLQR | ID_FLAG_PROFILE))) return ID_ERR_UNSUPPORTED;
   return factor_dispatch(A, dtype, m, n, lda, o, work, work_bytes, perm, R, ldr, k_out, info,
                          true, s);
 }
@@ -2309,7 +2309,7 @@ static int make_lock_plan(const id_batch_item* items, int32_t batch, int32_t dty
                           const id_opts* o, LockPlan* lp) {
   if (!items || batch < 0 || !o) return ID_ERR_ARG;
   if (dtype != ID_F32 && dtype != ID_F64) return ID_ERR_DTYPE;
-  if (o->flags & (ID_FLAG_GRAM | ID_FLAG_PROFILE)) return ID_ERR_UNSUPPORTED;
+  if (o->flags & (ID_FLAG_GRAM | ID_FLAG_CHOLQR | ID_FLAG_PROFILE)) return ID_ERR_UNSUPPORTED;
   lp->pl.resize(batch);
   lp->cw.resize(batch);
   int64_t max_m = 0;

@@ -415,6 +415,26 @@ static int gemm_launch2(const G64Args<TA, TC>& a0, const G64Args<TA, TC>& a1, hi
   return ID_OK;
 }
 
+// C = A B with A (M x K) in its storage dtype (fp32 or fp64, column-major, lda)
+// and B, C float64.
+int gemm64_typed_run(const void* A, int32_t dtype, int64_t M, int64_t N, int64_t K, int64_t lda,
+                     const double* B, int64_t ldb, double* C, int64_t ldc, hipStream_t s) {
+  if (dtype == ID_F64) {
+    G64Args<double, double> a;
+    std::memset(&a, 0, sizeof(a));
+    a.M = M, a.N = N, a.K = K, a.alpha = 1.0;
+    a.A = (const double*)A, a.lda = lda, a.B = B, a.ldb = ldb;
+    a.C = C, a.ldc = ldc;
+    return gemm_launch(a, s);
+  }
+  G64Args<float, double> a;
+  std::memset(&a, 0, sizeof(a));
+  a.M = M, a.N = N, a.K = K, a.alpha = 1.0;
+  a.A = (const float*)A, a.lda = lda, a.B = B, a.ldb = ldb;
+  a.C = C, a.ldc = ldc;
+  return gemm_launch(a, s);
+}
+
 int gemm64_run(int ta, int tb, int64_t M, int64_t N, int64_t K, double alpha, const double* A,
                int64_t lda, const double* B, int64_t ldb, double beta, double* C, int64_t ldc,
                hipStream_t s) {

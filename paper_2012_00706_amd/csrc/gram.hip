@@ -247,7 +247,7 @@ k_gram_partial64(const TA* __restrict__ A, int64_t lda, int64_t m, int64_t n, in
 __global__ __launch_bounds__(kThreads) void k_gram_reduce(const double* __restrict__ P, int64_t S,
                                                          int64_t ntiles, int64_t nt, int64_t gt,
                                                          int64_t n, double* __restrict__ G,
-                                                         GramState* st) {
+                                                         int32_t* info) {
   const int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x;
   const int64_t tt = gt * gt;
   if (e >= ntiles * tt) return;
@@ -263,7 +263,7 @@ __global__ __launch_bounds__(kThreads) void k_gram_reduce(const double* __restri
   if (I == J && w / gt > w % gt) return;  // diagonal tiles: upper half only (symmetric G)
   double v = 0.0;
   for (int64_t s = 0; s < S; ++s) v += P[(s * ntiles + tile) * tt + w];
-  if (!isfinite(v)) st->info = ID_INFO_NONFINITE;
+  if (!isfinite(v)) *info = ID_INFO_NONFINITE;
   G[jj * n + ii] = v;
   G[ii * n + jj] = v;
 }
@@ -502,6 +502,62 @@ __global__ void k_gram_state_init(GramState* st) {
   }
 }
 
+// G = A^T A in FP64 (both triangles): the partial tiles over row chunks, then
+// their sum in a fixed order; a non-finite entry sets *info.
+static int gram_product(const void* A, int32_t dtype, int64_t m, int64_t n, int64_t lda,
+                        const GramPlan& pl, double* P, double* G, int32_t* info, hipStream_t s) {
+  {
+    const dim3 g1((unsigned)round_up(pl.S * pl.ntiles, 8));
+    // 16-byte loads need 16-byte aligned columns of A
+    const int64_t esz = dtype == ID_F64 ? 8 : 4;
+    const bool vec = ((uintptr_t)A % 16 == 0) && ((lda * esz) % 16 == 0);
+    if (dtype == ID_F64) {
+      if (vec)
+        k_gram_partial64<double, true><<<g1, kThreads, 0, s>>>(
+            (const double*)A, lda, m, n, pl.nt, pl.ntiles, pl.S, pl.chunk, P);
+      else
+        k_gram_partial64<double, false><<<g1, kThreads, 0, s>>>(
+            (const double*)A, lda, m, n, pl.nt, pl.ntiles, pl.S, pl.chunk, P);
+    } else {
+      if (vec)
+        k_gram_partial64<float, true><<<g1, kThreads, 0, s>>>(
+            (const float*)A, lda, m, n, pl.nt, pl.ntiles, pl.S, pl.chunk, P);
+      else
+        k_gram_partial64<float, false><<<g1, kThreads, 0, s>>>(
+            (const float*)A, lda, m, n, pl.nt, pl.ntiles, pl.S, pl.chunk, P);
+    }
+  }
+  MPID_LAUNCH_CHECK();
+  k_gram_reduce<<<dim3((unsigned)ceil_div(pl.ntiles * pl.gt * pl.gt, kThreads)), kThreads, 0, s>>>(
+      P, pl.S, pl.ntiles, pl.nt, pl.gt, n, G, info);
+  MPID_LAUNCH_CHECK();
+  return ID_OK;
+}
+
+// For other front ends: the bytes of partial tiles gram_matrix_run needs, and
+// G = A^T A (FP64, n x n, both triangles) with *info = ID_INFO_NONFINITE if A
+// holds NaN/Inf (info is left alone otherwise).
+size_t gram_matrix_workspace(int64_t m, int64_t n) {
+  id_opts o;
+  std::memset(&o, 0, sizeof(o));
+  o.k_fixed = 1;
+  GramPlan pl;
+  if (!make_gram_plan(m, n, ID_F64, &o, &pl)) return 0;
+  return (size_t)pl.S * pl.ntiles * pl.gt * pl.gt * 8;
+}
+
+int gram_matrix_run(const void* A, int32_t dtype, int64_t m, int64_t n, int64_t lda, double* G,
+                    void* part, size_t part_bytes, int32_t* info, hipStream_t s) {
+  id_opts o;
+  std::memset(&o, 0, sizeof(o));
+  o.k_fixed = 1;
+  GramPlan pl;
+  if (!make_gram_plan(m, n, dtype, &o, &pl)) return ID_ERR_ARG;
+  if (part_bytes < (size_t)pl.S * pl.ntiles * pl.gt * pl.gt * 8) return ID_ERR_WORKSPACE;
+  if (m <= 0 || n <= 0) return ID_OK;
+  return gram_product(A, dtype, m, n, lda, pl, (double*)part, G, info, s);
+}
+
 int gram_factor_run(const void* A, int32_t dtype, int64_t m, int64_t n, int64_t lda,
                     const id_opts* o, void* work, size_t work_bytes, int32_t* perm, double* R,
                     int64_t ldr, int64_t* k_out, int32_t* info, hipStream_t s) {
@@ -534,30 +590,9 @@ int gram_factor_run(const void* A, int32_t dtype, int64_t m, int64_t n, int64_t 
   k_gram_state_init<<<1, 64, 0, s>>>(st);
   MPID_LAUNCH_CHECK();
   {
-    const dim3 g1((unsigned)round_up(pl.S * pl.ntiles, 8));
-    // 16-byte loads need 16-byte aligned columns of A
-    const int64_t esz = dtype == ID_F64 ? 8 : 4;
-    const bool vec = ((uintptr_t)A % 16 == 0) && ((lda * esz) % 16 == 0);
-    if (dtype == ID_F64) {
-      if (vec)
-        k_gram_partial64<double, true><<<g1, kThreads, 0, s>>>(
-            (const double*)A, lda, m, n, pl.nt, pl.ntiles, pl.S, pl.chunk, P);
-      else
-        k_gram_partial64<double, false><<<g1, kThreads, 0, s>>>(
-            (const double*)A, lda, m, n, pl.nt, pl.ntiles, pl.S, pl.chunk, P);
-    } else {
-      if (vec)
-        k_gram_partial64<float, true><<<g1, kThreads, 0, s>>>(
-            (const float*)A, lda, m, n, pl.nt, pl.ntiles, pl.S, pl.chunk, P);
-      else
-        k_gram_partial64<float, false><<<g1, kThreads, 0, s>>>(
-            (const float*)A, lda, m, n, pl.nt, pl.ntiles, pl.S, pl.chunk, P);
-    }
+    const int rg = gram_product(A, dtype, m, n, lda, pl, P, G, &st->info, s);
+    if (rg) return rg;
   }
-  MPID_LAUNCH_CHECK();
-  k_gram_reduce<<<dim3((unsigned)ceil_div(pl.ntiles * pl.gt * pl.gt, kThreads)), kThreads, 0, s>>>(
-      P, pl.S, pl.ntiles, pl.nt, pl.gt, n, G, st);
-  MPID_LAUNCH_CHECK();
   k_pchol_init<<<dim3((unsigned)pl.nblk), kThreads, 0, s>>>(G, n, d, pv, pos[0], am[0], st);
   MPID_LAUNCH_CHECK();
 

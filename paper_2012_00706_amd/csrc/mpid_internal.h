@@ -83,7 +83,8 @@ int factor_run(const void* A, int32_t dtype, int64_t m, int64_t n, int64_t lda,
 // The same factorization for callers that cannot allocate: "work" is the
 // library's static scratch, the host reads each panel's end state with a copy
 // into host memory it already owns (no pinned slot, no events), so nothing is
-// allocated.  ID_FLAG_GRAM and ID_FLAG_PROFILE are refused (ID_ERR_UNSUPPORTED).
+// allocated.  ID_FLAG_GRAM, ID_FLAG_CHOLQR and ID_FLAG_PROFILE are refused
+// (ID_ERR_UNSUPPORTED).
 int factor_run_noalloc(const void* A, int32_t dtype, int64_t m, int64_t n, int64_t lda,
                        const id_opts* o, void* work, size_t work_bytes, int32_t* perm, double* R,
                        int64_t ldr, int64_t* k_out, int32_t* info, hipStream_t s);
@@ -95,6 +96,18 @@ size_t gram_workspace(int64_t m, int64_t n, int32_t dtype, const id_opts* o);
 int gram_factor_run(const void* A, int32_t dtype, int64_t m, int64_t n, int64_t lda,
                     const id_opts* o, void* work, size_t work_bytes, int32_t* perm, double* R,
                     int64_t ldr, int64_t* k_out, int32_t* info, hipStream_t s);
+// G = A^T A (FP64, n x n, both triangles, ld n) with the Gram path's kernels;
+// part: gram_matrix_workspace(m, n) bytes of partial tiles; *info =
+// ID_INFO_NONFINITE when A holds NaN / Inf (left alone otherwise).
+size_t gram_matrix_workspace(int64_t m, int64_t n);
+int gram_matrix_run(const void* A, int32_t dtype, int64_t m, int64_t n, int64_t lda, double* G,
+                    void* part, size_t part_bytes, int32_t* info, hipStream_t s);
+
+// The factorization through a shifted CholeskyQR3 R factor (ID_FLAG_CHOLQR).
+size_t cholqr_workspace(int64_t m, int64_t n, int32_t dtype, const id_opts* o);
+int cholqr_factor_run(const void* A, int32_t dtype, int64_t m, int64_t n, int64_t lda,
+                      const id_opts* o, void* work, size_t work_bytes, int32_t* perm, double* R,
+                      int64_t ldr, int64_t* k_out, int32_t* info, hipStream_t s);
 
 int solve_T_run(const double* R, int64_t ldr, int64_t k, int64_t n, double* T, int64_t ldt,
                 int32_t* info, hipStream_t s);
@@ -109,6 +122,9 @@ int trsm_upper_run(const double* R, int64_t ldr, int64_t k, const double* B, int
 // Bytes of split-K partials gemm64 uses for an M x N product with contraction K
 // when given them (0: no split).
 size_t gemm64_split_workspace(int64_t M, int64_t N, int64_t K);
+// C = A B, A (M x K, lda) in its storage dtype, B and C float64 (column-major).
+int gemm64_typed_run(const void* A, int32_t dtype, int64_t M, int64_t N, int64_t K, int64_t lda,
+                     const double* B, int64_t ldb, double* C, int64_t ldc, hipStream_t s);
 int gemm64_run(int ta, int tb, int64_t M, int64_t N, int64_t K, double alpha, const double* A,
                int64_t lda, const double* B, int64_t ldb, double beta, double* C, int64_t ldc,
                hipStream_t s);

@@ -54,7 +54,7 @@ int id_factor_noalloc(const void* A, int32_t dtype, int64_t m, int64_t n, int64_
       opts->prec != ID_PREC_MIXED_BF16 && opts->prec != ID_PREC_MIXED_BF16X3 &&
       opts->prec != ID_PREC_MIXED_F32)
     return ID_ERR_DTYPE;
-  if (opts->flags & (ID_FLAG_GRAM | ID_FLAG_PROFILE)) return ID_ERR_UNSUPPORTED;
+  if (opts->flags & (ID_FLAG_GRAM | ID_FLAG_CHOLQR | ID_FLAG_PROFILE)) return ID_ERR_UNSUPPORTED;
   mpid::FactorPlan pl;
   if (!mpid::make_factor_plan(m, n, dtype, opts, &pl)) return ID_ERR_ARG;
   if (pl.bytes > kScratchBytes) return ID_ERR_SCRATCH;

@@ -233,3 +233,40 @@ def test_lockstep_host_checks(lib):
     # an empty batch does nothing
     assert lib.id_factor_lockstep(items, 0, C["ID_F32"], ctypes.byref(o), None, 0,
                                   None) == C["ID_OK"]
+
+
+def test_cholqr_host_checks(lib):
+    """ID_FLAG_CHOLQR: its workspace holds two m x n FP64 copies, and every
+    refusal (flag combinations, m < n, short workspace, the entry points that
+    do not take it) comes back before any device call."""
+    from paper_2012_00706_amd import C, _lib, make_opts
+    fake = ctypes.c_void_p(0x1000)
+    k = ctypes.c_int64(0)
+    info = ctypes.c_int32(0)
+    o = make_opts(tol=1e-3, cholqr=True)
+    ws = lib.id_workspace_size(1000, 200, C["ID_F32"], ctypes.byref(o))
+    assert ws >= 2 * 1000 * 200 * 8 + 7 * 200 * 200 * 8
+    assert ws > lib.id_workspace_size(1000, 200, C["ID_F32"], ctypes.byref(make_opts(tol=1e-3)))
+
+    def run(opts, m=1000, n=200, work_bytes=ws):
+        return lib.id_factor(fake, C["ID_F32"], m, n, m, ctypes.byref(opts), fake, work_bytes,
+                             fake, fake, n, ctypes.byref(k), ctypes.byref(info), None)
+    assert run(o, work_bytes=ws - 1) == C["ID_ERR_WORKSPACE"]
+    assert run(o, m=100, n=200) == C["ID_ERR_UNSUPPORTED"]  # m < n
+    both = make_opts(tol=1e-3, cholqr=True)
+    both.flags |= C["ID_FLAG_GRAM"]
+    assert lib.id_workspace_size(1000, 200, C["ID_F32"], ctypes.byref(both)) == 0
+    assert run(both) == C["ID_ERR_ARG"]
+    for extra in ("ID_FLAG_NO_PIVOT", "ID_FLAG_PROFILE"):
+        x = make_opts(tol=1e-3, cholqr=True)
+        x.flags |= C[extra]
+        assert run(x) == C["ID_ERR_UNSUPPORTED"], extra
+    r = make_opts(tol=1e-3, prec="mixed_f32", round_to="f32", cholqr=True)
+    assert run(r) == C["ID_ERR_UNSUPPORTED"]
+    rc = lib.id_factor_noalloc(fake, C["ID_F64"], 100, 10, 100, ctypes.byref(o), fake, fake, 10,
+                               ctypes.byref(k), ctypes.byref(info), None)
+    assert rc == C["ID_ERR_UNSUPPORTED"]
+    items = _lock_items([(300, 40), (200, 30)], fake)
+    assert lib.id_factor_lockstep(items, 2, C["ID_F32"], ctypes.byref(o), fake, 1 << 30,
+                                  None) == C["ID_ERR_UNSUPPORTED"]
+    assert lib.id_status_string(C["ID_INFO_CHOLQR_BREAKDOWN"]).decode() != "unknown code"
