@@ -414,6 +414,31 @@ def run_gram(args):
                   "note": "FP64 MFMA product over the upper triangle of 64 x 64 tiles"})
 
 
+def run_cholqr(args):
+    """Tall-skinny CholeskyQR front end alone on the snapshot stand-in
+    (1,048,576 x 512 fp32, tol 1e-3)."""
+    import numpy as np
+    import torch
+    import paper_2012_00706_amd as mp
+    import synth
+    log = lambda *a: print(*a, file=sys.stderr, flush=True)  # noqa: E731
+    A_np = synth.config3()
+    A = torch.from_numpy(np.ascontiguousarray(A_np.T)).cuda().t()
+    m, n = A_np.shape
+    del A_np
+    ms, res = _timed(lambda: mp.column_id(A, tol=1e-3, cholqr=True), args.steps, 2)
+    log(f"[bench] cholqr front end: k={res.k} info={res.info} {ms:.2f} ms/ID")
+    return _line(args, "column ID time through the CholeskyQR front end (snapshot matrix)", ms,
+                 "ms", ms, False, "f64",
+                 {"workload": "snapshot stand-in 1,048,576 x 512 fp32, CholeskyQR passes on the "
+                              "FP64 matrix cores + FP64 pivoted Householder QR of the 512 x 512 R "
+                              "factor, adaptive rank at tol 1e-3", "m": m, "n": n},
+                 {"k": res.k, "info": res.info,
+                  "pass_flops": {"gram": float(m) * n * n, "triangular_product": float(m) * n * n},
+                  "note": "per pass: FP64 MFMA Gram product (upper tiles) and A R^-1 over the "
+                          "upper triangle of R^-1; two passes when CholeskyQR2 is accepted"})
+
+
 def run_config1(args):
     """Parity workload at its own size: 1000 x 500 fp64, FP64 path, k = 50.
     Latency-bound (4 MB, cache-resident): reported in microseconds."""
@@ -757,7 +782,7 @@ def run_accuracy(args):
 
 WORKLOADS = {"config1": run_config1, "config3": run_config3, "config4": run_config4,
              "config5": run_config5, "accuracy": run_accuracy, "sketch": run_sketch,
-             "gram": run_gram}
+             "gram": run_gram, "cholqr": run_cholqr}
 
 
 def main():
@@ -765,7 +790,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--workload", default="config2",
                     choices=["config1", "config2", "config3", "config4", "config5", "accuracy",
-                             "sketch", "gram"],
+                             "sketch", "gram", "cholqr"],
                     help="config2 (default) is the headline; the others print their own line")
     ap.add_argument("--batch", type=int, default=256, help="items of the batched workload")
     ap.add_argument("--sketch-rows", type=int, default=320, help="rows of the sketch (--workload sketch)")

@@ -145,18 +145,21 @@ size_t id_workspace_size(int64_t m, int64_t n, int32_t dtype, const id_opts* opt
  * of those steps are valid).  The flag supports k <= 2048 and no
  * ID_FLAG_NO_PIVOT / ID_FLAG_PROFILE.
  *
- * ID_FLAG_CHOLQR (tall inputs, m >= n): A = Q R0 from three CholeskyQR passes
- * (the first with a shift of 11 (m n + n (n + 1)) 2^-53 ||A||_F^2, each pass a
- * Gram product and a right multiplication by the inverse factor on the FP64
- * matrix cores), then the FP64 pivoted factorization of the n x n R0, whose
- * pivots and R are those of A: residual norms resolved down to about
- * 2^-53 ||A|| (the Gram front end: about 2^-26.5 ||A||).  Needs full
- * numerical column rank: the shifted pass leaves A R1^{-1} with a condition
- * number of about kappa(A) sqrt(11 (m n + n^2) 2^-53), which the plain
- * passes take only below about 2^26.5, so kappa(A) must stay below about
- * 2^53 / sqrt(11 (m n + n^2)) (2e12 at 3000 x 200).  Beyond that a Cholesky
- * pivot fails or R3 is not near the identity: info = ID_INFO_CHOLQR_BREAKDOWN
- * and k = 0 (nothing factored; perm = identity).  A = 0 gives k = 0, info 0.
+ * ID_FLAG_CHOLQR (tall inputs, m >= n): A = Q R0 from CholeskyQR passes on
+ * the FP64 matrix cores (each a Gram product and a right multiplication by
+ * the inverse triangular factor): two (CholeskyQR2, R0 = R2 R1) when the
+ * first Cholesky factorization succeeds and ||R2 - I||_F <= 1/2, else three
+ * (R0 = R3 R2 R1), the first shifted by 11 (m n + n (n + 1)) 2^-53 ||A||_F^2
+ * when its plain factorization fails (shifted CholeskyQR3).  Then the FP64
+ * pivoted factorization of the n x n R0, whose pivots and R are those of A:
+ * residual norms resolved down to about 2^-53 ||A|| (the Gram front end:
+ * about 2^-26.5 ||A||).  Needs full numerical column rank: the shifted pass
+ * leaves A R1^{-1} with a condition number of about
+ * kappa(A) sqrt(11 (m n + n^2) 2^-53), which the plain passes take only below
+ * about 2^26.5, so kappa(A) must stay below about 2^53 / sqrt(11 (m n + n^2))
+ * (2e12 at 3000 x 200).  Beyond that a Cholesky pivot fails or R3 is not near
+ * the identity (||R3 - I||_F > 1/2): info = ID_INFO_CHOLQR_BREAKDOWN and
+ * k = 0 (nothing factored; perm = identity).  A = 0 gives k = 0, info 0.
  * The workspace holds two m x n FP64 copies.  opts->prec is ignored (the
  * factorization of R0 is FP64); ID_FLAG_GRAM, ID_FLAG_NO_PIVOT,
  * ID_FLAG_PROFILE and the ROUND flags are refused (ID_ERR_UNSUPPORTED), as is

@@ -37,6 +37,9 @@ struct G64Args {
   const double* Ein;
   int64_t ldein;
   const int32_t* einmap;
+  // op(B) upper triangular (zero below the diagonal): the large-tile kernel
+  // contracts a column tile only over the rows of B at or above its last column
+  int b_upper;
 };
 
 // C = alpha op(A) op(B) + beta Cin, 64 x 64 tile per block, K chunks of 16
@@ -205,7 +208,8 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 2))
   const int64_t m0 = (int64_t)blockIdx.x * 128, n0 = (int64_t)by * 128;
   const int wr = (wv & 1) * 64, wc = (wv >> 1) * 64;
   const int64_t kb = (int64_t)blockIdx.z * kc;
-  const int64_t ke = kb + kc < a.K ? kb + kc : a.K;
+  const int64_t ke0 = kb + kc < a.K ? kb + kc : a.K;
+  const int64_t ke = (a.b_upper && ke0 > n0 + 128) ? n0 + 128 : ke0;
   f64x4 acc[4][4];
 #pragma unroll
   for (int x = 0; x < 4; ++x)
@@ -416,22 +420,23 @@ static int gemm_launch2(const G64Args<TA, TC>& a0, const G64Args<TA, TC>& a1, hi
 }
 
 // C = A B with A (M x K) in its storage dtype (fp32 or fp64, column-major, lda)
-// and B, C float64.
+// and B, C float64; b_upper: B is upper triangular (its zeros are skipped).
 int gemm64_typed_run(const void* A, int32_t dtype, int64_t M, int64_t N, int64_t K, int64_t lda,
-                     const double* B, int64_t ldb, double* C, int64_t ldc, hipStream_t s) {
+                     const double* B, int64_t ldb, double* C, int64_t ldc, int b_upper,
+                     hipStream_t s) {
   if (dtype == ID_F64) {
     G64Args<double, double> a;
     std::memset(&a, 0, sizeof(a));
     a.M = M, a.N = N, a.K = K, a.alpha = 1.0;
     a.A = (const double*)A, a.lda = lda, a.B = B, a.ldb = ldb;
-    a.C = C, a.ldc = ldc;
+    a.C = C, a.ldc = ldc, a.b_upper = b_upper;
     return gemm_launch(a, s);
   }
   G64Args<float, double> a;
   std::memset(&a, 0, sizeof(a));
   a.M = M, a.N = N, a.K = K, a.alpha = 1.0;
   a.A = (const float*)A, a.lda = lda, a.B = B, a.ldb = ldb;
-  a.C = C, a.ldc = ldc;
+  a.C = C, a.ldc = ldc, a.b_upper = b_upper;
   return gemm_launch(a, s);
 }
 

@@ -122,9 +122,11 @@ int trsm_upper_run(const double* R, int64_t ldr, int64_t k, const double* B, int
 // Bytes of split-K partials gemm64 uses for an M x N product with contraction K
 // when given them (0: no split).
 size_t gemm64_split_workspace(int64_t M, int64_t N, int64_t K);
-// C = A B, A (M x K, lda) in its storage dtype, B and C float64 (column-major).
+// C = A B, A (M x K, lda) in its storage dtype, B and C float64 (column-major);
+// b_upper != 0: B is upper triangular and the products skip its zero part.
 int gemm64_typed_run(const void* A, int32_t dtype, int64_t M, int64_t N, int64_t K, int64_t lda,
-                     const double* B, int64_t ldb, double* C, int64_t ldc, hipStream_t s);
+                     const double* B, int64_t ldb, double* C, int64_t ldc, int b_upper,
+                     hipStream_t s);
 int gemm64_run(int ta, int tb, int64_t M, int64_t N, int64_t K, double alpha, const double* A,
                int64_t lda, const double* B, int64_t ldb, double beta, double* C, int64_t ldc,
                hipStream_t s);

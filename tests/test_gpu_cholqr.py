@@ -1,5 +1,6 @@
-"""The CholeskyQR3 tall front end (ID_FLAG_CHOLQR: the pivoted Householder
-factorization of R0 = R3 R2 R1 from three CholeskyQR passes, one shifted)
+"""The CholeskyQR tall front end (ID_FLAG_CHOLQR: the pivoted Householder
+factorization of R0 = R2 R1 from CholeskyQR2, or R3 R2 R1 from three passes,
+the first shifted when its plain Cholesky factorization fails)
 against the oracle's column-pivoted Householder QR of A itself.  A = Q R0
 with Q orthonormal, so both factorizations are the same one (Section 1.1):
 same pivots on gap-separated inputs, R up to row signs to FP64 rounding, T to
@@ -25,11 +26,12 @@ def _cq(A, **kw):
 
 
 @pytest.mark.parametrize("m,n,k,per_decade", [
-    (3000, 200, 60, 20.0),   # kappa(A) = 1e10
+    (3000, 200, 60, 20.0),   # kappa(A) = 1e10: shifted CholeskyQR3
     (3000, 100, 60, 8.0),    # sigma_60 / sigma_1 = 4e-8: below the Gram route's floor
-    (5000, 64, 64, 10.0),    # full rank, T empty
+    (5000, 64, 64, 10.0),    # full rank, T empty; CholeskyQR2
     (700, 130, 1, 20.0),
     (1001, 257, 70, 25.0),   # ragged: odd rows, a 257th column past the 64-wide panels
+    (3000, 150, 60, 18.0),   # kappa(A) = 2e8: ||R2 - I||_F near the two-pass bound
 ])
 def test_cholqr_fixed_rank_matches_oracle(m, n, k, per_decade):
     need_gpu()
