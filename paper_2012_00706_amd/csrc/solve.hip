@@ -4,11 +4,12 @@
 // Each block owns 16 right-hand-side columns and walks the 64-row blocks of R
 // in dependency order: the contribution of the already-solved row blocks is
 // accumulated tile by tile on the FP64 matrix cores, then the 64 x 64 diagonal
-// block is solved in LDS.  Columns are independent, so blocks never
+// block is solved in registers.  Columns are independent, so blocks never
 // synchronize with each other.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <utility>
 
 #include "device_util.h"
 #include "mpid_internal.h"
@@ -20,12 +21,51 @@ constexpr int kTB = 64;
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 constexpr int kTC = 16;  // right-hand-side columns per block
 
+// The value of v in lane SRC of each row of 16 lanes (DPP row broadcast).
+template <int SRC>
+__device__ __forceinline__ double row_bcast(double v) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_update_dpp(0, (int)(unsigned)b, 0x150 + SRC, 0xF,
+                                                            0xF, false);
+  const unsigned hi = (unsigned)__builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32),
+                                                            0x150 + SRC, 0xF, 0xF, false);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// Step II of the diagonal-block solve for one column held by a row of 16
+// lanes (lane rg holds rows rg, rg + 16, rg + 32, rg + 48 in x): x_II is
+// broadcast from its lane, scaled by 1 / op(R)(II, II), and eliminated from
+// the rows below (trans) or above (no trans) it.
+template <int II, int TRANS>
+__device__ __forceinline__ void diag_step(double (&x)[4], const double (*Rs)[kTB + 1],
+                                          const double* rinv, int rg) {
+  constexpr int Q = II >> 4, SRC = II & 15;
+  const double xi = row_bcast<SRC>(x[Q]) * rinv[II];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int r = rg + 16 * q;
+    const double rr = Rs[r][II];
+    const bool upd = TRANS ? (r > II) : (r < II);
+    x[q] = upd ? x[q] - rr * xi : x[q];
+  }
+  if (rg == SRC) x[Q] = xi;
+}
+
+template <int TRANS, int... Is>
+__device__ __forceinline__ void diag_solve(double (&x)[4], const double (*Rs)[kTB + 1],
+                                           const double* rinv, int rg,
+                                           std::integer_sequence<int, Is...>) {
+  (diag_step<TRANS ? Is : kTB - 1 - Is, TRANS>(x, Rs, rinv, rg), ...);
+}
+
 // trans = 0: R X = B (back substitution over row blocks, last first).
 // trans = 1: R^T X = B (forward substitution, first row block first).
 // Per row block I: As = B(I, cols) - sum_L op(R)(I, L) X(L, cols) on the FP64
 // matrix cores (wave w owns rows 16w..16w+15), then op(R)(I, I) As = rhs is
-// solved with each wave owning four columns -- the 64 dependent steps run
-// inside one wavefront, without block barriers.
+// solved with each wave owning four columns, one per row of 16 lanes, in
+// registers: the 64 dependent steps pass the solved entry by a DPP row
+// broadcast, without LDS round trips or block barriers (rows past the block's
+// end hold 0 and have 1 / op(R)(i, i) = 0, so their steps change nothing).
 // Columns c0 .. c0 + kTC - 1 of the solve, by one 256-thread block.
 __device__ __forceinline__ void trsm_block(const double* __restrict__ R, int64_t ldr, int64_t k,
                                            const double* B, int64_t ldb, int64_t ncols, double* X,
@@ -113,21 +153,16 @@ __device__ __forceinline__ void trsm_block(const double* __restrict__ R, int64_t
     load_R_tile(i0, i0);
     __syncthreads();
     {
-      const int col = 4 * wv + (lane & 3), rg = lane >> 2;  // 4 columns x 16 row groups
-      if (!trans) {
-        for (int ii = ib - 1; ii >= 0; --ii) {
-          const double xi = As[ii][col] * rinv[ii];
-          for (int r = rg; r < ii; r += 16) As[r][col] -= Rs[r][ii] * xi;
-          if (rg == (ii & 15)) As[ii][col] = xi;
-        }
-      } else {
-        for (int ii = 0; ii < ib; ++ii) {
-          const double xi = As[ii][col] * rinv[ii];
-          for (int r = rg; r < ib; r += 16)
-            if (r > ii) As[r][col] -= Rs[r][ii] * xi;
-          if (rg == (ii & 15)) As[ii][col] = xi;
-        }
-      }
+      const int col = 4 * wv + (lane >> 4), rg = lane & 15;  // 4 columns x 16 row groups
+      double x[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) x[q] = As[rg + 16 * q][col];
+      if (!trans)
+        diag_solve<0>(x, Rs, rinv, rg, std::make_integer_sequence<int, kTB>());
+      else
+        diag_solve<1>(x, Rs, rinv, rg, std::make_integer_sequence<int, kTB>());
+#pragma unroll
+      for (int q = 0; q < 4; ++q) As[rg + 16 * q][col] = x[q];
     }
     __syncthreads();
 #pragma unroll
