@@ -600,107 +600,127 @@ struct AdjArgs {
   int64_t ldga;
 };
 
-constexpr int kAdjRows = 16;    // rows of A per block (one matrix-core row block)
 constexpr int kAdjChunk = 128;  // coefficient columns per pass
 constexpr int kAdjKMax = 256;   // largest k the fused kernel takes
 
-// The adjoint's products for a strip of 16 rows i, without D and E in memory.
-// For each chunk of 128 columns j of the n - k coefficient columns:
+// The adjoint's products for a strip of 16 RB rows i, without D and E in
+// memory.  For each chunk of 128 columns j of the n - k coefficient columns:
 //   phase 1: P_X = B(i, :) X(:, j), P_T = B(i, :) T(:, j)        (K = k)
 //            gA(i, Jc[j]) = P_X,  E = gY(i, Jc[j]) - P_X,  D = A(i, Jc[j]) - P_T
 //            (E and D go to LDS)
 //   phase 2: acc(i, c) += sum_j D(i, j) X(c, j) + E(i, j) T(c, j)   (K = 2 x 128)
 // and finally gA(i, J[c]) = gY(i, J[c]) + acc(i, c).  Wave w owns columns
 // [32 w, 32 w + 32) of each chunk in phase 1 and NB2 blocks of 16 columns c
-// of k in phase 2 (4 NB2 16 >= k).  Operand lanes: a lane supplies A(row li,
-// kk) and B(kk, col li) and receives C(row li, col g + 4 r) (operands fed
-// swapped, as in k_gemm64t).  The contraction runs in groups of 16 in which
-// lane group g takes the four consecutive entries 4 g .. 4 g + 3, so a lane
-// reads each B operand as one aligned 32-byte load per group (from the padded
-// copies, L2-resident), two groups ahead of their products; the A operands
-// come from LDS in the same order.  Columns past nc or k read clamped
-// in-range columns and are never stored; rows past m are zero in LDS and not
-// stored.
-template <typename TA, int NB2>
+// of k in phase 2 (4 NB2 16 >= k), for all RB row blocks of the strip.
+// Operand lanes: a lane supplies A(row li, kk) and B(kk, col li) and receives
+// C(row li, col g + 4 r) (operands fed swapped, as in k_gemm64t).  The
+// contraction runs in groups of 16 in which lane group g takes the four
+// consecutive entries 4 g .. 4 g + 3, so a lane reads each B operand as one
+// aligned 32-byte load per group (from the padded copies, L2-resident), two
+// or four groups ahead of their products, and feeds it to the RB row blocks' products
+// (the strip height sets how much matrix-core work each operand byte carries:
+// the products are bound by these operand reads); the A operands come from
+// LDS in the same order.  Columns past nc or k read clamped in-range columns
+// and are never stored; rows past m are zero in LDS and not stored.
+template <typename TA, int NB2, int RB>
 __global__ __launch_bounds__(kThreads) void k_adj_fused(AdjArgs<TA> a) {
   constexpr int KB = 64 * NB2;                  // largest k of this instantiation
-  __shared__ double Bs[KB][kAdjRows];           // Bs[kk][i] = B(i0 + i, kk)
-  __shared__ double Es[kAdjChunk][kAdjRows];    // Es[j][i] = E(i0 + i, c0 + j)
-  __shared__ double Ds[kAdjChunk][kAdjRows];
+  constexpr int RS = 16 * RB;                   // rows of the strip
+  // operand groups in flight: a taller strip has fewer resident waves (its
+  // LDS allows one block per compute unit), so it keeps more loads ahead
+  constexpr int PD = RB == 2 ? 4 : 2;
+  __shared__ double Bs[KB][RS];                 // Bs[kk][i] = B(i0 + i, kk)
+  __shared__ double Es[kAdjChunk][RS];          // Es[j][i] = E(i0 + i, c0 + j)
+  __shared__ double Ds[kAdjChunk][RS];
   const int tid = threadIdx.x;
   const int lane = tid & 63, wv = tid >> 6, g = lane >> 4, li = lane & 15;
   const int64_t m = a.m, k = a.k, nc = a.nc;
-  const int64_t i0 = (int64_t)blockIdx.x * kAdjRows;
-  const int64_t i = i0 + li;  // this lane's output row
-  const int64_t ic = i < m ? i : m - 1;
+  const int64_t i0 = (int64_t)blockIdx.x * RS;
+  int64_t iw[RB], ic[RB];  // this lane's output rows (one per row block)
+#pragma unroll
+  for (int rb = 0; rb < RB; ++rb) {
+    iw[rb] = i0 + 16 * rb + li;
+    ic[rb] = iw[rb] < m ? iw[rb] : m - 1;
+  }
   const int ng1 = (int)(a.kq / 16);  // contraction groups of phase 1
   // the strip of B (rows past m and columns past k zero)
-  for (int e = tid; e < KB * kAdjRows; e += kThreads) {
-    const int r = e % kAdjRows, kk = e / kAdjRows;
+  for (int e = tid; e < KB * RS; e += kThreads) {
+    const int r = e % RS, kk = e / RS;
     const int64_t gi = i0 + r;
     Bs[kk][r] = (gi < m && kk < k) ? a.Bm[(int64_t)kk * m + gi] : 0.0;
   }
-  f64x4 acc2[NB2], acc3[NB2];
+  f64x4 acc2[RB][NB2], acc3[RB][NB2];
 #pragma unroll
-  for (int nb = 0; nb < NB2; ++nb) {
-    acc2[nb] = (f64x4){0.0, 0.0, 0.0, 0.0};
-    acc3[nb] = acc2[nb];
-  }
+  for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+    for (int nb = 0; nb < NB2; ++nb) {
+      acc2[rb][nb] = (f64x4){0.0, 0.0, 0.0, 0.0};
+      acc3[rb][nb] = acc2[rb][nb];
+    }
   for (int64_t c0 = 0; c0 < nc; c0 += kAdjChunk) {
     // the epilogue's inputs: rows i, columns Jc[j] for the lane's outputs
     // j = c0 + 32 w + 16 nb + g + 4 r (loaded ahead of the products)
-    double ein[2][4], cin[2][4];
+    double ein[RB][2][4], cin[RB][2][4];
 #pragma unroll
     for (int nb = 0; nb < 2; ++nb)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int64_t j = c0 + 32 * wv + 16 * nb + g + 4 * r;
         const int64_t col = a.perm[k + (j < nc ? j : nc - 1)];
-        ein[nb][r] = a.gY ? a.gY[col * a.ldgy + ic] : 0.0;
-        cin[nb][r] = (double)a.A[col * a.lda + ic];
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb) {
+          ein[rb][nb][r] = a.gY ? a.gY[col * a.ldgy + ic[rb]] : 0.0;
+          cin[rb][nb][r] = (double)a.A[col * a.lda + ic[rb]];
+        }
       }
     __syncthreads();  // Bs ready (first pass); Es / Ds free (later passes)
     // ---- phase 1, one 16-column block nb at a time: the B operands are
     // columns j = c0 + 32 w + 16 nb + li of X and T, two groups in flight
-    f64x4 px[2], pt[2];
+    f64x4 px[RB][2], pt[RB][2];
 #pragma unroll
     for (int nb = 0; nb < 2; ++nb) {
       const int64_t j = c0 + 32 * wv + 16 * nb + li;
       const int64_t jc = j < nc ? j : nc - 1;
       const double* xcol = a.Xp + jc * a.kq + 4 * g;
       const double* tcol = a.Tp + jc * a.kq + 4 * g;
-      f64x4 ax = (f64x4){0.0, 0.0, 0.0, 0.0}, at = ax;
-      f64x4v x0 = *(const f64x4v*)xcol, t0 = *(const f64x4v*)tcol, x1 = x0, t1 = t0;
-      if (ng1 > 1) {
-        x1 = *(const f64x4v*)(xcol + 16);
-        t1 = *(const f64x4v*)(tcol + 16);
-      }
-      for (int q = 0; q < ng1; q += 2) {
+      f64x4 ax[RB], at[RB];
 #pragma unroll
-        for (int s = 0; s < 4; ++s) {
-          const double af = Bs[16 * q + 4 * g + s][li];
-          ax = __builtin_amdgcn_mfma_f64_16x16x4f64(x0[s], af, ax, 0, 0, 0);
-          at = __builtin_amdgcn_mfma_f64_16x16x4f64(t0[s], af, at, 0, 0, 0);
-        }
-        if (q + 2 < ng1) {
-          x0 = *(const f64x4v*)(xcol + 16 * (q + 2));
-          t0 = *(const f64x4v*)(tcol + 16 * (q + 2));
-        }
-        if (q + 1 < ng1) {
+      for (int rb = 0; rb < RB; ++rb) {
+        ax[rb] = (f64x4){0.0, 0.0, 0.0, 0.0};
+        at[rb] = ax[rb];
+      }
+      // PD groups of operand loads in flight, rotated through registers
+      f64x4v xb[PD], tb[PD];
 #pragma unroll
-          for (int s = 0; s < 4; ++s) {
-            const double af = Bs[16 * (q + 1) + 4 * g + s][li];
-            ax = __builtin_amdgcn_mfma_f64_16x16x4f64(x1[s], af, ax, 0, 0, 0);
-            at = __builtin_amdgcn_mfma_f64_16x16x4f64(t1[s], af, at, 0, 0, 0);
-          }
-          if (q + 3 < ng1) {
-            x1 = *(const f64x4v*)(xcol + 16 * (q + 3));
-            t1 = *(const f64x4v*)(tcol + 16 * (q + 3));
+      for (int p = 0; p < PD; ++p) {
+        const int qq = p < ng1 ? p : 0;
+        xb[p] = *(const f64x4v*)(xcol + 16 * qq);
+        tb[p] = *(const f64x4v*)(tcol + 16 * qq);
+      }
+      for (int q = 0; q < ng1; q += PD) {
+#pragma unroll
+        for (int p = 0; p < PD; ++p) {
+          if (q + p < ng1) {
+#pragma unroll
+            for (int s = 0; s < 4; ++s)
+#pragma unroll
+              for (int rb = 0; rb < RB; ++rb) {
+                const double af = Bs[16 * (q + p) + 4 * g + s][16 * rb + li];
+                ax[rb] = __builtin_amdgcn_mfma_f64_16x16x4f64(xb[p][s], af, ax[rb], 0, 0, 0);
+                at[rb] = __builtin_amdgcn_mfma_f64_16x16x4f64(tb[p][s], af, at[rb], 0, 0, 0);
+              }
+            if (q + p + PD < ng1) {
+              xb[p] = *(const f64x4v*)(xcol + 16 * (q + p + PD));
+              tb[p] = *(const f64x4v*)(tcol + 16 * (q + p + PD));
+            }
           }
         }
       }
-      px[nb] = ax;
-      pt[nb] = at;
+#pragma unroll
+      for (int rb = 0; rb < RB; ++rb) {
+        px[rb][nb] = ax[rb];
+        pt[rb][nb] = at[rb];
+      }
     }
     // ---- epilogue: gA(i, Jc[j]) = P_X; E and D to LDS (zero past nc / m)
 #pragma unroll
@@ -709,16 +729,21 @@ __global__ __launch_bounds__(kThreads) void k_adj_fused(AdjArgs<TA> a) {
       for (int r = 0; r < 4; ++r) {
         const int jl = 32 * wv + 16 * nb + g + 4 * r;
         const int64_t j = c0 + jl;
-        const bool ok = j < nc && i < m;
-        const double w = px[nb][r];
-        if (ok) a.gA[(int64_t)a.perm[k + j] * a.ldga + i] = w;
-        Es[jl][li] = ok ? ein[nb][r] - w : 0.0;
-        Ds[jl][li] = ok ? cin[nb][r] - pt[nb][r] : 0.0;
+        const int64_t col = j < nc ? (int64_t)a.perm[k + j] : 0;
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb) {
+          const bool ok = j < nc && iw[rb] < m;
+          const double w = px[rb][nb][r];
+          if (ok) a.gA[col * a.ldga + iw[rb]] = w;
+          Es[jl][16 * rb + li] = ok ? ein[rb][nb][r] - w : 0.0;
+          Ds[jl][16 * rb + li] = ok ? cin[rb][nb][r] - pt[rb][nb][r] : 0.0;
+        }
       }
     __syncthreads();
     // ---- phase 2, one 16-column block nb of k at a time: acc2 += D X(c, j)^T
-    // and acc3 += E T(c, j)^T over the chunk's j (two independent chains), the
-    // B operands read from the transposed copies (j consecutive)
+    // and acc3 += E T(c, j)^T over the chunk's j (two independent chains per
+    // row block), the B operands read from the transposed copies (j
+    // consecutive)
     {
       const int64_t jn = nc - c0 < kAdjChunk ? nc - c0 : kAdjChunk;
       const int ng2 = (int)ceil_div(jn, (int64_t)16);
@@ -728,54 +753,65 @@ __global__ __launch_bounds__(kThreads) void k_adj_fused(AdjArgs<TA> a) {
         const int64_t cc = c < k ? c : k - 1;
         const double* xrow = a.Xq + cc * a.nq + c0 + 4 * g;
         const double* trow = a.Tq + cc * a.nq + c0 + 4 * g;
-        f64x4 ax = acc2[nb], at = acc3[nb];
-        f64x4v x0 = *(const f64x4v*)xrow, t0 = *(const f64x4v*)trow, x1 = x0, t1 = t0;
-        if (ng2 > 1) {
-          x1 = *(const f64x4v*)(xrow + 16);
-          t1 = *(const f64x4v*)(trow + 16);
-        }
-        for (int q = 0; q < ng2; q += 2) {
+        f64x4 ax[RB], at[RB];
 #pragma unroll
-          for (int s = 0; s < 4; ++s) {
-            const int jl = 16 * q + 4 * g + s;
-            ax = __builtin_amdgcn_mfma_f64_16x16x4f64(x0[s], Ds[jl][li], ax, 0, 0, 0);
-            at = __builtin_amdgcn_mfma_f64_16x16x4f64(t0[s], Es[jl][li], at, 0, 0, 0);
-          }
-          if (q + 2 < ng2) {
-            x0 = *(const f64x4v*)(xrow + 16 * (q + 2));
-            t0 = *(const f64x4v*)(trow + 16 * (q + 2));
-          }
-          if (q + 1 < ng2) {
+        for (int rb = 0; rb < RB; ++rb) {
+          ax[rb] = acc2[rb][nb];
+          at[rb] = acc3[rb][nb];
+        }
+        f64x4v xb[PD], tb[PD];
 #pragma unroll
-            for (int s = 0; s < 4; ++s) {
-              const int jl = 16 * (q + 1) + 4 * g + s;
-              ax = __builtin_amdgcn_mfma_f64_16x16x4f64(x1[s], Ds[jl][li], ax, 0, 0, 0);
-              at = __builtin_amdgcn_mfma_f64_16x16x4f64(t1[s], Es[jl][li], at, 0, 0, 0);
-            }
-            if (q + 3 < ng2) {
-              x1 = *(const f64x4v*)(xrow + 16 * (q + 3));
-              t1 = *(const f64x4v*)(trow + 16 * (q + 3));
+        for (int p = 0; p < PD; ++p) {
+          const int qq = p < ng2 ? p : 0;
+          xb[p] = *(const f64x4v*)(xrow + 16 * qq);
+          tb[p] = *(const f64x4v*)(trow + 16 * qq);
+        }
+        for (int q = 0; q < ng2; q += PD) {
+#pragma unroll
+          for (int p = 0; p < PD; ++p) {
+            if (q + p < ng2) {
+#pragma unroll
+              for (int s = 0; s < 4; ++s) {
+                const int jl = 16 * (q + p) + 4 * g + s;
+#pragma unroll
+                for (int rb = 0; rb < RB; ++rb) {
+                  ax[rb] = __builtin_amdgcn_mfma_f64_16x16x4f64(xb[p][s], Ds[jl][16 * rb + li],
+                                                                ax[rb], 0, 0, 0);
+                  at[rb] = __builtin_amdgcn_mfma_f64_16x16x4f64(tb[p][s], Es[jl][16 * rb + li],
+                                                                at[rb], 0, 0, 0);
+                }
+              }
+              if (q + p + PD < ng2) {
+                xb[p] = *(const f64x4v*)(xrow + 16 * (q + p + PD));
+                tb[p] = *(const f64x4v*)(trow + 16 * (q + p + PD));
+              }
             }
           }
         }
-        acc2[nb] = ax;
-        acc3[nb] = at;
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb) {
+          acc2[rb][nb] = ax[rb];
+          acc3[rb][nb] = at[rb];
+        }
       }
     }
   }
-  // ---- gA(i, J[c]) = gY(i, J[c]) + acc2
-  if (i < m) {
+  // ---- gA(i, J[c]) = gY(i, J[c]) + acc2 + acc3
 #pragma unroll
-    for (int nb = 0; nb < NB2; ++nb)
+  for (int rb = 0; rb < RB; ++rb) {
+    if (iw[rb] < m) {
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int64_t c = (int64_t)16 * (NB2 * wv + nb) + g + 4 * r;
-        if (c < k) {
-          const int64_t col = a.perm[c];
-          const double y = a.gY ? a.gY[col * a.ldgy + i] : 0.0;
-          a.gA[col * a.ldga + i] = y + (acc2[nb][r] + acc3[nb][r]);
+      for (int nb = 0; nb < NB2; ++nb)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int64_t c = (int64_t)16 * (NB2 * wv + nb) + g + 4 * r;
+          if (c < k) {
+            const int64_t col = a.perm[c];
+            const double y = a.gY ? a.gY[col * a.ldgy + iw[rb]] : 0.0;
+            a.gA[col * a.ldga + iw[rb]] = y + (acc2[rb][nb][r] + acc3[rb][nb][r]);
+          }
         }
-      }
+    }
   }
 }
 
@@ -978,11 +1014,25 @@ static int backward_impl(const TA* A, int64_t m, int64_t n, int64_t lda, const i
     fa.Bm = Bm, fa.Xp = Xp, fa.Tp = Tp, fa.Xq = Xq, fa.Tq = Tq;
     fa.A = A, fa.lda = lda, fa.gY = gY, fa.ldgy = ldgy, fa.perm = perm;
     fa.gA = gA, fa.ldga = ldga;
-    const dim3 fg((unsigned)ceil_div(m, kAdjRows));
-    if (k <= 128)
-      k_adj_fused<TA, 2><<<fg, kThreads, 0, s>>>(fa);
-    else
-      k_adj_fused<TA, 4><<<fg, kThreads, 0, s>>>(fa);
+    // strips of 32 rows while they still give every compute unit a block
+    // (twice the matrix-core work per operand read), else of 16
+    int dev = 0, cus = 0;
+    MPID_HIP(hipGetDevice(&dev));
+    MPID_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    const int rb = env_flag("MPID_ADJ_RB2", 1) && ceil_div(m, (int64_t)32) >= (cus > 0 ? cus : 256)
+                       ? 2 : 1;
+    const dim3 fg((unsigned)ceil_div(m, (int64_t)16 * rb));
+    if (k <= 128) {
+      if (rb == 2)
+        k_adj_fused<TA, 2, 2><<<fg, kThreads, 0, s>>>(fa);
+      else
+        k_adj_fused<TA, 2, 1><<<fg, kThreads, 0, s>>>(fa);
+    } else {
+      if (rb == 2)
+        k_adj_fused<TA, 4, 2><<<fg, kThreads, 0, s>>>(fa);
+      else
+        k_adj_fused<TA, 4, 1><<<fg, kThreads, 0, s>>>(fa);
+    }
     MPID_LAUNCH_CHECK();
   } else {
     if ((rc = products_unfused<TA>(A, m, k, nc, lda, perm, T, ldt, gY, ldgy, gA, ldga, Bm, DE, XT,

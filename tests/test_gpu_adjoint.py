@@ -144,3 +144,30 @@ def test_backward_product_paths(monkeypatch, m, n, k, fused):
                           R11=res.R[:, :k]))
     ref = orc.adjoint(A, perm, k, T, gT=gT, gY=gY)
     assert rel_err(gA, ref) <= 1e-10
+
+
+@pytest.mark.parametrize("k,dtype", [(100, np.float64), (200, np.float64), (90, np.float32)])
+def test_backward_tall_strips(monkeypatch, k, dtype):
+    """Tall inputs take the fused pass over 32-row strips (two matrix-core row
+    blocks per strip, chosen while the strips still give every compute unit a
+    block): against the oracle's adjoint, and against the 16-row strips
+    (MPID_ADJ_RB2=0), with a ragged last strip; k up to 128 and 129..256."""
+    need_gpu()
+    import paper_2012_00706_amd as mp
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    m, n = 32 * cus + 8, 300
+    rng = np.random.default_rng(k)
+    A = synth.spectrum_matrix(m, n, synth.sigma_exp(n, 40.0), m + 3, n + 3).astype(dtype)
+    res = mp.column_id(to_dev(A), k=k)
+    perm = host(res.perm).astype(np.int64)
+    T = host(res.T)
+    gT = rng.standard_normal(T.shape)
+    gY = rng.standard_normal((m, n))
+    args = (to_dev(A), res.perm, k, res.T)
+    kw = dict(gT=to_dev(gT), gY=to_dev(gY), R11=res.R[:, :k])
+    g2 = host(mp.backward(*args, **kw))
+    monkeypatch.setenv("MPID_ADJ_RB2", "0")
+    g1 = host(mp.backward(*args, **kw))
+    assert rel_err(g2, g1) <= 1e-12
+    ref = orc.adjoint(A.astype(np.float64), perm, k, T, gT=gT, gY=gY)
+    assert rel_err(g2, ref) <= 1e-10
