@@ -51,6 +51,8 @@ int main() {
           prev = w;
           id_opts g = opts(ID_PREC_F64, 0, 1e-3, ID_FLAG_GRAM);
           (void)id_workspace_size(m, n, dt, &g);
+          id_opts c = opts(prec, 0, 1e-3, ID_FLAG_CHOLQR);
+          (void)id_workspace_size(m, n, dt, &c);
         }
       }
   // invalid options and sizes give 0
@@ -110,6 +112,25 @@ int main() {
                              nullptr) == ID_ERR_SCRATCH);
     id_opts prof = opts(ID_PREC_F64, 2, 0.0, ID_FLAG_PROFILE);
     EXPECT(id_factor_noalloc(fake, ID_F64, 10, 5, 10, &prof, fi, fd, 2, &k, &info, nullptr) ==
+           ID_ERR_UNSUPPORTED);
+  }
+  {
+    // the CholeskyQR front end: refusals before any device call
+    id_opts c = opts(ID_PREC_F64, 0, 1e-3, ID_FLAG_CHOLQR);
+    const size_t ws = id_workspace_size(100, 10, ID_F64, &c);
+    EXPECT(ws >= 2 * 100 * 10 * 8);
+    EXPECT(id_factor(fake, ID_F64, 100, 10, 100, &c, fake, ws - 1, fi, fd, 10, &k, &info,
+                     nullptr) == ID_ERR_WORKSPACE);
+    EXPECT(id_factor(fake, ID_F64, 5, 10, 5, &c, fake, ws, fi, fd, 10, &k, &info, nullptr) ==
+           ID_ERR_UNSUPPORTED);  // m < n
+    id_opts both = opts(ID_PREC_F64, 0, 1e-3, ID_FLAG_CHOLQR | ID_FLAG_GRAM);
+    EXPECT(id_workspace_size(100, 10, ID_F64, &both) == 0);
+    EXPECT(id_factor(fake, ID_F64, 100, 10, 100, &both, fake, ws, fi, fd, 10, &k, &info,
+                     nullptr) == ID_ERR_ARG);
+    id_opts np = opts(ID_PREC_F64, 0, 1e-3, ID_FLAG_CHOLQR | ID_FLAG_NO_PIVOT);
+    EXPECT(id_factor(fake, ID_F64, 100, 10, 100, &np, fake, ws, fi, fd, 10, &k, &info,
+                     nullptr) == ID_ERR_UNSUPPORTED);
+    EXPECT(id_factor_noalloc(fake, ID_F64, 100, 10, 100, &c, fi, fd, 10, &k, &info, nullptr) ==
            ID_ERR_UNSUPPORTED);
   }
   EXPECT(id_solve_T(static_cast<const double*>(fake), 5, 6, 5, static_cast<double*>(fake), 6,
