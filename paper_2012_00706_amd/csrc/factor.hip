@@ -1818,6 +1818,7 @@ static int factor_impl(const TA* A, int64_t lda, const FactorPlan& pl, const id_
   const bool count_rule = o->k_fixed == 0 && o->rank_rule == ID_RANK_PIVOT_REL;
   const double count_tol = count_rule ? o->rel_tol : -1.0;
   int64_t step_lim = pl.nb;  // from the last settled end state
+  int64_t enq_last = 0;      // steps enqueued for the last panel
   int settled = 0;           // panels whose end state has been processed
   bool drain = false;        // near the end: settle every panel before the next
   const FactorState* fin_drain = nullptr;
@@ -1953,12 +1954,22 @@ static int factor_impl(const TA* A, int64_t lda, const FactorPlan& pl, const id_
     }
     const int64_t ncur_ub = n - off_lb;
     // the limit holds only when the previous panel's end state is known
-    const int64_t nsteps = settled == panel ? std::min<int64_t>(pl.nb, step_lim) : pl.nb;
+    int64_t nsteps = settled == panel ? std::min<int64_t>(pl.nb, step_lim) : pl.nb;
+    if (settled == panel - 1 && panel > 0) {
+      // the previous panel is still in flight from off_lb: when it runs all
+      // enqueued steps (a panel rarely ends early), this one starts at
+      // off_lb + enq_last and needs at most kcap - that many steps; if it
+      // does end early, a later panel takes the remaining steps
+      nsteps = std::min<int64_t>(nsteps, std::max<int64_t>(1, kcap - (off_lb + enq_last)));
+    }
+    int64_t launched = jj0;
     for (int jj = jj0; jj < nsteps; ++jj) {
       const int rl = launch_step(panel, jj, off_lb);
       if (rl < 0) return rl;
       if (rl != ID_OK) break;
+      ++launched;
     }
+    enq_last = launched;
     const GemmArgs<S> g = make_gemm_args<S>(pl, wb, cur, off_lb);
     prof.launch(PK_GEMM, (int64_t)panel * 1024, k_panel_gemm<S, OP, RM>,
                 dim3((unsigned)round_up(g.gx * g.gy, 8)), s, g);
