@@ -1958,9 +1958,13 @@ static int factor_impl(const TA* A, int64_t lda, const FactorPlan& pl, const id_
     if (settled == panel - 1 && panel > 0) {
       // the previous panel is still in flight from off_lb: when it runs all
       // enqueued steps (a panel rarely ends early), this one starts at
-      // off_lb + enq_last and needs at most kcap - that many steps; if it
-      // does end early, a later panel takes the remaining steps
+      // off_lb + enq_last and needs at most kcap - that many steps, and with
+      // the pivot-relative count from the state before that panel at most
+      // step_lim - enq_last; if it does end early, a later panel takes the
+      // remaining steps
       nsteps = std::min<int64_t>(nsteps, std::max<int64_t>(1, kcap - (off_lb + enq_last)));
+      if (count_rule && settled > 0)
+        nsteps = std::min<int64_t>(nsteps, std::max<int64_t>(1, step_lim - enq_last));
     }
     int64_t launched = jj0;
     for (int jj = jj0; jj < nsteps; ++jj) {
