@@ -904,6 +904,23 @@ def main():
         bound = 1.1 * e_o + 10.0 * U_LOW[p] * float(sigma[0])
         return {"err_oracle_same_k": e_o, "u_low": U_LOW[p], "bound": bound,
                 "pass": bool(r["err2"] <= bound)}
+    def tall_front_end(**kw):
+        # the Gram and CholeskyQR front ends at the headline tolerance: time,
+        # rank, pivots against the FP64 path, error
+        fe_ms, r = _timed(lambda: mp.column_id(A, tol=tol, **kw), 3, 1)
+        same = bool(r.k == f64["k"] and torch.equal(r.J.cpu().int(), f64["perm"][:r.k].cpu()))
+        e = float("nan")
+        if r.k > 0:
+            E = mp.reconstruct(A, r.perm, r.k, r.T, residual=True)
+            e = spectral_norm_dev(E)
+            del E
+        s_k1 = float(sigma[r.k]) if r.k < len(sigma) else 0.0
+        log(f"[bench] {next(iter(kw))} front end: k={r.k} info={r.info} {fe_ms:.2f} ms/ID "
+            f"same pivots as FP64: {same}")
+        return {"ms_per_id": fe_ms, "k": r.k, "info": r.info, "same_pivots_as_fp64": same,
+                "err2": e, "err_ratio_sigma_k1": e / s_k1 if s_k1 > 0 else None}
+    gram_fe = tall_front_end(gram=True)
+    cholqr_fe = tall_front_end(cholqr=True)
     sk = _sketch_front_end(A, 400, tol, args.steps, sigma)
     log(f"[bench] sketch front end (l=400): k={sk['k']} {sk['ms_per_id']:.2f} ms/ID "
         f"ratio={sk.get('err_ratio_sigma_k1', float('nan')):.3f} "
@@ -941,6 +958,8 @@ def main():
                      "err2": f64["err2"], "err_ratio_sigma_k1": f64["ratio"],
                      "acceptance": acceptance("f64")},
         "speedup_vs_fp64": f64["ms"] / mx["ms"],
+        "gram_front_end": gram_fe,
+        "cholqr_front_end": cholqr_fe,
         "sketch_front_end": sk,
         "other_precisions": {p: {"ms_per_id": res[p]["ms"], "k": res[p]["k"],
                                  "err2": res[p]["err2"],
