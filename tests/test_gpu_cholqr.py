@@ -32,6 +32,7 @@ def _cq(A, **kw):
     (700, 130, 1, 20.0),
     (1001, 257, 70, 25.0),   # ragged: odd rows, a 257th column past the 64-wide panels
     (3000, 150, 60, 18.0),   # kappa(A) = 2e8: ||R2 - I||_F near the two-pass bound
+    (300, 300, 100, 30.0),   # square (m = n), kappa(A) = 1e10
 ])
 def test_cholqr_fixed_rank_matches_oracle(m, n, k, per_decade):
     need_gpu()

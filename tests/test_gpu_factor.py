@@ -309,3 +309,30 @@ def test_row_and_column_permutations():
     assert np.array_equal(cols[p3[:k]], p1[:k])
     assert np.max(np.abs(np.abs(np.diag(R3[:, :k])) - np.abs(np.diag(R1[:, :k])))) <= \
         1e-12 * abs(R1[0, 0])
+
+
+@pytest.mark.parametrize("prec", ["f64", "mixed_bf16x3", "mixed_f32"])
+def test_fixed_rank_after_early_panel_end(prec):
+    """sigma_j = j^-2, k = 40: the FP32 working copy's downdated norms cancel
+    within the first panel, which ends after a few steps; the panel enqueued
+    behind it assumes that it ran all its steps (at most kcap minus that
+    optimistic start), so a later panel takes the rest.  The rank is exactly
+    k; FP64: the oracle's pivots, R and T; mixed: the acceptance rule and the
+    oracle's pivots up to the first margin below 1e-3."""
+    need_gpu()
+    s = np.arange(1, 201, dtype=np.float64) ** -2.0
+    A = synth.spectrum_matrix(3000, 200, s, 501, 502)
+    if prec != "f64":
+        A = A.astype(np.float32)
+    perm, kk, R, T = gpu_id(A, k=40, prec=prec)
+    assert kk == 40
+    ref = orc.cpqr(A.astype(np.float64), k=40)
+    if prec == "f64":
+        assert_f64_parity(perm, kk, R, T, ref, 200)
+        return
+    upto = int(np.argmax(ref.margins < 1e-3)) if np.any(ref.margins < 1e-3) else 40
+    assert upto >= 10
+    assert perm[:upto].tolist() == ref.perm[:upto].tolist()
+    e = orc.id_error(A, perm, 40, T)[0]
+    e_ref = orc.id_error(A, ref.perm, 40, orc.solve_T(ref.R, 40))[0]
+    assert e <= 1.1 * e_ref + 10 * U_LOW[prec] * s[0]
