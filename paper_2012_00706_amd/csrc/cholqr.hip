@@ -75,13 +75,21 @@ __global__ __launch_bounds__(kThreads) void k_cq_zero(double* __restrict__ X, in
   if (e < count) X[e] = 0.0;
 }
 
+// The wave-uniform value of lane "lane"'s v.
+__device__ __forceinline__ double readlane_f64(double v, int lane) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)b, lane);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), lane);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
 // Cholesky factorization of the diagonal block G(p0 : p0 + nb, same) after
 // the earlier panels' updates (upper factor R_pp with R_pp^T R_pp = G_pp), by
 // one wavefront: the block's upper triangle is staged through LDS
-// (coalesced), then lane j holds column j in registers.  Step c publishes row
-// c of the current matrix in LDS (double-buffered: one barrier per step),
-// every lane forms R(c, i) = G(c, i) / sqrt(G(c, c)) from it and updates its
-// column, G(i, j) -= R(c, i) R(c, j).  Rows and columns past nb are the
+// (coalesced), then lane j holds column j in registers.  Step c reads G(c, c)
+// from lane c, every lane scales its entry of row c by 1 / sqrt(G(c, c)) and
+// publishes it in LDS (double-buffered: one barrier per step), and every lane
+// updates its column, G(i, j) -= R(c, i) R(c, j).  Rows and columns past nb are the
 // identity (finite, and they leave the block's entries alone).  Writes
 // R(p0 + i, p0 + j) for i, j < nb (zero below the diagonal) and flags a
 // pivot that is not positive and finite (replaced by 1 so that nothing
@@ -93,10 +101,22 @@ __global__ __launch_bounds__(kCB) void k_cq_chol_diag(const double* __restrict__
   __shared__ double Gs[kCB][kCB + 1];  // Gs[i][j] = G(p0 + i, p0 + j), j >= i
   __shared__ double row[2][kCB];
   const int j = threadIdx.x;
-  for (int e = j; e < kCB * kCB; e += kCB) {
-    const int i = e % kCB, jj = e / kCB;
-    Gs[i][jj] = (i < nb && jj < nb) ? (jj >= i ? G[(p0 + jj) * n + p0 + i] : 0.0)
-                                    : (i == jj ? 1.0 : 0.0);
+  {
+    // lane i loads row i of the block, column by column (coalesced across
+    // lanes): all 64 loads unconditional from clamped in-bounds addresses and
+    // in flight together, masked when they go to LDS
+    const int i = j;
+    const int64_t ic = i < nb ? i : 0;
+    double t[kCB];
+#pragma unroll
+    for (int jj = 0; jj < kCB; ++jj) {
+      const int64_t jc = jj < nb ? jj : 0;
+      t[jj] = G[(p0 + jc) * n + p0 + ic];
+    }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int jj = 0; jj < kCB; ++jj)
+      Gs[i][jj] = (i < nb && jj < nb) ? (jj >= i ? t[jj] : 0.0) : (i == jj ? 1.0 : 0.0);
   }
   __syncthreads();
   double g[kCB];  // g[i] = G(i, j), then R(i, j)
@@ -106,18 +126,21 @@ __global__ __launch_bounds__(kCB) void k_cq_chol_diag(const double* __restrict__
 #pragma unroll
   for (int c = 0; c < kCB; ++c) {
     double* rw = row[c & 1];
-    rw[j] = g[c];
-    __syncthreads();
-    double d = rw[c];
+    double d = readlane_f64(g[c], c);  // G(c, c), from lane c
     if (!(d > 0.0) || !isfinite(d)) {
       bad = true;
       d = 1.0;
     }
-    const double r = sqrt(d), rinv = 1.0 / r;
-    const double rcj = j == c ? r : g[c] * rinv;
+    // 1 / sqrt(G(c, c)): the hardware estimate refined by two Newton steps
+    double y = __builtin_amdgcn_rsq(d);
+    y = y * (1.5 - 0.5 * d * y * y);
+    y = y * (1.5 - 0.5 * d * y * y);
+    const double rcj = j == c ? d * y : g[c] * y;  // R(c, j)
     g[c] = rcj;
+    rw[j] = rcj;  // row c of R, published
+    __syncthreads();
 #pragma unroll
-    for (int i = c + 1; i < kCB; ++i) g[i] -= (rw[i] * rinv) * rcj;
+    for (int i = c + 1; i < kCB; ++i) g[i] -= rw[i] * rcj;
   }
   if (bad && j == 0) flags[CF_BREAKDOWN] = 1;
 #pragma unroll
