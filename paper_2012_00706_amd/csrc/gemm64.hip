@@ -951,9 +951,7 @@ static int backward_impl(const TA* A, int64_t m, int64_t n, int64_t lda, const i
   if (nc == 0) {  // the skeleton is every column: Y = A, gA = gY
     rc = gY ? gather<double>(gY, ldgy, m, perm, k, gA, ldga, perm, 0, s)
             : gather<double>(nullptr, 1, m, nullptr, k, gA, ldga, perm, 1, s);
-    if (rc) return rc;
-    MPID_HIP(hipStreamSynchronize(s));
-    return ID_OK;
+    return rc;
   }
   if ((rc = gather<TA>(A, lda, m, perm, k, Bm, m, nullptr, 0, s))) return rc;
   // R factor of B: the caller's (any R with R^T R = B^T B, e.g. R11 of the
@@ -978,8 +976,19 @@ static int backward_impl(const TA* A, int64_t m, int64_t n, int64_t lda, const i
     Rf = Rq;
     ldrf = k;
   }
-  // the diagonal check of Rf (read at the end)
+  // the diagonal check of Rf, read before anything else is enqueued: the
+  // products run only for a nonsingular R, and the call then returns with
+  // them in flight (no wait at its end)
   if ((rc = solve_T_run(Rf, ldrf, k, k, nullptr, 1, dinfo, s))) return rc;
+  {
+    int32_t hinfo = 0;
+    MPID_HIP(hipMemcpyAsync(&hinfo, dinfo, 4, hipMemcpyDeviceToHost, s));
+    MPID_HIP(hipStreamSynchronize(s));
+    if (hinfo == ID_INFO_SINGULAR) {
+      *info = ID_INFO_SINGULAR;  // gA is left undefined
+      return ID_OK;
+    }
+  }
   // Tbar = gT + B^T gY(:, Jc)
   if (gT) {
     if ((rc = gather<double>(gT, ldgt, k, nullptr, nc, Tb, k, nullptr, 0, s))) return rc;
@@ -1039,10 +1048,6 @@ static int backward_impl(const TA* A, int64_t m, int64_t n, int64_t lda, const i
                                    (double*)(wb + p.off_p), p.p_bytes, s)))
       return rc;
   }
-  int32_t hinfo = 0;
-  MPID_HIP(hipMemcpyAsync(&hinfo, dinfo, 4, hipMemcpyDeviceToHost, s));
-  MPID_HIP(hipStreamSynchronize(s));
-  if (hinfo == ID_INFO_SINGULAR) *info = ID_INFO_SINGULAR;  // gA is then undefined
   return ID_OK;
 }
 
