@@ -1613,15 +1613,18 @@ struct ThreadRes {
   hipEvent_t pev[2] = {nullptr, nullptr};
   std::vector<hipEvent_t> prof_events;  // ID_FLAG_PROFILE
   PinnedBuf stage[2], lslots[2];  // lock-step tables and panel-end states
+  PinnedBuf probe;                // lock-step mid-panel end flags
   hipEvent_t ev_stage[2] = {nullptr, nullptr}, ev_slot[2] = {nullptr, nullptr};
+  hipEvent_t ev_probe = nullptr;
   int64_t ncalls = 0;             // tags the panel-end states of this thread's calls
   ThreadRes() = default;
   ThreadRes(const ThreadRes&) = delete;
   ThreadRes& operator=(const ThreadRes&) = delete;
   ~ThreadRes() {
-    for (PinnedBuf* b : {&slot, &stage[0], &stage[1], &lslots[0], &lslots[1]})
+    for (PinnedBuf* b : {&slot, &stage[0], &stage[1], &lslots[0], &lslots[1], &probe})
       if (b->p) (void)hipHostFree(b->p);
-    for (hipEvent_t e : {pev[0], pev[1], ev_stage[0], ev_stage[1], ev_slot[0], ev_slot[1]})
+    for (hipEvent_t e :
+         {pev[0], pev[1], ev_stage[0], ev_stage[1], ev_slot[0], ev_slot[1], ev_probe})
       if (e) (void)hipEventDestroy(e);
     for (hipEvent_t e : prof_events)
       if (e) (void)hipEventDestroy(e);
@@ -2299,18 +2302,31 @@ __global__ __launch_bounds__(kThreads) void k_check_many(const ManyItem<S>* __re
 
 namespace {
 
+// flags[t] = 1 when item t's current panel has ended (or the item is done),
+// for the first n items of the table: the host's mid-panel look at whether the
+// rest of a panel's steps would find anything to do.
+template <typename S>
+__global__ __launch_bounds__(kThreads) void k_probe_many(const ManyItem<S>* __restrict__ it, int n,
+                                                         int32_t* __restrict__ flags) {
+  const int t = (int)(blockIdx.x * kThreads + threadIdx.x);
+  if (t >= n) return;
+  const FactorState* st = it[t].step.st;
+  flags[t] = (st->end_flag || st->done) ? 1 : 0;
+}
+
 struct LockPlan {
   int Rt = 128;
   std::vector<FactorPlan> pl;   // per item
   std::vector<int> cw;          // sweep column chunk per item
   int64_t cap[LK_KINDS] = {0};  // map capacity per launch kind (blocks)
   int64_t max_n = 0;
-  size_t off_items = 0, off_ditems = 0, off_slots = 0, off_map[LK_KINDS] = {0};
+  size_t off_items = 0, off_ditems = 0, off_slots = 0, off_probe = 0, off_map[LK_KINDS] = {0};
   size_t bytes = 0;
 };
 
 constexpr int kManyTileMax = kFinZ * kFL;  // row tiles one finalization round trip covers
 constexpr int kManyBlocks = 4096;          // sweep blocks that fill the chip several times over
+constexpr int kProbe = 4;                  // steps before a panel's mid-panel look
 
 int lockstep_sweep_blocks(const FactorPlan& pl, int Rt, int cw, int64_t off) {
   const int64_t ntile = ceil_div(pl.m, Rt) - off / Rt;
@@ -2394,6 +2410,7 @@ static int make_lock_plan(const id_batch_item* items, int32_t batch, int32_t dty
   lp->off_items = take(sizeof(ManyItem<float>) * (size_t)std::max(batch, 1));
   lp->off_ditems = take(sizeof(id_batch_item) * (size_t)std::max(batch, 1));
   lp->off_slots = take(sizeof(FactorHostSlot) * (size_t)std::max(batch, 1));
+  lp->off_probe = take(sizeof(int32_t) * (size_t)std::max(batch, 1));
   for (int kd = 0; kd < LK_KINDS; ++kd) lp->off_map[kd] = take(4 * (size_t)std::max<int64_t>(lp->cap[kd], 1));
   lp->bytes = off;
   return ID_OK;
@@ -2416,6 +2433,7 @@ static int lockstep_impl(id_batch_item* items, int32_t batch, const id_opts* o, 
   ManyItem<S>* d_items = (ManyItem<S>*)(shared + lp.off_items);
   id_batch_item* d_bi = (id_batch_item*)(shared + lp.off_ditems);
   FactorHostSlot* d_slots = (FactorHostSlot*)(shared + lp.off_slots);
+  int32_t* d_probe = (int32_t*)(shared + lp.off_probe);
   int* d_map[LK_KINDS];
   for (int kd = 0; kd < LK_KINDS; ++kd) d_map[kd] = (int*)(shared + lp.off_map[kd]);
 
@@ -2438,6 +2456,13 @@ static int lockstep_impl(id_batch_item* items, int32_t batch, const id_opts* o, 
     rc = pinned_reserve(hslots[q], sizeof(FactorHostSlot) * (size_t)batch, hipHostMallocDefault);
     if (rc) return rc;
   }
+  {
+    const int rc = pinned_reserve(tr.probe, sizeof(int32_t) * (size_t)std::max(batch, 1),
+                                  hipHostMallocDefault);
+    if (rc) return rc;
+    if (!tr.ev_probe) MPID_HIP(hipEventCreateWithFlags(&tr.ev_probe, hipEventDisableTiming));
+  }
+  const int32_t* hprobe = (const int32_t*)tr.probe.p;
   int upload = 0;  // uploads so far (staging buffer upload & 1)
   // staging buffer for the next upload: its table and per-kind maps
   struct Stage {
@@ -2542,10 +2567,15 @@ static int lockstep_impl(id_batch_item* items, int32_t batch, const id_opts* o, 
   std::vector<int> in_panel[2];  // items (caller's index) of the last two panels
   std::vector<int> order;
   std::vector<int64_t> lim;
+  // the next panel enqueued takes the mid-panel look when every live item
+  // ended the last settled panel before its step limit (and the first panel)
+  bool probe_next = true;
+  std::vector<int64_t> lim_enq[2];  // the step limits the last two panels had
   auto settle = [&](int panel) -> int {
     const int q = panel & 1;
     MPID_HIP(hipEventSynchronize(ev_slot[q]));
     const FactorHostSlot* hs = (const FactorHostSlot*)hslots[q].p;
+    bool all_early = true;
     for (const int i : in_panel[q]) {
       if (done[i]) continue;
       const FactorHostSlot& sl = hs[i];
@@ -2558,8 +2588,10 @@ static int lockstep_impl(id_batch_item* items, int32_t batch, const id_opts* o, 
         continue;
       }
       if (h.last_jb <= 0) return ID_ERR_HIP;  // a live panel always makes progress
+      if (h.last_jb >= lim_enq[q][i]) all_early = false;
       known_off[i] += h.last_jb;
     }
+    probe_next = all_early;
     return ID_OK;
   };
   int panel = 0;
@@ -2576,6 +2608,7 @@ static int lockstep_impl(id_batch_item* items, int32_t batch, const id_opts* o, 
       lim[i] = std::min<int64_t>({(int64_t)pl.nb, pl.kcap - known_off[i], pl.n - known_off[i]});
     }
     std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return lim[x] > lim[y]; });
+    lim_enq[cur] = lim;
     Stage st;
     int rc = begin_stage(&st);
     if (rc) return rc;
@@ -2625,6 +2658,14 @@ static int lockstep_impl(id_batch_item* items, int32_t batch, const id_opts* o, 
              order.size(), (long long)used[LK_SWEEP], (long long)used[LK_GEMM]);
     const int64_t lmax = lim[order[0]];
     size_t live = order.size();
+    // Mid-panel looks (the first panel, and any panel after one in which
+    // every item ended early): every kProbe steps the items' end flags are
+    // copied to the host, which reads them once kProbe more steps are
+    // enqueued (the GPU is busy with those meanwhile) and launches no further
+    // steps when every live item's panel has already ended.  Stopping a panel
+    // early is always correct: its update applies the steps that ran.
+    const bool probe = probe_next && lmax >= 2 * kProbe;
+    size_t probe_live = 0;  // items the outstanding look covers (0: none)
     for (int jj = 0; jj < lmax; ++jj) {
       while (live > 0 && lim[order[live - 1]] <= jj) --live;
       if (live == 0) break;
@@ -2633,6 +2674,24 @@ static int lockstep_impl(id_batch_item* items, int32_t batch, const id_opts* o, 
       MPID_LAUNCH_CHECK();
       k_finalize_many<S, RM><<<dim3(gf), kThreads, 0, s>>>(d_items, d_map[LK_FIN], jj);
       MPID_LAUNCH_CHECK();
+      if (!probe || (jj + 1) % kProbe != 0 || jj + 1 >= lmax) continue;
+      if (probe_live > 0) {
+        // the look issued kProbe steps ago
+        MPID_HIP(hipEventSynchronize(tr.ev_probe));
+        bool all_ended = true;
+        for (size_t t = 0; t < probe_live && all_ended; ++t) all_ended = hprobe[t] != 0;
+        if (all_ended) {
+          MPID_LOG(2, "lock-step panel %d: every item ended by step %d", panel, jj + 1 - kProbe);
+          break;
+        }
+      }
+      probe_live = live;
+      k_probe_many<S><<<dim3((unsigned)ceil_div((int64_t)live, kThreads)), kThreads, 0, s>>>(
+          d_items, (int)live, d_probe);
+      MPID_LAUNCH_CHECK();
+      MPID_HIP(hipMemcpyAsync(tr.probe.p, d_probe, sizeof(int32_t) * live, hipMemcpyDeviceToHost,
+                              s));
+      MPID_HIP(hipEventRecord(tr.ev_probe, s));
     }
     k_panel_gemm_many<S, OP, RM><<<dim3((unsigned)used[LK_GEMM]), kThreads, 0, s>>>(
         d_items, d_map[LK_GEMM]);
