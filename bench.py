@@ -824,7 +824,7 @@ def main():
     args.profile_reps = max(args.profile_reps, 1)
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py: this build measures one GPU only (the column ID runs on a single "
+        print("bench.py: one GPU only (the column ID runs on a single "
               "MI355X); --gpus must be 1", file=sys.stderr)
         sys.exit(2)
 
