@@ -167,8 +167,11 @@ size_t id_workspace_size(int64_t m, int64_t n, int32_t dtype, const id_opts* opt
  *
  * Pivoting follows the largest remaining column norm with ties going to the
  * first column in the current (LAPACK swap) order.  The call enqueues work on
- * "stream" and synchronizes it before returning: the number of pivot steps is
- * data dependent.  Concurrent calls must use distinct workspaces.  A single
+ * "stream" and waits for it while it runs (the number of pivot steps is data
+ * dependent); it returns with k and info known and the final gather of perm
+ * and R still enqueued: they are complete when the stream's work is, and the
+ * workspace must not be reused on another stream before then.  Concurrent
+ * calls must use distinct workspaces.  A single
  * ID that can be captured in a graph (k and info left in device memory, no
  * host synchronization) is id_factor_batched with a batch of one item, whose
  * workgroups share it (up to ID_BATCH_MAX_GROUPS). */

@@ -2005,8 +2005,9 @@ static int factor_impl(const TA* A, int64_t lda, const FactorPlan& pl, const id_
     }
   }
   if (!fin->done) return ID_ERR_HIP;
-  // the panel enqueued after the stop (if any) only found the done flag
-  MPID_HIP(hipStreamSynchronize(s));
+  // (the panel enqueued after the stop, if any, only finds the done flag; its
+  // norm reduction writes the other host slot, so fin stays valid, and the
+  // gather below is ordered after it on the stream: no wait here)
   const int64_t k = fin->k;
   *k_out = k;
   *info = fin->info;
@@ -2014,6 +2015,9 @@ static int factor_impl(const TA* A, int64_t lda, const FactorPlan& pl, const id_
   k_finish<<<dim3((unsigned)n, (unsigned)(k > 0 ? ceil_div(k, kThreads) : 1)), kThreads, 0, s>>>(
       make_finish_args(pl, wb, perm, R, ldr, k));
   MPID_LAUNCH_CHECK();
+  // the static scratch is shared by every call on the device: it is free again
+  // only when this call's work is done
+  if (noalloc) MPID_HIP(hipStreamSynchronize(s));
   if (prof.on) {
     MPID_HIP(hipEventRecord(ev_t1, s));
     MPID_HIP(hipEventSynchronize(ev_t1));
