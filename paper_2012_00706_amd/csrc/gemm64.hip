@@ -609,9 +609,10 @@ constexpr int kAdjKMax = 256;   // largest k the fused kernel takes
 //            gA(i, Jc[j]) = P_X,  E = gY(i, Jc[j]) - P_X,  D = A(i, Jc[j]) - P_T
 //            (E and D go to LDS)
 //   phase 2: acc(i, c) += sum_j D(i, j) X(c, j) + E(i, j) T(c, j)   (K = 2 x 128)
-// and finally gA(i, J[c]) = gY(i, J[c]) + acc(i, c).  Wave w owns columns
-// [32 w, 32 w + 32) of each chunk in phase 1 and NB2 blocks of 16 columns c
-// of k in phase 2 (4 NB2 16 >= k), for all RB row blocks of the strip.
+// and finally gA(i, J[c]) = gY(i, J[c]) + acc(i, c).  Wave w of the NW owns
+// columns [CPW w, CPW (w + 1)) of each chunk in phase 1 (CPW = 128 / NW) and
+// 4 NB2 / NW blocks of 16 columns c of k in phase 2 (4 NB2 16 >= k), for all
+// RB row blocks of the strip.
 // Operand lanes: a lane supplies A(row li, kk) and B(kk, col li) and receives
 // C(row li, col g + 4 r) (operands fed swapped, as in k_gemm64t).  The
 // contraction runs in groups of 16 in which lane group g takes the four
@@ -622,10 +623,15 @@ constexpr int kAdjKMax = 256;   // largest k the fused kernel takes
 // the products are bound by these operand reads); the A operands come from
 // LDS in the same order.  Columns past nc or k read clamped in-range columns
 // and are never stored; rows past m are zero in LDS and not stored.
-template <typename TA, int NB2, int RB>
-__global__ __launch_bounds__(kThreads) void k_adj_fused(AdjArgs<TA> a) {
+template <typename TA, int NB2, int RB, int NW>
+__global__ __launch_bounds__(64 * NW) void k_adj_fused(AdjArgs<TA> a) {
+  constexpr int NT = 64 * NW;                   // threads (NW waves)
   constexpr int KB = 64 * NB2;                  // largest k of this instantiation
   constexpr int RS = 16 * RB;                   // rows of the strip
+  constexpr int CPW = kAdjChunk / NW;           // chunk columns per wave in phase 1
+  constexpr int NB1 = CPW / 16;                 // ... as 16-column blocks
+  constexpr int NBK = 4 * NB2 / NW;             // 16-column blocks of k per wave in phase 2
+  static_assert(NB1 >= 1 && NBK >= 1 && NBK * NW == 4 * NB2, "wave split");
   // operand groups in flight: a taller strip has fewer resident waves (its
   // LDS allows one block per compute unit), so it keeps more loads ahead
   constexpr int PD = RB == 2 ? 4 : 2;
@@ -644,28 +650,28 @@ __global__ __launch_bounds__(kThreads) void k_adj_fused(AdjArgs<TA> a) {
   }
   const int ng1 = (int)(a.kq / 16);  // contraction groups of phase 1
   // the strip of B (rows past m and columns past k zero)
-  for (int e = tid; e < KB * RS; e += kThreads) {
+  for (int e = tid; e < KB * RS; e += NT) {
     const int r = e % RS, kk = e / RS;
     const int64_t gi = i0 + r;
     Bs[kk][r] = (gi < m && kk < k) ? a.Bm[(int64_t)kk * m + gi] : 0.0;
   }
-  f64x4 acc2[RB][NB2], acc3[RB][NB2];
+  f64x4 acc2[RB][NBK], acc3[RB][NBK];
 #pragma unroll
   for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
-    for (int nb = 0; nb < NB2; ++nb) {
+    for (int nb = 0; nb < NBK; ++nb) {
       acc2[rb][nb] = (f64x4){0.0, 0.0, 0.0, 0.0};
       acc3[rb][nb] = acc2[rb][nb];
     }
   for (int64_t c0 = 0; c0 < nc; c0 += kAdjChunk) {
     // the epilogue's inputs: rows i, columns Jc[j] for the lane's outputs
-    // j = c0 + 32 w + 16 nb + g + 4 r (loaded ahead of the products)
-    double ein[RB][2][4], cin[RB][2][4];
+    // j = c0 + CPW w + 16 nb + g + 4 r (loaded ahead of the products)
+    double ein[RB][NB1][4], cin[RB][NB1][4];
 #pragma unroll
-    for (int nb = 0; nb < 2; ++nb)
+    for (int nb = 0; nb < NB1; ++nb)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int64_t j = c0 + 32 * wv + 16 * nb + g + 4 * r;
+        const int64_t j = c0 + CPW * wv + 16 * nb + g + 4 * r;
         const int64_t col = a.perm[k + (j < nc ? j : nc - 1)];
 #pragma unroll
         for (int rb = 0; rb < RB; ++rb) {
@@ -675,11 +681,11 @@ __global__ __launch_bounds__(kThreads) void k_adj_fused(AdjArgs<TA> a) {
       }
     __syncthreads();  // Bs ready (first pass); Es / Ds free (later passes)
     // ---- phase 1, one 16-column block nb at a time: the B operands are
-    // columns j = c0 + 32 w + 16 nb + li of X and T, two groups in flight
-    f64x4 px[RB][2], pt[RB][2];
+    // columns j = c0 + CPW w + 16 nb + li of X and T
+    f64x4 px[RB][NB1], pt[RB][NB1];
 #pragma unroll
-    for (int nb = 0; nb < 2; ++nb) {
-      const int64_t j = c0 + 32 * wv + 16 * nb + li;
+    for (int nb = 0; nb < NB1; ++nb) {
+      const int64_t j = c0 + CPW * wv + 16 * nb + li;
       const int64_t jc = j < nc ? j : nc - 1;
       const double* xcol = a.Xp + jc * a.kq + 4 * g;
       const double* tcol = a.Tp + jc * a.kq + 4 * g;
@@ -724,10 +730,10 @@ __global__ __launch_bounds__(kThreads) void k_adj_fused(AdjArgs<TA> a) {
     }
     // ---- epilogue: gA(i, Jc[j]) = P_X; E and D to LDS (zero past nc / m)
 #pragma unroll
-    for (int nb = 0; nb < 2; ++nb)
+    for (int nb = 0; nb < NB1; ++nb)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int jl = 32 * wv + 16 * nb + g + 4 * r;
+        const int jl = CPW * wv + 16 * nb + g + 4 * r;
         const int64_t j = c0 + jl;
         const int64_t col = j < nc ? (int64_t)a.perm[k + j] : 0;
 #pragma unroll
@@ -748,8 +754,8 @@ __global__ __launch_bounds__(kThreads) void k_adj_fused(AdjArgs<TA> a) {
       const int64_t jn = nc - c0 < kAdjChunk ? nc - c0 : kAdjChunk;
       const int ng2 = (int)ceil_div(jn, (int64_t)16);
 #pragma unroll
-      for (int nb = 0; nb < NB2; ++nb) {
-        const int64_t c = (int64_t)16 * (NB2 * wv + nb) + li;
+      for (int nb = 0; nb < NBK; ++nb) {
+        const int64_t c = (int64_t)16 * (NBK * wv + nb) + li;
         const int64_t cc = c < k ? c : k - 1;
         const double* xrow = a.Xq + cc * a.nq + c0 + 4 * g;
         const double* trow = a.Tq + cc * a.nq + c0 + 4 * g;
@@ -801,10 +807,10 @@ __global__ __launch_bounds__(kThreads) void k_adj_fused(AdjArgs<TA> a) {
   for (int rb = 0; rb < RB; ++rb) {
     if (iw[rb] < m) {
 #pragma unroll
-      for (int nb = 0; nb < NB2; ++nb)
+      for (int nb = 0; nb < NBK; ++nb)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          const int64_t c = (int64_t)16 * (NB2 * wv + nb) + g + 4 * r;
+          const int64_t c = (int64_t)16 * (NBK * wv + nb) + g + 4 * r;
           if (c < k) {
             const int64_t col = a.perm[c];
             const double y = a.gY ? a.gY[col * a.ldgy + iw[rb]] : 0.0;
@@ -1030,17 +1036,24 @@ static int backward_impl(const TA* A, int64_t m, int64_t n, int64_t lda, const i
     MPID_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
     const int rb = env_flag("MPID_ADJ_RB2", 1) && ceil_div(m, (int64_t)32) >= (cus > 0 ? cus : 256)
                        ? 2 : 1;
+    // the 32-row strips' LDS leaves one block per compute unit: eight waves
+    // per block then give each SIMD two to switch between
+    const int nw = env_flag("MPID_ADJ_WAVES", 8) == 4 ? 4 : 8;
     const dim3 fg((unsigned)ceil_div(m, (int64_t)16 * rb));
     if (k <= 128) {
-      if (rb == 2)
-        k_adj_fused<TA, 2, 2><<<fg, kThreads, 0, s>>>(fa);
+      if (rb == 2 && nw == 8)
+        k_adj_fused<TA, 2, 2, 8><<<fg, 512, 0, s>>>(fa);
+      else if (rb == 2)
+        k_adj_fused<TA, 2, 2, 4><<<fg, 256, 0, s>>>(fa);
       else
-        k_adj_fused<TA, 2, 1><<<fg, kThreads, 0, s>>>(fa);
+        k_adj_fused<TA, 2, 1, 4><<<fg, 256, 0, s>>>(fa);
     } else {
-      if (rb == 2)
-        k_adj_fused<TA, 4, 2><<<fg, kThreads, 0, s>>>(fa);
+      if (rb == 2 && nw == 8)
+        k_adj_fused<TA, 4, 2, 8><<<fg, 512, 0, s>>>(fa);
+      else if (rb == 2)
+        k_adj_fused<TA, 4, 2, 4><<<fg, 256, 0, s>>>(fa);
       else
-        k_adj_fused<TA, 4, 1><<<fg, kThreads, 0, s>>>(fa);
+        k_adj_fused<TA, 4, 1, 4><<<fg, 256, 0, s>>>(fa);
     }
     MPID_LAUNCH_CHECK();
   } else {
