@@ -632,9 +632,10 @@ __global__ __launch_bounds__(64 * NW) void k_adj_fused(AdjArgs<TA> a) {
   constexpr int NB1 = CPW / 16;                 // ... as 16-column blocks
   constexpr int NBK = 4 * NB2 / NW;             // 16-column blocks of k per wave in phase 2
   static_assert(NB1 >= 1 && NBK >= 1 && NBK * NW == 4 * NB2, "wave split");
-  // operand groups in flight: a taller strip has fewer resident waves (its
-  // LDS allows one block per compute unit), so it keeps more loads ahead
-  constexpr int PD = RB == 2 ? 4 : 2;
+  // operand groups in flight: four for a block that is the only one on its
+  // compute unit with one wave per SIMD (32-row strips, four waves), two
+  // when each SIMD has other waves to switch to
+  constexpr int PD = (RB == 2 && NW == 4) ? 4 : 2;
   __shared__ double Bs[KB][RS];                 // Bs[kk][i] = B(i0 + i, kk)
   __shared__ double Es[kAdjChunk][RS];          // Es[j][i] = E(i0 + i, c0 + j)
   __shared__ double Ds[kAdjChunk][RS];
