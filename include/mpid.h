@@ -267,9 +267,9 @@ size_t id_backward_workspace_size(int64_t m, int64_t n, int64_t k);
  *   work    [in]  workspace of >= id_backward_workspace_size(m, n, k) bytes.
  *   info    [host,out] 0 or ID_INFO_SINGULAR (B numerically rank deficient;
  *           gA is then left undefined and nothing more is enqueued).
- * Waits for "stream" once, to read the check of R's diagonal (and, with Rb
- * NULL, inside the QR of B), then enqueues the products on "stream" and
- * returns: gA is complete when the stream's work is (stream-ordered, like
+ * Waits once, for the check of R's diagonal (while the first products run;
+ * with Rb NULL also inside the QR of B), then enqueues the rest on "stream"
+ * and returns: gA is complete when the stream's work is (stream-ordered, like
  * id_reconstruct); work must not be reused on another stream before then. */
 int id_backward(const void* A, int32_t dtype, int64_t m, int64_t n, int64_t lda,
                 const int32_t* perm, int64_t k, const double* T, int64_t ldt, const double* Rb,

@@ -835,6 +835,25 @@ struct BwdPlan {
   size_t fws_bytes, sk_bytes, p_bytes, bytes;
 };
 
+// A thread's pinned word and event for reading the singular-R check of
+// id_backward without waiting for the whole stream (released when the thread
+// ends).
+struct BwdHostInfo {
+  int32_t* p = nullptr;
+  hipEvent_t ev = nullptr;
+  BwdHostInfo() = default;
+  BwdHostInfo(const BwdHostInfo&) = delete;
+  BwdHostInfo& operator=(const BwdHostInfo&) = delete;
+  ~BwdHostInfo() {
+    if (p) (void)hipHostFree(p);
+    if (ev) (void)hipEventDestroy(ev);
+  }
+};
+static BwdHostInfo& bwd_host_info() {
+  static thread_local BwdHostInfo h;
+  return h;
+}
+
 static bool make_bwd_plan(int64_t m, int64_t n, int64_t k, BwdPlan* p) {
   if (m < 0 || n < 0 || k < 0 || k > n) return false;
   const int64_t mm = m > 0 ? m : 1, kk = k > 0 ? k : 1, cc = (n - k) > 0 ? (n - k) : 1;
@@ -983,20 +1002,17 @@ static int backward_impl(const TA* A, int64_t m, int64_t n, int64_t lda, const i
     Rf = Rq;
     ldrf = k;
   }
-  // the diagonal check of Rf, read before anything else is enqueued: the
-  // products run only for a nonsingular R, and the call then returns with
-  // them in flight (no wait at its end)
+  // the diagonal check of Rf, copied to pinned host memory; the products
+  // that do not need it (Tbar = gT + B^T gY(:, Jc)) are enqueued before the
+  // host waits for that copy, so the GPU is busy with them meanwhile; the
+  // rest is enqueued only for a nonsingular R, and the call then returns with
+  // it in flight (no wait at its end)
   if ((rc = solve_T_run(Rf, ldrf, k, k, nullptr, 1, dinfo, s))) return rc;
-  {
-    int32_t hinfo = 0;
-    MPID_HIP(hipMemcpyAsync(&hinfo, dinfo, 4, hipMemcpyDeviceToHost, s));
-    MPID_HIP(hipStreamSynchronize(s));
-    if (hinfo == ID_INFO_SINGULAR) {
-      *info = ID_INFO_SINGULAR;  // gA is left undefined
-      return ID_OK;
-    }
-  }
-  // Tbar = gT + B^T gY(:, Jc)
+  BwdHostInfo& hi = bwd_host_info();
+  if (!hi.p) MPID_HIP(hipHostMalloc((void**)&hi.p, sizeof(int32_t), hipHostMallocDefault));
+  if (!hi.ev) MPID_HIP(hipEventCreateWithFlags(&hi.ev, hipEventDisableTiming));
+  MPID_HIP(hipMemcpyAsync(hi.p, dinfo, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  MPID_HIP(hipEventRecord(hi.ev, s));
   if (gT) {
     if ((rc = gather<double>(gT, ldgt, k, nullptr, nc, Tb, k, nullptr, 0, s))) return rc;
   } else {
@@ -1011,6 +1027,11 @@ static int backward_impl(const TA* A, int64_t m, int64_t n, int64_t lda, const i
     k_axpy_cols<<<dim3((unsigned)ceil_div(k, kThreads), (unsigned)nc), kThreads, 0, s>>>(
         Tb, k, btg, k, k, 1.0);
     MPID_LAUNCH_CHECK();
+  }
+  MPID_HIP(hipEventSynchronize(hi.ev));
+  if (*hi.p == ID_INFO_SINGULAR) {
+    *info = ID_INFO_SINGULAR;  // gA is left undefined
+    return ID_OK;
   }
   // X = (B^T B)^{-1} Tbar = R^{-1} R^{-T} Tbar into the left half of [X | T]
   double* X = XT;

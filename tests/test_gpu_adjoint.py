@@ -171,3 +171,33 @@ def test_backward_tall_strips(monkeypatch, k, dtype):
     assert rel_err(g2, g1) <= 1e-12
     ref = orc.adjoint(A.astype(np.float64), perm, k, T, gT=gT, gY=gY)
     assert rel_err(g2, ref) <= 1e-10
+
+
+def test_backward_singular_skeleton_reported():
+    """A singular R factor of the skeleton is reported (ID_INFO_SINGULAR, as
+    MpidError) instead of a gradient, with the caller's R11 and with the QR
+    computed inside; a regular call on the same thread afterwards still
+    matches the oracle's adjoint."""
+    need_gpu()
+    import paper_2012_00706_amd as mp
+    A = synth.spectrum_matrix(500, 40, synth.sigma_exp(40, 20.0), 501, 41)
+    k = 10
+    res = mp.column_id(to_dev(A), k=k)
+    rng = np.random.default_rng(3)
+    gT = rng.standard_normal((k, 40 - k))
+    gY = rng.standard_normal((500, 40))
+    R11 = res.R[:, :k].clone()
+    R11[4, 4] = 0.0
+    with pytest.raises(mp.MpidError) as e:
+        mp.backward(to_dev(A), res.perm, k, res.T, gT=to_dev(gT), gY=to_dev(gY), R11=R11)
+    assert e.value.code == mp.C["ID_INFO_SINGULAR"]
+    perm = host(res.perm).astype(np.int64)
+    A2 = A.copy()
+    A2[:, perm[1]] = A2[:, perm[0]]  # two equal skeleton columns
+    with pytest.raises(mp.MpidError) as e:
+        mp.backward(to_dev(A2), res.perm, k, res.T, gT=to_dev(gT), gY=to_dev(gY))
+    assert e.value.code == mp.C["ID_INFO_SINGULAR"]
+    gA = host(mp.backward(to_dev(A), res.perm, k, res.T, gT=to_dev(gT), gY=to_dev(gY),
+                          R11=res.R[:, :k]))
+    ref = orc.adjoint(A, perm, k, host(res.T), gT=gT, gY=gY)
+    assert rel_err(gA, ref) <= 1e-10
