@@ -488,14 +488,6 @@ static int gather(const TA* A, int64_t lda, int64_t m, const int32_t* cols, int6
   return ID_OK;
 }
 
-__global__ __launch_bounds__(kThreads) void k_axpy_cols(double* __restrict__ X, int64_t ldx,
-                                                        const double* __restrict__ Y, int64_t ldy,
-                                                        int64_t m, double alpha) {
-  const int64_t j = blockIdx.y;
-  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-  if (i < m) X[j * ldx + i] += alpha * Y[j * ldy + i];
-}
-
 template <typename TA>
 static int reconstruct_impl(const TA* A, int64_t m, int64_t n, int64_t lda, const int32_t* perm,
                             int64_t k, const double* T, int64_t ldt, double* Y, int64_t ldy,
@@ -830,7 +822,7 @@ __global__ __launch_bounds__(64 * NW) void k_adj_fused(AdjArgs<TA> a) {
 constexpr int kBwdSketchBlocks = 1024;
 
 struct BwdPlan {
-  size_t off_b, off_de, off_xt, off_tbar, off_rq, off_permq, off_info, off_fws, off_btg, off_sk,
+  size_t off_b, off_de, off_xt, off_tbar, off_rq, off_permq, off_info, off_fws, off_sk,
       off_p, off_pad;
   size_t fws_bytes, sk_bytes, p_bytes, bytes;
 };
@@ -880,9 +872,8 @@ static bool make_bwd_plan(int64_t m, int64_t n, int64_t k, BwdPlan* p) {
   if (!make_factor_plan(mm, kk, ID_F64, &o, &fp)) return false;
   p->fws_bytes = fp.bytes;
   p->off_fws = take(fp.bytes);
-  // B^T gY(:, Jc): k x (n-k) with a contraction over all m rows, split over
-  // row chunks (few output tiles, long contraction)
-  p->off_btg = take((size_t)kk * cc * 8);
+  // partials of B^T gY(:, Jc): k x (n-k) with a contraction over all m
+  // rows, split over row chunks (few output tiles, long contraction)
   p->sk_bytes = sketch_workspace_target(kk, mm, cc, kBwdSketchBlocks);
   p->off_sk = take(p->sk_bytes);
   // split-K partials of the m x k product with the 2(n-k) contraction
@@ -1019,14 +1010,11 @@ static int backward_impl(const TA* A, int64_t m, int64_t n, int64_t lda, const i
     if ((rc = gather<double>(nullptr, 1, k, nullptr, nc, Tb, k, nullptr, 1, s))) return rc;
   }
   if (gY) {
-    // B^T as a row-major k x m matrix is B's column-major storage
-    double* btg = (double*)(wb + p.off_btg);
-    if ((rc = sketch_run_cols(gY, ID_F64, m, nc, ldgy, perm + k, Bm, k, m, btg, k, wb + p.off_sk,
-                              p.sk_bytes, kBwdSketchBlocks, s)))
+    // Tbar += B^T gY(:, Jc), added by the product's reduction (B^T as a
+    // row-major k x m matrix is B's column-major storage)
+    if ((rc = sketch_run_cols(gY, ID_F64, m, nc, ldgy, perm + k, Bm, k, m, Tb, k, wb + p.off_sk,
+                              p.sk_bytes, kBwdSketchBlocks, s, 1)))
       return rc;
-    k_axpy_cols<<<dim3((unsigned)ceil_div(k, kThreads), (unsigned)nc), kThreads, 0, s>>>(
-        Tb, k, btg, k, k, 1.0);
-    MPID_LAUNCH_CHECK();
   }
   MPID_HIP(hipEventSynchronize(hi.ev));
   if (*hi.p == ID_INFO_SINGULAR) {
@@ -1035,8 +1023,7 @@ static int backward_impl(const TA* A, int64_t m, int64_t n, int64_t lda, const i
   }
   // X = (B^T B)^{-1} Tbar = R^{-1} R^{-T} Tbar into the left half of [X | T]
   double* X = XT;
-  if ((rc = trsm_upper_run(Rf, ldrf, k, Tb, k, nc, Tb, k, 1, s))) return rc;
-  if ((rc = trsm_upper_run(Rf, ldrf, k, Tb, k, nc, X, k, 0, s))) return rc;
+  if ((rc = trsm_normal_run(Rf, ldrf, k, Tb, k, nc, X, k, s))) return rc;
   double* pad = (double*)(wb + p.off_pad);
   // (the fused kernel reads the padded copies in aligned 32-byte groups)
   if (k <= kAdjKMax && (uintptr_t)pad % 32 == 0 && env_flag("MPID_ADJ_FUSED", 1)) {

@@ -117,6 +117,10 @@ int round_run(double* X, int64_t rows, int64_t cols, int64_t ld, int32_t mode, h
 // trans = 1 solves R^T X = B.  B (k x ncols, ldb) and X (ldx) may alias.
 int trsm_upper_run(const double* R, int64_t ldr, int64_t k, const double* B, int64_t ldb,
                    int64_t ncols, double* X, int64_t ldx, int trans, hipStream_t s);
+// X = R^{-1} R^{-T} B in one launch (B is overwritten with R^{-T} B; X may
+// alias B).
+int trsm_normal_run(const double* R, int64_t ldr, int64_t k, double* B, int64_t ldb,
+                    int64_t ncols, double* X, int64_t ldx, hipStream_t s);
 
 // C = alpha * op(A) op(B) + beta * C (column-major float64; ta/tb: 0 = N, 1 = T).
 // Bytes of split-K partials gemm64 uses for an M x N product with contraction K
@@ -157,11 +161,13 @@ int backward_run(const void* A, int32_t dtype, int64_t m, int64_t n, int64_t lda
 
 size_t sketch_workspace(int64_t l, int64_t m, int64_t n);
 // sketch_run with column j of A taken from A(:, acols[j]) (acols may be null)
-// and the contraction split for about target_blocks blocks (0: the default)
+// and the contraction split for about target_blocks blocks (0: the default);
+// accumulate != 0 adds the product to Y instead of overwriting it
 size_t sketch_workspace_target(int64_t l, int64_t m, int64_t n, int target_blocks);
 int sketch_run_cols(const void* A, int32_t dtype, int64_t m, int64_t n, int64_t lda,
                     const int32_t* acols, const double* Om, int64_t l, int64_t ldo, double* Y,
-                    int64_t ldy, void* work, size_t work_bytes, int target_blocks, hipStream_t s);
+                    int64_t ldy, void* work, size_t work_bytes, int target_blocks, hipStream_t s,
+                    int accumulate = 0);
 int sketch_run(const void* A, int32_t dtype, int64_t m, int64_t n, int64_t lda, const double* Om,
                int64_t l, int64_t ldo, double* Y, int64_t ldy, void* work, size_t work_bytes,
                hipStream_t s);

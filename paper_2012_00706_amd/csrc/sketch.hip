@@ -199,7 +199,8 @@ k_sketch_partial(const double* __restrict__ Om, int64_t ldo, const TA* __restric
 __global__ __launch_bounds__(kThreads) void k_sketch_reduce(const double* __restrict__ P,
                                                           int64_t S, int64_t ntiles, int64_t ntn,
                                                           int64_t l, int64_t n,
-                                                          double* __restrict__ Y, int64_t ldy) {
+                                                          double* __restrict__ Y, int64_t ldy,
+                                                          int accumulate) {
   const int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x;
   if (e >= ntiles * 4096) return;
   const int64_t tile = e / 4096, w = e % 4096;
@@ -207,13 +208,14 @@ __global__ __launch_bounds__(kThreads) void k_sketch_reduce(const double* __rest
   if (x >= l || y >= n) return;
   double v = 0.0;
   for (int64_t s = 0; s < S; ++s) v += P[(s * ntiles + tile) * 4096 + w];
-  Y[y * ldy + x] = v;
+  double* out = Y + y * ldy + x;
+  *out = accumulate ? *out + v : v;
 }
 
 template <typename TA>
 int sketch_impl(const TA* A, int64_t m, int64_t n, int64_t lda, const int32_t* acols,
                 const double* Om, int64_t l, int64_t ldo, double* Y, int64_t ldy,
-                const SketchPlan& p, double* P, hipStream_t s) {
+                const SketchPlan& p, double* P, hipStream_t s, int accumulate) {
   const dim3 grid((unsigned)round_up(p.S * p.ntiles, 8));
   // 16-byte loads need 16-byte aligned rows of Omega and columns of A
   const bool vec = ((uintptr_t)Om % 16 == 0) && (ldo % 2 == 0) && ((uintptr_t)A % 16 == 0) &&
@@ -226,7 +228,7 @@ int sketch_impl(const TA* A, int64_t m, int64_t n, int64_t lda, const int32_t* a
                                                           p.ntn, p.ntiles, p.S, p.chunk, P);
   MPID_LAUNCH_CHECK();
   k_sketch_reduce<<<dim3((unsigned)ceil_div(p.ntiles * 4096, kThreads)), kThreads, 0, s>>>(
-      P, p.S, p.ntiles, p.ntn, l, n, Y, ldy);
+      P, p.S, p.ntiles, p.ntn, l, n, Y, ldy, accumulate);
   MPID_LAUNCH_CHECK();
   return ID_OK;
 }
@@ -254,7 +256,8 @@ size_t sketch_workspace_target(int64_t l, int64_t m, int64_t n, int target_block
 
 int sketch_run_cols(const void* A, int32_t dtype, int64_t m, int64_t n, int64_t lda,
                     const int32_t* acols, const double* Om, int64_t l, int64_t ldo, double* Y,
-                    int64_t ldy, void* work, size_t work_bytes, int target_blocks, hipStream_t s) {
+                    int64_t ldy, void* work, size_t work_bytes, int target_blocks, hipStream_t s,
+                    int accumulate) {
   if (dtype != ID_F32 && dtype != ID_F64) return ID_ERR_DTYPE;
   SketchPlan p;
   if (!make_sketch_plan(l, m, n, &p, target_blocks)) return ID_ERR_ARG;
@@ -264,8 +267,10 @@ int sketch_run_cols(const void* A, int32_t dtype, int64_t m, int64_t n, int64_t 
   if (!work || work_bytes < p.bytes) return ID_ERR_WORKSPACE;
   double* P = (double*)work;
   if (dtype == ID_F64)
-    return sketch_impl<double>((const double*)A, m, n, lda, acols, Om, l, ldo, Y, ldy, p, P, s);
-  return sketch_impl<float>((const float*)A, m, n, lda, acols, Om, l, ldo, Y, ldy, p, P, s);
+    return sketch_impl<double>((const double*)A, m, n, lda, acols, Om, l, ldo, Y, ldy, p, P, s,
+                               accumulate);
+  return sketch_impl<float>((const float*)A, m, n, lda, acols, Om, l, ldo, Y, ldy, p, P, s,
+                            accumulate);
 }
 
 }  // namespace mpid

@@ -225,6 +225,28 @@ int trsm_upper_run(const double* R, int64_t ldr, int64_t k, const double* B, int
   return ID_OK;
 }
 
+// X = R^{-1} R^{-T} B (the normal-equations solve (R^T R)^{-1} B): both
+// solves of a column block back to back in one launch, R^{-T} B written over
+// B first.
+__global__ __launch_bounds__(kThreads) void k_trsm_upper_normal(const double* __restrict__ R,
+                                                               int64_t ldr, int64_t k, double* B,
+                                                               int64_t ldb, int64_t ncols,
+                                                               double* X, int64_t ldx) {
+  const int64_t c0 = (int64_t)blockIdx.x * kTC;
+  trsm_block(R, ldr, k, B, ldb, ncols, B, ldb, 1, c0);
+  __syncthreads();  // the first solve's last reads of LDS are done
+  trsm_block(R, ldr, k, B, ldb, ncols, X, ldx, 0, c0);
+}
+
+int trsm_normal_run(const double* R, int64_t ldr, int64_t k, double* B, int64_t ldb,
+                    int64_t ncols, double* X, int64_t ldx, hipStream_t s) {
+  if (k <= 0 || ncols <= 0) return ID_OK;
+  k_trsm_upper_normal<<<dim3((unsigned)ceil_div(ncols, kTC)), kThreads, 0, s>>>(R, ldr, k, B, ldb,
+                                                                                ncols, X, ldx);
+  MPID_LAUNCH_CHECK();
+  return ID_OK;
+}
+
 int trsm_batched_run(const id_batch_item* items, int32_t batch, int64_t max_n, hipStream_t s) {
   if (batch <= 0 || max_n <= 0) return ID_OK;
   k_trsm_batched<<<dim3((unsigned)batch, (unsigned)ceil_div(max_n, kTC)), kThreads, 0, s>>>(items);
