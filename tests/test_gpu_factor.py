@@ -336,3 +336,30 @@ def test_fixed_rank_after_early_panel_end(prec):
     e = orc.id_error(A, perm, 40, T)[0]
     e_ref = orc.id_error(A, ref.perm, 40, orc.solve_T(ref.R, 40))[0]
     assert e <= 1.1 * e_ref + 10 * U_LOW[prec] * s[0]
+
+
+def test_back_to_back_calls_share_a_workspace():
+    """id_factor returns once k is known, with its final gather of R and perm
+    still in flight on the stream: a second call on the same stream and the
+    same workspace (no synchronization in between) must not disturb the
+    first call's outputs, and both equal the results of separate calls."""
+    need_gpu()
+    import paper_2012_00706_amd as mp
+    A1 = synth.spectrum_matrix(2000, 300, synth.sigma_exp(300, 12.0), 71, 72)
+    A2 = synth.spectrum_matrix(2500, 280, synth.sigma_exp(280, 10.0), 73, 74)
+    d1, d2 = to_dev(A1), to_dev(A2)
+    ref = []
+    for d in (d1, d2):
+        fr = mp.factor(d, tol=1e-4, prec="f64")
+        torch.cuda.synchronize()
+        ref.append((fr.k, host(fr.perm).copy(), host(fr.R).copy()))
+    o = mp.make_opts(tol=1e-4, prec="f64")
+    work = torch.empty(mp.workspace_size(2500, 300, torch.float64, o), dtype=torch.uint8,
+                       device="cuda")
+    f1 = mp.factor(d1, tol=1e-4, prec="f64", work=work)
+    f2 = mp.factor(d2, tol=1e-4, prec="f64", work=work)
+    torch.cuda.synchronize()
+    for fr, (k, perm, R) in zip((f1, f2), ref):
+        assert fr.k == k
+        assert np.array_equal(host(fr.perm), perm)
+        assert np.array_equal(host(fr.R), R)
